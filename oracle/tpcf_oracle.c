@@ -1,0 +1,215 @@
+/*
+ * CPU oracle for angular pair counting -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this library.  The product path (the HIP library) shares no code
+ * with it and never calls it.
+ *
+ * What it computes (paper, Section 1 and Section 3, first two bullets):
+ *   - every object is a unit vector on the sky, built from (RA, Dec);
+ *   - the angle between two objects is the arc-cosine of the dot product of
+ *     their unit vectors;
+ *   - DD counts pairs of objects within the data catalog, RR within the
+ *     random catalog, and DR pairs of one data and one random object, each
+ *     as a histogram over angular-separation bins (theta space, not cos theta,
+ *     Section 2).
+ *
+ * Readings of points the paper leaves open (each is listed in the design
+ * notes of the repository):
+ *   - DD and RR count unordered pairs i < j, self-pairs excluded; DR counts
+ *     all N_D * N_R pairs, coincident positions included;
+ *   - the dot product is evaluated in FP64 as (x_i x_j + y_i y_j) + z_i z_j,
+ *     left to right, each operation rounded (no fused multiply-add), and is
+ *     clamped to [-1, 1] before the arc-cosine (host libm acos);
+ *   - edges are given in degrees and converted with edge * (pi / 180);
+ *     slot s of the output is the number of edges e_k with e_k <= theta, so
+ *     slot 0 is theta < e_0, slot k+1 is e_k <= theta < e_{k+1}, and slot
+ *     nbins+1 is theta >= e_nbins (ties go to the upper bin).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fno-builtin -shared -fPIC
+ * -pthread (no builtins: sin and cos stay separate libm calls).
+ * Every loop below is the plain definition; threads only split the rows i.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* Unit vector of an object at right ascension ra and declination dec, both
+ * in degrees: x = cos(dec) cos(ra), y = cos(dec) sin(ra), z = sin(dec).  The
+ * paper forms the angle from a dot product (Section 3), which presumes these
+ * unit vectors. */
+void oracle_radec_to_xyz(int64_t n, const double *ra_deg, const double *dec_deg,
+                         double *x, double *y, double *z)
+{
+    const double deg = M_PI / 180.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double a = ra_deg[i] * deg;
+        double b = dec_deg[i] * deg;
+        x[i] = cos(b) * cos(a);
+        y[i] = cos(b) * sin(a);
+        z[i] = sin(b);
+    }
+}
+
+/* Angle between two unit vectors: arc-cosine of the clamped dot product
+ * (Section 3, first bullet). */
+static double pair_angle(double xi, double yi, double zi,
+                         double xj, double yj, double zj)
+{
+    double d = (xi * xj + yi * yj) + zi * zj;
+    if (d < -1.0) d = -1.0;
+    if (d > 1.0) d = 1.0;
+    return acos(d);
+}
+
+/* Output slot of an angle: the number of edges at or below it. */
+static int slot_of(double t, const double *edge_rad, int nedges)
+{
+    int s = 0;
+    for (int k = 0; k < nedges; ++k)
+        if (edge_rad[k] <= t)
+            ++s;
+    return s;
+}
+
+typedef struct {
+    int cross;                       /* 0: pairs i<j within A; 1: A x B */
+    int64_t na, nb;
+    const double *ax, *ay, *az, *bx, *by, *bz;
+    int nedges;
+    const double *edge_rad;
+    int64_t row_begin, row_end;
+    int64_t next_row;                /* shared row counter (atomic) */
+    int64_t chunk;
+} job_t;
+
+typedef struct {
+    job_t *job;
+    uint64_t *hist;                  /* nedges + 1 slots, private */
+} worker_t;
+
+static void *worker(void *arg)
+{
+    worker_t *w = (worker_t *)arg;
+    job_t *jb = w->job;
+    for (;;) {
+        int64_t r0 = __atomic_fetch_add(&jb->next_row, jb->chunk, __ATOMIC_RELAXED);
+        if (r0 >= jb->row_end)
+            break;
+        int64_t r1 = r0 + jb->chunk;
+        if (r1 > jb->row_end)
+            r1 = jb->row_end;
+        for (int64_t i = r0; i < r1; ++i) {
+            double xi = jb->ax[i], yi = jb->ay[i], zi = jb->az[i];
+            if (jb->cross) {
+                for (int64_t j = 0; j < jb->nb; ++j) {
+                    double t = pair_angle(xi, yi, zi, jb->bx[j], jb->by[j], jb->bz[j]);
+                    w->hist[slot_of(t, jb->edge_rad, jb->nedges)] += 1;
+                }
+            } else {
+                for (int64_t j = i + 1; j < jb->na; ++j) {
+                    double t = pair_angle(xi, yi, zi, jb->ax[j], jb->ay[j], jb->az[j]);
+                    w->hist[slot_of(t, jb->edge_rad, jb->nedges)] += 1;
+                }
+            }
+        }
+    }
+    return NULL;
+}
+
+/*
+ * Pair-count histogram.
+ *   cross = 0: unordered pairs i < j of catalog A with i in [row_begin,
+ *              row_end) (DD or RR);
+ *   cross = 1: pairs (i, j), i in rows [row_begin, row_end) of A, j in B (DR).
+ * edges_deg: nbins+1 increasing edges in degrees.  out: nbins+2 slots.
+ * row_begin < 0 or row_end < 0 select all rows.  Returns 0, or -1 on bad
+ * arguments.
+ */
+int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
+                 const double *az, int64_t nb, const double *bx, const double *by,
+                 const double *bz, int32_t nbins, const double *edges_deg,
+                 int64_t row_begin, int64_t row_end, int nthreads, uint64_t *out)
+{
+    if (nbins < 1 || na < 0 || (cross && nb < 0) || !out)
+        return -1;
+    const double deg = M_PI / 180.0;
+    int nedges = nbins + 1;
+    double *edge_rad = (double *)malloc(sizeof(double) * (size_t)nedges);
+    if (!edge_rad)
+        return -1;
+    for (int k = 0; k < nedges; ++k)
+        edge_rad[k] = edges_deg[k] * deg;
+
+    if (row_begin < 0) row_begin = 0;
+    if (row_end < 0 || row_end > na) row_end = na;
+    if (row_begin > row_end) row_begin = row_end;
+    if (nthreads < 1) nthreads = 1;
+
+    job_t jb = {cross, na, nb, ax, ay, az, bx, by, bz, nedges, edge_rad,
+                row_begin, row_end, row_begin, 16};
+    worker_t *ws = (worker_t *)calloc((size_t)nthreads, sizeof(worker_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t *hists = (uint64_t *)calloc((size_t)nthreads * (size_t)(nedges + 1), sizeof(uint64_t));
+    if (!ws || !th || !hists) {
+        free(ws); free(th); free(hists); free(edge_rad);
+        return -1;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        ws[t].job = &jb;
+        ws[t].hist = hists + (size_t)t * (size_t)(nedges + 1);
+    }
+    for (int t = 1; t < nthreads; ++t)
+        pthread_create(&th[t], NULL, worker, &ws[t]);
+    worker(&ws[0]);
+    for (int t = 1; t < nthreads; ++t)
+        pthread_join(th[t], NULL);
+
+    for (int s = 0; s <= nedges; ++s) {
+        uint64_t acc = 0;
+        for (int t = 0; t < nthreads; ++t)
+            acc += ws[t].hist[s];
+        out[s] = acc;
+    }
+    free(ws); free(th); free(hists); free(edge_rad);
+    return 0;
+}
+
+/* Slot of each listed pair (i-th entry pairs point a_i with point b_i);
+ * used for probes placed next to bin edges. */
+int oracle_pair_slots(int64_t n, const double *ax, const double *ay, const double *az,
+                      const double *bx, const double *by, const double *bz,
+                      int32_t nbins, const double *edges_deg, int32_t *slots)
+{
+    if (nbins < 1 || n < 0)
+        return -1;
+    const double deg = M_PI / 180.0;
+    int nedges = nbins + 1;
+    double *edge_rad = (double *)malloc(sizeof(double) * (size_t)nedges);
+    if (!edge_rad)
+        return -1;
+    for (int k = 0; k < nedges; ++k)
+        edge_rad[k] = edges_deg[k] * deg;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = pair_angle(ax[i], ay[i], az[i], bx[i], by[i], bz[i]);
+        slots[i] = slot_of(t, edge_rad, nedges);
+    }
+    free(edge_rad);
+    return 0;
+}
+
+/* The angle itself (radians) for listed pairs, for pin tests. */
+int oracle_pair_angles(int64_t n, const double *ax, const double *ay, const double *az,
+                       const double *bx, const double *by, const double *bz, double *theta)
+{
+    for (int64_t i = 0; i < n; ++i)
+        theta[i] = pair_angle(ax[i], ay[i], az[i], bx[i], by[i], bz[i]);
+    return 0;
+}

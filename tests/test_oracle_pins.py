@@ -1,0 +1,370 @@
+"""Pins for the CPU oracle (no GPU).
+
+Each test fixes the oracle against something other than its own code:
+exact trigonometric values, an independent angle formula (chord ->
+2 asin(c/2) through scipy), constructed geometries with known separations,
+the full-sphere closed form, exact algebraic invariants, and hand-worked
+Landy-Szalay values.  A dropped term, a wrong sign or index, a transposed
+operand, a degree/radian slip or a "<" for "<=" in the binning fails at least
+one of them.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+import oracle
+import synthcat
+from oracle import tiny
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEG = math.pi / 180.0
+
+
+def _xyz(ra, dec):
+    return oracle.radec_to_xyz(ra, dec)
+
+
+def _stack(xyz):
+    return np.stack(xyz, axis=1)
+
+
+def _chord_angles(a, b):
+    """Independent angle formula: theta = 2 asin(|a-b| / 2) from scipy's
+    Euclidean distance."""
+    c = cdist(a, b)
+    return 2.0 * np.arcsin(np.minimum(c / 2.0, 1.0))
+
+
+def _random_rotation(g):
+    q, r = np.linalg.qr(g.normal(size=(3, 3)))
+    return q * np.sign(np.diag(r))
+
+
+# --------------------------------------------------------------------------
+# Unit vectors (Section 3: angles come from dot products of unit vectors)
+# --------------------------------------------------------------------------
+
+def test_unit_vectors_exact_values():
+    rows = np.loadtxt(os.path.join(GOLDEN, "unit_vectors.txt"))
+    x, y, z = _xyz(rows[:, 0], rows[:, 1])
+    got = np.stack([x, y, z], axis=1)
+    assert np.max(np.abs(got - rows[:, 2:5])) < 2e-16 * 4
+
+
+def test_unit_vectors_have_unit_norm():
+    g = synthcat.rng_for(90, 0)
+    ra, dec = synthcat.uniform_sphere(20000, g)
+    x, y, z = _xyz(ra, dec)
+    n2 = x * x + y * y + z * z
+    assert np.max(np.abs(n2 - 1.0)) < 8e-16
+
+
+# --------------------------------------------------------------------------
+# Angles: arc-cosine of the clamped dot product vs an independent formula
+# --------------------------------------------------------------------------
+
+def test_pair_angle_matches_chord_formula():
+    g = synthcat.rng_for(90, 1)
+    n = 4000
+    a = _stack(_xyz(*synthcat.uniform_sphere(n, g)))
+    # partners at log-uniform separations from 1e-6 rad to pi
+    theta = np.exp(g.uniform(math.log(1e-6), math.log(math.pi), size=n))
+    u = g.normal(size=(n, 3))
+    u -= np.sum(u * a, axis=1)[:, None] * a
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    b = np.cos(theta)[:, None] * a + np.sin(theta)[:, None] * u
+    b /= np.linalg.norm(b, axis=1)[:, None]
+    t_oracle = oracle.pair_angles(a.T, b.T)
+    t_ref = np.array([_chord_angles(a[i:i + 1], b[i:i + 1])[0, 0] for i in range(n)])
+    # acos loses accuracy as 1/sin(theta): the dot carries ~3 ulp of error
+    tol = 6e-16 / np.maximum(np.sin(t_ref), 1e-300) + 4e-16 * t_ref + 1e-15
+    assert np.all(np.abs(t_oracle - t_ref) <= tol)
+
+
+def test_pair_angle_clamps_duplicates_and_antipodes():
+    g = synthcat.rng_for(90, 2)
+    a = _stack(_xyz(*synthcat.uniform_sphere(500, g)))
+    t_same = oracle.pair_angles(a.T, a.T)
+    assert np.all(t_same < 3e-8)          # acos(clamped d ~ 1)
+    t_anti = oracle.pair_angles(a.T, (-a).T)
+    assert np.all(np.abs(t_anti - math.pi) < 3e-8)
+    assert np.all(np.isfinite(t_same)) and np.all(np.isfinite(t_anti))
+
+
+# --------------------------------------------------------------------------
+# Binning
+# --------------------------------------------------------------------------
+
+def _near_edge(theta, edges_rad, rel=1e-9):
+    d = np.abs(theta[..., None] - edges_rad[None, :])
+    return np.any(d <= rel * edges_rad[None, :] + 1e-12, axis=-1)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_histogram_matches_independent_binning(cfg):
+    """Per-pair slots and whole histograms against scipy chord distances
+    binned with numpy.searchsorted (side='right': theta == e_k goes up)."""
+    wl = synthcat.CONFIGS[cfg](scale=0.015 if cfg == 1 else 0.0015)
+    d = wl.data[0]
+    edges = wl.edges_deg
+    er = edges * DEG
+    a = _stack(_xyz(d.ra, d.dec))
+    n = a.shape[0]
+    th = _chord_angles(a, a)
+    iu, ju = np.triu_indices(n, k=1)
+    t = th[iu, ju]
+    ref = np.searchsorted(er, t, side="right")
+    near = _near_edge(t, er)
+    assert near.sum() <= 2  # only a handful of pairs can sit this close
+    slots = oracle.pair_slots(a[iu].T, a[ju].T, edges)
+    assert np.array_equal(slots[~near], ref[~near])
+    hist = oracle.count(oracle.DD, a.T, edges)
+    assert np.array_equal(hist, np.bincount(slots, minlength=edges.size + 1).astype(np.uint64))
+    ref_hist = np.bincount(ref, minlength=edges.size + 1)
+    assert np.sum(np.abs(hist.astype(np.int64) - ref_hist)) <= 2 * near.sum()
+
+
+def test_tie_on_edge_goes_to_upper_bin():
+    """A pair whose angle equals an edge exactly lands in the upper bin."""
+    g = synthcat.rng_for(90, 3)
+    a = _stack(_xyz(*synthcat.uniform_sphere(400, g)))
+    b = _stack(_xyz(*synthcat.uniform_sphere(400, g)))
+    t = oracle.pair_angles(a.T, b.T)
+    found = 0
+    for i in range(a.shape[0]):
+        e0 = t[i] / DEG
+        cands = [e0]
+        for _ in range(4):
+            cands.append(np.nextafter(cands[-1], np.inf))
+        c2 = [e0]
+        for _ in range(4):
+            c2.append(np.nextafter(c2[-1], -np.inf))
+        exact = [e for e in cands + c2 if e * DEG == t[i]]
+        if not exact:
+            continue
+        found += 1
+        e = exact[0]
+        above = next(c for c in cands if c * DEG > t[i])
+        below = next(c for c in c2 if c * DEG < t[i])
+        pa, pb = a[i:i + 1].T, b[i:i + 1].T
+        assert oracle.pair_slots(pa, pb, [e / 2, e, 2 * e])[0] == 2
+        assert oracle.pair_slots(pa, pb, [below / 2, below, 2 * e])[0] == 2
+        assert oracle.pair_slots(pa, pb, [e / 2, above, 2 * e])[0] == 1
+        assert oracle.pair_slots(pa, pb, [e, 2 * e])[0] == 1
+        assert oracle.pair_slots(pa, pb, [above, 2 * e])[0] == 0
+    assert found >= 100
+
+
+def test_isolated_probe_pairs_land_in_known_bins():
+    """Probe pairs separated by each bin's geometric centre, with probes far
+    apart from one another: bin k holds exactly the probes aimed at it and
+    every other pair is overflow."""
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    nb = edges.size - 1
+    g = synthcat.rng_for(90, 4)
+    # bases on a coarse grid: mutual separations >= ~25 deg
+    bases = []
+    for dec in (-60.0, -30.0, 0.0, 30.0, 60.0):
+        step = 30.0 / max(math.cos(math.radians(dec)), 0.5)
+        ra = 0.0
+        while ra < 360.0 - step / 2:
+            bases.append((ra, dec))
+            ra += step
+    bases = np.array(bases)
+    kbin = g.integers(0, nb, size=len(bases))
+    centre = np.sqrt(edges[kbin] * edges[kbin + 1]) * DEG
+    bx = _stack(_xyz(bases[:, 0], bases[:, 1]))
+    u = g.normal(size=bx.shape)
+    u -= np.sum(u * bx, axis=1)[:, None] * bx
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    px = np.cos(centre)[:, None] * bx + np.sin(centre)[:, None] * u
+    pts = np.concatenate([bx, px])
+    n = pts.shape[0]
+    # geometry check with the independent formula: cross-probe pairs are far
+    th = _chord_angles(pts, pts)
+    m = len(bases)
+    for i in range(m):
+        th[i, m + i] = th[m + i, i] = np.inf
+    np.fill_diagonal(th, np.inf)
+    assert th.min() > 15.0 * DEG
+    hist = oracle.count(oracle.DD, pts.T, edges)
+    expect = np.zeros(nb + 2, dtype=np.uint64)
+    for k in kbin:
+        expect[k + 1] += 1
+    expect[nb + 1] = n * (n - 1) // 2 - m
+    assert np.array_equal(hist, expect)
+    # the same probes through the RA/Dec entry (degrees, not radians)
+    ra = np.degrees(np.arctan2(pts[:, 1], pts[:, 0])) % 360.0
+    dec = np.degrees(np.arcsin(np.clip(pts[:, 2], -1, 1)))
+    hist2 = oracle.count(oracle.DD, _xyz(ra, dec), edges)
+    assert np.array_equal(hist2, expect)
+
+
+def test_duplicates_antipodes_and_tiny_catalogs():
+    g = synthcat.rng_for(90, 5)
+    p = _stack(_xyz(*synthcat.uniform_sphere(50, g)))
+    edges = np.array([0.01, 1.0, 179.0])
+    dup = np.concatenate([p, p])
+    h = oracle.count(oracle.DR, p.T, edges, b_xyz=p.T)
+    # DR of a catalog with itself: the 50 coincident pairs are underflow
+    assert h[0] >= 50
+    anti = oracle.count(oracle.DR, p.T, edges, b_xyz=(-p).T)
+    assert anti[3] >= 50
+    assert oracle.count(oracle.DD, dup.T, edges)[0] >= 50
+    # e_0 = 0: coincident pairs are theta = 0 >= e_0, slot 1
+    h0 = oracle.count(oracle.DR, p[:1].T, [0.0, 1.0], b_xyz=p[:1].T)
+    assert list(h0) == [0, 1, 0]
+    for n, tot in ((0, 0), (1, 0), (2, 1), (3, 3)):
+        h = oracle.count(oracle.DD, p[:n].T, edges)
+        assert int(h.sum()) == tot
+
+
+def test_full_sphere_closed_form():
+    """Uniform points on the whole sphere: P(theta in [a, b)) =
+    (cos a - cos b) / 2 and pair indicators are pairwise uncorrelated, so each
+    bin count is within 5 sigma of M p with sigma^2 = M p (1 - p)."""
+    g = synthcat.rng_for(90, 6)
+    n = 3000
+    a = _xyz(*synthcat.uniform_sphere(n, g))
+    edges = np.array([0.0, 0.5, 2.0, 5.0, 10.0, 20.0, 45.0, 90.0, 135.0, 170.0, 180.0])
+    h = oracle.count(oracle.DD, a, edges).astype(np.float64)
+    m = n * (n - 1) / 2
+    assert h[0] == 0
+    er = edges * DEG
+    p = (np.cos(er[:-1]) - np.cos(er[1:])) / 2.0
+    mean = m * p
+    sd = np.sqrt(m * p * (1 - p))
+    z = (h[1:-1] - mean) / sd
+    assert np.all(np.abs(z) < 5.0), z
+    assert h[-1] == 0   # no exact antipodes among random points
+
+
+# --------------------------------------------------------------------------
+# Totals and exact invariants
+# --------------------------------------------------------------------------
+
+def _small_sets(seed, na=700, nb=500):
+    g = synthcat.rng_for(91, seed)
+    a = _xyz(*synthcat.clustered(na, 20, 0.5, synthcat.PATCH_30, g))
+    b = _xyz(*synthcat.uniform_patch(nb, synthcat.PATCH_30, g))
+    return a, b
+
+
+def test_totals():
+    a, b = _small_sets(0)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    na, nb = a[0].size, b[0].size
+    assert int(oracle.count(oracle.DD, a, edges).sum()) == na * (na - 1) // 2
+    assert int(oracle.count(oracle.DR, a, edges, b_xyz=b).sum()) == na * nb
+    r = oracle.count(oracle.DD, a, edges, row_begin=100, row_end=250)
+    assert int(r.sum()) == sum(na - 1 - i for i in range(100, 250))
+    r = oracle.count(oracle.DR, a, edges, b_xyz=b, row_begin=10, row_end=20)
+    assert int(r.sum()) == 10 * nb
+
+
+def test_union_decomposition_and_symmetry():
+    a, b = _small_sets(1)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    u = tuple(np.concatenate([p, q]) for p, q in zip(a, b))
+    ddu = oracle.count(oracle.DD, u, edges)
+    dda = oracle.count(oracle.DD, a, edges)
+    ddb = oracle.count(oracle.DD, b, edges)
+    drab = oracle.count(oracle.DR, a, edges, b_xyz=b)
+    drba = oracle.count(oracle.DR, b, edges, b_xyz=a)
+    assert np.array_equal(ddu, dda + ddb + drab)
+    assert np.array_equal(drab, drba)
+
+
+def test_reflection_and_permutation_invariance():
+    a, b = _small_sets(2)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    base = oracle.count(oracle.DD, a, edges)
+    refl = oracle.count(oracle.DD, (a[0], a[1], -a[2]), edges)
+    perm = np.random.default_rng(5).permutation(a[0].size)
+    per = oracle.count(oracle.DD, tuple(c[perm] for c in a), edges)
+    assert np.array_equal(base, refl)
+    assert np.array_equal(base, per)
+    dr = oracle.count(oracle.DR, a, edges, b_xyz=b)
+    dr2 = oracle.count(oracle.DR, (-a[0], a[1], a[2]), edges, b_xyz=(-b[0], b[1], b[2]))
+    assert np.array_equal(dr, dr2)
+
+
+def test_row_ranges_add_up():
+    a, b = _small_sets(3)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    full = oracle.count(oracle.DD, a, edges)
+    cuts = [0, 1, 77, 300, 699, 700]
+    parts = sum(oracle.count(oracle.DD, a, edges, row_begin=c0, row_end=c1)
+                for c0, c1 in zip(cuts[:-1], cuts[1:]))
+    assert np.array_equal(full, parts)
+    fdr = oracle.count(oracle.DR, a, edges, b_xyz=b)
+    pdr = sum(oracle.count(oracle.DR, a, edges, b_xyz=b, row_begin=c0, row_end=c1)
+              for c0, c1 in zip(cuts[:-1], cuts[1:]))
+    assert np.array_equal(fdr, pdr)
+
+
+def test_thread_count_does_not_change_counts():
+    a, b = _small_sets(4)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    h1 = oracle.count(oracle.DR, a, edges, b_xyz=b, nthreads=1)
+    h7 = oracle.count(oracle.DR, a, edges, b_xyz=b, nthreads=7)
+    assert np.array_equal(h1, h7)
+
+
+def test_pure_python_transcription_agrees_bit_for_bit():
+    g = synthcat.rng_for(91, 9)
+    ra, dec = synthcat.clustered(300, 10, 0.3, synthcat.PATCH_30, g)
+    ra2, dec2 = synthcat.uniform_patch(120, synthcat.PATCH_30, g)
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    pa = [tiny.unit_vector(r, d) for r, d in zip(ra, dec)]
+    pb = [tiny.unit_vector(r, d) for r, d in zip(ra2, dec2)]
+    xa = _xyz(ra, dec)
+    xb = _xyz(ra2, dec2)
+    assert np.array_equal(np.array(pa), np.stack(xa, axis=1))
+    assert list(oracle.count(oracle.DD, xa, edges)) == tiny.count_pairs(pa, edges)
+    assert list(oracle.count(oracle.DR, xa, edges, b_xyz=xb)) == tiny.count_pairs(pa, edges, pb)
+
+
+# --------------------------------------------------------------------------
+# Landy-Szalay (Eq. 1)
+# --------------------------------------------------------------------------
+
+def test_landy_szalay_hand_worked_values():
+    with open(os.path.join(GOLDEN, "landy_szalay_closed_form.json")) as f:
+        fx = json.load(f)
+    for case in fx["cases"]:
+        for form, key in ((0, "w_form0"), (1, "w_form1")):
+            w = oracle.landy_szalay(case["dd"], case["dr"], case["rr"],
+                                    case["n_d"], case["n_r"], form=form)
+            for got, want in zip(w, case[key]):
+                if want is None:
+                    assert math.isnan(got)
+                else:
+                    assert abs(got - want) <= 1e-14 * max(1.0, abs(want))
+
+
+def test_landy_szalay_random_vs_random_is_zero():
+    """Independent uniform D and R on the same patch give w ~ 0 within a few
+    Poisson sigma (~1/sqrt(DD)), for both readings of Eq. 1; the literal
+    formula applied to unordered counts would give w ~ -2 instead."""
+    g1 = synthcat.rng_for(92, 0)
+    g2 = synthcat.rng_for(92, 1)
+    nd, nr = 3000, 6000
+    d = _xyz(*synthcat.uniform_patch(nd, synthcat.PATCH_30, g1))
+    r = _xyz(*synthcat.uniform_patch(nr, synthcat.PATCH_30, g2))
+    edges = synthcat.log_edges(0.5, 10.0, 8)
+    dd = oracle.count(oracle.DD, d, edges)[1:-1]
+    dr = oracle.count(oracle.DR, d, edges, b_xyz=r)[1:-1]
+    rr = oracle.count(oracle.RR, r, edges)[1:-1]
+    sigma = np.sqrt(2.0 / dd.astype(np.float64))
+    for form in (0, 1):
+        w = oracle.landy_szalay(dd, dr, rr, nd, nr, form=form)
+        assert np.all(np.abs(w) < 5 * sigma), (form, w, sigma)
+    ratio = nr / nd
+    naive = 1 + ratio ** 2 * dd / rr - 2 * ratio * dr / rr
+    assert np.all(np.abs(naive + 2.0) < 0.2)
