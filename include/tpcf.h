@@ -1,0 +1,204 @@
+/*
+ * tpcf.h -- angular two-point correlation pair counting on AMD MI355X (gfx950).
+ *
+ * C ABI of libtpcf.so.  The library counts, for a catalog of objects on the
+ * sky, the pairs of objects per bin of angular separation: DD within a data
+ * catalog, RR within a random catalog, DR across the two (paper, Section 1,
+ * the definitions under Eq. 1), and combines the three histograms into the
+ * Landy-Szalay estimator w(theta) (Eq. 1).  The angle of a pair is the
+ * arc-cosine of the dot product of the two unit vectors (Section 3, first
+ * bullet); pairs are binned in theta, not in cos theta (Section 2), with
+ * per-block partial histograms combined into one global histogram (Section 3,
+ * second bullet).
+ *
+ * Conventions for every entry point:
+ *   - plain C types only; no exception crosses the boundary;
+ *   - every call returns an int status (TPCF_OK or a negative TPCF_E_* code);
+ *     tpcf_last_error() returns a message for the calling thread;
+ *   - sizes and row indices are int64_t; catalogs hold at most 2^31 - 1024
+ *     objects;
+ *   - host input arrays are read during the call only (copied if needed);
+ *   - output arrays are written only when the call returns TPCF_OK;
+ *   - a context is used by one host thread at a time;
+ *   - counts are exact: for the same catalog and edges, every precision mode
+ *     returns the same integers as a plain FP64 CPU double loop using host
+ *     libm acos on the same machine (see "Counting rule" below).
+ *
+ * Counting rule (shared by every precision mode):
+ *   unit vector   x = cos(dec) cos(ra), y = cos(dec) sin(ra), z = sin(dec),
+ *                 angles in radians as deg * (pi / 180), FP64 libm;
+ *   dot product   d = (x_i x_j + y_i y_j) + z_i z_j, FP64, no fused
+ *                 multiply-add, evaluated left to right;
+ *   angle         theta = acos(clamp(d, -1, 1)) (host libm);
+ *   edges         e_k = edge_deg[k] * (pi / 180), k = 0..nbins;
+ *   slot          number of edges with e_k <= theta: slot 0 is theta < e_0,
+ *                 slot k+1 is e_k <= theta < e_{k+1}, slot nbins+1 is
+ *                 theta >= e_nbins (a tie goes to the upper bin).
+ *   DD and RR count unordered pairs i < j (self-pairs excluded, N(N-1)/2 in
+ *   total); DR counts all N_D * N_R pairs.
+ *   The GPU never evaluates acos: each edge is compiled on the host into the
+ *   largest double D_k with acos(D_k) >= e_k, and a pair counts past edge k
+ *   exactly when clamp(d) <= D_k.
+ */
+#ifndef TPCF_H
+#define TPCF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpcf_ctx tpcf_ctx;   /* opaque; owns device state */
+
+/* Pair kinds (Section 1). */
+enum { TPCF_DD = 0, TPCF_DR = 1, TPCF_RR = 2 };
+
+/* Precision modes.
+ * TPCF_FP32_CHORD: bulk pairs are classified from the FP32 squared chord
+ *   |f_i - f_j|^2 of FP32 copies of the unit vectors, against FP32 chord^2
+ *   bands proven to contain every edge; a pair inside a band is re-decided in
+ *   FP64 with the exact counting rule.
+ * TPCF_FP64: every pair's FP64 dot product d is computed as in the counting
+ *   rule and compared with D_k (the plain path). */
+enum { TPCF_FP32_CHORD = 0, TPCF_FP64 = 1 };
+
+enum {
+    TPCF_OK = 0,
+    TPCF_E_INVALID = -1,    /* bad argument; nothing launched */
+    TPCF_E_NOMEM = -2,      /* device or host allocation failed */
+    TPCF_E_HIP = -3,        /* a HIP runtime call failed */
+    TPCF_E_BADID = -4,      /* unknown catalog or job id */
+    TPCF_E_BUDGET = -5,     /* request exceeds the configured HBM budget */
+    TPCF_E_CANCELLED = -6,  /* job was cancelled */
+    TPCF_E_INTERNAL = -7    /* an internal consistency check failed */
+};
+
+/* Open a context on HIP device `device`.  hip_stream: a hipStream_t to launch
+ * on (borrowed; it must outlive the context), or NULL for a stream owned by
+ * the context.  *out receives the context. */
+int tpcf_open(int device, void *hip_stream, tpcf_ctx **out);
+
+/* Release every catalog and device buffer of the context, then the context. */
+int tpcf_close(tpcf_ctx *ctx);
+
+/* Upload a catalog given right ascension and declination in degrees (host
+ * FP64 arrays of n finite values).  The library builds the FP64 unit vectors
+ * with the counting rule's formula on the host, keeps them on the device as
+ * structure-of-arrays (x[], y[], z[]) together with FP32 copies rounded to
+ * nearest, and returns a catalog id in *out_cat.  Device memory is owned by
+ * the library until tpcf_release_catalog or tpcf_close.  n may be 0. */
+int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg,
+                        int64_t n, int32_t *out_cat);
+
+/* Same, from caller-computed FP64 unit vectors (host arrays).  Each vector
+ * must satisfy | x^2 + y^2 + z^2 - 1 | <= 2^-20, else TPCF_E_INVALID. */
+int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
+                            const double *z, int64_t n, int32_t *out_cat);
+
+/* Zero-copy attach of caller-owned device memory: d_xyz64 points to 3*n
+ * doubles on the context's device laid out as x[0..n), y[0..n), z[0..n)
+ * (unit vectors, same norm limit as above).  The caller keeps the memory
+ * alive and unchanged until the catalog is released.  The library adds its
+ * own FP32 copy.  Checked on the device; TPCF_E_INVALID if a vector fails
+ * the norm limit or is not finite. */
+int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t *out_cat);
+
+/* Number of objects of a catalog. */
+int tpcf_catalog_size(tpcf_ctx *ctx, int32_t cat, int64_t *out_n);
+
+/* Release a catalog id and the device memory the library owns for it. */
+int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat);
+
+/* Count pairs (synchronous).
+ * kind       TPCF_DD or TPCF_RR: unordered pairs i < j of cat_a, cat_b must be
+ *            -1; TPCF_DR: every pair (i in cat_a, j in cat_b).
+ * bin_edges_deg  nbins+1 finite, strictly increasing values in [0, 180]
+ *            (host array); 1 <= nbins <= 256.
+ * precision  TPCF_FP32_CHORD or TPCF_FP64 (identical results).
+ * row_begin, row_end  restrict i to rows [row_begin, row_end) of cat_a (rows
+ *            in upload order); -1, -1 selects all rows.  For DD/RR the pairs
+ *            are (i, j) with i in the range and j > i.
+ * out_u64    host array of nbins+2 slots: [theta < e_0, bin 0 .. bin nbins-1,
+ *            theta >= e_nbins].  Written on TPCF_OK only.
+ * The total over slots always equals the number of pairs in the request; a
+ * mismatch is reported as TPCF_E_INTERNAL. */
+int tpcf_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
+               const double *bin_edges_deg, int32_t nbins, int precision,
+               int64_t row_begin, int64_t row_end, uint64_t *out_u64);
+
+/* Asynchronous count into device memory: d_out_u64 is a device pointer to
+ * nbins+2 uint64 slots, overwritten (not accumulated) by work enqueued on the
+ * context stream; the call returns once the work is enqueued.  Same
+ * arguments and results as tpcf_count otherwise.  The totals check is not
+ * performed (the caller may check the sum). */
+int tpcf_count_async(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
+                     const double *bin_edges_deg, int32_t nbins, int precision,
+                     int64_t row_begin, int64_t row_end, uint64_t *d_out_u64);
+
+/* Wait for all work enqueued on the context stream. */
+int tpcf_synchronize(tpcf_ctx *ctx);
+
+/* Kernel timing.  With timing on, the library records a HIP event pair on
+ * the context stream around every pair-kernel launch.  tpcf_kernel_time
+ * waits for them and returns the summed kernel time in milliseconds and the
+ * number of launches since the last reset; reset = 1 clears the record. */
+int tpcf_set_timing(tpcf_ctx *ctx, int on);
+int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int reset);
+
+/* Work statistics since the last reset: pairs evaluated, pairs that left the
+ * table-driven path for a threshold comparison, and pairs re-decided with
+ * the exact FP64 rule (FP32_CHORD band pairs, or FP64 ties). Waits for the
+ * context stream. */
+int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged,
+               uint64_t *out_exact, int reset);
+
+/* Landy-Szalay estimator (Eq. 1), host FP64; no context needed.
+ * dd, dr, rr  histograms of nbins+2 slots as returned by tpcf_count (DD and
+ *             RR of unordered pairs); only the nbins in-range bins are used.
+ * n_d, n_r    catalog sizes (>= 2 each).
+ * form 0      w_k = (DD_k/n_DD - 2 DR_k/n_DR + RR_k/n_RR) / (RR_k/n_RR) with
+ *             n_DD = N_D(N_D-1)/2, n_DR = N_D N_R, n_RR = N_R(N_R-1)/2;
+ * form 1      Eq. 1 as printed, the exponent read as a square and DD, RR
+ *             doubled to ordered counts:
+ *             w_k = 1 + (N_R/N_D)^2 (2 DD_k)/(2 RR_k) - 2 (N_R/N_D) DR_k/(2 RR_k).
+ * out_w       host array of nbins doubles; NaN where RR_k = 0. */
+int tpcf_landy_szalay(const uint64_t *dd, const uint64_t *dr, const uint64_t *rr,
+                      int32_t nbins, int64_t n_d, int64_t n_r, int form, double *out_w);
+
+/* Host-side edge compilation, exposed for inspection and CPU tests of the
+ * host logic (no device work).  For nbins+1 edges in degrees it writes:
+ *   out_D    nbins+1 doubles: D_k = largest double d in [-1, 1] with
+ *            acos(d) >= e_k (+inf if e_k == 0, -inf if acos(-1) < e_k);
+ *   out_qlo, out_qhi  nbins+1 floats: the FP32 chord^2 band of edge k for
+ *            catalogs whose squared norms deviate from 1 by at most
+ *            delta_max: q < qlo_k implies d > D_k and q >= qhi_k implies
+ *            d <= D_k for the kernel's q = fl32 |f_i - f_j|^2;
+ * any output pointer may be NULL. */
+int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_max,
+                       double *out_D, float *out_qlo, float *out_qhi);
+
+/* Cell table of the pair kernels for the given edges (host only, for CPU
+ * tests of the host logic).  precision selects the key: TPCF_FP32_CHORD uses
+ * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 the high 32 bits of
+ * e = fl64(1 - d) as a signed integer.  A key maps to cell
+ * clamp(key >> shift, lo, hi); entry cells[cell - lo] is a slot (< 0x8000),
+ * 0x8000 | k when only edge k is undecided in the cell, or 0xFFFF when
+ * several edges are.  out_cells must hold max_cells entries (16..8192);
+ * out_E (nbins+1 doubles, may be NULL) receives fl(1 - D_k). */
+int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
+                       int32_t max_cells, int32_t *out_shift, int32_t *out_lo, int32_t *out_hi,
+                       uint16_t *out_cells, double *out_E);
+
+/* Message describing the last failed call on the calling thread ("" if none).
+ * Valid until the next call on the same thread. */
+const char *tpcf_last_error(void);
+
+/* Library version string. */
+const char *tpcf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCF_H */

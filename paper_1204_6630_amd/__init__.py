@@ -1,0 +1,264 @@
+"""Python binding of libtpcf.so (angular two-point pair counting on MI355X).
+
+Argument marshalling only: every pair is counted by the HIP kernels behind the
+C ABI declared in ``include/tpcf.h``.  The functions keep the C names and
+semantics; see that header for the counting rule, layouts and error codes.
+
+If the library is not built, importing this package still works (so the
+build step can run), but every call raises ``RuntimeError``: there is no
+fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "DD", "DR", "RR", "FP32_CHORD", "FP64", "TpcfError", "Context", "lib", "lib_path",
+    "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS",
+]
+
+DD, DR, RR = 0, 1, 2
+FP32_CHORD, FP64 = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtpcf.so")
+_lib = None
+
+# every symbol declared in include/tpcf.h
+EXPORTED_SYMBOLS = (
+    "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
+    "tpcf_attach_catalog", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
+    "tpcf_count_async", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
+    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_edges",
+    "tpcf_last_error", "tpcf_version",
+)
+
+_ERRORS = {
+    -1: "TPCF_E_INVALID", -2: "TPCF_E_NOMEM", -3: "TPCF_E_HIP", -4: "TPCF_E_BADID",
+    -5: "TPCF_E_BUDGET", -6: "TPCF_E_CANCELLED", -7: "TPCF_E_INTERNAL",
+}
+
+
+class TpcfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _share_torch_hip_runtime():
+    """Make libtpcf.so resolve to the HIP runtime torch uses, if torch is
+    installed.  torch ships its own libamdhip64 (needed by file name); the
+    library needs it by SONAME.  Loading torch first puts that runtime in the
+    process under the SONAME, so both share one runtime, and torch streams and
+    device pointers are valid handles for the library.  Loading the library
+    first would pull in a second runtime that torch cannot initialise beside."""
+    try:
+        import torch  # noqa: F401
+    except Exception:  # pragma: no cover - torch is optional for the binding
+        pass
+
+
+def lib():
+    """Load libtpcf.so (raises RuntimeError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    _share_torch_hip_runtime()
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_1204_6630_amd.build`")
+    L = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    cint = ctypes.c_int
+    sig = {
+        "tpcf_open": ([cint, P, P], cint),
+        "tpcf_close": ([P], cint),
+        "tpcf_upload_catalog": ([P, P, P, i64, P], cint),
+        "tpcf_upload_catalog_xyz": ([P, P, P, P, i64, P], cint),
+        "tpcf_attach_catalog": ([P, P, i64, P], cint),
+        "tpcf_catalog_size": ([P, i32, P], cint),
+        "tpcf_release_catalog": ([P, i32], cint),
+        "tpcf_count": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
+        "tpcf_count_async": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
+        "tpcf_synchronize": ([P], cint),
+        "tpcf_set_timing": ([P, cint], cint),
+        "tpcf_kernel_time": ([P, P, P, cint], cint),
+        "tpcf_stats": ([P, P, P, P, cint], cint),
+        "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
+        "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, P, P, P, P, P], cint),
+        "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
+        "tpcf_last_error": ([], ctypes.c_char_p),
+        "tpcf_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().tpcf_last_error().decode(errors="replace")
+        raise TpcfError(rc, msg)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def version() -> str:
+    return lib().tpcf_version().decode()
+
+
+class Context:
+    """One device context (``tpcf_open``); ``stream`` is an optional
+    ``hipStream_t`` handle (e.g. ``torch.cuda.Stream().cuda_stream``)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self._h = ctypes.c_void_p()
+        _check(lib().tpcf_open(device, ctypes.c_void_p(stream) if stream else None,
+                               ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(lib().tpcf_close(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- catalogs ---------------------------------------------------------
+    def upload_catalog(self, ra_deg, dec_deg) -> int:
+        ra, dec = _f64(ra_deg), _f64(dec_deg)
+        if ra.shape != dec.shape or ra.ndim != 1:
+            raise ValueError("ra and dec must be 1-D arrays of the same length")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_upload_catalog(self._h, _p(ra), _p(dec), ra.size, ctypes.byref(cid)))
+        return cid.value
+
+    def upload_catalog_xyz(self, x, y, z) -> int:
+        x, y, z = _f64(x), _f64(y), _f64(z)
+        if not (x.shape == y.shape == z.shape) or x.ndim != 1:
+            raise ValueError("x, y, z must be 1-D arrays of the same length")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_upload_catalog_xyz(self._h, _p(x), _p(y), _p(z), x.size,
+                                             ctypes.byref(cid)))
+        return cid.value
+
+    def attach_catalog(self, xyz64_device) -> int:
+        """Attach a contiguous float64 device tensor of shape (3, n) (rows x, y,
+        z); the tensor must stay alive and unchanged while the id is in use."""
+        t = xyz64_device
+        if getattr(t, "dtype", None) is None or str(t.dtype) != "torch.float64" or t.dim() != 2 \
+                or t.shape[0] != 3 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("need a contiguous float64 CUDA tensor of shape (3, n)")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_attach_catalog(self._h, ctypes.c_void_p(t.data_ptr()), t.shape[1],
+                                         ctypes.byref(cid)))
+        return cid.value
+
+    def catalog_size(self, cat: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().tpcf_catalog_size(self._h, cat, ctypes.byref(n)))
+        return n.value
+
+    def release_catalog(self, cat: int):
+        _check(lib().tpcf_release_catalog(self._h, cat))
+
+    # -- counting -----------------------------------------------------------
+    def count(self, kind: int, cat_a: int, edges_deg, cat_b: int = -1,
+              precision: int = FP32_CHORD, row_begin: int = -1, row_end: int = -1) -> np.ndarray:
+        e = _f64(edges_deg)
+        out = np.zeros(e.size + 1, dtype=np.uint64)
+        _check(lib().tpcf_count(self._h, kind, cat_a, cat_b, _p(e), e.size - 1, precision,
+                                row_begin, row_end, _p(out)))
+        return out
+
+    def count_async(self, kind: int, cat_a: int, edges_deg, out_device_ptr: int, cat_b: int = -1,
+                    precision: int = FP32_CHORD, row_begin: int = -1, row_end: int = -1):
+        e = _f64(edges_deg)
+        _check(lib().tpcf_count_async(self._h, kind, cat_a, cat_b, _p(e), e.size - 1, precision,
+                                      row_begin, row_end, ctypes.c_void_p(out_device_ptr)))
+
+    def synchronize(self):
+        _check(lib().tpcf_synchronize(self._h))
+
+    def set_timing(self, on: bool = True):
+        _check(lib().tpcf_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, reset: bool = False):
+        """(summed pair-kernel milliseconds, launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().tpcf_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
+    def stats(self, reset: bool = False):
+        """(pairs, flagged, exact) since the last reset."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().tpcf_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                1 if reset else 0))
+        return a.value, b.value, c.value
+
+
+def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:
+    """w(theta) per in-range bin from nbins+2-slot histograms (tpcf_landy_szalay)."""
+    dd = np.ascontiguousarray(dd, dtype=np.uint64)
+    dr = np.ascontiguousarray(dr, dtype=np.uint64)
+    rr = np.ascontiguousarray(rr, dtype=np.uint64)
+    if not (dd.shape == dr.shape == rr.shape) or dd.ndim != 1 or dd.size < 3:
+        raise ValueError("need three slot arrays of the same length nbins+2")
+    nbins = dd.size - 2
+    w = np.empty(nbins, dtype=np.float64)
+    _check(lib().tpcf_landy_szalay(_p(dd), _p(dr), _p(rr), nbins, n_d, n_r, form, _p(w)))
+    return w
+
+
+def compile_edges(edges_deg, delta_max: float = 0.0):
+    """(D, qlo, qhi) of tpcf_compile_edges."""
+    e = _f64(edges_deg)
+    D = np.empty(e.size, np.float64)
+    qlo = np.empty(e.size, np.float32)
+    qhi = np.empty(e.size, np.float32)
+    _check(lib().tpcf_compile_edges(_p(e), e.size - 1, delta_max, _p(D), _p(qlo), _p(qhi)))
+    return D, qlo, qhi
+
+
+def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int = 8192):
+    """(shift, lo, hi, cells, E) of tpcf_compile_cells."""
+    e = _f64(edges_deg)
+    cells = np.zeros(max_cells, np.uint16)
+    E = np.empty(e.size, np.float64)
+    sh, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().tpcf_compile_cells(_p(e), e.size - 1, precision, delta_max, max_cells,
+                                    ctypes.byref(sh), ctypes.byref(lo), ctypes.byref(hi),
+                                    _p(cells), _p(E)))
+    return sh.value, lo.value, hi.value, cells[:hi.value - lo.value + 1].copy(), E

@@ -1,0 +1,358 @@
+// Edge compiler.
+//
+// The counting rule bins a pair by theta = acos(clamp(d, -1, 1)) against the
+// edges e_k (paper, Section 3: angle from the dot product and arc-cosine;
+// Section 2: results in theta space).  acos is non-increasing, so
+//     theta >= e_k   <=>   clamp(d) <= D_k,
+// with D_k the largest double in [-1, 1] whose acos is still >= e_k.  D_k is
+// found here by bisection over the ordered doubles in [-1, 1], calling the
+// same host libm acos that defines the rule, so the GPU never evaluates acos
+// and still reproduces the rule bit for bit.  A window of doubles around
+// each D_k is then checked exhaustively: every d below D_k must give
+// acos(d) >= e_k and every d above must not.  The window is sized so that it
+// covers every d whose exact arc-cosine lies within a few ulps of e_k; outside
+// it a libm result within 1 ulp cannot reach e_k from the wrong side.
+//
+// This file must keep sin, cos and acos as plain libm calls (built with
+// -fno-builtin and contraction off).
+#include "edges.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+
+namespace tpcf {
+
+namespace {
+
+inline int64_t okey(double d) {
+    int64_t b;
+    memcpy(&b, &d, 8);
+    return b >= 0 ? b : -(b & 0x7fffffffffffffffLL);
+}
+
+inline double from_okey(int64_t k) {
+    int64_t b = k >= 0 ? k : ((-k) | (int64_t)0x8000000000000000ULL);
+    double d;
+    memcpy(&d, &b, 8);
+    return d;
+}
+
+inline bool reaches(double d, double e) { return acos(d) >= e; }
+
+// Largest double d in [-1, 1] with acos(d) >= e, assuming acos is
+// non-increasing; +inf / -inf for the two degenerate cases.
+double threshold_of(double e) {
+    if (!(e > 0.0))
+        return HUGE_VAL;                       // theta >= 0 always
+    if (!reaches(-1.0, e))
+        return -HUGE_VAL;                      // no angle reaches e
+    int64_t lo = okey(-1.0), hi = okey(1.0);   // reaches(lo) true, reaches(hi) false
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (reaches(from_okey(mid), e))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return from_okey(lo);
+}
+
+// Half-width, in doubles, of the window checked around D (see above).
+int64_t window_of(double e, double D) {
+    double ulp_e = nextafter(e, HUGE_VAL) - e;
+    double span = 8.0 * ulp_e * sin(e) + 1e-300;          // |d - D| that can matter
+    double ulp_d = nextafter(fabs(D), HUGE_VAL) - fabs(D);
+    double w = ulp_d > 0 ? span / ulp_d : 1e30;
+    if (w > (double)(1 << 16))
+        w = (double)(1 << 16);
+    return (int64_t)w + 64;
+}
+
+bool verify_threshold(double e, double D, std::string *why) {
+    if (isinf(D))
+        return true;
+    const int64_t w = window_of(e, D);
+    const int64_t k = okey(D);
+    const int64_t kmin = okey(-1.0), kmax = okey(1.0);
+    for (int64_t t = std::max(kmin, k - w); t <= k; ++t) {
+        if (!reaches(from_okey(t), e)) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "acos not monotone below threshold %.17g for edge %.17g rad", D, e);
+            *why = buf;
+            return false;
+        }
+    }
+    for (int64_t t = k + 1; t <= std::min(kmax, k + w); ++t) {
+        if (reaches(from_okey(t), e)) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "acos not monotone above threshold %.17g for edge %.17g rad", D, e);
+            *why = buf;
+            return false;
+        }
+    }
+    return true;
+}
+
+inline float round_up32(double x) {
+    float f = (float)x;
+    if ((double)f < x)
+        f = nextafterf(f, HUGE_VALF);
+    return f;
+}
+
+inline float round_down32(double x) {
+    float f = (float)x;
+    if ((double)f > x)
+        f = nextafterf(f, -HUGE_VALF);
+    return f;
+}
+
+inline uint32_t fbits(float f) {
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    return b;
+}
+
+inline float ffrom(uint32_t b) {
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+inline int32_t dhi(double d) {
+    uint64_t b;
+    memcpy(&b, &d, 8);
+    return (int32_t)(uint32_t)(b >> 32);
+}
+
+inline double dfrom(uint64_t b) {
+    double d;
+    memcpy(&d, &b, 8);
+    return d;
+}
+
+uint16_t encode(int s_min, int s_max) {
+    if (s_min == s_max)
+        return (uint16_t)s_min;
+    if (s_max == s_min + 1)
+        return (uint16_t)(0x8000 | s_min);
+    return 0xFFFF;
+}
+
+void tally(CellTable *t) {
+    t->n_certain = t->n_medium = t->n_multi = 0;
+    for (uint16_t c : t->cells) {
+        if (c == 0xFFFF)
+            ++t->n_multi;
+        else if (c & 0x8000)
+            ++t->n_medium;
+        else
+            ++t->n_certain;
+    }
+}
+
+}  // namespace
+
+bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::string *err) {
+    if (nbins < 1 || nbins > 256) {
+        *err = "nbins must be in [1, 256]";
+        return false;
+    }
+    if (!edges_deg) {
+        *err = "bin_edges_deg is NULL";
+        return false;
+    }
+    for (int k = 0; k <= nbins; ++k) {
+        double v = edges_deg[k];
+        if (!isfinite(v) || v < 0.0 || v > 180.0) {
+            *err = "bin edges must be finite and within [0, 180] degrees";
+            return false;
+        }
+        if (k > 0 && !(v > edges_deg[k - 1])) {
+            *err = "bin edges must be strictly increasing";
+            return false;
+        }
+    }
+    const double deg = M_PI / 180.0;
+    EdgeTables t;
+    t.nbins = nbins;
+    t.edge_rad.resize(nbins + 1);
+    t.D.resize(nbins + 1);
+    t.E.resize(nbins + 1);
+    for (int k = 0; k <= nbins; ++k) {
+        double e = edges_deg[k] * deg;
+        t.edge_rad[k] = e;
+        double D = threshold_of(e);
+        std::string why;
+        if (!verify_threshold(e, D, &why)) {
+            *err = why;
+            return false;
+        }
+        t.D[k] = D;
+        if (D == HUGE_VAL)
+            t.E[k] = -HUGE_VAL;
+        else if (D == -HUGE_VAL)
+            t.E[k] = HUGE_VAL;
+        else
+            t.E[k] = 1.0 - D;
+    }
+    *out = std::move(t);
+    return true;
+}
+
+// Band of edge k.  Let v be the FP64 master vectors (| |v|^2 - 1 | <= delta),
+// f = fl32(v) their FP32 copies, c_v = |v_i - v_j|, c_f = |f_i - f_j|.
+//  * d, the counting rule's FP64 dot, is within eps_d = gamma_3 (1 + delta)
+//    of v_i . v_j (recursive summation of 3 products), and
+//    v_i . v_j = (|v_i|^2 + |v_j|^2 - c_v^2) / 2, so
+//      c_v^2 >= 2(1 - D_k) + 2(delta + eps_d)  =>  d <= D_k,
+//      c_v^2 <  2(1 - D_k) - 2(delta + eps_d)  =>  d >  D_k.
+//  * |f - v| <= u |v| per vector (u = 2^-24), so |c_f - c_v| <= a = 2u(1 + delta).
+//  * the kernel's q = fl(fma(dz, dz, fma(dy, dy, dx*dx))) with dx = fl(fx_i - fx_j)
+//    etc. (or the same with separate multiply and add) satisfies
+//    (1-u)^5 c_f^2 - tau <= q <= (1+u)^5 c_f^2 + tau (every term is
+//    non-negative; tau covers gradual or flushed underflow).
+//  Hence q >= qhi_k => d <= D_k and q < qlo_k => d > D_k with
+//      qhi_k = RU32(((C+ + a)^2 (1+u)^5 + tau) s),
+//      qlo_k = RD32((((C- - a)_+)^2 (1-u)^5 - tau) / s),
+//  C+- = sqrt(2(1 - D_k) +- 2(delta + eps_d)), and s = 1 + 2^-20 absorbing
+//  the rounding of this host arithmetic (a few ulps of FP64).
+Band32 make_band32(const EdgeTables &t, double delta) {
+    const double U = ldexp(1.0, -53), u = ldexp(1.0, -24);
+    const double eps_d = 3.0 * U / (1.0 - 3.0 * U) * (1.0 + delta);
+    const double a = 2.0 * u * (1.0 + delta);
+    const double grow = pow(1.0 + u, 5.0), shrink = pow(1.0 - u, 5.0);
+    const double tau = ldexp(1.0, -120);
+    const double s = 1.0 + ldexp(1.0, -20);
+    const double slack = 2.0 * (delta + eps_d);
+    Band32 b;
+    b.delta = delta;
+    const int ne = (int)t.D.size();
+    b.qlo.resize(ne);
+    b.qhi.resize(ne);
+    for (int k = 0; k < ne; ++k) {
+        double D = t.D[k];
+        if (D == HUGE_VAL) {
+            b.qlo[k] = b.qhi[k] = -HUGE_VALF;
+            continue;
+        }
+        if (D == -HUGE_VAL) {
+            b.qlo[k] = b.qhi[k] = HUGE_VALF;
+            continue;
+        }
+        double base = 2.0 * (1.0 - D);
+        double cp = sqrt(base + slack);
+        b.qhi[k] = round_up32(((cp + a) * (cp + a) * grow + tau) * s);
+        double tm = base - slack;
+        if (tm <= 0.0) {
+            b.qlo[k] = 0.0f;
+        } else {
+            double cm = sqrt(tm) - a;
+            if (cm <= 0.0) {
+                b.qlo[k] = 0.0f;
+            } else {
+                double v = (cm * cm * shrink - tau) / s;
+                b.qlo[k] = v > 0.0 ? round_down32(v) : 0.0f;
+            }
+        }
+    }
+    return b;
+}
+
+// FP32 cells: key = bits(q) >> shift for q >= 0.  The bottom cell also holds
+// every q below its range and the top cell every q above.
+CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells) {
+    const int ne = (int)t.D.size();
+    // largest possible q: |f_i - f_j| <= 2 sqrt(1 + delta) + a, then rounding
+    const double qtop_d = pow(2.0 * sqrt(1.0 + delta) + 4.0 * ldexp(1.0, -24), 2.0) * 1.0001;
+    const uint32_t ktop = fbits(round_up32(qtop_d));
+    // smallest positive finite threshold
+    float tmin = HUGE_VALF;
+    for (int k = 0; k < ne; ++k) {
+        if (isfinite(b.qlo[k]) && b.qlo[k] > 0.0f)
+            tmin = std::min(tmin, b.qlo[k]);
+        if (isfinite(b.qhi[k]) && b.qhi[k] > 0.0f)
+            tmin = std::min(tmin, b.qhi[k]);
+    }
+    CellTable ct;
+    for (int shift = 12; shift <= 23; ++shift) {
+        int64_t hi = ktop >> shift;
+        int64_t lo = isfinite(tmin) ? (int64_t)(fbits(tmin) >> shift) - 1 : hi - 1;
+        if (lo < 0)
+            lo = 0;
+        if (hi - lo + 1 <= max_cells || shift == 23) {
+            if (hi - lo + 1 > max_cells)
+                lo = hi - max_cells + 1;
+            ct.shift = shift;
+            ct.lo = (int32_t)lo;
+            ct.hi = (int32_t)hi;
+            break;
+        }
+    }
+    const int n = ct.hi - ct.lo + 1;
+    ct.cells.resize(n);
+    for (int c = ct.lo; c <= ct.hi; ++c) {
+        float lo = c == ct.lo ? 0.0f : ffrom((uint32_t)c << ct.shift);
+        float hi = c == ct.hi ? HUGE_VALF : ffrom((((uint32_t)c + 1u) << ct.shift) - 1u);
+        int s_min = 0, s_max = 0;
+        for (int k = 0; k < ne; ++k) {
+            if (lo >= b.qhi[k])
+                ++s_min;
+            if (hi >= b.qlo[k])
+                ++s_max;
+        }
+        ct.cells[c - ct.lo] = encode(s_min, s_max);
+    }
+    tally(&ct);
+    return ct;
+}
+
+// FP64 cells: key = (int32) high word of e = fl(1 - d), arithmetic shift.
+// e < 0 (d > 1 from rounding) falls into the bottom cell, whose range is
+// taken to start at -inf.
+CellTable make_cells64(const EdgeTables &t, int max_cells) {
+    const int ne = (int)t.E.size();
+    const int32_t ktop = dhi(2.0 + ldexp(1.0, -18));
+    double tmin = HUGE_VAL;
+    for (int k = 0; k < ne; ++k)
+        if (isfinite(t.E[k]) && t.E[k] > 0.0)
+            tmin = std::min(tmin, t.E[k]);
+    CellTable ct;
+    for (int shift = 9; shift <= 20; ++shift) {
+        int64_t hi = ktop >> shift;
+        int64_t lo = isfinite(tmin) ? (int64_t)(dhi(tmin) >> shift) - 1 : hi - 1;
+        if (lo < 0)
+            lo = 0;
+        if (hi - lo + 1 <= max_cells || shift == 20) {
+            if (hi - lo + 1 > max_cells)
+                lo = hi - max_cells + 1;
+            ct.shift = shift;
+            ct.lo = (int32_t)lo;
+            ct.hi = (int32_t)hi;
+            break;
+        }
+    }
+    const int n = ct.hi - ct.lo + 1;
+    ct.cells.resize(n);
+    for (int c = ct.lo; c <= ct.hi; ++c) {
+        double lo = c == ct.lo ? -HUGE_VAL : dfrom((uint64_t)((uint32_t)c << ct.shift) << 32);
+        double hi = c == ct.hi ? HUGE_VAL
+                               : dfrom(((uint64_t)((((uint32_t)c + 1u) << ct.shift) - 1u) << 32) |
+                                       0xffffffffULL);
+        int s_min = 0, s_max = 0;
+        for (int k = 0; k < ne; ++k) {
+            if (lo > t.E[k])
+                ++s_min;
+            if (hi >= t.E[k])
+                ++s_max;
+        }
+        ct.cells[c - ct.lo] = encode(s_min, s_max);
+    }
+    tally(&ct);
+    return ct;
+}
+
+}  // namespace tpcf

@@ -1,0 +1,45 @@
+// Host-side compilation of angular bin edges into the thresholds and cell
+// tables the pair kernels use.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace tpcf {
+
+struct EdgeTables {
+    int nbins = 0;
+    std::vector<double> edge_rad;   // e_k = edge_deg[k] * (pi / 180)
+    std::vector<double> D;          // largest d with acos(d) >= e_k (+-inf at the ends)
+    std::vector<double> E;          // fl(1 - D_k); -inf where D_k = +inf, +inf where D_k = -inf
+};
+
+struct Band32 {
+    double delta = 0;               // bound on | |v|^2 - 1 | used for the band
+    std::vector<float> qlo, qhi;
+};
+
+struct CellTable {
+    int shift = 0;                  // cell = key >> shift
+    int32_t lo = 0, hi = 0;         // clamp range of cells (inclusive)
+    std::vector<uint16_t> cells;    // hi - lo + 1 entries
+    int n_certain = 0, n_medium = 0, n_multi = 0;
+};
+
+// Validate edges (finite, strictly increasing, within [0, 180], 1 <= nbins <=
+// 256) and compile them.  Returns false with a message on invalid input or
+// if acos fails the local monotonicity check around a threshold.
+bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::string *err);
+
+// FP32 squared-chord band of every edge for catalogs whose squared norms
+// deviate from 1 by at most delta.
+Band32 make_band32(const EdgeTables &t, double delta);
+
+// Cell tables.  FP32: key = bits of q (q >= 0).  FP64: key = high 32 bits of
+// e = fl(1 - d) read as a signed integer.
+CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
+CellTable make_cells64(const EdgeTables &t, int max_cells);
+
+}  // namespace tpcf

@@ -1,0 +1,86 @@
+// Internal declarations shared by the host library and the HIP kernels.
+// Not part of the public ABI (see include/tpcf.h).
+#pragma once
+
+#include <stdint.h>
+
+namespace tpcf {
+
+// Threads per block and the i-points each lane keeps in registers.
+constexpr int kWaves = 4;
+constexpr int kWaveSize = 64;
+constexpr int kBlock = kWaves * kWaveSize;
+
+// Largest table of cells kept in LDS (16-bit entries).
+constexpr int kMaxLutCells = 8192;
+// Histogram copies in global memory (u64), indexed by work unit.
+constexpr int kGlobalCopies = 64;
+// Largest number of output slots (nbins <= 256 -> nbins + 2 slots).
+constexpr int kMaxSlots = 258;
+
+// Table entry encoding.  A cell of the squared-chord (FP32) or 1 - d (FP64)
+// axis maps to:
+//   0 .. kMaxSlots-1   the slot, certain for every value in the cell;
+//   kMedium | k        exactly one edge k is undecided inside the cell;
+//   kMulti             several edges are undecided: use the exact rule.
+constexpr uint16_t kMedium = 0x8000;
+constexpr uint16_t kMulti = 0xFFFF;
+
+// One work unit: rows i in [i0, i1) against columns j in [j0, j1).
+// flags bit 0: the unit needs per-pair masking (i tail or j <= i diagonal).
+struct Unit {
+    int32_t i0, i1, j0, j1;
+};
+
+enum : int32_t { kUnitMasked = 1 };
+
+struct PairArgs {
+    // Catalog A (rows i) and B (columns j), structure of arrays.
+    const float *ax32, *ay32, *az32;
+    const float *bx32, *by32, *bz32;
+    const double *ax64, *ay64, *az64;
+    const double *bx64, *by64, *bz64;
+    int32_t auto_pairs;          // 1: DD/RR (count j > i only), 0: DR
+
+    const Unit *units;           // device
+    int32_t n_units;
+
+    // Cell table (device, copied into LDS by every block).
+    const uint16_t *lut;
+    int32_t lut_cells;           // c_hi - c_lo + 1
+    int32_t lut_shift;           // cell = key >> shift
+    int32_t lut_lo, lut_hi;      // clamp range of cells
+
+    // Edge thresholds (device).
+    const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
+    const double *E;             // fl(1 - D_k), nedges
+    const double *D;             // D_k, nedges
+    int32_t nedges;              // nbins + 1
+    int32_t nslots;              // nbins + 2
+
+    // Per-wave LDS histogram: row stride in bytes (copies * 4) and copies.
+    int32_t hist_copies;         // 64, 32, 16 or 8
+
+    unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
+    unsigned long long *stats;   // [pairs, flagged, exact]
+};
+
+// LDS bytes used by one block for the given table sizes.
+inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int nedges) {
+    int hist = kWaves * (nslots + 1) * hist_copies * 4;      // +1: discard row
+    int lut = ((lut_cells * 2) + 15) & ~15;
+    int thr = nedges * (4 + 4 + 8 + 8);
+    return hist + lut + thr;
+}
+
+}  // namespace tpcf
+
+// Launchers implemented in kernels.hip.
+extern "C" {
+int tpcf_launch_pairs(const tpcf::PairArgs *args, int precision, void *stream);
+int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
+int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots,
+                              unsigned long long *out, void *stream);
+int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
+                         double *maxdev_out, void *stream);
+}

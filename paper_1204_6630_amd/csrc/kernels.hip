@@ -1,0 +1,553 @@
+// Pair-counting kernels for gfx950 (MI355X).
+//
+// The method (paper, Section 3): form the angle of every pair of objects from
+// the dot product of their unit vectors, and histogram it with atomic
+// updates of per-block partial histograms in on-chip memory that are later
+// combined in one histogram in global memory.
+//
+// gfx950 design:
+//   * one work unit = a tile of rows i (four wavefronts, each holding
+//     kRowsPerLane points per lane in registers) against a range of columns
+//     j; every wavefront walks the same j range, reading each j through the
+//     scalar unit (the address is uniform), so no LDS staging of j is needed;
+//   * a pair is classified with one table lookup in LDS: the key is the top
+//     bits of q = fl32 |f_i - f_j|^2 (FP32_CHORD) or of e = fl64(1 - d)
+//     (FP64); a cell whose whole range lies between two edges gives the slot
+//     directly, a cell that straddles one edge's band is settled by one
+//     threshold comparison, and anything closer is re-decided with the
+//     exact FP64 rule d <= D_k;
+//   * every wavefront owns a private LDS histogram with one column per lane
+//     (layout [slot][copy], copy = lane mod copies), updated with ds_add_u32;
+//     with 64 copies no two lanes ever touch the same word and the lanes of a
+//     half-wave hit 32 distinct banks;
+//   * after each unit a wavefront sums its histogram and adds it with 64-bit
+//     atomics into one of kGlobalCopies global copies, which a final kernel
+//     reduces into the output slots.
+//
+// The whole file is compiled with -ffp-contract=off: the FP64 dot product is
+// evaluated unfused and left to right exactly like the counting rule; the
+// FP32 chord^2 uses explicit fmaf, which the error band accounts for.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+using namespace tpcf;
+
+namespace {
+
+constexpr int kRowsPerLane = 4;
+constexpr int kRowsPerWave = kRowsPerLane * kWaveSize;
+
+// Number of k with d <= D[k]; D is non-increasing in k.
+__device__ __forceinline__ uint32_t count_le(double d, const double *D, int n) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (d <= D[mid])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+// FP64 dot product of the counting rule: (x_i x_j + y_i y_j) + z_i z_j with
+// every operation rounded (contraction is off for this file).
+__device__ __forceinline__ double exact_dot(double xi, double yi, double zi,
+                                            double xj, double yj, double zj) {
+    double t = xi * xj;
+    double u = yi * yj;
+    double s = t + u;
+    double v = zi * zj;
+    return s + v;
+}
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+
+// Clamp into [lo, hi] in one instruction (all operands in VGPRs: gfx9 VOP3
+// reads at most one SGPR, which keeps the compiler from forming v_med3).
+__device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t hi) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t lo, int32_t hi) {
+    int32_t r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Copy a wavefront-uniform value into a VGPR once, so loops do not
+// re-materialise it for every VOP3 that needs a VGPR operand.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// LDS access by 32-bit byte address.
+__device__ __forceinline__ uint32_t lds_read_u16(uint32_t addr) {
+    return *(const lds_u16 *)(uintptr_t)addr;
+}
+
+__device__ __forceinline__ void lds_inc(uint32_t addr) {
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+struct Smem {
+    uint32_t *hist;     // kWaves x (nslots + 1) x copies
+    double *D;
+    double *E;
+    float *qlo;
+    float *qhi;
+    uint16_t *lut;
+    uint32_t hist_addr;  // LDS byte address of hist
+    uint32_t lut_addr;   // LDS byte address of lut
+};
+
+__device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
+    Smem s;
+    int hist_words = kWaves * (a.nslots + 1) * a.hist_copies;
+    s.hist = reinterpret_cast<uint32_t *>(base);
+    s.D = reinterpret_cast<double *>(base + hist_words * 4);
+    s.E = s.D + a.nedges;
+    s.qlo = reinterpret_cast<float *>(s.E + a.nedges);
+    s.qhi = s.qlo + a.nedges;
+    s.lut = reinterpret_cast<uint16_t *>(s.qhi + a.nedges);
+    s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
+    s.lut_addr = (uint32_t)(uintptr_t)(lds_u16 *)s.lut;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, kWaveSize);
+    return v;
+}
+
+// Sum one wavefront's LDS histogram into the global copy and clear it.
+__device__ void flush_wave(const PairArgs &a, const Smem &s, int wave, int lane, int copy) {
+    const int C = a.hist_copies;
+    uint32_t *h = s.hist + wave * (a.nslots + 1) * C;
+    unsigned long long *g = a.hist + (size_t)copy * a.nslots;
+    for (int s0 = 0; s0 < a.nslots; s0 += kWaveSize) {
+        int slot = s0 + lane;
+        if (slot < a.nslots) {
+            uint32_t acc = 0;
+            uint32_t *row = h + slot * C;
+            // skewed walk over the copies: lanes of a half-wave hit distinct banks
+            for (int c = 0; c < C; ++c) {
+                int cc = (c + lane) & (C - 1);
+                acc += row[cc];
+                row[cc] = 0;
+            }
+            if (acc)
+                atomicAdd(&g[slot], (unsigned long long)acc);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Smem &s,
+                                                 const PairArgs &a, int i, int j,
+                                                 uint32_t &n_exact) {
+    if (ent != kMulti) {
+        int k = ent & 0x7FFF;
+        if (q < s.qlo[k])
+            return (uint32_t)k;
+        if (q >= s.qhi[k])
+            return (uint32_t)(k + 1);
+        ++n_exact;
+        double d = exact_dot(a.ax64[i], a.ay64[i], a.az64[i], a.bx64[j], a.by64[j], a.bz64[j]);
+        return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
+    }
+    ++n_exact;
+    double d = exact_dot(a.ax64[i], a.ay64[i], a.az64[i], a.bx64[j], a.by64[j], a.bz64[j]);
+    return count_le(d, s.D, a.nedges);
+}
+
+__device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, double e, double d,
+                                                 const Smem &s, const PairArgs &a,
+                                                 uint32_t &n_exact) {
+    if (ent != kMulti) {
+        int k = ent & 0x7FFF;
+        double Ek = s.E[k];
+        if (e > Ek)
+            return (uint32_t)(k + 1);
+        if (e < Ek)
+            return (uint32_t)k;
+        ++n_exact;
+        return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
+    }
+    ++n_exact;
+    return count_le(d, s.D, a.nedges);
+}
+
+// Column coordinates are read through the constant address space: every lane
+// of a wavefront reads the same j, so these become scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) float *cfloat_p;
+typedef const __attribute__((address_space(4))) double *cdouble_p;
+
+// One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
+// Each step takes JN columns: all JN * P table lookups are issued first, one
+// test sends the wavefront to the rare path if any lane needs it, then the
+// JN * P histogram increments follow.
+template <bool MASKED, int P, int JN>
+__device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, const float (&xi)[P],
+                                          const float (&yi)[P], const float (&zi)[P],
+                                          const int (&ii)[P], const int (&il)[P], int ie, int j,
+                                          cfloat_p bx, cfloat_p by, cfloat_p bz, uint32_t shift,
+                                          uint32_t clo, uint32_t chi, uint32_t lutbias, uint32_t rowstep,
+                                          uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
+    float xj[JN], yj[JN], zj[JN];
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+        xj[t] = bx[j + t];
+        yj[t] = by[j + t];
+        zj[t] = bz[j + t];
+    }
+    float q[JN][P];
+    uint32_t ent[JN][P];
+    uint32_t any = 0;
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            float dx = xi[p] - xj[t];
+            float dy = yi[p] - yj[t];
+            float dz = zi[p] - zj[t];
+            float v = dx * dx;
+            v = __fmaf_rn(dy, dy, v);
+            v = __fmaf_rn(dz, dz, v);
+            q[t][p] = v;
+            uint32_t c = med3_u32(__float_as_uint(v) >> shift, clo, chi);
+            ent[t][p] = lds_read_u16(c * 2u + lutbias);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            any |= ent[t][p];
+    if ((int16_t)any < 0) {     // some entry has kMedium (bit 15) set
+#pragma unroll
+        for (int t = 0; t < JN; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (ent[t][p] & kMedium) {
+                    ++n_flag;
+                    ent[t][p] = resolve_fp32(ent[t][p], q[t][p], s, a, il[p], j + t, n_exact);
+                }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            uint32_t e = ent[t][p];
+            if (MASKED) {
+                bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
+                e = ok ? e : (uint32_t)a.nslots;
+            }
+            lds_inc(__umul24(e, rowstep) + lanebase);
+        }
+}
+
+template <bool MASKED, int P>
+__device__ void rows_fp32(const PairArgs &a, const Smem &s, int ib, int ie, int j0, int j1,
+                          int lane, uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
+    float xi[P], yi[P], zi[P];
+    int ii[P], il[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        int i = ib + p * kWaveSize + lane;
+        ii[p] = i;
+        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
+        xi[p] = a.ax32[il[p]];
+        yi[p] = a.ay32[il[p]];
+        zi[p] = a.az32[il[p]];
+    }
+    const uint32_t shift = (uint32_t)a.lut_shift;
+    const uint32_t clo = to_vgpr((uint32_t)a.lut_lo), chi = to_vgpr((uint32_t)a.lut_hi);
+    const uint32_t lutbias = s.lut_addr - 2u * (uint32_t)a.lut_lo;   // address of cell c is 2c + lutbias
+    const uint32_t rowstep = (uint32_t)a.hist_copies * 4u;
+    cfloat_p bx = (cfloat_p)a.bx32;
+    cfloat_p by = (cfloat_p)a.by32;
+    cfloat_p bz = (cfloat_p)a.bz32;
+    constexpr int JN = 2;
+    int j = j0;
+    for (; j + JN <= j1; j += JN)
+        step_fp32<MASKED, P, JN>(a, s, xi, yi, zi, ii, il, ie, j, bx, by, bz, shift, clo, chi,
+                                 lutbias, rowstep, lanebase, n_flag, n_exact);
+    for (; j < j1; ++j)
+        step_fp32<MASKED, P, 1>(a, s, xi, yi, zi, ii, il, ie, j, bx, by, bz, shift, clo, chi,
+                                lutbias, rowstep, lanebase, n_flag, n_exact);
+}
+
+template <bool MASKED, int P, int JN>
+__device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, const double (&xi)[P],
+                                          const double (&yi)[P], const double (&zi)[P],
+                                          const int (&ii)[P], int ie, int j, cdouble_p bx,
+                                          cdouble_p by, cdouble_p bz, int shift, int clo, int chi,
+                                          uint32_t lutbias, uint32_t rowstep, uint32_t lanebase, uint32_t &n_flag,
+                                          uint32_t &n_exact) {
+    double xj[JN], yj[JN], zj[JN];
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+        xj[t] = bx[j + t];
+        yj[t] = by[j + t];
+        zj[t] = bz[j + t];
+    }
+    double d[JN][P], e[JN][P];
+    uint32_t ent[JN][P];
+    uint32_t any = 0;
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double dd = exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
+            double ee = 1.0 - dd;
+            d[t][p] = dd;
+            e[t][p] = ee;
+            // arithmetic shift: e < 0 (d > 1 from rounding) lands in the bottom cell
+            int32_t c = med3_i32(__double2hiint(ee) >> shift, clo, chi);
+            ent[t][p] = lds_read_u16((uint32_t)c * 2u + lutbias);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            any |= ent[t][p];
+    if ((int16_t)any < 0) {     // some entry has kMedium (bit 15) set
+#pragma unroll
+        for (int t = 0; t < JN; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (ent[t][p] & kMedium) {
+                    ++n_flag;
+                    ent[t][p] = resolve_fp64(ent[t][p], e[t][p], d[t][p], s, a, n_exact);
+                }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            uint32_t v = ent[t][p];
+            if (MASKED) {
+                bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
+                v = ok ? v : (uint32_t)a.nslots;
+            }
+            lds_inc(__umul24(v, rowstep) + lanebase);
+        }
+}
+
+template <bool MASKED, int P>
+__device__ void rows_fp64(const PairArgs &a, const Smem &s, int ib, int ie, int j0, int j1,
+                          int lane, uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
+    double xi[P], yi[P], zi[P];
+    int ii[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        int i = ib + p * kWaveSize + lane;
+        ii[p] = i;
+        int il = i < ie ? i : ib;
+        xi[p] = a.ax64[il];
+        yi[p] = a.ay64[il];
+        zi[p] = a.az64[il];
+    }
+    const int shift = a.lut_shift;
+    const int clo = (int)to_vgpr((uint32_t)a.lut_lo), chi = (int)to_vgpr((uint32_t)a.lut_hi);
+    const uint32_t lutbias = s.lut_addr - 2u * (uint32_t)a.lut_lo;
+    const uint32_t rowstep = (uint32_t)a.hist_copies * 4u;
+    cdouble_p bx = (cdouble_p)a.bx64;
+    cdouble_p by = (cdouble_p)a.by64;
+    cdouble_p bz = (cdouble_p)a.bz64;
+    constexpr int JN = 2;
+    int j = j0;
+    for (; j + JN <= j1; j += JN)
+        step_fp64<MASKED, P, JN>(a, s, xi, yi, zi, ii, ie, j, bx, by, bz, shift, clo, chi, lutbias,
+                                 rowstep, lanebase, n_flag, n_exact);
+    for (; j < j1; ++j)
+        step_fp64<MASKED, P, 1>(a, s, xi, yi, zi, ii, ie, j, bx, by, bz, shift, clo, chi, lutbias,
+                                rowstep, lanebase, n_flag, n_exact);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Smem s = carve(smem, a);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWaveSize - 1);
+    const int wave = tid >> 6;
+
+    const int hist_words = kWaves * (a.nslots + 1) * a.hist_copies;
+    for (int w = tid; w < hist_words; w += kBlock)
+        s.hist[w] = 0;
+    for (int c = tid; c < a.lut_cells; c += kBlock)
+        s.lut[c] = a.lut[c];
+    for (int k = tid; k < a.nedges; k += kBlock) {
+        s.D[k] = a.D[k];
+        s.E[k] = a.E[k];
+        s.qlo[k] = a.qlo[k];
+        s.qhi[k] = a.qhi[k];
+    }
+    __syncthreads();
+
+    const uint32_t lanebase =
+        s.hist_addr + (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
+    uint32_t n_flag = 0, n_exact = 0;
+
+    for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+        const Unit un = a.units[u];
+        const int ib = un.i0 + wave * kRowsPerWave;
+        if (ib < un.i1) {
+            const int ie = min(un.i1, ib + kRowsPerWave);
+            const bool masked = (ie - ib < kRowsPerWave) || (a.auto_pairs && un.j0 < ie);
+            if (PREC == 0) {
+                if (masked)
+                    rows_fp32<true, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                else
+                    rows_fp32<false, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+            } else {
+                if (masked)
+                    rows_fp64<true, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                else
+                    rows_fp64<false, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+            }
+            // the wave's own LDS region only: no block barrier needed
+            flush_wave(a, s, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
+        }
+    }
+    uint32_t f = wave_sum(n_flag);
+    uint32_t x = wave_sum(n_exact);
+    if (lane == 0) {
+        if (f)
+            atomicAdd(&a.stats[1], (unsigned long long)f);
+        if (x)
+            atomicAdd(&a.stats[2], (unsigned long long)x);
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = 0ull;
+}
+
+__global__ void reduce_copies_kernel(const unsigned long long *copies, int32_t nslots,
+                                     unsigned long long *out) {
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+        unsigned long long acc = 0;
+        for (int g = 0; g < kGlobalCopies; ++g)
+            acc += copies[(size_t)g * nslots + s];
+        out[s] = acc;
+    }
+}
+
+// FP32 copies (round to nearest) of an FP64 SoA block of 3n values, and the
+// largest |x^2 + y^2 + z^2 - 1| (FP64, unfused), +inf if a value is not finite.
+__global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsigned long long *maxdev) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+        out[i] = (float)x;
+        out[n + i] = (float)y;
+        out[2 * n + i] = (float)z;
+        double t = x * x;
+        double u = y * y;
+        double v = z * z;
+        double r = (t + u) + v;
+        double dev = fabs(r - 1.0);
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !(dev == dev))
+            dev = __builtin_huge_val();
+        m = dev > m ? dev : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + off] ? red[threadIdx.x] : red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMax(maxdev, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+int grid_for(int n_units, int lds) {
+    static int cus = 0, lds_per_cu = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            cus = prop.multiProcessorCount;
+            lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+        }
+        if (cus <= 0)
+            cus = 256;
+        if (lds_per_cu <= 0)
+            lds_per_cu = 160 * 1024;
+    }
+    int per_cu = lds > 0 ? lds_per_cu / lds : 8;
+    if (per_cu < 1)
+        per_cu = 1;
+    if (per_cu > 8)
+        per_cu = 8;
+    long long g = (long long)cus * per_cu * 4;
+    if (g > n_units)
+        g = n_units;
+    if (g < 1)
+        g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stream) {
+    if (args->n_units <= 0)
+        return 0;
+    const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->nedges);
+    const int grid = grid_for(args->n_units, lds);
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == 0) {
+        hipLaunchKernelGGL(pairs_kernel<0>, dim3(grid), dim3(kBlock), lds, st, *args);
+    } else {
+        hipLaunchKernelGGL(pairs_kernel<1>, dim3(grid), dim3(kBlock), lds, st, *args);
+    }
+    return (int)hipGetLastError();
+}
+
+extern "C" int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stream) {
+    if (n <= 0)
+        return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, n);
+    return (int)hipGetLastError();
+}
+
+extern "C" int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots,
+                                         unsigned long long *out, void *stream) {
+    hipLaunchKernelGGL(reduce_copies_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, copies,
+                       nslots, out);
+    return (int)hipGetLastError();
+}
+
+extern "C" int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
+                                    double *maxdev_out, void *stream) {
+    // maxdev_out is a device double, zeroed by the caller
+    if (n <= 0)
+        return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048)
+        blocks = 2048;
+    hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       xyz64, n, xyz32, reinterpret_cast<unsigned long long *>(maxdev_out));
+    return (int)hipGetLastError();
+}

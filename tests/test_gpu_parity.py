@@ -1,0 +1,290 @@
+"""GPU parity: libtpcf.so against the CPU oracle (needs an MI355X).
+
+Counts are integers, so the bar is bit-exact equality of every slot, for
+both precision modes.  Sizes: the small configuration in full, ragged sizes
+around the tile sizes (64 lanes x 4 rows x 4 wavefronts = 1024 rows per
+unit), the larger configurations in full on the GPU with sampled row blocks
+checked against the oracle, plus exact-dot probes on every edge threshold.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1204_6630_amd as tp
+import synthcat
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [tp.FP32_CHORD, tp.FP64]
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tp.Context(0)
+    yield c
+    c.close()
+
+
+def _xyz(cat):
+    return oracle.radec_to_xyz(cat.ra, cat.dec)
+
+
+def _workload(cfg):
+    if cfg not in _cache:
+        _cache[cfg] = synthcat.CONFIGS[cfg]()
+    return _cache[cfg]
+
+
+def _oracle(key, fn):
+    if key not in _cache:
+        _cache[key] = fn()
+    return _cache[key]
+
+
+@pytest.fixture(scope="module")
+def cfg1(ctx):
+    wl = _workload(1)
+    d, r = wl.data[0], wl.randoms[0]
+    cd = ctx.upload_catalog(d.ra, d.dec)
+    cr = ctx.upload_catalog(r.ra, r.dec)
+    xd, xr = _xyz(d), _xyz(r)
+    ref = {
+        "DD": oracle.count(oracle.DD, xd, wl.edges_deg),
+        "DR": oracle.count(oracle.DR, xd, wl.edges_deg, b_xyz=xr),
+        "RR": oracle.count(oracle.RR, xr, wl.edges_deg),
+    }
+    return wl, cd, cr, ref
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config1_full_bit_exact(ctx, cfg1, prec):
+    wl, cd, cr, ref = cfg1
+    dd = ctx.count(tp.DD, cd, wl.edges_deg, precision=prec)
+    dr = ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=prec)
+    rr = ctx.count(tp.RR, cr, wl.edges_deg, precision=prec)
+    assert np.array_equal(dd, ref["DD"])
+    assert np.array_equal(dr, ref["DR"])
+    assert np.array_equal(rr, ref["RR"])
+    nd, nr = wl.data[0].n, wl.randoms[0].n
+    for form in (0, 1):
+        w = tp.landy_szalay(dd, dr, rr, nd, nr, form)
+        wref = oracle.landy_szalay(ref["DD"][1:-1], ref["DR"][1:-1], ref["RR"][1:-1], nd, nr, form)
+        fin = np.isfinite(wref)
+        assert np.array_equal(np.isnan(w), np.isnan(wref))
+        assert np.all(np.abs(w[fin] - wref[fin]) <= 1e-12 * np.maximum(1.0, np.abs(wref[fin])))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_sizes_and_tails(ctx, prec):
+    g = synthcat.rng_for(95, 0)
+    edges = np.concatenate([[0.0], synthcat.log_edges(0.002, 5.0, 17)])
+    ra, dec = synthcat.clustered(6000, 30, 0.4, synthcat.PATCH_30, g)
+    xyz = oracle.radec_to_xyz(ra, dec)
+    cid = ctx.upload_catalog(ra, dec)
+    for n in (0, 1, 2, 3, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 2049, 4097, 6000):
+        sub = ctx.upload_catalog(ra[:n], dec[:n])
+        got = ctx.count(tp.DD, sub, edges, precision=prec)
+        ref = oracle.count(oracle.DD, tuple(c[:n] for c in xyz), edges)
+        assert np.array_equal(got, ref), n
+        got = ctx.count(tp.DR, sub, edges, cat_b=cid, precision=prec)
+        ref = oracle.count(oracle.DR, tuple(c[:n] for c in xyz), edges, b_xyz=xyz)
+        assert np.array_equal(got, ref), n
+        ctx.release_catalog(sub)
+    ctx.release_catalog(cid)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_row_ranges(ctx, cfg1, prec):
+    wl, cd, cr, _ = cfg1
+    xd, xr = _xyz(wl.data[0]), _xyz(wl.randoms[0])
+    n = wl.data[0].n
+    for rb, re in ((0, 1), (17, 1500), (1023, 1025), (n - 1, n), (5, 5), (0, n)):
+        got = ctx.count(tp.DD, cd, wl.edges_deg, precision=prec, row_begin=rb, row_end=re)
+        ref = oracle.count(oracle.DD, xd, wl.edges_deg, row_begin=rb, row_end=re)
+        assert np.array_equal(got, ref), (rb, re)
+        got = ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=prec, row_begin=rb, row_end=re)
+        ref = oracle.count(oracle.DR, xd, wl.edges_deg, b_xyz=xr, row_begin=rb, row_end=re)
+        assert np.array_equal(got, ref), (rb, re)
+
+
+def _next(d, n):
+    for _ in range(abs(n)):
+        d = np.nextafter(d, np.inf if n > 0 else -np.inf)
+    return d
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_exact_dot_probes_on_every_threshold(ctx, prec):
+    """P1: i = (1,0,0) and j = (d, sqrt(1 - d^2), 0) have FP64 dot exactly d;
+    d runs over D_k and its neighbours for every edge, so ties at the edge and
+    the D_k translation are exercised directly."""
+    for edges in (synthcat.log_edges(0.01, 10.0, 20), synthcat.log_edges(0.0005, 30.0, 40),
+                  np.array([0.0, 0.5, 60.0, 90.0, 120.0, 179.0])):
+        D, _, _ = tp.compile_edges(edges)
+        ds = []
+        for Dk in D:
+            if np.isfinite(Dk):
+                ds += [_next(Dk, s) for s in (-3, -2, -1, 0, 1, 2, 3)]
+        ds = np.array([x for x in ds if -1.0 <= x <= 1.0])
+        a = (np.ones(1), np.zeros(1), np.zeros(1))
+        b = (ds, np.sqrt(1.0 - ds * ds), np.zeros_like(ds))
+        ca = ctx.upload_catalog_xyz(*a)
+        cb = ctx.upload_catalog_xyz(*b)
+        got = ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec)
+        ref = oracle.count(oracle.DR, a, edges, b_xyz=b)
+        assert np.array_equal(got, ref)
+        # the same probes one per row (j > i via DD on the concatenation)
+        u = tuple(np.concatenate([p, q]) for p, q in zip(a, b))
+        cu = ctx.upload_catalog_xyz(*u)
+        got = ctx.count(tp.DD, cu, edges, precision=prec, row_begin=0, row_end=1)
+        ref = oracle.count(oracle.DD, u, edges, row_begin=0, row_end=1)
+        assert np.array_equal(got, ref)
+        for c in (ca, cb, cu):
+            ctx.release_catalog(c)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_duplicates_and_antipodes(ctx, prec):
+    g = synthcat.rng_for(95, 1)
+    p = np.stack(oracle.radec_to_xyz(*synthcat.uniform_sphere(700, g)), axis=1)
+    pts = np.concatenate([p, p[:300], -p[:200]])
+    xyz = tuple(pts.T.copy())
+    for edges in (np.array([0.01, 1.0, 179.0]), np.array([0.0, 1e-4, 90.0, 180.0])):
+        cid = ctx.upload_catalog_xyz(*xyz)
+        got = ctx.count(tp.DD, cid, edges, precision=prec)
+        ref = oracle.count(oracle.DD, xyz, edges)
+        assert np.array_equal(got, ref)
+        got = ctx.count(tp.DR, cid, edges, cat_b=cid, precision=prec)
+        ref = oracle.count(oracle.DR, xyz, edges, b_xyz=xyz)
+        assert np.array_equal(got, ref)
+        ctx.release_catalog(cid)
+
+
+def _sample_blocks(n, nblocks, size, seed):
+    g = np.random.default_rng(seed)
+    starts = np.sort(g.choice(max(1, n - size), size=nblocks, replace=False))
+    return [(int(s), int(min(n, s + size))) for s in starts]
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
+    wl = _workload(cfg)
+    d, r = wl.data[0], wl.randoms[0]
+    cd = ctx.upload_catalog(d.ra, d.dec)
+    cr = ctx.upload_catalog(r.ra, r.dec)
+    e = wl.edges_deg
+    full = {}
+    for prec in PRECS:
+        dd = ctx.count(tp.DD, cd, e, precision=prec)
+        dr = ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec)
+        rr = ctx.count(tp.RR, cr, e, precision=prec)
+        assert int(dd.sum()) == d.n * (d.n - 1) // 2
+        assert int(dr.sum()) == d.n * r.n
+        assert int(rr.sum()) == r.n * (r.n - 1) // 2
+        full[prec] = (dd, dr, rr)
+    for a, b in zip(full[tp.FP32_CHORD], full[tp.FP64]):
+        assert np.array_equal(a, b)
+    xd, xr = _xyz(d), _xyz(r)
+    size = 200 if cfg == 2 else 150
+    for rb, re in _sample_blocks(d.n, 2, size, 11 + cfg):
+        for prec in PRECS:
+            got = ctx.count(tp.DD, cd, e, precision=prec, row_begin=rb, row_end=re)
+            ref = _oracle(("DD", cfg, rb), lambda: oracle.count(oracle.DD, xd, e, row_begin=rb, row_end=re))
+            assert np.array_equal(got, ref), ("DD", prec, rb)
+            got = ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec, row_begin=rb, row_end=re)
+            ref = _oracle(("DR", cfg, rb), lambda: oracle.count(oracle.DR, xd, e, b_xyz=xr, row_begin=rb, row_end=re))
+            assert np.array_equal(got, ref), ("DR", prec, rb)
+    for rb, re in _sample_blocks(r.n, 1, size, 21 + cfg):
+        for prec in PRECS:
+            got = ctx.count(tp.RR, cr, e, precision=prec, row_begin=rb, row_end=re)
+            ref = _oracle(("RR", cfg, rb), lambda: oracle.count(oracle.RR, xr, e, row_begin=rb, row_end=re))
+            assert np.array_equal(got, ref), ("RR", prec, rb)
+    ctx.release_catalog(cd)
+    ctx.release_catalog(cr)
+
+
+def test_union_invariant_on_gpu(ctx, cfg1):
+    """DD(A u B) = DD(A) + DD(B) + DR(A, B) and DR(A, B) = DR(B, A)."""
+    wl, cd, cr, _ = cfg1
+    d, r = wl.data[0], wl.randoms[0]
+    cu = ctx.upload_catalog(np.concatenate([d.ra, r.ra]), np.concatenate([d.dec, r.dec]))
+    e = wl.edges_deg
+    for prec in PRECS:
+        ddu = ctx.count(tp.DD, cu, e, precision=prec)
+        parts = (ctx.count(tp.DD, cd, e, precision=prec) + ctx.count(tp.RR, cr, e, precision=prec)
+                 + ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec))
+        assert np.array_equal(ddu, parts)
+        assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
+                              ctx.count(tp.DR, cr, e, cat_b=cd, precision=prec))
+    ctx.release_catalog(cu)
+
+
+def test_attach_torch_tensor_and_async(ctx, cfg1):
+    import torch
+    wl, cd, cr, ref = cfg1
+    x = np.stack(_xyz(wl.data[0]))
+    t = torch.from_numpy(x).to("cuda:0").contiguous()
+    ca = ctx.attach_catalog(t)
+    for prec in PRECS:
+        got = ctx.count(tp.DD, ca, wl.edges_deg, precision=prec)
+        assert np.array_equal(got, ref["DD"])
+    out = torch.zeros(wl.edges_deg.size + 1, dtype=torch.int64, device="cuda:0")
+    ctx.count_async(tp.DR, ca, wl.edges_deg, out.data_ptr(), cat_b=cr)
+    ctx.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.uint64), ref["DR"])
+    ctx.release_catalog(ca)
+    del t
+
+
+def test_timing_and_stats(ctx, cfg1):
+    wl, cd, cr, _ = cfg1
+    ctx.stats(reset=True)
+    ctx.kernel_time(reset=True)
+    ctx.set_timing(True)
+    ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
+    ms, n = ctx.kernel_time(reset=True)
+    ctx.set_timing(False)
+    pairs, flagged, exact = ctx.stats(reset=True)
+    assert n == 1 and ms > 0
+    assert pairs == wl.data[0].n * wl.randoms[0].n
+    assert exact <= flagged <= pairs
+    assert flagged < 0.2 * pairs
+
+
+def test_repeatable(ctx, cfg1):
+    wl, cd, cr, _ = cfg1
+    a = [ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD) for _ in range(3)]
+    assert all(np.array_equal(a[0], x) for x in a[1:])
+
+
+def test_gpu_error_paths(ctx, cfg1):
+    wl, cd, cr, _ = cfg1
+    e = wl.edges_deg
+    with pytest.raises(tp.TpcfError) as ei:
+        ctx.count(tp.DD, 9999, e)
+    assert ei.value.code == -4
+    with pytest.raises(tp.TpcfError) as ei:
+        ctx.count(tp.DD, cd, e, cat_b=cr)
+    assert ei.value.code == -1
+    with pytest.raises(tp.TpcfError) as ei:
+        ctx.count(tp.DR, cd, e, cat_b=9999)
+    assert ei.value.code == -4
+    with pytest.raises(tp.TpcfError):
+        ctx.count(tp.DD, cd, e, row_begin=5, row_end=4)
+    with pytest.raises(tp.TpcfError):
+        ctx.count(tp.DD, cd, e, row_begin=0, row_end=10**9)
+    with pytest.raises(tp.TpcfError):
+        ctx.count(tp.DD, cd, e, precision=7)
+    with pytest.raises(tp.TpcfError):
+        ctx.count(tp.DD, cd, e[::-1].copy())
+    with pytest.raises(tp.TpcfError):
+        ctx.upload_catalog_xyz([2.0], [0.0], [0.0])
+    with pytest.raises(tp.TpcfError):
+        ctx.upload_catalog([np.nan], [0.0])
+    with pytest.raises(tp.TpcfError) as ei:
+        ctx.release_catalog(9999)
+    assert ei.value.code == -4

@@ -1,0 +1,276 @@
+"""CPU tests of libtpcf.so's host logic (no GPU needed).
+
+* every symbol declared in include/tpcf.h is exported;
+* edge thresholds D_k bracket the counting rule (checked with Python's
+  math.acos, an independent caller of the same libm routine);
+* FP32 chord^2 bands: pairs placed at theta = e_k (1 +- 10^-s) in random
+  orientations; every decision the band calls certain agrees with the oracle;
+* a numpy emulation of the kernels' table-driven classification (FP32 q and
+  FP64 e = 1 - d, one lookup, threshold comparison in flagged cells, exact
+  d <= D_k when still undecided) reproduces the oracle slot of every pair;
+* Landy-Szalay and argument errors of host-only entry points.
+"""
+
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1204_6630_amd as tp
+import synthcat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DEG = math.pi / 180.0
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tpcf.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char \*)\s*(tpcf_\w+)\s*\(", header, re.M))
+    assert declared, "no declarations found"
+    L = tp.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(tp.EXPORTED_SYMBOLS)
+
+
+def _next(d, n=1):
+    for _ in range(abs(n)):
+        d = np.nextafter(d, np.inf if n > 0 else -np.inf)
+    return d
+
+
+@pytest.mark.parametrize("edges", [
+    synthcat.log_edges(0.01, 10.0, 20),
+    synthcat.log_edges(0.0005, 30.0, 40),
+    np.array([0.0, 1e-6, 0.1, 45.0, 89.0, 91.0, 135.0, 179.9, 180.0]),
+])
+def test_thresholds_bracket_the_rule(edges):
+    D, _, _ = tp.compile_edges(edges)
+    for k, e_deg in enumerate(edges):
+        e = e_deg * DEG
+        if e == 0.0:
+            assert D[k] == np.inf
+            continue
+        if math.acos(-1.0) < e:
+            assert D[k] == -np.inf
+            continue
+        assert -1.0 <= D[k] <= 1.0
+        assert math.acos(D[k]) >= e
+        if D[k] < 1.0:
+            assert math.acos(_next(D[k])) < e
+        for s in range(1, 40):
+            lo = _next(D[k], -s)
+            if lo >= -1.0:
+                assert math.acos(lo) >= e
+            hi = _next(D[k], s)
+            if hi <= 1.0:
+                assert math.acos(hi) < e
+    finite = D[np.isfinite(D)]
+    assert np.all(np.diff(finite) <= 0)
+
+
+def test_edges_validation():
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0, 1.0, 2.0])
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0, 0.5])
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0, 181.0])
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([-1.0, 1.0])
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0, np.nan])
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0])             # nbins = 0
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges(np.linspace(1, 2, 258))  # nbins = 257
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges([1.0, 2.0], delta_max=1e-3)
+
+
+def _rand_perp(g, a):
+    u = g.normal(size=a.shape)
+    u -= np.sum(u * a, axis=1)[:, None] * a
+    return u / np.linalg.norm(u, axis=1)[:, None]
+
+
+def _pairs_at(g, theta):
+    n = theta.size
+    a = g.normal(size=(n, 3))
+    a /= np.linalg.norm(a, axis=1)[:, None]
+    u = _rand_perp(g, a)
+    b = np.cos(theta)[:, None] * a + np.sin(theta)[:, None] * u
+    b /= np.linalg.norm(b, axis=1)[:, None]
+    return a, b
+
+
+def _q32(a, b):
+    """Kernel arithmetic in FP32 (separate multiply and add; the band covers
+    both this and the fused form)."""
+    fa = a.astype(np.float32)
+    fb = b.astype(np.float32)
+    d = fa - fb
+    q = d[:, 0] * d[:, 0]
+    q = q + d[:, 1] * d[:, 1]
+    q = q + d[:, 2] * d[:, 2]
+    return q.astype(np.float32)
+
+
+def _dot64(a, b):
+    return (a[:, 0] * b[:, 0] + a[:, 1] * b[:, 1]) + a[:, 2] * b[:, 2]
+
+
+@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
+                                   synthcat.log_edges(0.001, 20.0, 30)])
+def test_fp32_band_adversary(edges):
+    """P10: pairs at theta = e_k (1 +- 10^-s), s = 3..9, every edge."""
+    g = np.random.default_rng(7)
+    D, qlo, qhi = tp.compile_edges(edges, delta_max=4.5e-16)
+    er = edges * DEG
+    thetas, rel, edge_of = [], [], []
+    for k, e in enumerate(er):
+        for s in range(3, 10):
+            for sign in (-1.0, 1.0):
+                thetas.append(np.full(60, e * (1.0 + sign * 10.0 ** -s)))
+                rel.append(np.full(60, 10.0 ** -s))
+                edge_of.append(np.full(60, k))
+    theta = np.concatenate(thetas)
+    rel = np.concatenate(rel)
+    edge_of = np.concatenate(edge_of)
+    a, b = _pairs_at(g, theta)
+    q = _q32(a, b)
+    d = _dot64(a, b)
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    in_band = np.zeros(theta.size, bool)
+    for k in range(edges.size):
+        above = q >= qhi[k]
+        below = q < qlo[k]
+        # rule: past edge k  <=>  d <= D_k  <=>  slot >= k+1
+        past = truth >= k + 1
+        assert np.all(past[above]), k
+        assert not np.any(past[below]), k
+        assert np.array_equal(past, d <= D[k])
+        in_band |= ~above & ~below & (edge_of == k)
+    # tightness: the chord half-width is about a = 2^-23 plus ~5 ulp of q, so
+    # in theta the band reaches a relative distance ~ 1.2e-7 / e_k + 6e-7
+    half = 1.2e-7 / er[edge_of] + 6e-7
+    assert not np.any(in_band & (rel > 3.0 * half))
+    assert np.all(in_band[rel < 0.1 * half])
+
+
+def _emulate(a, b, edges, precision, delta):
+    """Numpy transcription of the kernels' per-pair classification."""
+    D, qlo, qhi = tp.compile_edges(edges, delta_max=delta)
+    shift, lo, hi, cells, E = tp.compile_cells(edges, precision, delta_max=delta)
+    d = _dot64(a, b)
+    if precision == tp.FP32_CHORD:
+        q = _q32(a, b)
+        key = q.view(np.uint32) >> np.uint32(shift)
+        c = np.clip(key.astype(np.int64), lo, hi) - lo
+    else:
+        e = 1.0 - d
+        hiw = (e.view(np.uint64) >> np.uint64(32)).astype(np.uint32).view(np.int32)
+        key = hiw.astype(np.int64) >> shift
+        c = np.clip(key, lo, hi) - lo
+    ent = cells[c].astype(np.int64)
+    slot = ent.copy()
+    flag = ent >= 0x8000
+    exact = np.zeros(ent.shape, bool)
+    for idx in np.nonzero(flag)[0]:
+        en = ent[idx]
+        if en != 0xFFFF:
+            k = en & 0x7FFF
+            if precision == tp.FP32_CHORD:
+                if q[idx] < qlo[k]:
+                    slot[idx] = k
+                    continue
+                if q[idx] >= qhi[k]:
+                    slot[idx] = k + 1
+                    continue
+            else:
+                if e[idx] > E[k]:
+                    slot[idx] = k + 1
+                    continue
+                if e[idx] < E[k]:
+                    slot[idx] = k
+                    continue
+            exact[idx] = True
+            slot[idx] = k + (1 if d[idx] <= D[k] else 0)
+        else:
+            exact[idx] = True
+            slot[idx] = int(np.sum(d[idx] <= D))
+    return slot, flag, exact
+
+
+@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64])
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_emulated_classification_matches_oracle(cfg, precision):
+    wl = synthcat.CONFIGS[cfg](scale={1: 0.06, 2: 0.006, 3: 0.0006}[cfg])
+    d = wl.data[0]
+    r = wl.randoms[0]
+    xa = np.stack(oracle.radec_to_xyz(d.ra, d.dec), axis=1)
+    xb = np.stack(oracle.radec_to_xyz(r.ra, r.dec), axis=1)
+    ia, ib = np.triu_indices(xa.shape[0], k=1)
+    a = np.concatenate([xa[ia], xa[:, None, :].repeat(xb.shape[0], 1).reshape(-1, 3)])
+    b = np.concatenate([xa[ib], np.tile(xb, (xa.shape[0], 1))])
+    delta = 4.5e-16
+    slot, flag, exact = _emulate(a, b, wl.edges_deg, precision, delta)
+    truth = oracle.pair_slots(a.T, b.T, wl.edges_deg)
+    assert np.array_equal(slot, truth)
+    assert flag.mean() < 0.05
+
+
+def test_emulation_on_exact_dot_probes():
+    """P1 on the CPU: i = (1,0,0), j = (d, sqrt(1-d^2), 0) has FP64 dot d
+    exactly; d in {D_k, next up, next down} for every edge."""
+    edges = synthcat.log_edges(0.01, 10.0, 20)
+    D, _, _ = tp.compile_edges(edges)
+    ds = []
+    for Dk in D:
+        ds += [Dk, _next(Dk, 1), _next(Dk, -1)]
+    ds = np.array([x for x in ds if -1.0 <= x <= 1.0])
+    a = np.tile([1.0, 0.0, 0.0], (ds.size, 1))
+    b = np.stack([ds, np.sqrt(1.0 - ds * ds), np.zeros_like(ds)], axis=1)
+    assert np.array_equal(_dot64(a, b), ds)
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    for prec in (tp.FP32_CHORD, tp.FP64):
+        # the probe vectors' norms deviate from 1 by a few ulps
+        n2 = np.sum(b * b, axis=1)
+        delta = float(np.max(np.abs(n2 - 1.0))) + 4 * 2.0 ** -53
+        slot, _, _ = _emulate(a, b, edges, prec, delta)
+        assert np.array_equal(slot, truth)
+
+
+def test_landy_szalay_library_matches_oracle():
+    g = np.random.default_rng(3)
+    nb = 25
+    dd = g.integers(0, 10**9, size=nb + 2).astype(np.uint64)
+    dr = g.integers(0, 10**9, size=nb + 2).astype(np.uint64)
+    rr = g.integers(1, 10**9, size=nb + 2).astype(np.uint64)
+    rr[5] = 0
+    for form in (0, 1):
+        w = tp.landy_szalay(dd, dr, rr, 123457, 234567, form)
+        ref = oracle.landy_szalay(dd[1:-1], dr[1:-1], rr[1:-1], 123457, 234567, form)
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isnan(w), np.isnan(ref))
+        assert np.all(np.abs(w[fin] - ref[fin]) <= 1e-12 * np.maximum(1.0, np.abs(ref[fin])))
+
+
+def test_landy_szalay_argument_errors():
+    z = np.zeros(5, np.uint64)
+    with pytest.raises(tp.TpcfError) as ei:
+        tp.landy_szalay(z, z, z, 1, 10)
+    assert ei.value.code == -1
+    with pytest.raises(tp.TpcfError):
+        tp.landy_szalay(z, z, z, 10, 10, form=2)
+
+
+def test_open_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(tp.TpcfError):
+        tp.Context(0)
