@@ -46,11 +46,15 @@ def cpu_baseline(xd, xr, edges, seconds):
     the data catalog against the whole random catalog."""
     import oracle
     threads = oracle.default_threads()
-    r0 = 8
-    t = time.perf_counter()
-    oracle.count(oracle.DR, xd, edges, b_xyz=xr, row_begin=0, row_end=r0, nthreads=threads)
-    dt = max(time.perf_counter() - t, 1e-3)
-    rows = int(min(xd[0].size, max(r0, r0 * seconds / dt)))
+    rows = max(8, 2 * threads)
+    while True:     # grow the sample until it takes a quarter of the budget
+        t = time.perf_counter()
+        oracle.count(oracle.DR, xd, edges, b_xyz=xr, row_begin=0, row_end=rows, nthreads=threads)
+        dt = time.perf_counter() - t
+        if dt >= seconds / 4 or rows >= xd[0].size:
+            break
+        rows = min(xd[0].size, rows * 4)
+    rows = int(min(xd[0].size, max(rows, rows * seconds / max(dt, 1e-3))))
     t = time.perf_counter()
     oracle.count(oracle.DR, xd, edges, b_xyz=xr, row_begin=0, row_end=rows, nthreads=threads)
     dt = time.perf_counter() - t

@@ -87,7 +87,10 @@ int tpcf_close(tpcf_ctx *ctx);
  * with the counting rule's formula on the host, keeps them on the device as
  * structure-of-arrays (x[], y[], z[]) together with FP32 copies rounded to
  * nearest, and returns a catalog id in *out_cat.  Device memory is owned by
- * the library until tpcf_release_catalog or tpcf_close.  n may be 0. */
+ * the library until tpcf_release_catalog or tpcf_close.  n may be 0.
+ * Rows are stored in a spatially coherent order (a Morton curve of the unit
+ * vectors), which the counts do not depend on; tpcf_catalog_order returns
+ * it.  Row ranges in tpcf_count refer to this stored order. */
 int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg,
                         int64_t n, int32_t *out_cat);
 
@@ -104,6 +107,11 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
  * the norm limit or is not finite. */
 int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t *out_cat);
 
+/* Storage order of a catalog: out_order (host, n int64) receives, for each
+ * stored row r, the index of that object in the uploaded arrays.  Attached
+ * catalogs keep the caller's order (identity). */
+int tpcf_catalog_order(tpcf_ctx *ctx, int32_t cat, int64_t *out_order);
+
 /* Number of objects of a catalog. */
 int tpcf_catalog_size(tpcf_ctx *ctx, int32_t cat, int64_t *out_n);
 
@@ -116,9 +124,10 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat);
  * bin_edges_deg  nbins+1 finite, strictly increasing values in [0, 180]
  *            (host array); 1 <= nbins <= 256.
  * precision  TPCF_FP32_CHORD or TPCF_FP64 (identical results).
- * row_begin, row_end  restrict i to rows [row_begin, row_end) of cat_a (rows
- *            in upload order); -1, -1 selects all rows.  For DD/RR the pairs
- *            are (i, j) with i in the range and j > i.
+ * row_begin, row_end  restrict i to rows [row_begin, row_end) of cat_a, in
+ *            the catalog's stored order (tpcf_catalog_order); -1, -1 selects
+ *            all rows.  For DD/RR the pairs are (i, j) with i in the range and
+ *            j > i in stored order.
  * out_u64    host array of nbins+2 slots: [theta < e_0, bin 0 .. bin nbins-1,
  *            theta >= e_nbins].  Written on TPCF_OK only.
  * The total over slots always equals the number of pairs in the request; a
@@ -184,7 +193,8 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
  * e = fl64(1 - d) as a signed integer.  A key maps to cell
  * clamp(key >> shift, lo, hi); entry cells[cell - lo] is a slot (< 0x8000),
  * 0x8000 | k when only edge k is undecided in the cell, or 0xFFFF when
- * several edges are.  out_cells must hold max_cells entries (16..8192);
+ * several edges are.  out_cells must hold max_cells entries (16..24576;
+ * the kernels use 24576 cells for up to 125 bins, 12288 beyond);
  * out_E (nbins+1 doubles, may be NULL) receives fl(1 - D_k). */
 int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
                        int32_t max_cells, int32_t *out_shift, int32_t *out_lo, int32_t *out_hi,

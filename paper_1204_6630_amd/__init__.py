@@ -31,7 +31,7 @@ _lib = None
 # every symbol declared in include/tpcf.h
 EXPORTED_SYMBOLS = (
     "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
-    "tpcf_attach_catalog", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
+    "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
     "tpcf_count_async", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_edges",
     "tpcf_last_error", "tpcf_version",
@@ -85,6 +85,7 @@ def lib():
         "tpcf_upload_catalog": ([P, P, P, i64, P], cint),
         "tpcf_upload_catalog_xyz": ([P, P, P, P, i64, P], cint),
         "tpcf_attach_catalog": ([P, P, i64, P], cint),
+        "tpcf_catalog_order": ([P, i32, P], cint),
         "tpcf_catalog_size": ([P, i32, P], cint),
         "tpcf_release_catalog": ([P, i32], cint),
         "tpcf_count": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
@@ -185,6 +186,12 @@ class Context:
                                          ctypes.byref(cid)))
         return cid.value
 
+    def catalog_order(self, cat: int) -> np.ndarray:
+        """Upload index of every stored row (row ranges use stored order)."""
+        out = np.empty(self.catalog_size(cat), dtype=np.int64)
+        _check(lib().tpcf_catalog_order(self._h, cat, _p(out)))
+        return out
+
     def catalog_size(self, cat: int) -> int:
         n = ctypes.c_int64()
         _check(lib().tpcf_catalog_size(self._h, cat, ctypes.byref(n)))
@@ -252,9 +259,12 @@ def compile_edges(edges_deg, delta_max: float = 0.0):
     return D, qlo, qhi
 
 
-def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int = 8192):
-    """(shift, lo, hi, cells, E) of tpcf_compile_cells."""
+def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None):
+    """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the table
+    size the kernels use for this many bins."""
     e = _f64(edges_deg)
+    if max_cells is None:
+        max_cells = 24576 if e.size + 1 <= 127 else 12288
     cells = np.zeros(max_cells, np.uint16)
     E = np.empty(e.size, np.float64)
     sh, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

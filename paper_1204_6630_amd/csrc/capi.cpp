@@ -8,6 +8,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <map>
 #include <memory>
@@ -16,7 +17,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/tpcf.h"
+#include "tpcf.h"
 #include "edges.h"
 #include "internal.h"
 
@@ -69,6 +70,7 @@ struct Catalog {
     int64_t n = 0;
     double *d64 = nullptr;      // x[n], y[n], z[n]
     float *d32 = nullptr;       // x[n], y[n], z[n]
+    std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
     bool owns64 = true;
     double delta = 0;           // bound on | |v|^2 - 1 |
 };
@@ -80,6 +82,7 @@ struct Compiled {
     CellTable cells;
     Band32 band;
     int precision = 0;
+    int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
 };
 
 struct Plan {
@@ -137,6 +140,40 @@ double norm_bound(const double *x, const double *y, const double *z, int64_t n, 
 
 constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
 
+// Spatially coherent storage order: sort the points along a Morton (Z-order)
+// curve of their unit vectors, 21 bits per coordinate.  Neighbouring rows are
+// then close on the sky, so the 64 lanes of a wavefront see nearly the same
+// separation to each column point.  Counts do not depend on the order.
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+uint64_t quant21(double c) {
+    double t = (c + 1.0) * 0.5 * 2097151.0;
+    if (!(t > 0.0))
+        return 0;
+    if (t > 2097151.0)
+        return 2097151;
+    return (uint64_t)t;
+}
+
+std::vector<int64_t> morton_order(const double *x, const double *y, const double *z, int64_t n) {
+    std::vector<std::pair<uint64_t, int64_t>> k((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        k[i] = {spread3(quant21(x[i])) | spread3(quant21(y[i])) << 1 | spread3(quant21(z[i])) << 2, i};
+    std::sort(k.begin(), k.end());
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        order[i] = k[i].second;
+    return order;
+}
+
 int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
                 int32_t *out_cat) {
     if (!out_cat)
@@ -157,16 +194,18 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
     Catalog c;
     c.n = n;
     c.delta = delta;
+    c.order = morton_order(x, y, z, n);
     size_t alloc_n = (size_t)(n > 0 ? n : 1);
     std::vector<double> h64(3 * alloc_n, 0.0);
     std::vector<float> h32(3 * alloc_n, 0.0f);
-    for (int64_t i = 0; i < n; ++i) {
-        h64[i] = x[i];
-        h64[alloc_n + i] = y[i];
-        h64[2 * alloc_n + i] = z[i];
-        h32[i] = (float)x[i];
-        h32[alloc_n + i] = (float)y[i];
-        h32[2 * alloc_n + i] = (float)z[i];
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = c.order[r];
+        h64[r] = x[i];
+        h64[alloc_n + r] = y[i];
+        h64[2 * alloc_n + r] = z[i];
+        h32[r] = (float)x[i];
+        h32[alloc_n + r] = (float)y[i];
+        h32[2 * alloc_n + r] = (float)z[i];
     }
     hipError_t e = hipMalloc((void **)&c.d64, sizeof(double) * 3 * alloc_n);
     if (e != hipSuccess)
@@ -223,21 +262,35 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     if (!compile_edges(edges, nbins, &c->edges, &err))
         return fail(TPCF_E_INVALID, err);
     c->precision = precision;
+    const int nslots = nbins + 2;
+    c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
+    const int max_cells = kMaxLutBytes / c->entry_bytes;
     std::vector<float> qlo, qhi;
     if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
-        c->cells = make_cells32(c->edges, c->band, delta, kMaxLutCells);
+        c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
     } else {
-        c->cells = make_cells64(c->edges, kMaxLutCells);
+        c->cells = make_cells64(c->edges, max_cells);
         qlo.assign(c->edges.D.size(), 0.0f);
         qhi.assign(c->edges.D.size(), 0.0f);
+    }
+    std::vector<uint8_t> packed;
+    if (c->entry_bytes == 1) {
+        packed.resize(c->cells.cells.size());
+        for (size_t i = 0; i < packed.size(); ++i) {
+            uint16_t v = c->cells.cells[i];
+            packed[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
+        }
+    } else {
+        packed.resize(c->cells.cells.size() * 2);
+        memcpy(packed.data(), c->cells.cells.data(), packed.size());
     }
     int rc;
     if ((rc = upload(c->dD, c->edges.D, ctx->stream)) || (rc = upload(c->dE, c->edges.E, ctx->stream)) ||
         (rc = upload(c->dqlo, qlo, ctx->stream)) || (rc = upload(c->dqhi, qhi, ctx->stream)) ||
-        (rc = upload(c->dlut, c->cells.cells, ctx->stream)))
+        (rc = upload(c->dlut, packed, ctx->stream)))
         return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));   // host vectors stay alive; keep it simple
     if (ctx->compiled.size() > 64) {
@@ -324,14 +377,16 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
     return TPCF_OK;
 }
 
+// Histogram copies per wavefront: 32 (conflict-free within a half-wave) while
+// the four wavefronts' histograms stay within ~24 KB, fewer for many bins.
 int hist_copies_for(int nslots) {
-    if ((nslots + 1) <= 44)
-        return 64;
-    if ((nslots + 1) <= 88)
+    if ((nslots + 1) <= 48)
         return 32;
-    if ((nslots + 1) <= 176)
+    if ((nslots + 1) <= 96)
         return 16;
-    return 8;
+    if ((nslots + 1) <= 192)
+        return 8;
+    return 4;
 }
 
 // Validate and enqueue one count; the result lands in d_out (nslots u64).
@@ -406,8 +461,9 @@ int enqueue_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const d
     a.auto_pairs = auto_pairs ? 1 : 0;
     a.units = (const Unit *)plan->dunits.p;
     a.n_units = (int32_t)plan->units.size();
-    a.lut = (const uint16_t *)cp->dlut.p;
+    a.lut = cp->dlut.p;
     a.lut_cells = (int32_t)cp->cells.cells.size();
+    a.lut_entry_bytes = cp->entry_bytes;
     a.lut_shift = cp->cells.shift;
     a.lut_lo = cp->cells.lo;
     a.lut_hi = cp->cells.hi;
@@ -600,6 +656,18 @@ int tpcf_catalog_size(tpcf_ctx *ctx, int32_t cat, int64_t *out_n) {
     return TPCF_OK;
 }
 
+int tpcf_catalog_order(tpcf_ctx *ctx, int32_t cat, int64_t *out_order) {
+    if (!ctx || !out_order)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    auto it = ctx->cats.find(cat);
+    if (it == ctx->cats.end())
+        return fail(TPCF_E_BADID, "unknown catalog id");
+    const Catalog &c = it->second;
+    for (int64_t r = 0; r < c.n; ++r)
+        out_order[r] = c.order.empty() ? r : c.order[(size_t)r];
+    return TPCF_OK;
+}
+
 int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
@@ -757,7 +825,7 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
     if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
         return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
     if (max_cells < 16 || max_cells > kMaxLutCells)
-        return fail(TPCF_E_INVALID, "max_cells must be in [16, 8192]");
+        return fail(TPCF_E_INVALID, "max_cells must be in [16, 24576]");
     EdgeTables t;
     std::string err;
     if (!compile_edges(bin_edges_deg, nbins, &t, &err))

@@ -11,8 +11,10 @@ constexpr int kWaves = 4;
 constexpr int kWaveSize = 64;
 constexpr int kBlock = kWaves * kWaveSize;
 
-// Largest table of cells kept in LDS (16-bit entries).
-constexpr int kMaxLutCells = 8192;
+// LDS budget of the cell table; entries are one byte when every slot and
+// edge index fits in 7 bits, else two bytes.
+constexpr int kMaxLutBytes = 24576;
+constexpr int kMaxLutCells = kMaxLutBytes;        // with one-byte entries
 // Histogram copies in global memory (u64), indexed by work unit.
 constexpr int kGlobalCopies = 64;
 // Largest number of output slots (nbins <= 256 -> nbins + 2 slots).
@@ -23,16 +25,17 @@ constexpr int kMaxSlots = 258;
 //   0 .. kMaxSlots-1   the slot, certain for every value in the cell;
 //   kMedium | k        exactly one edge k is undecided inside the cell;
 //   kMulti             several edges are undecided: use the exact rule.
+// One-byte tables use 0x80 | k and 0xFF instead (slots and k below 0x7F).
 constexpr uint16_t kMedium = 0x8000;
 constexpr uint16_t kMulti = 0xFFFF;
+constexpr int kMaxSlots8 = 127;
 
-// One work unit: rows i in [i0, i1) against columns j in [j0, j1).
-// flags bit 0: the unit needs per-pair masking (i tail or j <= i diagonal).
+// One work unit: rows i in [i0, i1) against columns j in [j0, j1).  A unit
+// needs per-pair masking when its row tile is cut short or, for auto-pairs,
+// when its columns overlap its rows (the j <= i diagonal).
 struct Unit {
     int32_t i0, i1, j0, j1;
 };
-
-enum : int32_t { kUnitMasked = 1 };
 
 struct PairArgs {
     // Catalog A (rows i) and B (columns j), structure of arrays.
@@ -46,8 +49,9 @@ struct PairArgs {
     int32_t n_units;
 
     // Cell table (device, copied into LDS by every block).
-    const uint16_t *lut;
+    const void *lut;
     int32_t lut_cells;           // c_hi - c_lo + 1
+    int32_t lut_entry_bytes;     // 1 or 2
     int32_t lut_shift;           // cell = key >> shift
     int32_t lut_lo, lut_hi;      // clamp range of cells
 
@@ -58,17 +62,17 @@ struct PairArgs {
     int32_t nedges;              // nbins + 1
     int32_t nslots;              // nbins + 2
 
-    // Per-wave LDS histogram: row stride in bytes (copies * 4) and copies.
-    int32_t hist_copies;         // 64, 32, 16 or 8
+    // Per-wave LDS histogram copies (layout [slot][copy]).
+    int32_t hist_copies;         // 32, 16, 8 or 4
 
     unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
     unsigned long long *stats;   // [pairs, flagged, exact]
 };
 
 // LDS bytes used by one block for the given table sizes.
-inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int nedges) {
+inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_bytes, int nedges) {
     int hist = kWaves * (nslots + 1) * hist_copies * 4;      // +1: discard row
-    int lut = ((lut_cells * 2) + 15) & ~15;
+    int lut = ((lut_cells * lut_entry_bytes) + 15) & ~15;
     int thr = nedges * (4 + 4 + 8 + 8);
     return hist + lut + thr;
 }

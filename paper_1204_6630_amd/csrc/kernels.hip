@@ -16,10 +16,10 @@
 //     directly, a cell that straddles one edge's band is settled by one
 //     threshold comparison, and anything closer is re-decided with the
 //     exact FP64 rule d <= D_k;
-//   * every wavefront owns a private LDS histogram with one column per lane
-//     (layout [slot][copy], copy = lane mod copies), updated with ds_add_u32;
-//     with 64 copies no two lanes ever touch the same word and the lanes of a
-//     half-wave hit 32 distinct banks;
+//   * every wavefront owns a private LDS histogram, layout [slot][copy] with
+//     copy = lane mod copies, updated with ds_add_u32; with 32 copies the
+//     lanes of each half-wave (the LDS serves 32 lanes per pass) always hit
+//     32 distinct banks;
 //   * after each unit a wavefront sums its histogram and adds it with 64-bit
 //     atomics into one of kGlobalCopies global copies, which a final kernel
 //     reduces into the output slots.
@@ -37,6 +37,61 @@ namespace {
 
 constexpr int kRowsPerLane = 4;
 constexpr int kRowsPerWave = kRowsPerLane * kWaveSize;
+constexpr int kColsPerStep = 2;
+
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// Column coordinates are read through the constant address space: every lane
+// of a wavefront reads the same j, so these become scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) float *cfloat_p;
+typedef const __attribute__((address_space(4))) double *cdouble_p;
+
+// Clamp into [lo, hi] in one instruction (all operands in VGPRs: gfx9 VOP3
+// reads at most one SGPR, which keeps the compiler from forming v_med3).
+__device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t hi) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t lo, int32_t hi) {
+    int32_t r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Copy a wavefront-uniform value into a VGPR once, so loops do not
+// re-materialise it for every VOP3 that needs a VGPR operand.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// LDS access by 32-bit byte address.
+template <bool LUT8>
+__device__ __forceinline__ uint32_t lds_read_entry(uint32_t addr) {
+    if (LUT8)
+        return *(const lds_u8 *)(uintptr_t)addr;
+    return *(const lds_u16 *)(uintptr_t)addr;
+}
+
+__device__ __forceinline__ void lds_inc(uint32_t addr) {
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool LUT8>
+struct Code {
+    static constexpr uint32_t flag = LUT8 ? 0x80u : 0x8000u;
+    static constexpr uint32_t multi = LUT8 ? 0xFFu : 0xFFFFu;
+    static constexpr uint32_t kmask = LUT8 ? 0x7Fu : 0x7FFFu;
+    // true if any entry OR-ed into `any` carries the flag bit
+    __device__ static bool any_flag(uint32_t any) {
+        return LUT8 ? ((int8_t)any < 0) : ((int16_t)any < 0);
+    }
+};
 
 // Number of k with d <= D[k]; D is non-increasing in k.
 __device__ __forceinline__ uint32_t count_le(double d, const double *D, int n) {
@@ -62,47 +117,13 @@ __device__ __forceinline__ double exact_dot(double xi, double yi, double zi,
     return s + v;
 }
 
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) uint16_t lds_u16;
-
-// Clamp into [lo, hi] in one instruction (all operands in VGPRs: gfx9 VOP3
-// reads at most one SGPR, which keeps the compiler from forming v_med3).
-__device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t hi) {
-    uint32_t r;
-    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
-    return r;
-}
-
-__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t lo, int32_t hi) {
-    int32_t r;
-    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
-    return r;
-}
-
-// Copy a wavefront-uniform value into a VGPR once, so loops do not
-// re-materialise it for every VOP3 that needs a VGPR operand.
-__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
-    uint32_t r;
-    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-    return r;
-}
-
-// LDS access by 32-bit byte address.
-__device__ __forceinline__ uint32_t lds_read_u16(uint32_t addr) {
-    return *(const lds_u16 *)(uintptr_t)addr;
-}
-
-__device__ __forceinline__ void lds_inc(uint32_t addr) {
-    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 struct Smem {
-    uint32_t *hist;     // kWaves x (nslots + 1) x copies
+    uint32_t *hist;      // kWaves x (nslots + 1) x copies
     double *D;
     double *E;
     float *qlo;
     float *qhi;
-    uint16_t *lut;
+    unsigned char *lut;
     uint32_t hist_addr;  // LDS byte address of hist
     uint32_t lut_addr;   // LDS byte address of lut
 };
@@ -115,9 +136,9 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     s.E = s.D + a.nedges;
     s.qlo = reinterpret_cast<float *>(s.E + a.nedges);
     s.qhi = s.qlo + a.nedges;
-    s.lut = reinterpret_cast<uint16_t *>(s.qhi + a.nedges);
+    s.lut = reinterpret_cast<unsigned char *>(s.qhi + a.nedges);
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
-    s.lut_addr = (uint32_t)(uintptr_t)(lds_u16 *)s.lut;
+    s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
     return s;
 }
 
@@ -128,7 +149,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Sum one wavefront's LDS histogram into the global copy and clear it.
+// Sum one wavefront's LDS histogram into a global copy and clear it.
 __device__ void flush_wave(const PairArgs &a, const Smem &s, int wave, int lane, int copy) {
     const int C = a.hist_copies;
     uint32_t *h = s.hist + wave * (a.nslots + 1) * C;
@@ -150,11 +171,12 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, int wave, int lane,
     }
 }
 
+template <bool LUT8>
 __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Smem &s,
                                                  const PairArgs &a, int i, int j,
                                                  uint32_t &n_exact) {
-    if (ent != kMulti) {
-        int k = ent & 0x7FFF;
+    if (ent != Code<LUT8>::multi) {
+        int k = (int)(ent & Code<LUT8>::kmask);
         if (q < s.qlo[k])
             return (uint32_t)k;
         if (q >= s.qhi[k])
@@ -168,11 +190,12 @@ __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Sm
     return count_le(d, s.D, a.nedges);
 }
 
+template <bool LUT8>
 __device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, double e, double d,
                                                  const Smem &s, const PairArgs &a,
                                                  uint32_t &n_exact) {
-    if (ent != kMulti) {
-        int k = ent & 0x7FFF;
+    if (ent != Code<LUT8>::multi) {
+        int k = (int)(ent & Code<LUT8>::kmask);
         double Ek = s.E[k];
         if (e > Ek)
             return (uint32_t)(k + 1);
@@ -185,22 +208,25 @@ __device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, double e, double 
     return count_le(d, s.D, a.nedges);
 }
 
-// Column coordinates are read through the constant address space: every lane
-// of a wavefront reads the same j, so these become scalar loads into SGPRs.
-typedef const __attribute__((address_space(4))) float *cfloat_p;
-typedef const __attribute__((address_space(4))) double *cdouble_p;
+// Loop constants of one wavefront.
+struct Consts {
+    uint32_t shift;
+    uint32_t clo, chi;      // clamp range (VGPR copies)
+    uint32_t lutbias;       // LDS address of cell c is c * entry_bytes + lutbias
+    uint32_t rowstep;       // bytes between slots of the histogram
+    uint32_t lanebase;      // LDS address of this lane's copy of slot 0
+};
 
-// One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
-// Each step takes JN columns: all JN * P table lookups are issued first, one
-// test sends the wavefront to the rare path if any lane needs it, then the
-// JN * P histogram increments follow.
-template <bool MASKED, int P, int JN>
-__device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, const float (&xi)[P],
-                                          const float (&yi)[P], const float (&zi)[P],
-                                          const int (&ii)[P], const int (&il)[P], int ie, int j,
-                                          cfloat_p bx, cfloat_p by, cfloat_p bz, uint32_t shift,
-                                          uint32_t clo, uint32_t chi, uint32_t lutbias, uint32_t rowstep,
-                                          uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
+// One step: JN columns against the P rows of every lane.  All JN * P table
+// lookups are issued first; one test sends the wavefront to the rare path if
+// any lane needs it; then the JN * P histogram increments follow.
+template <bool LUT8, bool MASKED, int P, int JN>
+__device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, const Consts &k,
+                                          const float (&xi)[P], const float (&yi)[P],
+                                          const float (&zi)[P], const int (&ii)[P],
+                                          const int (&il)[P], int ie, int j, cfloat_p bx,
+                                          cfloat_p by, cfloat_p bz, uint32_t &n_flag,
+                                          uint32_t &n_exact) {
     float xj[JN], yj[JN], zj[JN];
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
@@ -210,7 +236,6 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
     }
     float q[JN][P];
     uint32_t ent[JN][P];
-    uint32_t any = 0;
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
@@ -222,23 +247,24 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
             v = __fmaf_rn(dy, dy, v);
             v = __fmaf_rn(dz, dz, v);
             q[t][p] = v;
-            uint32_t c = med3_u32(__float_as_uint(v) >> shift, clo, chi);
-            ent[t][p] = lds_read_u16(c * 2u + lutbias);
+            uint32_t c = med3_u32(__float_as_uint(v) >> k.shift, k.clo, k.chi);
+            ent[t][p] = lds_read_entry<LUT8>(c * (LUT8 ? 1u : 2u) + k.lutbias);
         }
     }
+    uint32_t any = 0;
 #pragma unroll
     for (int t = 0; t < JN; ++t)
 #pragma unroll
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
-    if ((int16_t)any < 0) {     // some entry has kMedium (bit 15) set
+    if (Code<LUT8>::any_flag(any)) {
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                if (ent[t][p] & kMedium) {
+                if (ent[t][p] & Code<LUT8>::flag) {
                     ++n_flag;
-                    ent[t][p] = resolve_fp32(ent[t][p], q[t][p], s, a, il[p], j + t, n_exact);
+                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, il[p], j + t, n_exact);
                 }
     }
 #pragma unroll
@@ -250,48 +276,16 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
                 bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
                 e = ok ? e : (uint32_t)a.nslots;
             }
-            lds_inc(__umul24(e, rowstep) + lanebase);
+            lds_inc(__umul24(e, k.rowstep) + k.lanebase);
         }
 }
 
-template <bool MASKED, int P>
-__device__ void rows_fp32(const PairArgs &a, const Smem &s, int ib, int ie, int j0, int j1,
-                          int lane, uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
-    float xi[P], yi[P], zi[P];
-    int ii[P], il[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        int i = ib + p * kWaveSize + lane;
-        ii[p] = i;
-        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
-        xi[p] = a.ax32[il[p]];
-        yi[p] = a.ay32[il[p]];
-        zi[p] = a.az32[il[p]];
-    }
-    const uint32_t shift = (uint32_t)a.lut_shift;
-    const uint32_t clo = to_vgpr((uint32_t)a.lut_lo), chi = to_vgpr((uint32_t)a.lut_hi);
-    const uint32_t lutbias = s.lut_addr - 2u * (uint32_t)a.lut_lo;   // address of cell c is 2c + lutbias
-    const uint32_t rowstep = (uint32_t)a.hist_copies * 4u;
-    cfloat_p bx = (cfloat_p)a.bx32;
-    cfloat_p by = (cfloat_p)a.by32;
-    cfloat_p bz = (cfloat_p)a.bz32;
-    constexpr int JN = 2;
-    int j = j0;
-    for (; j + JN <= j1; j += JN)
-        step_fp32<MASKED, P, JN>(a, s, xi, yi, zi, ii, il, ie, j, bx, by, bz, shift, clo, chi,
-                                 lutbias, rowstep, lanebase, n_flag, n_exact);
-    for (; j < j1; ++j)
-        step_fp32<MASKED, P, 1>(a, s, xi, yi, zi, ii, il, ie, j, bx, by, bz, shift, clo, chi,
-                                lutbias, rowstep, lanebase, n_flag, n_exact);
-}
-
-template <bool MASKED, int P, int JN>
-__device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, const double (&xi)[P],
-                                          const double (&yi)[P], const double (&zi)[P],
-                                          const int (&ii)[P], int ie, int j, cdouble_p bx,
-                                          cdouble_p by, cdouble_p bz, int shift, int clo, int chi,
-                                          uint32_t lutbias, uint32_t rowstep, uint32_t lanebase, uint32_t &n_flag,
-                                          uint32_t &n_exact) {
+template <bool LUT8, bool MASKED, int P, int JN>
+__device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, const Consts &k,
+                                          const double (&xi)[P], const double (&yi)[P],
+                                          const double (&zi)[P], const int (&ii)[P], int ie,
+                                          int j, cdouble_p bx, cdouble_p by, cdouble_p bz,
+                                          uint32_t &n_flag, uint32_t &n_exact) {
     double xj[JN], yj[JN], zj[JN];
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
@@ -301,7 +295,6 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, cons
     }
     double d[JN][P], e[JN][P];
     uint32_t ent[JN][P];
-    uint32_t any = 0;
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
@@ -311,23 +304,24 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, cons
             d[t][p] = dd;
             e[t][p] = ee;
             // arithmetic shift: e < 0 (d > 1 from rounding) lands in the bottom cell
-            int32_t c = med3_i32(__double2hiint(ee) >> shift, clo, chi);
-            ent[t][p] = lds_read_u16((uint32_t)c * 2u + lutbias);
+            int32_t c = med3_i32(__double2hiint(ee) >> (int)k.shift, (int32_t)k.clo, (int32_t)k.chi);
+            ent[t][p] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
         }
     }
+    uint32_t any = 0;
 #pragma unroll
     for (int t = 0; t < JN; ++t)
 #pragma unroll
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
-    if ((int16_t)any < 0) {     // some entry has kMedium (bit 15) set
+    if (Code<LUT8>::any_flag(any)) {
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                if (ent[t][p] & kMedium) {
+                if (ent[t][p] & Code<LUT8>::flag) {
                     ++n_flag;
-                    ent[t][p] = resolve_fp64(ent[t][p], e[t][p], d[t][p], s, a, n_exact);
+                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], e[t][p], d[t][p], s, a, n_exact);
                 }
     }
 #pragma unroll
@@ -339,13 +333,39 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, cons
                 bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
                 v = ok ? v : (uint32_t)a.nslots;
             }
-            lds_inc(__umul24(v, rowstep) + lanebase);
+            lds_inc(__umul24(v, k.rowstep) + k.lanebase);
         }
 }
 
-template <bool MASKED, int P>
-__device__ void rows_fp64(const PairArgs &a, const Smem &s, int ib, int ie, int j0, int j1,
-                          int lane, uint32_t lanebase, uint32_t &n_flag, uint32_t &n_exact) {
+// One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
+template <bool LUT8, bool MASKED, int P>
+__device__ void rows_fp32(const PairArgs &a, const Smem &s, const Consts &k, int ib, int ie,
+                          int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
+    float xi[P], yi[P], zi[P];
+    int ii[P], il[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        int i = ib + p * kWaveSize + lane;
+        ii[p] = i;
+        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
+        xi[p] = a.ax32[il[p]];
+        yi[p] = a.ay32[il[p]];
+        zi[p] = a.az32[il[p]];
+    }
+    cfloat_p bx = (cfloat_p)a.bx32;
+    cfloat_p by = (cfloat_p)a.by32;
+    cfloat_p bz = (cfloat_p)a.bz32;
+    int j = j0;
+    for (; j + kColsPerStep <= j1; j += kColsPerStep)
+        step_fp32<LUT8, MASKED, P, kColsPerStep>(a, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz,
+                                                 n_flag, n_exact);
+    for (; j < j1; ++j)
+        step_fp32<LUT8, MASKED, P, 1>(a, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, n_flag, n_exact);
+}
+
+template <bool LUT8, bool MASKED, int P>
+__device__ void rows_fp64(const PairArgs &a, const Smem &s, const Consts &k, int ib, int ie,
+                          int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
     double xi[P], yi[P], zi[P];
     int ii[P];
 #pragma unroll
@@ -357,24 +377,18 @@ __device__ void rows_fp64(const PairArgs &a, const Smem &s, int ib, int ie, int 
         yi[p] = a.ay64[il];
         zi[p] = a.az64[il];
     }
-    const int shift = a.lut_shift;
-    const int clo = (int)to_vgpr((uint32_t)a.lut_lo), chi = (int)to_vgpr((uint32_t)a.lut_hi);
-    const uint32_t lutbias = s.lut_addr - 2u * (uint32_t)a.lut_lo;
-    const uint32_t rowstep = (uint32_t)a.hist_copies * 4u;
     cdouble_p bx = (cdouble_p)a.bx64;
     cdouble_p by = (cdouble_p)a.by64;
     cdouble_p bz = (cdouble_p)a.bz64;
-    constexpr int JN = 2;
     int j = j0;
-    for (; j + JN <= j1; j += JN)
-        step_fp64<MASKED, P, JN>(a, s, xi, yi, zi, ii, ie, j, bx, by, bz, shift, clo, chi, lutbias,
-                                 rowstep, lanebase, n_flag, n_exact);
+    for (; j + kColsPerStep <= j1; j += kColsPerStep)
+        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag,
+                                                 n_exact);
     for (; j < j1; ++j)
-        step_fp64<MASKED, P, 1>(a, s, xi, yi, zi, ii, ie, j, bx, by, bz, shift, clo, chi, lutbias,
-                                rowstep, lanebase, n_flag, n_exact);
+        step_fp64<LUT8, MASKED, P, 1>(a, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag, n_exact);
 }
 
-template <int PREC>
+template <int PREC, bool LUT8>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
@@ -385,18 +399,26 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     const int hist_words = kWaves * (a.nslots + 1) * a.hist_copies;
     for (int w = tid; w < hist_words; w += kBlock)
         s.hist[w] = 0;
-    for (int c = tid; c < a.lut_cells; c += kBlock)
-        s.lut[c] = a.lut[c];
-    for (int k = tid; k < a.nedges; k += kBlock) {
-        s.D[k] = a.D[k];
-        s.E[k] = a.E[k];
-        s.qlo[k] = a.qlo[k];
-        s.qhi[k] = a.qhi[k];
+    const int lut_bytes = a.lut_cells * (LUT8 ? 1 : 2);
+    const unsigned char *glut = reinterpret_cast<const unsigned char *>(a.lut);
+    for (int b = tid; b < lut_bytes; b += kBlock)
+        s.lut[b] = glut[b];
+    for (int e = tid; e < a.nedges; e += kBlock) {
+        s.D[e] = a.D[e];
+        s.E[e] = a.E[e];
+        s.qlo[e] = a.qlo[e];
+        s.qhi[e] = a.qhi[e];
     }
     __syncthreads();
 
-    const uint32_t lanebase =
-        s.hist_addr + (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
+    Consts k;
+    k.shift = (uint32_t)a.lut_shift;
+    k.clo = to_vgpr((uint32_t)a.lut_lo);
+    k.chi = to_vgpr((uint32_t)a.lut_hi);
+    k.lutbias = s.lut_addr - (uint32_t)a.lut_lo * (LUT8 ? 1u : 2u);
+    k.rowstep = (uint32_t)a.hist_copies * 4u;
+    k.lanebase = s.hist_addr +
+                 (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     uint32_t n_flag = 0, n_exact = 0;
 
     for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
@@ -407,14 +429,14 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             const bool masked = (ie - ib < kRowsPerWave) || (a.auto_pairs && un.j0 < ie);
             if (PREC == 0) {
                 if (masked)
-                    rows_fp32<true, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                    rows_fp32<LUT8, true, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
                 else
-                    rows_fp32<false, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                    rows_fp32<LUT8, false, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
             } else {
                 if (masked)
-                    rows_fp64<true, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                    rows_fp64<LUT8, true, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
                 else
-                    rows_fp64<false, kRowsPerLane>(a, s, ib, ie, un.j0, un.j1, lane, lanebase, n_flag, n_exact);
+                    rows_fp64<LUT8, false, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
             }
             // the wave's own LDS region only: no block barrier needed
             flush_wave(a, s, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
@@ -511,13 +533,21 @@ int grid_for(int n_units, int lds) {
 extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stream) {
     if (args->n_units <= 0)
         return 0;
-    const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->nedges);
+    const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->lut_entry_bytes,
+                              args->nedges);
     const int grid = grid_for(args->n_units, lds);
     hipStream_t st = (hipStream_t)stream;
+    const bool b8 = args->lut_entry_bytes == 1;
     if (precision == 0) {
-        hipLaunchKernelGGL(pairs_kernel<0>, dim3(grid), dim3(kBlock), lds, st, *args);
+        if (b8)
+            hipLaunchKernelGGL((pairs_kernel<0, true>), dim3(grid), dim3(kBlock), lds, st, *args);
+        else
+            hipLaunchKernelGGL((pairs_kernel<0, false>), dim3(grid), dim3(kBlock), lds, st, *args);
     } else {
-        hipLaunchKernelGGL(pairs_kernel<1>, dim3(grid), dim3(kBlock), lds, st, *args);
+        if (b8)
+            hipLaunchKernelGGL((pairs_kernel<1, true>), dim3(grid), dim3(kBlock), lds, st, *args);
+        else
+            hipLaunchKernelGGL((pairs_kernel<1, false>), dim3(grid), dim3(kBlock), lds, st, *args);
     }
     return (int)hipGetLastError();
 }

@@ -39,6 +39,12 @@ def _workload(cfg):
     return _cache[cfg]
 
 
+def _stored(ctx, cid, xyz):
+    """The catalog's coordinates in the library's stored row order."""
+    order = ctx.catalog_order(cid)
+    return tuple(c[order] for c in xyz)
+
+
 def _oracle(key, fn):
     if key not in _cache:
         _cache[key] = fn()
@@ -100,7 +106,8 @@ def test_ragged_sizes_and_tails(ctx, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_row_ranges(ctx, cfg1, prec):
     wl, cd, cr, _ = cfg1
-    xd, xr = _xyz(wl.data[0]), _xyz(wl.randoms[0])
+    xd = _stored(ctx, cd, _xyz(wl.data[0]))
+    xr = _xyz(wl.randoms[0])
     n = wl.data[0].n
     for rb, re in ((0, 1), (17, 1500), (1023, 1025), (n - 1, n), (5, 5), (0, n)):
         got = ctx.count(tp.DD, cd, wl.edges_deg, precision=prec, row_begin=rb, row_end=re)
@@ -140,9 +147,13 @@ def test_exact_dot_probes_on_every_threshold(ctx, prec):
         # the same probes one per row (j > i via DD on the concatenation)
         u = tuple(np.concatenate([p, q]) for p, q in zip(a, b))
         cu = ctx.upload_catalog_xyz(*u)
-        got = ctx.count(tp.DD, cu, edges, precision=prec, row_begin=0, row_end=1)
-        ref = oracle.count(oracle.DD, u, edges, row_begin=0, row_end=1)
+        us = _stored(ctx, cu, u)
+        row = int(np.nonzero(ctx.catalog_order(cu) == 0)[0][0])   # where (1,0,0) is stored
+        got = ctx.count(tp.DD, cu, edges, precision=prec, row_begin=row, row_end=row + 1)
+        ref = oracle.count(oracle.DD, us, edges, row_begin=row, row_end=row + 1)
         assert np.array_equal(got, ref)
+        got = ctx.count(tp.DD, cu, edges, precision=prec)
+        assert np.array_equal(got, oracle.count(oracle.DD, u, edges))
         for c in (ca, cb, cu):
             ctx.release_catalog(c)
 
@@ -188,7 +199,7 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
         full[prec] = (dd, dr, rr)
     for a, b in zip(full[tp.FP32_CHORD], full[tp.FP64]):
         assert np.array_equal(a, b)
-    xd, xr = _xyz(d), _xyz(r)
+    xd, xr = _stored(ctx, cd, _xyz(d)), _stored(ctx, cr, _xyz(r))
     size = 200 if cfg == 2 else 150
     for rb, re in _sample_blocks(d.n, 2, size, 11 + cfg):
         for prec in PRECS:
