@@ -145,7 +145,57 @@ int tpcf_count_async(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
                      const double *bin_edges_deg, int32_t nbins, int precision,
                      int64_t row_begin, int64_t row_end, uint64_t *d_out_u64);
 
-/* Wait for all work enqueued on the context stream. */
+/* One counting request, as used by batches and submitted jobs.  Fields have
+ * the meaning of the tpcf_count arguments of the same names; the edges array
+ * is read during the call only. */
+typedef struct tpcf_job_desc {
+    int kind;
+    int32_t cat_a, cat_b;
+    const double *bin_edges_deg;
+    int32_t nbins;
+    int precision;
+    int64_t row_begin, row_end;
+} tpcf_job_desc;
+
+enum { TPCF_BATCH_GRAPH = 1 };
+
+/* Count many requests in one launch (e.g. many data catalogs of uneven size
+ * against one resident random catalog, or jackknife subsamples).  All jobs
+ * must share the same edges, nbins and precision.  The work units of every
+ * job form one list, largest first, processed by one kernel launch; each job
+ * gets its own histogram.  out_u64: host array of njobs * (nbins+2) slots,
+ * job k at offset k * (nbins+2), written on TPCF_OK only.  flags:
+ * TPCF_BATCH_GRAPH captures the launch sequence in a hipGraph on the first
+ * call for a given batch (same job descriptions and catalogs) and replays it
+ * on later calls; the graph is dropped when any catalog is released.
+ * Synchronous; totals are checked for every job. */
+int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, int flags,
+                     uint64_t *out_u64);
+
+/* Asynchronous jobs for serving.  tpcf_submit validates and enqueues one
+ * request on one of four library streams (jobs on different streams overlap
+ * on the device) and returns a job id.  An RR request whose result is
+ * cached (same catalog, edges, precision and rows; the cache is cleared for a
+ * catalog when it is released) completes at submit without device work.
+ * tpcf_poll sets *done = 1 and writes nbins+2 slots to out_u64 (may be NULL)
+ * when the job has finished, and then retires the id; *done = 0 otherwise.
+ * tpcf_wait blocks until the job finishes, then acts like tpcf_poll.
+ * tpcf_cancel sets a flag in host memory that the kernel reads before every
+ * work unit; the job's poll/wait then returns TPCF_E_CANCELLED and retires
+ * it.  A catalog cannot be released while an unretired job uses it. */
+int tpcf_submit(tpcf_ctx *ctx, const tpcf_job_desc *job, int64_t *out_job);
+int tpcf_poll(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64, int *done);
+int tpcf_wait(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64);
+int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
+
+/* HBM budget for everything the context allocates (catalogs, tables, plans,
+ * workspaces); 0 = unlimited.  An allocation that would exceed it fails with
+ * TPCF_E_BUDGET and leaves the context unchanged.  tpcf_hbm_usage reports
+ * the bytes in use and the budget. */
+int tpcf_set_hbm_budget(tpcf_ctx *ctx, int64_t bytes);
+int tpcf_hbm_usage(tpcf_ctx *ctx, int64_t *out_used, int64_t *out_budget);
+
+/* Wait for all work enqueued by the context (its stream and job streams). */
 int tpcf_synchronize(tpcf_ctx *ctx);
 
 /* Kernel timing.  With timing on, the library records a HIP event pair on

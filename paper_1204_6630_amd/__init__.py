@@ -18,7 +18,8 @@ import numpy as np
 
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "TpcfError", "Context", "lib", "lib_path",
-    "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS",
+    "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
+    "BATCH_GRAPH",
 ]
 
 DD, DR, RR = 0, 1, 2
@@ -32,7 +33,8 @@ _lib = None
 EXPORTED_SYMBOLS = (
     "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
     "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
-    "tpcf_count_async", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
+    "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
+    "tpcf_cancel", "tpcf_set_hbm_budget", "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_edges",
     "tpcf_last_error", "tpcf_version",
 )
@@ -41,6 +43,17 @@ _ERRORS = {
     -1: "TPCF_E_INVALID", -2: "TPCF_E_NOMEM", -3: "TPCF_E_HIP", -4: "TPCF_E_BADID",
     -5: "TPCF_E_BUDGET", -6: "TPCF_E_CANCELLED", -7: "TPCF_E_INTERNAL",
 }
+
+
+class JobDesc(ctypes.Structure):
+    """struct tpcf_job_desc"""
+    _fields_ = [("kind", ctypes.c_int), ("cat_a", ctypes.c_int32), ("cat_b", ctypes.c_int32),
+                ("bin_edges_deg", ctypes.c_void_p), ("nbins", ctypes.c_int32),
+                ("precision", ctypes.c_int), ("row_begin", ctypes.c_int64),
+                ("row_end", ctypes.c_int64)]
+
+
+BATCH_GRAPH = 1
 
 
 class TpcfError(RuntimeError):
@@ -90,6 +103,13 @@ def lib():
         "tpcf_release_catalog": ([P, i32], cint),
         "tpcf_count": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
         "tpcf_count_async": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
+        "tpcf_count_batch": ([P, P, i32, cint, P], cint),
+        "tpcf_submit": ([P, P, P], cint),
+        "tpcf_poll": ([P, i64, P, P], cint),
+        "tpcf_wait": ([P, i64, P], cint),
+        "tpcf_cancel": ([P, i64], cint),
+        "tpcf_set_hbm_budget": ([P, i64], cint),
+        "tpcf_hbm_usage": ([P, P, P], cint),
         "tpcf_synchronize": ([P], cint),
         "tpcf_set_timing": ([P, cint], cint),
         "tpcf_kernel_time": ([P, P, P, cint], cint),
@@ -217,6 +237,59 @@ class Context:
 
     def synchronize(self):
         _check(lib().tpcf_synchronize(self._h))
+
+    # -- batches and jobs -----------------------------------------------------
+    @staticmethod
+    def _desc(kind, cat_a, edges, cat_b=-1, precision=FP32_CHORD, row_begin=-1, row_end=-1):
+        return JobDesc(kind, cat_a, cat_b, edges.ctypes.data, edges.size - 1, precision,
+                       row_begin, row_end)
+
+    def count_batch(self, jobs, edges_deg, precision: int = FP32_CHORD,
+                    graph: bool = False) -> np.ndarray:
+        """jobs: list of (kind, cat_a, cat_b) or (kind, cat_a, cat_b, row_begin,
+        row_end); returns an array (njobs, nbins+2)."""
+        e = _f64(edges_deg)
+        arr = (JobDesc * len(jobs))()
+        for k, jb in enumerate(jobs):
+            kind, ca, cb = jb[:3]
+            rb, re = (jb[3], jb[4]) if len(jb) > 3 else (-1, -1)
+            arr[k] = self._desc(kind, ca, e, cb, precision, rb, re)
+        out = np.zeros((len(jobs), e.size + 1), dtype=np.uint64)
+        _check(lib().tpcf_count_batch(self._h, arr, len(jobs), BATCH_GRAPH if graph else 0,
+                                      _p(out)))
+        return out
+
+    def submit(self, kind: int, cat_a: int, edges_deg, cat_b: int = -1,
+               precision: int = FP32_CHORD, row_begin: int = -1, row_end: int = -1) -> int:
+        e = _f64(edges_deg)
+        d = self._desc(kind, cat_a, e, cat_b, precision, row_begin, row_end)
+        jid = ctypes.c_int64()
+        _check(lib().tpcf_submit(self._h, ctypes.byref(d), ctypes.byref(jid)))
+        return jid.value
+
+    def poll(self, job: int, nslots: int):
+        """None while running; the nslots histogram once done (the id retires)."""
+        out = np.zeros(nslots, dtype=np.uint64)
+        done = ctypes.c_int()
+        _check(lib().tpcf_poll(self._h, job, _p(out), ctypes.byref(done)))
+        return out if done.value else None
+
+    def wait(self, job: int, nslots: int) -> np.ndarray:
+        out = np.zeros(nslots, dtype=np.uint64)
+        _check(lib().tpcf_wait(self._h, job, _p(out)))
+        return out
+
+    def cancel(self, job: int):
+        _check(lib().tpcf_cancel(self._h, job))
+
+    def set_hbm_budget(self, nbytes: int):
+        _check(lib().tpcf_set_hbm_budget(self._h, int(nbytes)))
+
+    def hbm_usage(self):
+        """(bytes in use, budget)"""
+        u, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tpcf_hbm_usage(self._h, ctypes.byref(u), ctypes.byref(b)))
+        return u.value, b.value
 
     def set_timing(self, on: bool = True):
         _check(lib().tpcf_set_timing(self._h, 1 if on else 0))

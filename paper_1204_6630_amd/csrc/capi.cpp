@@ -1,9 +1,11 @@
-// C ABI of libtpcf.so: contexts, catalogs, pair counting, Landy-Szalay.
+// C ABI of libtpcf.so: contexts, catalogs, pair counting, batches, jobs,
+// Landy-Szalay.
 //
 // Host side of the pair-counting path.  Everything here runs on the host:
 // argument checks, the unit vectors of uploaded catalogs, the edge compiler
-// (edges.cpp), the work-unit plan, and the launches.  Every pair is counted
-// on the GPU by the kernels in kernels.hip; there is no host fallback.
+// (edges.cpp), the work-unit plan, device-memory accounting, and the
+// launches.  Every pair is counted on the GPU by the kernels in kernels.hip;
+// there is no host fallback.
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <string.h>
@@ -12,14 +14,12 @@
 #include <cstdio>
 #include <map>
 #include <memory>
-#include <mutex>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
-#include "tpcf.h"
 #include "edges.h"
 #include "internal.h"
+#include "tpcf.h"
 
 using namespace tpcf;
 
@@ -40,27 +40,61 @@ int fail(int code, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
+#define TRY(expr)          \
+    do {                   \
+        int r_ = (expr);   \
+        if (r_)            \
+            return r_;     \
+    } while (0)
+
+constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
+constexpr int kRowsPerUnit = kWaves * kWaveSize * 4;  // four wavefronts x 4 rows per lane
+constexpr int kPoolStreams = 4;
+
+// Device memory of one context, with an optional budget on the total.
+struct MemAccount {
+    int64_t used = 0;
+    int64_t budget = 0;   // 0: unlimited
+};
+
+int dev_alloc(MemAccount &m, void **p, size_t bytes) {
+    if (m.budget > 0 && m.used + (int64_t)bytes > m.budget) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "allocation of %zu bytes exceeds the HBM budget (%lld of %lld in use)",
+                 bytes, (long long)m.used, (long long)m.budget);
+        return fail(TPCF_E_BUDGET, buf);
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(TPCF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    m.used += (int64_t)bytes;
+    return TPCF_OK;
+}
+
+void dev_free(MemAccount &m, void *p, size_t bytes) {
+    if (p) {
+        (void)hipFree(p);
+        m.used -= (int64_t)bytes;
+    }
+}
+
 // Device buffer that grows on demand.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
-    int ensure(size_t bytes) {
-        if (bytes <= cap)
+    int ensure(MemAccount &m, size_t bytes) {
+        if (bytes <= cap && p)
             return TPCF_OK;
-        if (p)
-            (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
+        release(m);
         size_t want = bytes < 256 ? 256 : bytes;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess)
-            return fail(TPCF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        TRY(dev_alloc(m, &p, want));
         cap = want;
         return TPCF_OK;
     }
-    void release() {
-        if (p)
-            (void)hipFree(p);
+    void release(MemAccount &m) {
+        dev_free(m, p, cap);
         p = nullptr;
         cap = 0;
     }
@@ -70,19 +104,20 @@ struct Catalog {
     int64_t n = 0;
     double *d64 = nullptr;      // x[n], y[n], z[n]
     float *d32 = nullptr;       // x[n], y[n], z[n]
-    std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
+    size_t bytes64 = 0, bytes32 = 0;
     bool owns64 = true;
     double delta = 0;           // bound on | |v|^2 - 1 |
+    std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
 };
 
 struct Compiled {
     EdgeTables edges;
-    // device copies: D, E (nedges doubles each), per precision cell table and bands
     DevBuf dD, dE, dqlo, dqhi, dlut;
     CellTable cells;
     Band32 band;
     int precision = 0;
     int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
+    double delta = 0;
 };
 
 struct Plan {
@@ -91,20 +126,63 @@ struct Plan {
     uint64_t pairs = 0;
 };
 
+// Launch resources of one stream.  Work on one stream runs in order, so the
+// buffers are reused by consecutive launches on it.
+struct Workspace {
+    hipStream_t stream = nullptr;
+    bool own = false;
+    DevBuf copies;   // kGlobalCopies x nslots u64
+    DevBuf out;      // kMaxSlots u64
+    DevBuf stats;    // 4 u64
+    int inflight = 0;
+};
+
+// A validated counting request.
+struct Request {
+    int kind = 0;
+    bool auto_pairs = false;
+    int32_t cat_a = -1, cat_b = -1;
+    const Catalog *A = nullptr, *B = nullptr;
+    int64_t rb = 0, re = 0;
+    int nbins = 0, precision = 0;
+    Compiled *cp = nullptr;
+    Plan *plan = nullptr;
+    uint64_t pairs = 0;
+    std::string cache_key;   // RR requests: key of the result cache
+};
+
+struct AsyncJob {
+    Request req;
+    int ws = -1;
+    hipEvent_t ev = nullptr;
+    uint64_t *hres = nullptr;   // pinned: kMaxSlots results, then the cancel word
+    volatile int *hcancel = nullptr;
+    bool cancelled = false;
+    bool ready = false;          // result known at submit (result cache)
+    std::vector<uint64_t> result;
+};
+
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevBuf copies, out, jobs, units;
+};
+
 }  // namespace
 
 struct tpcf_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    MemAccount mem;
+    Workspace main;                      // the context stream
+    std::vector<Workspace> pool;         // streams for submitted jobs
     int32_t next_id = 1;
+    int64_t next_job = 1;
     std::map<int32_t, Catalog> cats;
     std::map<std::string, std::unique_ptr<Compiled>> compiled;
     std::map<std::string, std::unique_ptr<Plan>> plans;
-    DevBuf copies;      // kGlobalCopies x kMaxSlots u64
-    DevBuf outbuf;      // kMaxSlots u64 (synchronous path)
-    DevBuf stats;       // 4 u64
-    DevBuf scratch;     // small device scratch (attach)
+    std::map<int64_t, AsyncJob> jobs;
+    std::map<std::string, std::unique_ptr<BatchGraph>> graphs;
+    std::map<std::string, std::vector<uint64_t>> result_cache;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     uint64_t pairs_since_reset = 0;
@@ -115,6 +193,54 @@ namespace {
 int set_device(tpcf_ctx *ctx) {
     HIP_TRY(hipSetDevice(ctx->device));
     return TPCF_OK;
+}
+
+int sync_all(tpcf_ctx *ctx) {
+    HIP_TRY(hipStreamSynchronize(ctx->main.stream));
+    for (auto &w : ctx->pool)
+        HIP_TRY(hipStreamSynchronize(w.stream));
+    return TPCF_OK;
+}
+
+int init_workspace(tpcf_ctx *ctx, Workspace &w, hipStream_t borrowed) {
+    if (borrowed) {
+        w.stream = borrowed;
+        w.own = false;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+        w.own = true;
+    }
+    TRY(w.stats.ensure(ctx->mem, sizeof(unsigned long long) * 4));
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w.stats.p, 4, w.stream));
+    return TPCF_OK;
+}
+
+void free_workspace(tpcf_ctx *ctx, Workspace &w) {
+    w.copies.release(ctx->mem);
+    w.out.release(ctx->mem);
+    w.stats.release(ctx->mem);
+    if (w.own && w.stream)
+        (void)hipStreamDestroy(w.stream);
+    w.stream = nullptr;
+}
+
+void free_graph(tpcf_ctx *ctx, BatchGraph &g) {
+    if (g.exec)
+        (void)hipGraphExecDestroy(g.exec);
+    if (g.graph)
+        (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    g.copies.release(ctx->mem);
+    g.out.release(ctx->mem);
+    g.jobs.release(ctx->mem);
+    g.units.release(ctx->mem);
+}
+
+void drop_graphs(tpcf_ctx *ctx) {
+    for (auto &kv : ctx->graphs)
+        free_graph(ctx, *kv.second);
+    ctx->graphs.clear();
 }
 
 // Bound on the exact | |v|^2 - 1 | of FP64 vectors: the largest computed
@@ -137,8 +263,6 @@ double norm_bound(const double *x, const double *y, const double *z, int64_t n, 
     }
     return m + 4.0 * ldexp(1.0, -53);
 }
-
-constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
 
 // Spatially coherent storage order: sort the points along a Morton (Z-order)
 // curve of their unit vectors, 21 bits per coordinate.  Neighbouring rows are
@@ -188,9 +312,7 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
         return fail(TPCF_E_INVALID, "coordinates must be finite");
     if (delta > kMaxDelta)
         return fail(TPCF_E_INVALID, "unit vectors must satisfy | |v|^2 - 1 | <= 2^-20");
-    int rc = set_device(ctx);
-    if (rc)
-        return rc;
+    TRY(set_device(ctx));
     Catalog c;
     c.n = n;
     c.delta = delta;
@@ -207,26 +329,25 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
         h32[alloc_n + r] = (float)y[i];
         h32[2 * alloc_n + r] = (float)z[i];
     }
-    hipError_t e = hipMalloc((void **)&c.d64, sizeof(double) * 3 * alloc_n);
-    if (e != hipSuccess)
-        return fail(TPCF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    e = hipMalloc((void **)&c.d32, sizeof(float) * 3 * alloc_n);
-    if (e != hipSuccess) {
-        (void)hipFree(c.d64);
-        return fail(TPCF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c.bytes64 = sizeof(double) * 3 * alloc_n;
+    c.bytes32 = sizeof(float) * 3 * alloc_n;
+    TRY(dev_alloc(ctx->mem, (void **)&c.d64, c.bytes64));
+    int rc = dev_alloc(ctx->mem, (void **)&c.d32, c.bytes32);
+    if (rc) {
+        dev_free(ctx->mem, c.d64, c.bytes64);
+        return rc;
     }
-    e = hipMemcpyAsync(c.d64, h64.data(), sizeof(double) * 3 * alloc_n, hipMemcpyHostToDevice, ctx->stream);
+    // blocking copies: the host vectors go out of scope on return
+    hipError_t e = hipMemcpy(c.d64, h64.data(), c.bytes64, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c.d32, h32.data(), sizeof(float) * 3 * alloc_n, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(ctx->stream);
+        e = hipMemcpy(c.d32, h32.data(), c.bytes32, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(c.d64);
-        (void)hipFree(c.d32);
+        dev_free(ctx->mem, c.d64, c.bytes64);
+        dev_free(ctx->mem, c.d32, c.bytes32);
         return fail(TPCF_E_HIP, std::string("upload: ") + hipGetErrorString(e));
     }
     int32_t id = ctx->next_id++;
-    ctx->cats[id] = c;
+    ctx->cats[id] = std::move(c);
     *out_cat = id;
     return TPCF_OK;
 }
@@ -240,13 +361,19 @@ std::string edges_key(const double *edges, int nbins, int precision, double delt
 }
 
 template <typename T>
-int upload(DevBuf &b, const std::vector<T> &v, hipStream_t st) {
-    int rc = b.ensure(sizeof(T) * (v.size() ? v.size() : 1));
-    if (rc)
-        return rc;
+int upload_blocking(MemAccount &m, DevBuf &b, const std::vector<T> &v) {
+    TRY(b.ensure(m, sizeof(T) * (v.size() ? v.size() : 1)));
     if (!v.empty())
-        HIP_TRY(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
     return TPCF_OK;
+}
+
+void free_compiled(tpcf_ctx *ctx, Compiled &c) {
+    c.dD.release(ctx->mem);
+    c.dE.release(ctx->mem);
+    c.dqlo.release(ctx->mem);
+    c.dqhi.release(ctx->mem);
+    c.dlut.release(ctx->mem);
 }
 
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta,
@@ -257,11 +384,19 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         *out = it->second.get();
         return TPCF_OK;
     }
+    if (ctx->compiled.size() >= 64) {   // bounded cache: drop all (in-flight work first)
+        TRY(sync_all(ctx));
+        drop_graphs(ctx);
+        for (auto &kv : ctx->compiled)
+            free_compiled(ctx, *kv.second);
+        ctx->compiled.clear();
+    }
     auto c = std::make_unique<Compiled>();
     std::string err;
     if (!compile_edges(edges, nbins, &c->edges, &err))
         return fail(TPCF_E_INVALID, err);
     c->precision = precision;
+    c->delta = delta;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
     const int max_cells = kMaxLutBytes / c->entry_bytes;
@@ -288,27 +423,16 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         memcpy(packed.data(), c->cells.cells.data(), packed.size());
     }
     int rc;
-    if ((rc = upload(c->dD, c->edges.D, ctx->stream)) || (rc = upload(c->dE, c->edges.E, ctx->stream)) ||
-        (rc = upload(c->dqlo, qlo, ctx->stream)) || (rc = upload(c->dqhi, qhi, ctx->stream)) ||
-        (rc = upload(c->dlut, packed, ctx->stream)))
+    if ((rc = upload_blocking(ctx->mem, c->dD, c->edges.D)) || (rc = upload_blocking(ctx->mem, c->dE, c->edges.E)) ||
+        (rc = upload_blocking(ctx->mem, c->dqlo, qlo)) || (rc = upload_blocking(ctx->mem, c->dqhi, qhi)) ||
+        (rc = upload_blocking(ctx->mem, c->dlut, packed))) {
+        free_compiled(ctx, *c);
         return rc;
-    HIP_TRY(hipStreamSynchronize(ctx->stream));   // host vectors stay alive; keep it simple
-    if (ctx->compiled.size() > 64) {
-        for (auto &kv : ctx->compiled) {
-            kv.second->dD.release();
-            kv.second->dE.release();
-            kv.second->dqlo.release();
-            kv.second->dqhi.release();
-            kv.second->dlut.release();
-        }
-        ctx->compiled.clear();
     }
     *out = c.get();
     ctx->compiled[key] = std::move(c);
     return TPCF_OK;
 }
-
-constexpr int kRowsPerUnit = kWaves * kWaveSize * 4;   // four wavefronts x 4 rows per lane
 
 // Work units.  DR: every row tile against column chunks of the B catalog.
 // DD/RR: every row tile [i0, i1) against j in [i0, n): one masked unit for the
@@ -318,8 +442,9 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re) 
     const int64_t T = kRowsPerUnit;
     uint64_t pairs = 0;
     if (auto_pairs) {
-        for (int64_t i = rb; i < re; ++i)
-            pairs += (uint64_t)(na - 1 - i);
+        // sum over i in [rb, re) of (na - 1 - i)
+        const int64_t cnt = re - rb;
+        pairs = (uint64_t)cnt * (uint64_t)(na - 1) - (uint64_t)((rb + re - 1) * cnt / 2);
     } else {
         pairs = (uint64_t)(re - rb) * (uint64_t)nb;
     }
@@ -337,15 +462,15 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re) 
         if (auto_pairs) {
             int64_t dend = i0 + T < na ? i0 + T : na;
             if (i0 + 1 < dend)
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend});
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend, 0, 0, 0, 0});
             for (int64_t j0 = dend; j0 < na; j0 += bj) {
                 int64_t j1 = j0 + bj < na ? j0 + bj : na;
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1});
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, 0, 0, 0});
             }
         } else {
             for (int64_t j0 = 0; j0 < nb; j0 += bj) {
                 int64_t j1 = j0 + bj < nb ? j0 + bj : nb;
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1});
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, 0, 0, 0});
             }
         }
     }
@@ -362,16 +487,15 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
         *out = it->second.get();
         return TPCF_OK;
     }
-    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re));
-    int rc = upload(p->dunits, p->units, ctx->stream);
-    if (rc)
-        return rc;
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (ctx->plans.size() > 32) {
+    if (ctx->plans.size() >= 256) {   // bounded cache: drop all (in-flight work first)
+        TRY(sync_all(ctx));
+        drop_graphs(ctx);
         for (auto &kv : ctx->plans)
-            kv.second->dunits.release();
+            kv.second->dunits.release(ctx->mem);
         ctx->plans.clear();
     }
+    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re));
+    TRY(upload_blocking(ctx->mem, p->dunits, p->units));
     *out = p.get();
     ctx->plans[buf] = std::move(p);
     return TPCF_OK;
@@ -389,113 +513,220 @@ int hist_copies_for(int nslots) {
     return 4;
 }
 
-// Validate and enqueue one count; the result lands in d_out (nslots u64).
-int enqueue_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const double *edges,
-                  int32_t nbins, int precision, int64_t row_begin, int64_t row_end,
-                  unsigned long long *d_out, uint64_t *expected_pairs) {
-    if (!ctx)
-        return fail(TPCF_E_INVALID, "context is NULL");
-    if (kind != TPCF_DD && kind != TPCF_DR && kind != TPCF_RR)
+std::string cache_key(int32_t cat, const double *edges, int nbins, int precision, int64_t rb, int64_t re) {
+    std::string k((const char *)&cat, sizeof cat);
+    k.append((const char *)edges, sizeof(double) * (size_t)(nbins + 1));
+    k.append((const char *)&precision, sizeof precision);
+    k.append((const char *)&rb, sizeof rb);
+    k.append((const char *)&re, sizeof re);
+    return k;
+}
+
+// Validate one request.  delta_override >= 0 compiles the FP32 band for that
+// norm bound (shared by every job of a batch) instead of the request's own.
+int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r) {
+    if (d.kind != TPCF_DD && d.kind != TPCF_DR && d.kind != TPCF_RR)
         return fail(TPCF_E_INVALID, "kind must be TPCF_DD, TPCF_DR or TPCF_RR");
-    if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64)
+    if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64)
         return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD or TPCF_FP64");
-    if (nbins < 1 || nbins > 256)
+    if (d.nbins < 1 || d.nbins > 256)
         return fail(TPCF_E_INVALID, "nbins must be in [1, 256]");
-    if (!edges)
+    if (!d.bin_edges_deg)
         return fail(TPCF_E_INVALID, "bin_edges_deg is NULL");
-    const bool auto_pairs = kind != TPCF_DR;
-    auto ia = ctx->cats.find(cat_a);
+    r->kind = d.kind;
+    r->auto_pairs = d.kind != TPCF_DR;
+    r->precision = d.precision;
+    r->nbins = d.nbins;
+    auto ia = ctx->cats.find(d.cat_a);
     if (ia == ctx->cats.end())
         return fail(TPCF_E_BADID, "unknown catalog id cat_a");
-    const Catalog &A = ia->second;
-    const Catalog *B = &A;
-    if (auto_pairs) {
-        if (cat_b != -1)
+    r->cat_a = d.cat_a;
+    r->A = &ia->second;
+    r->B = r->A;
+    r->cat_b = -1;
+    if (r->auto_pairs) {
+        if (d.cat_b != -1)
             return fail(TPCF_E_INVALID, "DD/RR take one catalog: cat_b must be -1");
     } else {
-        auto ib = ctx->cats.find(cat_b);
+        auto ib = ctx->cats.find(d.cat_b);
         if (ib == ctx->cats.end())
             return fail(TPCF_E_BADID, "unknown catalog id cat_b");
-        B = &ib->second;
+        r->cat_b = d.cat_b;
+        r->B = &ib->second;
     }
-    int64_t rb = row_begin, re = row_end;
+    int64_t rb = d.row_begin, re = d.row_end;
     if (rb == -1 && re == -1) {
         rb = 0;
-        re = A.n;
+        re = r->A->n;
     }
-    if (rb < 0 || re < rb || re > A.n)
+    if (rb < 0 || re < rb || re > r->A->n)
         return fail(TPCF_E_INVALID, "row range must satisfy 0 <= row_begin <= row_end <= n");
-    int rc = set_device(ctx);
-    if (rc)
-        return rc;
-    const double delta = A.delta > B->delta ? A.delta : B->delta;
-    Compiled *cp = nullptr;
-    if ((rc = get_compiled(ctx, edges, nbins, precision, delta, &cp)))
-        return rc;
-    Plan *plan = nullptr;
-    if ((rc = get_plan(ctx, auto_pairs, A.n, B->n, rb, re, &plan)))
-        return rc;
-    const int nslots = nbins + 2;
-    if ((rc = ctx->copies.ensure(sizeof(unsigned long long) * kGlobalCopies * kMaxSlots)))
-        return rc;
-    if ((rc = ctx->stats.ensure(sizeof(unsigned long long) * 4)))
-        return rc;
-    unsigned long long *copies = (unsigned long long *)ctx->copies.p;
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots, ctx->stream));
+    r->rb = rb;
+    r->re = re;
+    TRY(set_device(ctx));
+    const double delta = delta_override >= 0 ? delta_override
+                                             : (r->A->delta > r->B->delta ? r->A->delta : r->B->delta);
+    TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, &r->cp));
+    TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, &r->plan));
+    r->pairs = r->plan->pairs;
+    r->cache_key.clear();
+    if (d.kind == TPCF_RR)
+        r->cache_key = cache_key(d.cat_a, d.bin_edges_deg, d.nbins, d.precision, rb, re);
+    return TPCF_OK;
+}
 
+JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
+    JobDev j;
+    memset(&j, 0, sizeof j);
+    const size_t na = (size_t)(r.A->n > 0 ? r.A->n : 1), nb = (size_t)(r.B->n > 0 ? r.B->n : 1);
+    j.ax32 = r.A->d32;
+    j.ay32 = r.A->d32 + na;
+    j.az32 = r.A->d32 + 2 * na;
+    j.bx32 = r.B->d32;
+    j.by32 = r.B->d32 + nb;
+    j.bz32 = r.B->d32 + 2 * nb;
+    j.ax64 = r.A->d64;
+    j.ay64 = r.A->d64 + na;
+    j.az64 = r.A->d64 + 2 * na;
+    j.bx64 = r.B->d64;
+    j.by64 = r.B->d64 + nb;
+    j.bz64 = r.B->d64 + 2 * nb;
+    j.hist = hist;
+    j.cancel = cancel;
+    j.auto_pairs = r.auto_pairs ? 1 : 0;
+    return j;
+}
+
+PairArgs args_of(const Compiled &cp, int nbins, unsigned long long *stats) {
     PairArgs a;
     memset(&a, 0, sizeof a);
-    const size_t na = (size_t)(A.n > 0 ? A.n : 1), nbb = (size_t)(B->n > 0 ? B->n : 1);
-    a.ax32 = A.d32;
-    a.ay32 = A.d32 + na;
-    a.az32 = A.d32 + 2 * na;
-    a.bx32 = B->d32;
-    a.by32 = B->d32 + nbb;
-    a.bz32 = B->d32 + 2 * nbb;
-    a.ax64 = A.d64;
-    a.ay64 = A.d64 + na;
-    a.az64 = A.d64 + 2 * na;
-    a.bx64 = B->d64;
-    a.by64 = B->d64 + nbb;
-    a.bz64 = B->d64 + 2 * nbb;
-    a.auto_pairs = auto_pairs ? 1 : 0;
-    a.units = (const Unit *)plan->dunits.p;
-    a.n_units = (int32_t)plan->units.size();
-    a.lut = cp->dlut.p;
-    a.lut_cells = (int32_t)cp->cells.cells.size();
-    a.lut_entry_bytes = cp->entry_bytes;
-    a.lut_shift = cp->cells.shift;
-    a.lut_lo = cp->cells.lo;
-    a.lut_hi = cp->cells.hi;
-    a.qlo = (const float *)cp->dqlo.p;
-    a.qhi = (const float *)cp->dqhi.p;
-    a.E = (const double *)cp->dE.p;
-    a.D = (const double *)cp->dD.p;
+    a.lut = cp.dlut.p;
+    a.lut_cells = (int32_t)cp.cells.cells.size();
+    a.lut_entry_bytes = cp.entry_bytes;
+    a.lut_shift = cp.cells.shift;
+    a.lut_lo = cp.cells.lo;
+    a.lut_hi = cp.cells.hi;
+    a.qlo = (const float *)cp.dqlo.p;
+    a.qhi = (const float *)cp.dqhi.p;
+    a.E = (const double *)cp.dE.p;
+    a.D = (const double *)cp.dD.p;
     a.nedges = nbins + 1;
-    a.nslots = nslots;
-    a.hist_copies = hist_copies_for(nslots);
-    a.hist = copies;
-    a.stats = (unsigned long long *)ctx->stats.p;
+    a.nslots = nbins + 2;
+    a.hist_copies = hist_copies_for(nbins + 2);
+    a.stats = stats;
+    return a;
+}
 
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->timing && a.n_units > 0) {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, ctx->stream));
-    }
-    int lrc = tpcf_launch_pairs(&a, precision == TPCF_FP32_CHORD ? 0 : 1, ctx->stream);
+int record_start(tpcf_ctx *ctx, hipStream_t st, hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (!ctx->timing)
+        return TPCF_OK;
+    HIP_TRY(hipEventCreate(e0));
+    HIP_TRY(hipEventCreate(e1));
+    HIP_TRY(hipEventRecord(*e0, st));
+    return TPCF_OK;
+}
+
+int record_stop(tpcf_ctx *ctx, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (!e0)
+        return TPCF_OK;
+    HIP_TRY(hipEventRecord(e1, st));
+    ctx->events.emplace_back(e0, e1);
+    return TPCF_OK;
+}
+
+// Enqueue one request on a workspace: zero its histogram copies, count, and
+// reduce into d_out (nslots u64).  Every argument travels by value in the
+// kernel arguments, so nothing on the host must outlive the call.
+int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long *d_out,
+               const int *cancel) {
+    const int nslots = r.nbins + 2;
+    TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * kGlobalCopies * kMaxSlots));
+    unsigned long long *copies = (unsigned long long *)w.copies.p;
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots, w.stream));
+    PairArgs a = args_of(*r.cp, r.nbins, (unsigned long long *)w.stats.p);
+    a.jobs = nullptr;
+    a.job0 = job_of(r, copies, cancel);
+    a.units = (const Unit *)r.plan->dunits.p;
+    a.n_units = (int32_t)r.plan->units.size();
+    hipEvent_t e0, e1;
+    if (a.n_units > 0)
+        TRY(record_start(ctx, w.stream, &e0, &e1));
+    else
+        e0 = e1 = nullptr;
+    int lrc = tpcf_launch_pairs(&a, r.precision == TPCF_FP32_CHORD ? 0 : 1, w.stream);
     if (lrc)
         return fail(TPCF_E_HIP, std::string("pair kernel launch: ") + hipGetErrorString((hipError_t)lrc));
-    if (e0) {
-        HIP_TRY(hipEventRecord(e1, ctx->stream));
-        ctx->events.emplace_back(e0, e1);
-    }
-    lrc = tpcf_launch_reduce_copies(copies, nslots, d_out, ctx->stream);
+    TRY(record_stop(ctx, w.stream, e0, e1));
+    lrc = tpcf_launch_reduce_copies(copies, nslots, 1, d_out, w.stream);
     if (lrc)
         return fail(TPCF_E_HIP, std::string("reduce launch: ") + hipGetErrorString((hipError_t)lrc));
-    ctx->pairs_since_reset += plan->pairs;
-    if (expected_pairs)
-        *expected_pairs = plan->pairs;
+    ctx->pairs_since_reset += r.pairs;
+    return TPCF_OK;
+}
+
+int check_total(const uint64_t *h, int nslots, uint64_t expected) {
+    uint64_t tot = 0;
+    for (int s = 0; s < nslots; ++s)
+        tot += h[s];
+    if (tot != expected) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "slot total %llu differs from the %llu pairs requested",
+                 (unsigned long long)tot, (unsigned long long)expected);
+        return fail(TPCF_E_INTERNAL, buf);
+    }
+    return TPCF_OK;
+}
+
+tpcf_job_desc desc_of(int kind, int32_t cat_a, int32_t cat_b, const double *edges, int32_t nbins,
+                      int precision, int64_t rb, int64_t re) {
+    tpcf_job_desc d;
+    d.kind = kind;
+    d.cat_a = cat_a;
+    d.cat_b = cat_b;
+    d.bin_edges_deg = edges;
+    d.nbins = nbins;
+    d.precision = precision;
+    d.row_begin = rb;
+    d.row_end = re;
+    return d;
+}
+
+void retire_job(tpcf_ctx *ctx, std::map<int64_t, AsyncJob>::iterator it) {
+    AsyncJob &j = it->second;
+    if (j.ev)
+        (void)hipEventDestroy(j.ev);
+    if (j.hres)
+        (void)hipHostFree(j.hres);
+    if (j.ws >= 0)
+        ctx->pool[j.ws].inflight--;
+    ctx->jobs.erase(it);
+}
+
+// Finish a completed job: result into out (may be null), retire it.
+int finish_job(tpcf_ctx *ctx, std::map<int64_t, AsyncJob>::iterator it, uint64_t *out) {
+    AsyncJob &j = it->second;
+    const int nslots = j.req.nbins + 2;
+    if (j.cancelled) {
+        retire_job(ctx, it);
+        return fail(TPCF_E_CANCELLED, "job was cancelled");
+    }
+    std::vector<uint64_t> h;
+    if (j.ready) {
+        h = j.result;
+    } else {
+        h.assign(j.hres, j.hres + nslots);
+        int rc = check_total(h.data(), nslots, j.req.pairs);
+        if (rc) {
+            retire_job(ctx, it);
+            return rc;
+        }
+        if (!j.req.cache_key.empty())
+            ctx->result_cache[j.req.cache_key] = h;
+    }
+    if (out)
+        memcpy(out, h.data(), sizeof(uint64_t) * (size_t)nslots);
+    retire_job(ctx, it);
     return TPCF_OK;
 }
 
@@ -505,7 +736,7 @@ extern "C" {
 
 const char *tpcf_last_error(void) { return g_err.c_str(); }
 
-const char *tpcf_version(void) { return "tpcf 0.1 (gfx950)"; }
+const char *tpcf_version(void) { return "tpcf 0.2 (gfx950)"; }
 
 int tpcf_open(int device, void *hip_stream, tpcf_ctx **out) {
     if (!out)
@@ -517,17 +748,8 @@ int tpcf_open(int device, void *hip_stream, tpcf_ctx **out) {
     auto ctx = std::make_unique<tpcf_ctx>();
     ctx->device = device;
     HIP_TRY(hipSetDevice(device));
-    if (hip_stream) {
-        ctx->stream = (hipStream_t)hip_stream;
-    } else {
-        HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-        ctx->own_stream = true;
-    }
-    int rc;
-    if ((rc = ctx->stats.ensure(sizeof(unsigned long long) * 4)))
-        return rc;
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)ctx->stats.p, 4, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(init_workspace(ctx.get(), ctx->main, (hipStream_t)hip_stream));
+    HIP_TRY(hipStreamSynchronize(ctx->main.stream));
     *out = ctx.release();
     return TPCF_OK;
 }
@@ -536,32 +758,26 @@ int tpcf_close(tpcf_ctx *ctx) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)sync_all(ctx);
+    while (!ctx->jobs.empty())
+        retire_job(ctx, ctx->jobs.begin());
+    drop_graphs(ctx);
     for (auto &kv : ctx->cats) {
-        if (kv.second.owns64 && kv.second.d64)
-            (void)hipFree(kv.second.d64);
-        if (kv.second.d32)
-            (void)hipFree(kv.second.d32);
+        if (kv.second.owns64)
+            dev_free(ctx->mem, kv.second.d64, kv.second.bytes64);
+        dev_free(ctx->mem, kv.second.d32, kv.second.bytes32);
     }
-    for (auto &kv : ctx->compiled) {
-        kv.second->dD.release();
-        kv.second->dE.release();
-        kv.second->dqlo.release();
-        kv.second->dqhi.release();
-        kv.second->dlut.release();
-    }
+    for (auto &kv : ctx->compiled)
+        free_compiled(ctx, *kv.second);
     for (auto &kv : ctx->plans)
-        kv.second->dunits.release();
+        kv.second->dunits.release(ctx->mem);
     for (auto &ev : ctx->events) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
     }
-    ctx->copies.release();
-    ctx->outbuf.release();
-    ctx->stats.release();
-    ctx->scratch.release();
-    if (ctx->own_stream)
-        (void)hipStreamDestroy(ctx->stream);
+    for (auto &w : ctx->pool)
+        free_workspace(ctx, w);
+    free_workspace(ctx, ctx->main);
     delete ctx;
     return TPCF_OK;
 }
@@ -604,9 +820,7 @@ int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t
         return fail(TPCF_E_INVALID, "attach needs 1 <= n < 2^31 - 1024");
     if (!d_xyz64)
         return fail(TPCF_E_INVALID, "d_xyz64 is NULL");
-    int rc = set_device(ctx);
-    if (rc)
-        return rc;
+    TRY(set_device(ctx));
     hipPointerAttribute_t attr;
     memset(&attr, 0, sizeof attr);
     if (hipPointerGetAttributes(&attr, d_xyz64) != hipSuccess || attr.type != hipMemoryTypeDevice ||
@@ -618,30 +832,35 @@ int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t
     c.n = n;
     c.owns64 = false;
     c.d64 = const_cast<double *>(d_xyz64);
-    HIP_TRY(hipMalloc((void **)&c.d32, sizeof(float) * 3 * (size_t)n));
-    if ((rc = ctx->scratch.ensure(64)))
+    c.bytes32 = sizeof(float) * 3 * (size_t)n;
+    TRY(dev_alloc(ctx->mem, (void **)&c.d32, c.bytes32));
+    Workspace &w = ctx->main;
+    int rc = w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots);
+    if (rc) {
+        dev_free(ctx->mem, c.d32, c.bytes32);
         return rc;
-    double *dmax = (double *)ctx->scratch.p;
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)dmax, 1, ctx->stream));
-    int lrc = tpcf_launch_to_float(c.d64, n, c.d32, dmax, ctx->stream);
+    }
+    double *dmax = (double *)w.out.p;
+    hipError_t e = (hipError_t)tpcf_launch_zero_u64((unsigned long long *)dmax, 1, w.stream);
+    if (e == hipSuccess)
+        e = (hipError_t)tpcf_launch_to_float(c.d64, n, c.d32, dmax, w.stream);
     double dev = 0.0;
-    hipError_t e = (hipError_t)lrc;
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&dev, dmax, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        e = hipMemcpyAsync(&dev, dmax, sizeof(double), hipMemcpyDeviceToHost, w.stream);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(ctx->stream);
+        e = hipStreamSynchronize(w.stream);
     if (e != hipSuccess) {
-        (void)hipFree(c.d32);
+        dev_free(ctx->mem, c.d32, c.bytes32);
         return fail(TPCF_E_HIP, std::string("attach: ") + hipGetErrorString(e));
     }
     double delta = dev + 4.0 * ldexp(1.0, -53);
     if (!(delta <= kMaxDelta)) {
-        (void)hipFree(c.d32);
+        dev_free(ctx->mem, c.d32, c.bytes32);
         return fail(TPCF_E_INVALID, "attached vectors must be finite with | |v|^2 - 1 | <= 2^-20");
     }
     c.delta = delta;
     int32_t id = ctx->next_id++;
-    ctx->cats[id] = c;
+    ctx->cats[id] = std::move(c);
     *out_cat = id;
     return TPCF_OK;
 }
@@ -674,43 +893,52 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat) {
     auto it = ctx->cats.find(cat);
     if (it == ctx->cats.end())
         return fail(TPCF_E_BADID, "unknown catalog id");
-    (void)hipSetDevice(ctx->device);
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (it->second.owns64 && it->second.d64)
-        (void)hipFree(it->second.d64);
-    if (it->second.d32)
-        (void)hipFree(it->second.d32);
+    for (auto &kv : ctx->jobs)
+        if (kv.second.req.cat_a == cat || kv.second.req.cat_b == cat)
+            return fail(TPCF_E_INVALID, "catalog is used by a job that has not been polled to completion");
+    TRY(set_device(ctx));
+    TRY(sync_all(ctx));
+    drop_graphs(ctx);   // captured launches hold catalog pointers
+    for (auto c = ctx->result_cache.begin(); c != ctx->result_cache.end();) {
+        int32_t k;
+        memcpy(&k, c->first.data(), sizeof k);
+        if (k == cat)
+            c = ctx->result_cache.erase(c);
+        else
+            ++c;
+    }
+    if (it->second.owns64)
+        dev_free(ctx->mem, it->second.d64, it->second.bytes64);
+    dev_free(ctx->mem, it->second.d32, it->second.bytes32);
     ctx->cats.erase(it);
     return TPCF_OK;
 }
 
 int tpcf_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const double *bin_edges_deg,
                int32_t nbins, int precision, int64_t row_begin, int64_t row_end, uint64_t *out_u64) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
     if (!out_u64)
         return fail(TPCF_E_INVALID, "out_u64 is NULL");
-    if (ctx) {
-        int rc = ctx->outbuf.ensure(sizeof(unsigned long long) * kMaxSlots);
-        if (rc)
-            return rc;
+    Request r;
+    TRY(prepare(ctx, desc_of(kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end), -1, &r));
+    const int nslots = nbins + 2;
+    if (!r.cache_key.empty()) {
+        auto c = ctx->result_cache.find(r.cache_key);
+        if (c != ctx->result_cache.end()) {
+            memcpy(out_u64, c->second.data(), sizeof(uint64_t) * (size_t)nslots);
+            return TPCF_OK;
+        }
     }
-    uint64_t expected = 0;
-    int rc = enqueue_count(ctx, kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end,
-                           (unsigned long long *)(ctx ? ctx->outbuf.p : nullptr), &expected);
-    if (rc)
-        return rc;
-    std::vector<uint64_t> h((size_t)nbins + 2);
-    HIP_TRY(hipMemcpyAsync(h.data(), ctx->outbuf.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    uint64_t tot = 0;
-    for (uint64_t v : h)
-        tot += v;
-    if (tot != expected) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "slot total %llu differs from the %llu pairs requested",
-                 (unsigned long long)tot, (unsigned long long)expected);
-        return fail(TPCF_E_INTERNAL, buf);
-    }
+    Workspace &w = ctx->main;
+    TRY(w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots));
+    TRY(launch_one(ctx, w, r, (unsigned long long *)w.out.p, nullptr));
+    std::vector<uint64_t> h((size_t)nslots);
+    HIP_TRY(hipMemcpyAsync(h.data(), w.out.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, w.stream));
+    HIP_TRY(hipStreamSynchronize(w.stream));
+    TRY(check_total(h.data(), nslots, r.pairs));
+    if (!r.cache_key.empty())
+        ctx->result_cache[r.cache_key] = h;
     memcpy(out_u64, h.data(), sizeof(uint64_t) * h.size());
     return TPCF_OK;
 }
@@ -718,17 +946,274 @@ int tpcf_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const doub
 int tpcf_count_async(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const double *bin_edges_deg,
                      int32_t nbins, int precision, int64_t row_begin, int64_t row_end,
                      uint64_t *d_out_u64) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
     if (!d_out_u64)
         return fail(TPCF_E_INVALID, "d_out_u64 is NULL");
-    return enqueue_count(ctx, kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end,
-                         (unsigned long long *)d_out_u64, nullptr);
+    Request r;
+    TRY(prepare(ctx, desc_of(kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end), -1, &r));
+    return launch_one(ctx, ctx->main, r, (unsigned long long *)d_out_u64, nullptr);
+}
+
+int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, int flags, uint64_t *out_u64) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    if (!jobs || !out_u64 || njobs < 1 || njobs > 65536)
+        return fail(TPCF_E_INVALID, "need 1 <= njobs <= 65536 job descriptions and an output array");
+    if (flags & ~TPCF_BATCH_GRAPH)
+        return fail(TPCF_E_INVALID, "unknown batch flags");
+    const int nbins = jobs[0].nbins;
+    if (nbins < 1 || nbins > 256 || !jobs[0].bin_edges_deg)
+        return fail(TPCF_E_INVALID, "nbins must be in [1, 256] and edges non-NULL");
+    for (int32_t k = 1; k < njobs; ++k) {
+        if (jobs[k].nbins != nbins || jobs[k].precision != jobs[0].precision || !jobs[k].bin_edges_deg ||
+            memcmp(jobs[k].bin_edges_deg, jobs[0].bin_edges_deg, sizeof(double) * (size_t)(nbins + 1)) != 0)
+            return fail(TPCF_E_INVALID, "every job of a batch must use the same edges and precision");
+    }
+    // one norm bound for the whole batch, so all jobs share one set of tables
+    double delta = 0.0;
+    for (int32_t k = 0; k < njobs; ++k) {
+        auto a = ctx->cats.find(jobs[k].cat_a);
+        if (a != ctx->cats.end())
+            delta = std::max(delta, a->second.delta);
+        auto b = ctx->cats.find(jobs[k].cat_b);
+        if (b != ctx->cats.end())
+            delta = std::max(delta, b->second.delta);
+    }
+    std::vector<Request> reqs((size_t)njobs);
+    for (int32_t k = 0; k < njobs; ++k)
+        TRY(prepare(ctx, jobs[k], delta, &reqs[k]));
+    const int nslots = nbins + 2;
+    const int prec = jobs[0].precision == TPCF_FP32_CHORD ? 0 : 1;
+    const size_t copies_bytes = sizeof(unsigned long long) * (size_t)njobs * kGlobalCopies * nslots;
+    const size_t out_bytes = sizeof(unsigned long long) * (size_t)njobs * nslots;
+    hipStream_t st = ctx->main.stream;
+    const bool use_graph = (flags & TPCF_BATCH_GRAPH) != 0;
+
+    std::string key;
+    key.append((const char *)&njobs, sizeof njobs);
+    for (int32_t k = 0; k < njobs; ++k) {
+        tpcf_job_desc d = jobs[k];
+        d.bin_edges_deg = nullptr;
+        key.append((const char *)&d, sizeof d);
+    }
+    key.append((const char *)jobs[0].bin_edges_deg, sizeof(double) * (size_t)(nbins + 1));
+    key.append((const char *)&delta, sizeof delta);
+
+    BatchGraph *g = nullptr;
+    std::unique_ptr<BatchGraph> fresh;
+    auto git = ctx->graphs.find(key);
+    if (use_graph && git != ctx->graphs.end())
+        g = git->second.get();
+    if (!g) {
+        fresh = std::make_unique<BatchGraph>();
+        g = fresh.get();
+        int rc;
+        if ((rc = g->copies.ensure(ctx->mem, copies_bytes)) || (rc = g->out.ensure(ctx->mem, out_bytes))) {
+            free_graph(ctx, *g);
+            return rc;
+        }
+        std::vector<JobDev> hj((size_t)njobs);
+        std::vector<Unit> hu;
+        for (int32_t k = 0; k < njobs; ++k) {
+            hj[k] = job_of(reqs[k], (unsigned long long *)g->copies.p + (size_t)k * kGlobalCopies * nslots, nullptr);
+            for (Unit u : reqs[k].plan->units) {
+                u.job = k;
+                hu.push_back(u);
+            }
+        }
+        // units of all jobs interleaved by size: largest units first
+        std::stable_sort(hu.begin(), hu.end(), [](const Unit &x, const Unit &y) {
+            return (int64_t)(x.i1 - x.i0) * (x.j1 - x.j0) > (int64_t)(y.i1 - y.i0) * (y.j1 - y.j0);
+        });
+        if ((rc = upload_blocking(ctx->mem, g->jobs, hj)) || (rc = upload_blocking(ctx->mem, g->units, hu))) {
+            free_graph(ctx, *g);
+            return rc;
+        }
+        PairArgs a = args_of(*reqs[0].cp, nbins, (unsigned long long *)ctx->main.stats.p);
+        a.jobs = (const JobDev *)g->jobs.p;
+        a.units = (const Unit *)g->units.p;
+        a.n_units = (int32_t)hu.size();
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (use_graph) {
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                free_graph(ctx, *g);
+                return fail(TPCF_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+            }
+        }
+        int lrc = tpcf_launch_zero_u64((unsigned long long *)g->copies.p, (int64_t)njobs * kGlobalCopies * nslots, st);
+        if (!lrc && !use_graph)
+            rc = record_start(ctx, st, &e0, &e1);
+        if (!lrc && !rc)
+            lrc = tpcf_launch_pairs(&a, prec, st);
+        if (!lrc && !rc && !use_graph)
+            rc = record_stop(ctx, st, e0, e1);
+        if (!lrc && !rc)
+            lrc = tpcf_launch_reduce_copies((unsigned long long *)g->copies.p, nslots, njobs,
+                                            (unsigned long long *)g->out.p, st);
+        if (use_graph) {
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &graph);
+            g->graph = graph;
+            if (!lrc && !rc && e == hipSuccess)
+                e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+            if (!lrc && !rc && e != hipSuccess) {
+                free_graph(ctx, *g);
+                return fail(TPCF_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            }
+        }
+        if (lrc || rc) {
+            (void)hipStreamSynchronize(st);
+            free_graph(ctx, *g);
+            return rc ? rc : fail(TPCF_E_HIP, std::string("batch launch: ") + hipGetErrorString((hipError_t)lrc));
+        }
+    }
+    if (use_graph) {
+        hipEvent_t e0, e1;
+        TRY(record_start(ctx, st, &e0, &e1));
+        HIP_TRY(hipGraphLaunch(g->exec, st));
+        TRY(record_stop(ctx, st, e0, e1));
+    }
+    std::vector<uint64_t> h((size_t)njobs * nslots);
+    HIP_TRY(hipMemcpyAsync(h.data(), g->out.p, out_bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int rc = TPCF_OK;
+    for (int32_t k = 0; k < njobs && !rc; ++k) {
+        ctx->pairs_since_reset += reqs[k].pairs;
+        rc = check_total(h.data() + (size_t)k * nslots, nslots, reqs[k].pairs);
+    }
+    if (fresh) {
+        if (use_graph && !rc) {
+            if (ctx->graphs.size() >= 16)
+                drop_graphs(ctx);
+            ctx->graphs[key] = std::move(fresh);
+        } else {
+            free_graph(ctx, *fresh);
+        }
+    }
+    if (rc)
+        return rc;
+    memcpy(out_u64, h.data(), sizeof(uint64_t) * h.size());
+    return TPCF_OK;
+}
+
+int tpcf_submit(tpcf_ctx *ctx, const tpcf_job_desc *job, int64_t *out_job) {
+    if (!ctx || !job || !out_job)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    AsyncJob j;
+    TRY(prepare(ctx, *job, -1, &j.req));
+    const int nslots = j.req.nbins + 2;
+    if (!j.req.cache_key.empty()) {
+        auto c = ctx->result_cache.find(j.req.cache_key);
+        if (c != ctx->result_cache.end()) {
+            j.ready = true;
+            j.result = c->second;
+        }
+    }
+    if (!j.ready) {
+        if (ctx->pool.empty()) {
+            ctx->pool.resize(kPoolStreams);
+            for (auto &w : ctx->pool)
+                TRY(init_workspace(ctx, w, nullptr));
+        }
+        int best = 0;
+        for (int s = 1; s < (int)ctx->pool.size(); ++s)
+            if (ctx->pool[s].inflight < ctx->pool[best].inflight)
+                best = s;
+        Workspace &w = ctx->pool[best];
+        TRY(w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots));
+        void *pinned = nullptr;
+        HIP_TRY(hipHostMalloc(&pinned, sizeof(uint64_t) * (kMaxSlots + 8), hipHostMallocCoherent));
+        j.hres = (uint64_t *)pinned;
+        j.hcancel = (volatile int *)(j.hres + kMaxSlots);
+        *j.hcancel = 0;
+        int rc = launch_one(ctx, w, j.req, (unsigned long long *)w.out.p, (const int *)j.hcancel);
+        hipError_t e = hipSuccess;
+        if (!rc)
+            e = hipMemcpyAsync(j.hres, w.out.p, sizeof(uint64_t) * (size_t)nslots, hipMemcpyDeviceToHost, w.stream);
+        if (!rc && e == hipSuccess)
+            e = hipEventCreateWithFlags(&j.ev, hipEventDisableTiming);
+        if (!rc && e == hipSuccess)
+            e = hipEventRecord(j.ev, w.stream);
+        if (rc || e != hipSuccess) {
+            (void)hipStreamSynchronize(w.stream);
+            if (j.ev)
+                (void)hipEventDestroy(j.ev);
+            (void)hipHostFree(pinned);
+            return rc ? rc : fail(TPCF_E_HIP, std::string("submit: ") + hipGetErrorString(e));
+        }
+        j.ws = best;
+        w.inflight++;
+    }
+    int64_t id = ctx->next_job++;
+    ctx->jobs[id] = std::move(j);
+    *out_job = id;
+    return TPCF_OK;
+}
+
+int tpcf_poll(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64, int *done) {
+    if (!ctx || !done)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end())
+        return fail(TPCF_E_BADID, "unknown job id");
+    *done = 0;
+    if (!it->second.ready) {
+        hipError_t e = hipEventQuery(it->second.ev);
+        if (e == hipErrorNotReady)
+            return TPCF_OK;
+        if (e != hipSuccess)
+            return fail(TPCF_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+    }
+    *done = 1;
+    return finish_job(ctx, it, out_u64);
+}
+
+int tpcf_wait(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end())
+        return fail(TPCF_E_BADID, "unknown job id");
+    if (!it->second.ready)
+        HIP_TRY(hipEventSynchronize(it->second.ev));
+    return finish_job(ctx, it, out_u64);
+}
+
+int tpcf_cancel(tpcf_ctx *ctx, int64_t job) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end())
+        return fail(TPCF_E_BADID, "unknown job id");
+    it->second.cancelled = true;
+    if (it->second.hcancel)
+        *it->second.hcancel = 1;
+    return TPCF_OK;
+}
+
+int tpcf_set_hbm_budget(tpcf_ctx *ctx, int64_t bytes) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    if (bytes < 0)
+        return fail(TPCF_E_INVALID, "budget must be >= 0 (0: unlimited)");
+    ctx->mem.budget = bytes;
+    return TPCF_OK;
+}
+
+int tpcf_hbm_usage(tpcf_ctx *ctx, int64_t *out_used, int64_t *out_budget) {
+    if (!ctx || !out_used || !out_budget)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    *out_used = ctx->mem.used;
+    *out_budget = ctx->mem.budget;
+    return TPCF_OK;
 }
 
 int tpcf_synchronize(tpcf_ctx *ctx) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    return TPCF_OK;
+    return sync_all(ctx);
 }
 
 int tpcf_set_timing(tpcf_ctx *ctx, int on) {
@@ -741,7 +1226,7 @@ int tpcf_set_timing(tpcf_ctx *ctx, int on) {
 int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int reset) {
     if (!ctx || !out_ms || !out_launches)
         return fail(TPCF_E_INVALID, "NULL argument");
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(sync_all(ctx));
     double ms = 0.0;
     for (auto &ev : ctx->events) {
         float t = 0.0f;
@@ -763,21 +1248,30 @@ int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int r
 int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact, int reset) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
-    HIP_TRY(hipSetDevice(ctx->device));
-    unsigned long long h[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(h, ctx->stats.p, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    TRY(set_device(ctx));
+    TRY(sync_all(ctx));
+    unsigned long long tot[4] = {0, 0, 0, 0};
+    std::vector<Workspace *> ws{&ctx->main};
+    for (auto &w : ctx->pool)
+        ws.push_back(&w);
+    for (Workspace *w : ws) {
+        unsigned long long h[4] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpy(h, w->stats.p, sizeof h, hipMemcpyDeviceToHost));
+        for (int i = 0; i < 4; ++i)
+            tot[i] += h[i];
+        if (reset)
+            HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w->stats.p, 4, w->stream));
+    }
+    if (reset)
+        TRY(sync_all(ctx));
     if (out_pairs)
         *out_pairs = ctx->pairs_since_reset;
     if (out_flagged)
-        *out_flagged = h[1];
+        *out_flagged = tot[1];
     if (out_exact)
-        *out_exact = h[2];
-    if (reset) {
-        HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)ctx->stats.p, 4, ctx->stream));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        *out_exact = tot[2];
+    if (reset)
         ctx->pairs_since_reset = 0;
-    }
     return TPCF_OK;
 }
 

@@ -30,21 +30,30 @@ constexpr uint16_t kMedium = 0x8000;
 constexpr uint16_t kMulti = 0xFFFF;
 constexpr int kMaxSlots8 = 127;
 
-// One work unit: rows i in [i0, i1) against columns j in [j0, j1).  A unit
-// needs per-pair masking when its row tile is cut short or, for auto-pairs,
-// when its columns overlap its rows (the j <= i diagonal).
+// One work unit: rows i in [i0, i1) against columns j in [j0, j1) of job
+// `job`.  A unit needs per-pair masking when its row tile is cut short or,
+// for auto-pairs, when its columns overlap its rows (the j <= i diagonal).
 struct Unit {
     int32_t i0, i1, j0, j1;
+    int32_t job, pad0, pad1, pad2;
 };
 
-struct PairArgs {
-    // Catalog A (rows i) and B (columns j), structure of arrays.
+// One counting job of a launch: catalogs A (rows i) and B (columns j) as
+// structures of arrays, the pair kind, and where its histogram goes.
+struct JobDev {
     const float *ax32, *ay32, *az32;
     const float *bx32, *by32, *bz32;
     const double *ax64, *ay64, *az64;
     const double *bx64, *by64, *bz64;
+    unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
+    const int *cancel;           // host-visible flag (non-zero: skip the rest), or null
     int32_t auto_pairs;          // 1: DD/RR (count j > i only), 0: DR
+    int32_t pad;
+};
 
+struct PairArgs {
+    const JobDev *jobs;          // device job table, or null: every unit belongs to job0
+    JobDev job0;                 // the job of a single-job launch (passed by value)
     const Unit *units;           // device
     int32_t n_units;
 
@@ -65,8 +74,7 @@ struct PairArgs {
     // Per-wave LDS histogram copies (layout [slot][copy]).
     int32_t hist_copies;         // 32, 16, 8 or 4
 
-    unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
-    unsigned long long *stats;   // [pairs, flagged, exact]
+    unsigned long long *stats;   // [pairs, flagged, exact, skipped units]
 };
 
 // LDS bytes used by one block for the given table sizes.
@@ -83,7 +91,9 @@ inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_b
 extern "C" {
 int tpcf_launch_pairs(const tpcf::PairArgs *args, int precision, void *stream);
 int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
-int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots,
+// Sum the kGlobalCopies copies of each of njobs histograms (contiguous,
+// njobs x kGlobalCopies x nslots) into out (njobs x nslots).
+int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots, int32_t njobs,
                               unsigned long long *out, void *stream);
 int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
                          double *maxdev_out, void *stream);

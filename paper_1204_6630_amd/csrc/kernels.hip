@@ -47,6 +47,21 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 // of a wavefront reads the same j, so these become scalar loads into SGPRs.
 typedef const __attribute__((address_space(4))) float *cfloat_p;
 typedef const __attribute__((address_space(4))) double *cdouble_p;
+typedef const __attribute__((address_space(4))) uint32_t *cword_p;
+
+// Unit and job descriptors are read-only and wavefront-uniform as well: copy
+// them word by word through the constant address space (scalar loads).
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T out;
+    cword_p src = (cword_p)p;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(T) / 4); ++w)
+        dst[w] = src[w];
+    return out;
+}
 
 // Clamp into [lo, hi] in one instruction (all operands in VGPRs: gfx9 VOP3
 // reads at most one SGPR, which keeps the compiler from forming v_med3).
@@ -150,10 +165,11 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // Sum one wavefront's LDS histogram into a global copy and clear it.
-__device__ void flush_wave(const PairArgs &a, const Smem &s, int wave, int lane, int copy) {
+__device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long *hist, int wave,
+                           int lane, int copy) {
     const int C = a.hist_copies;
     uint32_t *h = s.hist + wave * (a.nslots + 1) * C;
-    unsigned long long *g = a.hist + (size_t)copy * a.nslots;
+    unsigned long long *g = hist + (size_t)copy * a.nslots;
     for (int s0 = 0; s0 < a.nslots; s0 += kWaveSize) {
         int slot = s0 + lane;
         if (slot < a.nslots) {
@@ -173,7 +189,7 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, int wave, int lane,
 
 template <bool LUT8>
 __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Smem &s,
-                                                 const PairArgs &a, int i, int j,
+                                                 const PairArgs &a, const JobDev &jb, int i, int j,
                                                  uint32_t &n_exact) {
     if (ent != Code<LUT8>::multi) {
         int k = (int)(ent & Code<LUT8>::kmask);
@@ -182,11 +198,11 @@ __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Sm
         if (q >= s.qhi[k])
             return (uint32_t)(k + 1);
         ++n_exact;
-        double d = exact_dot(a.ax64[i], a.ay64[i], a.az64[i], a.bx64[j], a.by64[j], a.bz64[j]);
+        double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
         return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
     }
     ++n_exact;
-    double d = exact_dot(a.ax64[i], a.ay64[i], a.az64[i], a.bx64[j], a.by64[j], a.bz64[j]);
+    double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
     return count_le(d, s.D, a.nedges);
 }
 
@@ -221,7 +237,7 @@ struct Consts {
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
 template <bool LUT8, bool MASKED, int P, int JN>
-__device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, const Consts &k,
+__device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
                                           const int (&il)[P], int ie, int j, cfloat_p bx,
@@ -264,7 +280,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & Code<LUT8>::flag) {
                     ++n_flag;
-                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, il[p], j + t, n_exact);
+                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, jb, il[p], j + t, n_exact);
                 }
     }
 #pragma unroll
@@ -273,7 +289,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
         for (int p = 0; p < P; ++p) {
             uint32_t e = ent[t][p];
             if (MASKED) {
-                bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
+                bool ok = ii[p] < ie && (!jb.auto_pairs || j + t > ii[p]);
                 e = ok ? e : (uint32_t)a.nslots;
             }
             lds_inc(__umul24(e, k.rowstep) + k.lanebase);
@@ -281,7 +297,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const Smem &s, cons
 }
 
 template <bool LUT8, bool MASKED, int P, int JN>
-__device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, const Consts &k,
+__device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie,
                                           int j, cdouble_p bx, cdouble_p by, cdouble_p bz,
@@ -330,7 +346,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, cons
         for (int p = 0; p < P; ++p) {
             uint32_t v = ent[t][p];
             if (MASKED) {
-                bool ok = ii[p] < ie && (!a.auto_pairs || j + t > ii[p]);
+                bool ok = ii[p] < ie && (!jb.auto_pairs || j + t > ii[p]);
                 v = ok ? v : (uint32_t)a.nslots;
             }
             lds_inc(__umul24(v, k.rowstep) + k.lanebase);
@@ -339,7 +355,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const Smem &s, cons
 
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
 template <bool LUT8, bool MASKED, int P>
-__device__ void rows_fp32(const PairArgs &a, const Smem &s, const Consts &k, int ib, int ie,
+__device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
     float xi[P], yi[P], zi[P];
     int ii[P], il[P];
@@ -348,23 +364,23 @@ __device__ void rows_fp32(const PairArgs &a, const Smem &s, const Consts &k, int
         int i = ib + p * kWaveSize + lane;
         ii[p] = i;
         il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
-        xi[p] = a.ax32[il[p]];
-        yi[p] = a.ay32[il[p]];
-        zi[p] = a.az32[il[p]];
+        xi[p] = jb.ax32[il[p]];
+        yi[p] = jb.ay32[il[p]];
+        zi[p] = jb.az32[il[p]];
     }
-    cfloat_p bx = (cfloat_p)a.bx32;
-    cfloat_p by = (cfloat_p)a.by32;
-    cfloat_p bz = (cfloat_p)a.bz32;
+    cfloat_p bx = (cfloat_p)jb.bx32;
+    cfloat_p by = (cfloat_p)jb.by32;
+    cfloat_p bz = (cfloat_p)jb.bz32;
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp32<LUT8, MASKED, P, kColsPerStep>(a, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz,
+        step_fp32<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz,
                                                  n_flag, n_exact);
     for (; j < j1; ++j)
-        step_fp32<LUT8, MASKED, P, 1>(a, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, n_flag, n_exact);
+        step_fp32<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, n_flag, n_exact);
 }
 
 template <bool LUT8, bool MASKED, int P>
-__device__ void rows_fp64(const PairArgs &a, const Smem &s, const Consts &k, int ib, int ie,
+__device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
     double xi[P], yi[P], zi[P];
     int ii[P];
@@ -373,19 +389,19 @@ __device__ void rows_fp64(const PairArgs &a, const Smem &s, const Consts &k, int
         int i = ib + p * kWaveSize + lane;
         ii[p] = i;
         int il = i < ie ? i : ib;
-        xi[p] = a.ax64[il];
-        yi[p] = a.ay64[il];
-        zi[p] = a.az64[il];
+        xi[p] = jb.ax64[il];
+        yi[p] = jb.ay64[il];
+        zi[p] = jb.az64[il];
     }
-    cdouble_p bx = (cdouble_p)a.bx64;
-    cdouble_p by = (cdouble_p)a.by64;
-    cdouble_p bz = (cdouble_p)a.bz64;
+    cdouble_p bx = (cdouble_p)jb.bx64;
+    cdouble_p by = (cdouble_p)jb.by64;
+    cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag,
+        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag,
                                                  n_exact);
     for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1>(a, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag, n_exact);
+        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag, n_exact);
 }
 
 template <int PREC, bool LUT8>
@@ -421,25 +437,32 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     uint32_t n_flag = 0, n_exact = 0;
 
+    uint32_t n_skip = 0;
     for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
-        const Unit un = a.units[u];
+        const Unit un = load_uniform(a.units + u);
+        const JobDev jb = a.jobs ? load_uniform(a.jobs + un.job) : a.job0;
         const int ib = un.i0 + wave * kRowsPerWave;
         if (ib < un.i1) {
+            // a cancelled job skips its remaining units (the flag lives in host memory)
+            if (jb.cancel && __hip_atomic_load(jb.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                ++n_skip;
+                continue;
+            }
             const int ie = min(un.i1, ib + kRowsPerWave);
-            const bool masked = (ie - ib < kRowsPerWave) || (a.auto_pairs && un.j0 < ie);
+            const bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie);
             if (PREC == 0) {
                 if (masked)
-                    rows_fp32<LUT8, true, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp32<LUT8, true, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
                 else
-                    rows_fp32<LUT8, false, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp32<LUT8, false, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
             } else {
                 if (masked)
-                    rows_fp64<LUT8, true, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp64<LUT8, true, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
                 else
-                    rows_fp64<LUT8, false, kRowsPerLane>(a, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp64<LUT8, false, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
             }
             // the wave's own LDS region only: no block barrier needed
-            flush_wave(a, s, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
+            flush_wave(a, s, jb.hist, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
         }
     }
     uint32_t f = wave_sum(n_flag);
@@ -449,6 +472,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[1], (unsigned long long)f);
         if (x)
             atomicAdd(&a.stats[2], (unsigned long long)x);
+        if (n_skip)
+            atomicAdd(&a.stats[3], (unsigned long long)n_skip);
     }
 }
 
@@ -459,13 +484,15 @@ __global__ void zero_u64_kernel(unsigned long long *p, int64_t n) {
         p[i] = 0ull;
 }
 
+// One block per job: sum its kGlobalCopies histogram copies.
 __global__ void reduce_copies_kernel(const unsigned long long *copies, int32_t nslots,
                                      unsigned long long *out) {
+    const unsigned long long *c = copies + (size_t)blockIdx.x * kGlobalCopies * nslots;
     for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
         unsigned long long acc = 0;
         for (int g = 0; g < kGlobalCopies; ++g)
-            acc += copies[(size_t)g * nslots + s];
-        out[s] = acc;
+            acc += c[(size_t)g * nslots + s];
+        out[(size_t)blockIdx.x * nslots + s] = acc;
     }
 }
 
@@ -563,9 +590,11 @@ extern "C" int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stre
 }
 
 extern "C" int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots,
-                                         unsigned long long *out, void *stream) {
-    hipLaunchKernelGGL(reduce_copies_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, copies,
-                       nslots, out);
+                                         int32_t njobs, unsigned long long *out, void *stream) {
+    if (njobs <= 0)
+        return 0;
+    hipLaunchKernelGGL(reduce_copies_kernel, dim3((unsigned)njobs), dim3(256), 0, (hipStream_t)stream,
+                       copies, nslots, out);
     return (int)hipGetLastError();
 }
 
