@@ -35,6 +35,8 @@ def parse():
                     help="octant: 1e6 x 2e6 DD+DR+RR (default); batched: 64 uneven catalogs "
                          "against one 1e6 random in one launch; serving: Poisson job stream")
     ap.add_argument("--jobs", type=int, default=300, help="serving: number of jobs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape instead of tuning on a sample")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0,
@@ -233,6 +235,14 @@ def main():
     cd = ctx.upload_catalog(d.ra, d.dec)
     cr = ctx.upload_catalog(r.ra, r.dec)
     out = torch.zeros((3, nslots), dtype=torch.int64, device=dev)
+    tuning = None
+    if not args.no_autotune:
+        from paper_1204_6630_amd.autotune import autotune
+        rows = min(nd, 32768)
+        sample = [(tp.DR, cd, cr, 0, rows), (tp.DD, cd, -1, 0, rows)]
+        tuning = autotune(ctx, sample, edges, tp.FP32_CHORD)
+        print(f"# tuning: {tuning['tuning']} (cached: {tuning['cached']})", file=sys.stderr,
+              flush=True)
 
     def step(prec):
         ctx.count_async(tp.DD, cd, edges, out[0].data_ptr(), precision=prec)
@@ -256,11 +266,11 @@ def main():
         t1 = time.perf_counter()
         ctx.set_timing(False)
         kms, launches = ctx.kernel_time(reset=True)
-        pairs, flagged, exact = ctx.stats(reset=True)
+        pairs, flagged, exact, rare = ctx.stats(reset=True)
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
-                "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs}
+                "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare}
 
     print(f"# workload {wl.name}: N_D={nd} N_R={nr} nbins={edges.size - 1} "
           f"pairs/step={pairs_step:.4e}", file=sys.stderr, flush=True)
@@ -299,9 +309,12 @@ def main():
                      "unit": "Gpairs/s", "frac": round(k_gpairs / PEAK_GPAIRS, 4),
                      "traffic": None, "kernel": "pairs_kernel<0> (FP32 chord)",
                      "kernel_ms_per_launch": round(f32["kernel_ms"] / max(1, f32["launches"]), 3)},
+        "tuning": tuning["tuning"] if tuning else None,
         "fp32_chord": {"gpairs_s": round(value, 2), "kernel_gpairs_s": round(k_gpairs, 1),
                        "flagged_rate": f32["flagged"] / max(1, f32["pairs"]),
-                       "recheck_rate": f32["exact"] / max(1, f32["pairs"])},
+                       "recheck_rate": f32["exact"] / max(1, f32["pairs"]),
+                       "rare_step_rate": f32["rare"] * 64 * 2 * ctx.get_tuning()["rows_per_lane"]
+                       / max(1, f32["pairs"])},
     }
     if f64 is not None:
         v64 = pairs_step * args.steps / f64["s"] / 1e9

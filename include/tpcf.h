@@ -60,8 +60,14 @@ enum { TPCF_DD = 0, TPCF_DR = 1, TPCF_RR = 2 };
  *   bands proven to contain every edge; a pair inside a band is re-decided in
  *   FP64 with the exact counting rule.
  * TPCF_FP64: every pair's FP64 dot product d is computed as in the counting
- *   rule and compared with D_k (the plain path). */
-enum { TPCF_FP32_CHORD = 0, TPCF_FP64 = 1 };
+ *   rule and compared with D_k (the plain path).
+ * TPCF_FP64_MATRIX: the FP64 matrix cores evaluate e = 1 - d for tiles of
+ *   16 x 16 pairs (A rows (-x_i, -y_i, -z_i, 1) times B columns
+ *   (x_j, y_j, z_j, 1), one v_mfma_f64_16x16x4 per tile); pairs whose e lies
+ *   within 2^-48 of 1 - D_k are re-decided with the exact rule.  The vector
+ *   units then only bin.  The library keeps a 32-byte-per-point operand pack
+ *   of each catalog used this way. */
+enum { TPCF_FP32_CHORD = 0, TPCF_FP64 = 1, TPCF_FP64_MATRIX = 2 };
 
 enum {
     TPCF_OK = 0,
@@ -123,7 +129,7 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat);
  *            -1; TPCF_DR: every pair (i in cat_a, j in cat_b).
  * bin_edges_deg  nbins+1 finite, strictly increasing values in [0, 180]
  *            (host array); 1 <= nbins <= 256.
- * precision  TPCF_FP32_CHORD or TPCF_FP64 (identical results).
+ * precision  TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX (identical results).
  * row_begin, row_end  restrict i to rows [row_begin, row_end) of cat_a, in
  *            the catalog's stored order (tpcf_catalog_order); -1, -1 selects
  *            all rows.  For DD/RR the pairs are (i, j) with i in the range and
@@ -188,6 +194,19 @@ int tpcf_poll(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64, int *done);
 int tpcf_wait(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64);
 int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
 
+/* Launch shape of later launches (set by the autotuner; defaults are fine).
+ * rows_per_lane   2 or 4 rows held in registers per lane (0: 4);
+ * hist_copies     LDS histogram copies per wavefront, 4..32 (0: 32, fewer
+ *                 for many bins); a value above the default is ignored;
+ * max_cols        largest column range of a work unit, multiple of 256 in
+ *                 [256, 65536] (0: 16384);
+ * blocks_per_cu   grid size per compute unit (0: resident blocks x 4).
+ * Results never depend on these. */
+int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, int32_t max_cols,
+                    int32_t blocks_per_cu);
+int tpcf_get_tuning(tpcf_ctx *ctx, int32_t *rows_per_lane, int32_t *hist_copies, int32_t *max_cols,
+                    int32_t *blocks_per_cu);
+
 /* HBM budget for everything the context allocates (catalogs, tables, plans,
  * workspaces); 0 = unlimited.  An allocation that would exceed it fails with
  * TPCF_E_BUDGET and leaves the context unchanged.  tpcf_hbm_usage reports
@@ -206,11 +225,12 @@ int tpcf_set_timing(tpcf_ctx *ctx, int on);
 int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int reset);
 
 /* Work statistics since the last reset: pairs evaluated, pairs that left the
- * table-driven path for a threshold comparison, and pairs re-decided with
- * the exact FP64 rule (FP32_CHORD band pairs, or FP64 ties). Waits for the
- * context stream. */
-int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged,
-               uint64_t *out_exact, int reset);
+ * table-driven path for a threshold comparison, pairs re-decided with the
+ * exact FP64 rule (FP32_CHORD band pairs, or FP64 ties), and wavefront steps
+ * (64 lanes x a few pairs each) that took the rare path.  Waits for all of
+ * the context's streams.  Any output pointer may be NULL. */
+int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
+               uint64_t *out_rare_steps, int reset);
 
 /* Landy-Szalay estimator (Eq. 1), host FP64; no context needed.
  * dd, dr, rr  histograms of nbins+2 slots as returned by tpcf_count (DD and
@@ -249,6 +269,11 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
 int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
                        int32_t max_cells, int32_t *out_shift, int32_t *out_lo, int32_t *out_hi,
                        uint16_t *out_cells, double *out_E);
+
+/* Matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
+ * doubles each) such that e >= out_hi[k] implies d <= D_k and e < out_lo[k]
+ * implies d > D_k whenever e is within 2^-48 of 1 - d. */
+int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_lo, double *out_hi);
 
 /* Message describing the last failed call on the calling thread ("" if none).
  * Valid until the next call on the same thread. */

@@ -17,13 +17,13 @@ import os
 import numpy as np
 
 __all__ = [
-    "DD", "DR", "RR", "FP32_CHORD", "FP64", "TpcfError", "Context", "lib", "lib_path",
+    "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
     "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH",
 ]
 
 DD, DR, RR = 0, 1, 2
-FP32_CHORD, FP64 = 0, 1
+FP32_CHORD, FP64, FP64_MATRIX = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libtpcf.so")
@@ -34,8 +34,10 @@ EXPORTED_SYMBOLS = (
     "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
     "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
     "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
-    "tpcf_cancel", "tpcf_set_hbm_budget", "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
-    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_edges",
+    "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
+    "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
+    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_band64",
+    "tpcf_compile_edges",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -108,14 +110,17 @@ def lib():
         "tpcf_poll": ([P, i64, P, P], cint),
         "tpcf_wait": ([P, i64, P], cint),
         "tpcf_cancel": ([P, i64], cint),
+        "tpcf_set_tuning": ([P, i32, i32, i32, i32], cint),
+        "tpcf_get_tuning": ([P, P, P, P, P], cint),
         "tpcf_set_hbm_budget": ([P, i64], cint),
         "tpcf_hbm_usage": ([P, P, P], cint),
         "tpcf_synchronize": ([P], cint),
         "tpcf_set_timing": ([P, cint], cint),
         "tpcf_kernel_time": ([P, P, P, cint], cint),
-        "tpcf_stats": ([P, P, P, P, cint], cint),
+        "tpcf_stats": ([P, P, P, P, P, cint], cint),
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, P, P, P, P, P], cint),
+        "tpcf_compile_band64": ([P, i32, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_last_error": ([], ctypes.c_char_p),
         "tpcf_version": ([], ctypes.c_char_p),
@@ -282,6 +287,16 @@ class Context:
     def cancel(self, job: int):
         _check(lib().tpcf_cancel(self._h, job))
 
+    def set_tuning(self, rows_per_lane: int = 0, hist_copies: int = 0, max_cols: int = 0,
+                   blocks_per_cu: int = 0):
+        _check(lib().tpcf_set_tuning(self._h, rows_per_lane, hist_copies, max_cols, blocks_per_cu))
+
+    def get_tuning(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().tpcf_get_tuning(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("rows_per_lane", "hist_copies", "max_cols", "blocks_per_cu"),
+                        (x.value for x in v)))
+
     def set_hbm_budget(self, nbytes: int):
         _check(lib().tpcf_set_hbm_budget(self._h, int(nbytes)))
 
@@ -302,11 +317,10 @@ class Context:
         return ms.value, n.value
 
     def stats(self, reset: bool = False):
-        """(pairs, flagged, exact) since the last reset."""
-        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-        _check(lib().tpcf_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                1 if reset else 0))
-        return a.value, b.value, c.value
+        """(pairs, flagged, exact, rare_steps) since the last reset."""
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().tpcf_stats(self._h, *[ctypes.byref(x) for x in v], 1 if reset else 0))
+        return tuple(x.value for x in v)
 
 
 def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:
@@ -330,6 +344,15 @@ def compile_edges(edges_deg, delta_max: float = 0.0):
     qhi = np.empty(e.size, np.float32)
     _check(lib().tpcf_compile_edges(_p(e), e.size - 1, delta_max, _p(D), _p(qlo), _p(qhi)))
     return D, qlo, qhi
+
+
+def compile_band64(edges_deg):
+    """(lo, hi) of tpcf_compile_band64."""
+    e = _f64(edges_deg)
+    lo = np.empty(e.size, np.float64)
+    hi = np.empty(e.size, np.float64)
+    _check(lib().tpcf_compile_band64(_p(e), e.size - 1, _p(lo), _p(hi)))
+    return lo, hi
 
 
 def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None):

@@ -48,8 +48,16 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
-constexpr int kRowsPerUnit = kWaves * kWaveSize * 4;  // four wavefronts x 4 rows per lane
+constexpr double kMatrixTau = 3.552713678800501e-15; // 2^-48, see make_band64
 constexpr int kPoolStreams = 4;
+
+// Launch shape, set by tpcf_set_tuning (the autotuner) or left at defaults.
+struct Tuning {
+    int rows_per_lane = 4;   // 2 or 4
+    int hist_copies = 0;     // 0: by the number of slots
+    int max_cols = 16384;    // largest column range of a work unit
+    int blocks_per_cu = 0;   // 0: resident blocks x 4
+};
 
 // Device memory of one context, with an optional budget on the total.
 struct MemAccount {
@@ -108,11 +116,13 @@ struct Catalog {
     bool owns64 = true;
     double delta = 0;           // bound on | |v|^2 - 1 |
     std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
+    double *dpack = nullptr;    // matrix-core operand pack, built on first use
+    size_t bytes_pack = 0;
 };
 
 struct Compiled {
     EdgeTables edges;
-    DevBuf dD, dE, dqlo, dqhi, dlut;
+    DevBuf dD, dE, dqlo, dqhi, dlut, dTlo, dThi;
     CellTable cells;
     Band32 band;
     int precision = 0;
@@ -133,7 +143,7 @@ struct Workspace {
     bool own = false;
     DevBuf copies;   // kGlobalCopies x nslots u64
     DevBuf out;      // kMaxSlots u64
-    DevBuf stats;    // 4 u64
+    DevBuf stats;    // 8 u64
     int inflight = 0;
 };
 
@@ -186,6 +196,7 @@ struct tpcf_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     uint64_t pairs_since_reset = 0;
+    Tuning tune;
 };
 
 namespace {
@@ -210,8 +221,8 @@ int init_workspace(tpcf_ctx *ctx, Workspace &w, hipStream_t borrowed) {
         HIP_TRY(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
         w.own = true;
     }
-    TRY(w.stats.ensure(ctx->mem, sizeof(unsigned long long) * 4));
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w.stats.p, 4, w.stream));
+    TRY(w.stats.ensure(ctx->mem, sizeof(unsigned long long) * 8));
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w.stats.p, 8, w.stream));
     return TPCF_OK;
 }
 
@@ -374,6 +385,8 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
     c.dqlo.release(ctx->mem);
     c.dqhi.release(ctx->mem);
     c.dlut.release(ctx->mem);
+    c.dTlo.release(ctx->mem);
+    c.dThi.release(ctx->mem);
 }
 
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta,
@@ -400,16 +413,20 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
     const int max_cells = kMaxLutBytes / c->entry_bytes;
-    std::vector<float> qlo, qhi;
+    std::vector<float> qlo(c->edges.D.size(), 0.0f), qhi(c->edges.D.size(), 0.0f);
+    std::vector<double> tlo = c->edges.E, thi = c->edges.E;
     if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
         c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
+    } else if (precision == TPCF_FP64_MATRIX) {
+        Band64 b = make_band64(c->edges, kMatrixTau);
+        c->cells = make_cells64_band(b, max_cells);
+        tlo = b.lo;
+        thi = b.hi;
     } else {
         c->cells = make_cells64(c->edges, max_cells);
-        qlo.assign(c->edges.D.size(), 0.0f);
-        qhi.assign(c->edges.D.size(), 0.0f);
     }
     std::vector<uint8_t> packed;
     if (c->entry_bytes == 1) {
@@ -425,7 +442,8 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     int rc;
     if ((rc = upload_blocking(ctx->mem, c->dD, c->edges.D)) || (rc = upload_blocking(ctx->mem, c->dE, c->edges.E)) ||
         (rc = upload_blocking(ctx->mem, c->dqlo, qlo)) || (rc = upload_blocking(ctx->mem, c->dqhi, qhi)) ||
-        (rc = upload_blocking(ctx->mem, c->dlut, packed))) {
+        (rc = upload_blocking(ctx->mem, c->dlut, packed)) || (rc = upload_blocking(ctx->mem, c->dTlo, tlo)) ||
+        (rc = upload_blocking(ctx->mem, c->dThi, thi))) {
         free_compiled(ctx, *c);
         return rc;
     }
@@ -437,9 +455,9 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
 // Work units.  DR: every row tile against column chunks of the B catalog.
 // DD/RR: every row tile [i0, i1) against j in [i0, n): one masked unit for the
 // diagonal block [i0, i0 + T), then unmasked chunks from i0 + T on.
-Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re) {
+Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, int64_t T,
+               int64_t max_cols, int64_t align) {
     Plan p;
-    const int64_t T = kRowsPerUnit;
     uint64_t pairs = 0;
     if (auto_pairs) {
         // sum over i in [rb, re) of (na - 1 - i)
@@ -449,28 +467,30 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re) 
         pairs = (uint64_t)(re - rb) * (uint64_t)nb;
     }
     p.pairs = pairs;
-    // column chunk: aim for >= ~4096 units on big requests, within [256, 16384]
+    // column chunk: aim for >= ~4096 units on big requests, within [256, max_cols]
     double per_unit = (double)pairs / 4096.0 / (double)T;
     int64_t bj = (int64_t)per_unit;
     bj = (bj + 255) / 256 * 256;
+    if (bj > max_cols)
+        bj = max_cols;
     if (bj < 256)
         bj = 256;
-    if (bj > 16384)
-        bj = 16384;
-    for (int64_t i0 = rb; i0 < re; i0 += T) {
-        int64_t i1 = i0 + T < re ? i0 + T : re;
+    // row tiles start on multiples of `align` (valid rows from row_lo = rb)
+    for (int64_t i0 = rb - rb % align; i0 < re; i0 += T) {
+        const int64_t i1 = i0 + T < re ? i0 + T : re;
+        const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
         if (auto_pairs) {
             int64_t dend = i0 + T < na ? i0 + T : na;
-            if (i0 + 1 < dend)
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend, 0, 0, 0, 0});
+            if (lo + 1 < dend)
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend, 0, lo, 0, 0});
             for (int64_t j0 = dend; j0 < na; j0 += bj) {
                 int64_t j1 = j0 + bj < na ? j0 + bj : na;
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, 0, 0, 0});
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
             }
         } else {
             for (int64_t j0 = 0; j0 < nb; j0 += bj) {
                 int64_t j1 = j0 + bj < nb ? j0 + bj : nb;
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, 0, 0, 0});
+                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
             }
         }
     }
@@ -478,10 +498,15 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re) 
 }
 
 int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re,
-             Plan **out) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld:%lld", (int)auto_pairs, (long long)na,
-             (long long)nb, (long long)rb, (long long)re);
+             bool matrix, Plan **out) {
+    // vector paths: 64 lanes x rows_per_lane rows per wavefront; matrix-core
+    // path: rows_per_lane groups of 16 rows per wavefront, 16-aligned tiles
+    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * ctx->tune.rows_per_lane;
+    const int64_t align = matrix ? 16 : 1;
+    const int64_t max_cols = ctx->tune.max_cols;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld:%lld:%lld:%lld:%lld", (int)auto_pairs, (long long)na,
+             (long long)nb, (long long)rb, (long long)re, (long long)T, (long long)max_cols, (long long)align);
     auto it = ctx->plans.find(buf);
     if (it != ctx->plans.end()) {
         *out = it->second.get();
@@ -494,7 +519,7 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
             kv.second->dunits.release(ctx->mem);
         ctx->plans.clear();
     }
-    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re));
+    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re, T, max_cols, align));
     TRY(upload_blocking(ctx->mem, p->dunits, p->units));
     *out = p.get();
     ctx->plans[buf] = std::move(p);
@@ -522,13 +547,35 @@ std::string cache_key(int32_t cat, const double *edges, int nbins, int precision
     return k;
 }
 
+// Matrix-core operand pack of a catalog, built on the device on first use.
+int ensure_pack(tpcf_ctx *ctx, Catalog &c) {
+    if (c.dpack)
+        return TPCF_OK;
+    const int64_t groups = (c.n + 15) / 16 > 0 ? (c.n + 15) / 16 : 1;
+    c.bytes_pack = sizeof(double) * 64 * (size_t)groups;
+    TRY(dev_alloc(ctx->mem, (void **)&c.dpack, c.bytes_pack));
+    hipError_t e = hipSuccess;
+    if (c.n > 0)
+        e = (hipError_t)tpcf_launch_pack16(c.d64, c.n, c.dpack, ctx->main.stream);
+    else
+        e = (hipError_t)tpcf_launch_zero_u64((unsigned long long *)c.dpack, (int64_t)(c.bytes_pack / 8), ctx->main.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->main.stream);
+    if (e != hipSuccess) {
+        dev_free(ctx->mem, c.dpack, c.bytes_pack);
+        c.dpack = nullptr;
+        return fail(TPCF_E_HIP, std::string("operand pack: ") + hipGetErrorString(e));
+    }
+    return TPCF_OK;
+}
+
 // Validate one request.  delta_override >= 0 compiles the FP32 band for that
 // norm bound (shared by every job of a batch) instead of the request's own.
 int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r) {
     if (d.kind != TPCF_DD && d.kind != TPCF_DR && d.kind != TPCF_RR)
         return fail(TPCF_E_INVALID, "kind must be TPCF_DD, TPCF_DR or TPCF_RR");
-    if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64)
-        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD or TPCF_FP64");
+    if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64 && d.precision != TPCF_FP64_MATRIX)
+        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX");
     if (d.nbins < 1 || d.nbins > 256)
         return fail(TPCF_E_INVALID, "nbins must be in [1, 256]");
     if (!d.bin_edges_deg)
@@ -567,7 +614,12 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
     const double delta = delta_override >= 0 ? delta_override
                                              : (r->A->delta > r->B->delta ? r->A->delta : r->B->delta);
     TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, &r->cp));
-    TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, &r->plan));
+    const bool matrix = d.precision == TPCF_FP64_MATRIX;
+    if (matrix) {
+        TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->A)));
+        TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->B)));
+    }
+    TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, matrix, &r->plan));
     r->pairs = r->plan->pairs;
     r->cache_key.clear();
     if (d.kind == TPCF_RR)
@@ -591,13 +643,19 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
     j.bx64 = r.B->d64;
     j.by64 = r.B->d64 + nb;
     j.bz64 = r.B->d64 + 2 * nb;
+    j.apack = r.A->dpack;
+    j.bpack = r.B->dpack;
+    j.a_groups = (int32_t)((r.A->n + 15) / 16);
+    j.b_groups = (int32_t)((r.B->n + 15) / 16);
     j.hist = hist;
     j.cancel = cancel;
     j.auto_pairs = r.auto_pairs ? 1 : 0;
+    j.na = (int32_t)r.A->n;
+    j.nb = (int32_t)r.B->n;
     return j;
 }
 
-PairArgs args_of(const Compiled &cp, int nbins, unsigned long long *stats) {
+PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned long long *stats) {
     PairArgs a;
     memset(&a, 0, sizeof a);
     a.lut = cp.dlut.p;
@@ -609,10 +667,16 @@ PairArgs args_of(const Compiled &cp, int nbins, unsigned long long *stats) {
     a.qlo = (const float *)cp.dqlo.p;
     a.qhi = (const float *)cp.dqhi.p;
     a.E = (const double *)cp.dE.p;
+    a.Tlo = (const double *)cp.dTlo.p;
+    a.Thi = (const double *)cp.dThi.p;
     a.D = (const double *)cp.dD.p;
     a.nedges = nbins + 1;
     a.nslots = nbins + 2;
     a.hist_copies = hist_copies_for(nbins + 2);
+    if (ctx->tune.hist_copies > 0 && ctx->tune.hist_copies < a.hist_copies)
+        a.hist_copies = ctx->tune.hist_copies;
+    a.rows_per_lane = ctx->tune.rows_per_lane;
+    a.blocks_per_cu = ctx->tune.blocks_per_cu;
     a.stats = stats;
     return a;
 }
@@ -644,7 +708,7 @@ int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long
     TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * kGlobalCopies * kMaxSlots));
     unsigned long long *copies = (unsigned long long *)w.copies.p;
     HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots, w.stream));
-    PairArgs a = args_of(*r.cp, r.nbins, (unsigned long long *)w.stats.p);
+    PairArgs a = args_of(ctx, *r.cp, r.nbins, (unsigned long long *)w.stats.p);
     a.jobs = nullptr;
     a.job0 = job_of(r, copies, cancel);
     a.units = (const Unit *)r.plan->dunits.p;
@@ -654,7 +718,7 @@ int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long
         TRY(record_start(ctx, w.stream, &e0, &e1));
     else
         e0 = e1 = nullptr;
-    int lrc = tpcf_launch_pairs(&a, r.precision == TPCF_FP32_CHORD ? 0 : 1, w.stream);
+    int lrc = tpcf_launch_pairs(&a, r.precision, w.stream);
     if (lrc)
         return fail(TPCF_E_HIP, std::string("pair kernel launch: ") + hipGetErrorString((hipError_t)lrc));
     TRY(record_stop(ctx, w.stream, e0, e1));
@@ -766,6 +830,7 @@ int tpcf_close(tpcf_ctx *ctx) {
         if (kv.second.owns64)
             dev_free(ctx->mem, kv.second.d64, kv.second.bytes64);
         dev_free(ctx->mem, kv.second.d32, kv.second.bytes32);
+        dev_free(ctx->mem, kv.second.dpack, kv.second.bytes_pack);
     }
     for (auto &kv : ctx->compiled)
         free_compiled(ctx, *kv.second);
@@ -910,6 +975,7 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat) {
     if (it->second.owns64)
         dev_free(ctx->mem, it->second.d64, it->second.bytes64);
     dev_free(ctx->mem, it->second.d32, it->second.bytes32);
+    dev_free(ctx->mem, it->second.dpack, it->second.bytes_pack);
     ctx->cats.erase(it);
     return TPCF_OK;
 }
@@ -984,7 +1050,7 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
     for (int32_t k = 0; k < njobs; ++k)
         TRY(prepare(ctx, jobs[k], delta, &reqs[k]));
     const int nslots = nbins + 2;
-    const int prec = jobs[0].precision == TPCF_FP32_CHORD ? 0 : 1;
+    const int prec = jobs[0].precision;
     const size_t copies_bytes = sizeof(unsigned long long) * (size_t)njobs * kGlobalCopies * nslots;
     const size_t out_bytes = sizeof(unsigned long long) * (size_t)njobs * nslots;
     hipStream_t st = ctx->main.stream;
@@ -999,6 +1065,7 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
     }
     key.append((const char *)jobs[0].bin_edges_deg, sizeof(double) * (size_t)(nbins + 1));
     key.append((const char *)&delta, sizeof delta);
+    key.append((const char *)&ctx->tune, sizeof ctx->tune);
 
     BatchGraph *g = nullptr;
     std::unique_ptr<BatchGraph> fresh;
@@ -1030,7 +1097,7 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
             free_graph(ctx, *g);
             return rc;
         }
-        PairArgs a = args_of(*reqs[0].cp, nbins, (unsigned long long *)ctx->main.stats.p);
+        PairArgs a = args_of(ctx, *reqs[0].cp, nbins, (unsigned long long *)ctx->main.stats.p);
         a.jobs = (const JobDev *)g->jobs.p;
         a.units = (const Unit *)g->units.p;
         a.n_units = (int32_t)hu.size();
@@ -1193,6 +1260,40 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job) {
     return TPCF_OK;
 }
 
+int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, int32_t max_cols,
+                    int32_t blocks_per_cu) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    if (rows_per_lane != 0 && rows_per_lane != 2 && rows_per_lane != 4)
+        return fail(TPCF_E_INVALID, "rows_per_lane must be 0 (default), 2 or 4");
+    if (hist_copies != 0 && hist_copies != 4 && hist_copies != 8 && hist_copies != 16 && hist_copies != 32)
+        return fail(TPCF_E_INVALID, "hist_copies must be 0 (by bins), 4, 8, 16 or 32");
+    if (max_cols != 0 && (max_cols < 256 || max_cols > 65536 || max_cols % 256))
+        return fail(TPCF_E_INVALID, "max_cols must be 0 (default) or a multiple of 256 in [256, 65536]");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64)
+        return fail(TPCF_E_INVALID, "blocks_per_cu must be in [0, 64]");
+    Tuning t;
+    if (rows_per_lane)
+        t.rows_per_lane = rows_per_lane;
+    t.hist_copies = hist_copies;
+    if (max_cols)
+        t.max_cols = max_cols;
+    t.blocks_per_cu = blocks_per_cu;
+    ctx->tune = t;
+    return TPCF_OK;
+}
+
+int tpcf_get_tuning(tpcf_ctx *ctx, int32_t *rows_per_lane, int32_t *hist_copies, int32_t *max_cols,
+                    int32_t *blocks_per_cu) {
+    if (!ctx || !rows_per_lane || !hist_copies || !max_cols || !blocks_per_cu)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    *rows_per_lane = ctx->tune.rows_per_lane;
+    *hist_copies = ctx->tune.hist_copies;
+    *max_cols = ctx->tune.max_cols;
+    *blocks_per_cu = ctx->tune.blocks_per_cu;
+    return TPCF_OK;
+}
+
 int tpcf_set_hbm_budget(tpcf_ctx *ctx, int64_t bytes) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
@@ -1245,22 +1346,23 @@ int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int r
     return TPCF_OK;
 }
 
-int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact, int reset) {
+int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
+               uint64_t *out_rare_steps, int reset) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     TRY(set_device(ctx));
     TRY(sync_all(ctx));
-    unsigned long long tot[4] = {0, 0, 0, 0};
+    unsigned long long tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     std::vector<Workspace *> ws{&ctx->main};
     for (auto &w : ctx->pool)
         ws.push_back(&w);
     for (Workspace *w : ws) {
-        unsigned long long h[4] = {0, 0, 0, 0};
+        unsigned long long h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         HIP_TRY(hipMemcpy(h, w->stats.p, sizeof h, hipMemcpyDeviceToHost));
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 8; ++i)
             tot[i] += h[i];
         if (reset)
-            HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w->stats.p, 4, w->stream));
+            HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w->stats.p, 8, w->stream));
     }
     if (reset)
         TRY(sync_all(ctx));
@@ -1270,6 +1372,8 @@ int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64
         *out_flagged = tot[1];
     if (out_exact)
         *out_exact = tot[2];
+    if (out_rare_steps)
+        *out_rare_steps = tot[4];
     if (reset)
         ctx->pairs_since_reset = 0;
     return TPCF_OK;
@@ -1314,8 +1418,8 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
                        uint16_t *out_cells, double *out_E) {
     if (!out_shift || !out_lo || !out_hi || !out_cells)
         return fail(TPCF_E_INVALID, "NULL argument");
-    if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64)
-        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD or TPCF_FP64");
+    if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64 && precision != TPCF_FP64_MATRIX)
+        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX");
     if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
         return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
     if (max_cells < 16 || max_cells > kMaxLutCells)
@@ -1325,7 +1429,8 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
     if (!compile_edges(bin_edges_deg, nbins, &t, &err))
         return fail(TPCF_E_INVALID, err);
     CellTable c = precision == TPCF_FP32_CHORD ? make_cells32(t, make_band32(t, delta_max), delta_max, max_cells)
-                                               : make_cells64(t, max_cells);
+                  : precision == TPCF_FP64_MATRIX ? make_cells64_band(make_band64(t, kMatrixTau), max_cells)
+                                                   : make_cells64(t, max_cells);
     *out_shift = c.shift;
     *out_lo = c.lo;
     *out_hi = c.hi;
@@ -1333,6 +1438,21 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
     if (out_E)
         for (int k = 0; k <= nbins; ++k)
             out_E[k] = t.E[k];
+    return TPCF_OK;
+}
+
+int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_lo, double *out_hi) {
+    if (!out_lo || !out_hi)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges(bin_edges_deg, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    Band64 b = make_band64(t, kMatrixTau);
+    for (int k = 0; k <= nbins; ++k) {
+        out_lo[k] = b.lo[k];
+        out_hi[k] = b.hi[k];
+    }
     return TPCF_OK;
 }
 

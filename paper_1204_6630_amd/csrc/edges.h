@@ -21,6 +21,14 @@ struct Band32 {
     std::vector<float> qlo, qhi;
 };
 
+// FP64 band of every edge for e = 1 - d evaluated by the matrix cores (fused
+// products, unspecified summation order): e >= hi_k implies d <= D_k and
+// e < lo_k implies d > D_k for the counting rule's d.
+struct Band64 {
+    double tau = 0;
+    std::vector<double> lo, hi;
+};
+
 struct CellTable {
     int shift = 0;                  // cell = key >> shift
     int32_t lo = 0, hi = 0;         // clamp range of cells (inclusive)
@@ -41,5 +49,9 @@ Band32 make_band32(const EdgeTables &t, double delta);
 // e = fl(1 - d) read as a signed integer.
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
 CellTable make_cells64(const EdgeTables &t, int max_cells);
+
+Band64 make_band64(const EdgeTables &t, double tau);
+// Cells over the high word of e (as make_cells64) against a Band64.
+CellTable make_cells64_band(const Band64 &b, int max_cells);
 
 }  // namespace tpcf

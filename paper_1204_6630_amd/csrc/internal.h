@@ -30,12 +30,14 @@ constexpr uint16_t kMedium = 0x8000;
 constexpr uint16_t kMulti = 0xFFFF;
 constexpr int kMaxSlots8 = 127;
 
-// One work unit: rows i in [i0, i1) against columns j in [j0, j1) of job
-// `job`.  A unit needs per-pair masking when its row tile is cut short or,
-// for auto-pairs, when its columns overlap its rows (the j <= i diagonal).
+// One work unit: the row tile starting at i0 with valid rows [row_lo, i1),
+// against columns j in [j0, j1), of job `job`.  A unit needs per-pair masking
+// when its valid rows do not fill the tile, when j1 cuts a column group short
+// (matrix-core path), or, for auto-pairs, when its columns overlap its rows
+// (the j <= i diagonal).  Matrix-core units start i0 and j0 on multiples of 16.
 struct Unit {
     int32_t i0, i1, j0, j1;
-    int32_t job, pad0, pad1, pad2;
+    int32_t job, row_lo, pad1, pad2;
 };
 
 // One counting job of a launch: catalogs A (rows i) and B (columns j) as
@@ -45,9 +47,15 @@ struct JobDev {
     const float *bx32, *by32, *bz32;
     const double *ax64, *ay64, *az64;
     const double *bx64, *by64, *bz64;
+    // Matrix-core operands: groups of 16 points, 64 doubles per group in lane
+    // order (lane l holds component l / 16 of point 16 g + l % 16; component 3
+    // is 1), zero-padded to whole groups.
+    const double *apack, *bpack;
+    int32_t a_groups, b_groups;
     unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
     const int *cancel;           // host-visible flag (non-zero: skip the rest), or null
     int32_t auto_pairs;          // 1: DD/RR (count j > i only), 0: DR
+    int32_t na, nb;              // catalog sizes
     int32_t pad;
 };
 
@@ -67,21 +75,24 @@ struct PairArgs {
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
     const double *E;             // fl(1 - D_k), nedges
+    const double *Tlo, *Thi;     // matrix-core band of e = 1 - d, nedges each
     const double *D;             // D_k, nedges
     int32_t nedges;              // nbins + 1
     int32_t nslots;              // nbins + 2
 
     // Per-wave LDS histogram copies (layout [slot][copy]).
     int32_t hist_copies;         // 32, 16, 8 or 4
+    int32_t rows_per_lane;       // 2 or 4: a unit spans kWaves * 64 * rows_per_lane rows
+    int32_t blocks_per_cu;       // grid = CUs x this (0: resident blocks x 4)
 
-    unsigned long long *stats;   // [pairs, flagged, exact, skipped units]
+    unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps, -, -, -]
 };
 
 // LDS bytes used by one block for the given table sizes.
 inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_bytes, int nedges) {
     int hist = kWaves * (nslots + 1) * hist_copies * 4;      // +1: discard row
     int lut = ((lut_cells * lut_entry_bytes) + 15) & ~15;
-    int thr = nedges * (4 + 4 + 8 + 8);
+    int thr = nedges * (4 + 4 + 8 + 8 + 8 + 8);
     return hist + lut + thr;
 }
 
@@ -97,4 +108,6 @@ int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots, 
                               unsigned long long *out, void *stream);
 int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
                          double *maxdev_out, void *stream);
+// Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack).
+int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream);
 }

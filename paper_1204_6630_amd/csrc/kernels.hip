@@ -6,8 +6,8 @@
 // combined in one histogram in global memory.
 //
 // gfx950 design:
-//   * one work unit = a tile of rows i (four wavefronts, each holding
-//     kRowsPerLane points per lane in registers) against a range of columns
+//   * one work unit = a tile of rows i (four wavefronts, each holding P = 2
+//     or 4 points per lane in registers) against a range of columns
 //     j; every wavefront walks the same j range, reading each j through the
 //     scalar unit (the address is uniform), so no LDS staging of j is needed;
 //   * a pair is classified with one table lookup in LDS: the key is the top
@@ -35,8 +35,6 @@ using namespace tpcf;
 
 namespace {
 
-constexpr int kRowsPerLane = 4;
-constexpr int kRowsPerWave = kRowsPerLane * kWaveSize;
 constexpr int kColsPerStep = 2;
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
@@ -136,6 +134,7 @@ struct Smem {
     uint32_t *hist;      // kWaves x (nslots + 1) x copies
     double *D;
     double *E;
+    double *Tlo, *Thi;
     float *qlo;
     float *qhi;
     unsigned char *lut;
@@ -149,7 +148,9 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     s.hist = reinterpret_cast<uint32_t *>(base);
     s.D = reinterpret_cast<double *>(base + hist_words * 4);
     s.E = s.D + a.nedges;
-    s.qlo = reinterpret_cast<float *>(s.E + a.nedges);
+    s.Tlo = s.E + a.nedges;
+    s.Thi = s.Tlo + a.nedges;
+    s.qlo = reinterpret_cast<float *>(s.Thi + a.nedges);
     s.qhi = s.qlo + a.nedges;
     s.lut = reinterpret_cast<unsigned char *>(s.qhi + a.nedges);
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
@@ -224,6 +225,12 @@ __device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, double e, double 
     return count_le(d, s.D, a.nedges);
 }
 
+// Work statistics of one lane: pairs that left the table path, pairs decided
+// by the exact FP64 rule, and (wavefront-uniform) steps that took the rare path.
+struct Counters {
+    uint32_t flag = 0, exact = 0, rare = 0;
+};
+
 // Loop constants of one wavefront.
 struct Consts {
     uint32_t shift;
@@ -241,8 +248,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
                                           const int (&il)[P], int ie, int j, cfloat_p bx,
-                                          cfloat_p by, cfloat_p bz, uint32_t &n_flag,
-                                          uint32_t &n_exact) {
+                                          cfloat_p by, cfloat_p bz, Counters &cnt) {
     float xj[JN], yj[JN], zj[JN];
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
@@ -274,13 +280,14 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
     if (Code<LUT8>::any_flag(any)) {
+        ++cnt.rare;             // wavefront steps that took the rare path
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & Code<LUT8>::flag) {
-                    ++n_flag;
-                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, jb, il[p], j + t, n_exact);
+                    ++cnt.flag;
+                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, jb, il[p], j + t, cnt.exact);
                 }
     }
 #pragma unroll
@@ -301,7 +308,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie,
                                           int j, cdouble_p bx, cdouble_p by, cdouble_p bz,
-                                          uint32_t &n_flag, uint32_t &n_exact) {
+                                          Counters &cnt) {
     double xj[JN], yj[JN], zj[JN];
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
@@ -331,13 +338,14 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
     if (Code<LUT8>::any_flag(any)) {
+        ++cnt.rare;             // wavefront steps that took the rare path
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & Code<LUT8>::flag) {
-                    ++n_flag;
-                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], e[t][p], d[t][p], s, a, n_exact);
+                    ++cnt.flag;
+                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], e[t][p], d[t][p], s, a, cnt.exact);
                 }
     }
 #pragma unroll
@@ -356,7 +364,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
 template <bool LUT8, bool MASKED, int P>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
-                          int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
+                          int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
     int ii[P], il[P];
 #pragma unroll
@@ -374,14 +382,14 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
         step_fp32<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz,
-                                                 n_flag, n_exact);
+                                                 cnt);
     for (; j < j1; ++j)
-        step_fp32<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, n_flag, n_exact);
+        step_fp32<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, cnt);
 }
 
 template <bool LUT8, bool MASKED, int P>
 __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
-                          int j0, int j1, int lane, uint32_t &n_flag, uint32_t &n_exact) {
+                          int j0, int j1, int lane, Counters &cnt) {
     double xi[P], yi[P], zi[P];
     int ii[P];
 #pragma unroll
@@ -398,14 +406,111 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
     cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag,
-                                                 n_exact);
+        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
     for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, n_flag, n_exact);
+        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
 }
 
-template <int PREC, bool LUT8>
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Output layout of v_mfma_f64_16x16x4f64 (checked on the device by the
+// layout test): lane l holds rows 4 (l / 16) + r, r = 0..3, of column l % 16.
+// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+__device__ __forceinline__ int mma_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+__device__ __forceinline__ int mma_col(int lane) { return lane & 15; }
+
+template <bool LUT8>
+__device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, double e, const Smem &s,
+                                                const PairArgs &a, const JobDev &jb, int i, int j,
+                                                uint32_t &n_exact) {
+    if (ent != Code<LUT8>::multi) {
+        int k = (int)(ent & Code<LUT8>::kmask);
+        if (e < s.Tlo[k])
+            return (uint32_t)k;
+        if (e >= s.Thi[k])
+            return (uint32_t)(k + 1);
+        ++n_exact;
+        double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+        return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
+    }
+    ++n_exact;
+    double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+    return count_le(d, s.D, a.nedges);
+}
+
+// Matrix-core path, one wavefront: RG groups of 16 rows starting at ib
+// (valid rows [rlo, ie)) against the column groups of [j0, j1).  For every
+// 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
+// (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
+// then binned exactly as on the vector path, against the matrix-core band.
+template <bool LUT8, bool MASKED, int RG>
+__device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                         int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
+    double A[RG];
+    const int g0 = ib >> 4;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
+        const double v = jb.apack[(size_t)gg * 64 + lane];
+        A[g] = lane < 48 ? -v : v;
+    }
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    const int jg_end = (j1 + 15) >> 4;
+    for (int jg = j0 >> 4; jg < jg_end; ++jg) {
+        const double b = jb.bpack[(size_t)jg * 64 + lane];
+        v4d d[RG];
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
+        uint32_t ent[RG][4];
+        uint32_t any = 0;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int32_t c = med3_i32(__double2hiint(d[g][r]) >> (int)k.shift, (int32_t)k.clo,
+                                           (int32_t)k.chi);
+                ent[g][r] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
+            }
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                any |= ent[g][r];
+        if (Code<LUT8>::any_flag(any)) {
+            ++cnt.rare;
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (ent[g][r] & Code<LUT8>::flag) {
+                        ++cnt.flag;
+                        const int i = min(ib + 16 * g + mma_row(lane, r), jb.na - 1);
+                        const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
+                        ent[g][r] = resolve_mma<LUT8>(ent[g][r], d[g][r], s, a, jb, i, j, cnt.exact);
+                    }
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                uint32_t v = ent[g][r];
+                if (MASKED) {
+                    const int i = ib + 16 * g + mma_row(lane, r);
+                    const int j = 16 * jg + mma_col(lane);
+                    bool ok = i >= rlo && i < ie && j < j1 && (!jb.auto_pairs || j > i);
+                    v = ok ? v : (uint32_t)a.nslots;
+                }
+                lds_inc(__umul24(v, k.rowstep) + k.lanebase);
+            }
+    }
+}
+
+// P: rows per lane of the vector paths (a wavefront covers P * 64 rows of a
+// unit) or row groups of 16 of the matrix-core path (P * 16 rows).
+template <int PREC, bool LUT8, int P>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
+    constexpr int kRowsPerWave = PREC == 2 ? P * 16 : P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
     const int tid = threadIdx.x;
@@ -422,6 +527,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     for (int e = tid; e < a.nedges; e += kBlock) {
         s.D[e] = a.D[e];
         s.E[e] = a.E[e];
+        s.Tlo[e] = a.Tlo[e];
+        s.Thi[e] = a.Thi[e];
         s.qlo[e] = a.qlo[e];
         s.qhi[e] = a.qhi[e];
     }
@@ -435,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     k.rowstep = (uint32_t)a.hist_copies * 4u;
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
-    uint32_t n_flag = 0, n_exact = 0;
+    Counters cnt;
 
     uint32_t n_skip = 0;
     for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
@@ -449,24 +556,31 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                 continue;
             }
             const int ie = min(un.i1, ib + kRowsPerWave);
-            const bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie);
-            if (PREC == 0) {
+            const int rlo = max(un.row_lo, ib);
+            bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib;
+            if (PREC == 2) {
+                masked = masked || (un.j1 & 15) != 0;
                 if (masked)
-                    rows_fp32<LUT8, true, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_mma<LUT8, true, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp32<LUT8, false, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_mma<LUT8, false, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
+            } else if (PREC == 0) {
+                if (masked)
+                    rows_fp32<LUT8, true, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                else
+                    rows_fp32<LUT8, false, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             } else {
                 if (masked)
-                    rows_fp64<LUT8, true, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp64<LUT8, true, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp64<LUT8, false, kRowsPerLane>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, n_flag, n_exact);
+                    rows_fp64<LUT8, false, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             }
             // the wave's own LDS region only: no block barrier needed
             flush_wave(a, s, jb.hist, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
         }
     }
-    uint32_t f = wave_sum(n_flag);
-    uint32_t x = wave_sum(n_exact);
+    uint32_t f = wave_sum(cnt.flag);
+    uint32_t x = wave_sum(cnt.exact);
     if (lane == 0) {
         if (f)
             atomicAdd(&a.stats[1], (unsigned long long)f);
@@ -474,6 +588,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[2], (unsigned long long)x);
         if (n_skip)
             atomicAdd(&a.stats[3], (unsigned long long)n_skip);
+        if (cnt.rare)
+            atomicAdd(&a.stats[4], (unsigned long long)cnt.rare);
     }
 }
 
@@ -527,7 +643,23 @@ __global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsign
         atomicMax(maxdev, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-int grid_for(int n_units, int lds) {
+// Matrix-core operand pack: pack[64 g + l] = component l / 16 of point
+// 16 g + l % 16 (component 3 is 1), zero past the end of the catalog.
+__global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_t total) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = idx >> 6;
+        const int l = (int)(idx & 63);
+        const int64_t p = 16 * g + (l & 15);
+        const int c = l >> 4;
+        double v = 0.0;
+        if (p < n)
+            v = c < 3 ? xyz[(int64_t)c * n + p] : 1.0;
+        pack[idx] = v;
+    }
+}
+
+int grid_for(int n_units, int lds, int blocks_per_cu) {
     static int cus = 0, lds_per_cu = 0;
     if (!cus) {
         int dev = 0;
@@ -547,7 +679,8 @@ int grid_for(int n_units, int lds) {
         per_cu = 1;
     if (per_cu > 8)
         per_cu = 8;
-    long long g = (long long)cus * per_cu * 4;
+    // resident blocks x 4 by default; blocks_per_cu > 0 overrides
+    long long g = blocks_per_cu > 0 ? (long long)cus * blocks_per_cu : (long long)cus * per_cu * 4;
     if (g > n_units)
         g = n_units;
     if (g < 1)
@@ -562,20 +695,48 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
         return 0;
     const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->lut_entry_bytes,
                               args->nedges);
-    const int grid = grid_for(args->n_units, lds);
+    const int grid = grid_for(args->n_units, lds, args->blocks_per_cu);
     hipStream_t st = (hipStream_t)stream;
     const bool b8 = args->lut_entry_bytes == 1;
+    const int P = args->rows_per_lane;
+#define TPCF_LAUNCH(PR, B8, PP) \
+    hipLaunchKernelGGL((pairs_kernel<PR, B8, PP>), dim3(grid), dim3(kBlock), lds, st, *args)
+    if (P != 2 && P != 4)
+        return (int)hipErrorInvalidValue;
     if (precision == 0) {
-        if (b8)
-            hipLaunchKernelGGL((pairs_kernel<0, true>), dim3(grid), dim3(kBlock), lds, st, *args);
-        else
-            hipLaunchKernelGGL((pairs_kernel<0, false>), dim3(grid), dim3(kBlock), lds, st, *args);
+        if (b8) {
+            if (P == 2) TPCF_LAUNCH(0, true, 2); else TPCF_LAUNCH(0, true, 4);
+        } else {
+            if (P == 2) TPCF_LAUNCH(0, false, 2); else TPCF_LAUNCH(0, false, 4);
+        }
+    } else if (precision == 1) {
+        if (b8) {
+            if (P == 2) TPCF_LAUNCH(1, true, 2); else TPCF_LAUNCH(1, true, 4);
+        } else {
+            if (P == 2) TPCF_LAUNCH(1, false, 2); else TPCF_LAUNCH(1, false, 4);
+        }
+    } else if (precision == 2) {
+        if (b8) {
+            if (P == 2) TPCF_LAUNCH(2, true, 2); else TPCF_LAUNCH(2, true, 4);
+        } else {
+            if (P == 2) TPCF_LAUNCH(2, false, 2); else TPCF_LAUNCH(2, false, 4);
+        }
     } else {
-        if (b8)
-            hipLaunchKernelGGL((pairs_kernel<1, true>), dim3(grid), dim3(kBlock), lds, st, *args);
-        else
-            hipLaunchKernelGGL((pairs_kernel<1, false>), dim3(grid), dim3(kBlock), lds, st, *args);
+        return (int)hipErrorInvalidValue;
     }
+#undef TPCF_LAUNCH
+    return (int)hipGetLastError();
+}
+
+extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream) {
+    const int64_t total = ((n + 15) / 16) * 64;
+    if (total <= 0)
+        return 0;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(pack16_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
+                       pack, total);
     return (int)hipGetLastError();
 }
 

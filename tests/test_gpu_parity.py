@@ -18,7 +18,7 @@ import synthcat
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [tp.FP32_CHORD, tp.FP64]
+PRECS = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
 _cache = {}
 
 
@@ -197,8 +197,9 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
         assert int(dr.sum()) == d.n * r.n
         assert int(rr.sum()) == r.n * (r.n - 1) // 2
         full[prec] = (dd, dr, rr)
-    for a, b in zip(full[tp.FP32_CHORD], full[tp.FP64]):
-        assert np.array_equal(a, b)
+    for p in PRECS[1:]:
+        for a, b in zip(full[PRECS[0]], full[p]):
+            assert np.array_equal(a, b), p
     xd, xr = _stored(ctx, cd, _xyz(d)), _stored(ctx, cr, _xyz(r))
     size = 200 if cfg == 2 else 150
     for rb, re in _sample_blocks(d.n, 2, size, 11 + cfg):
@@ -259,10 +260,11 @@ def test_timing_and_stats(ctx, cfg1):
     ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
     ms, n = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    pairs, flagged, exact = ctx.stats(reset=True)
+    pairs, flagged, exact, rare = ctx.stats(reset=True)
     assert n == 1 and ms > 0
     assert pairs == wl.data[0].n * wl.randoms[0].n
     assert exact <= flagged <= pairs
+    assert rare <= flagged
     assert flagged < 0.2 * pairs
 
 
@@ -299,3 +301,36 @@ def test_gpu_error_paths(ctx, cfg1):
     with pytest.raises(tp.TpcfError) as ei:
         ctx.release_catalog(9999)
     assert ei.value.code == -4
+
+
+def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
+    """Race detector: every tuning choice (rows per lane, histogram copies,
+    unit width, grid size) gives bit-identical counts."""
+    wl, cd, cr, ref = cfg1
+    e = wl.edges_deg
+    try:
+        for rpl in (2, 4):
+            for hc in (32, 16, 8, 4):
+                for mc, bpc in ((256, 1), (16384, 0), (4096, 3)):
+                    ctx.set_tuning(rows_per_lane=rpl, hist_copies=hc, max_cols=mc, blocks_per_cu=bpc)
+                    for prec in PRECS:
+                        assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), ref["DD"])
+                        assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
+                                              ref["DR"])
+    finally:
+        ctx.set_tuning()
+
+
+def test_autotuner_picks_a_candidate(ctx, cfg1, tmp_path, monkeypatch):
+    from paper_1204_6630_amd.autotune import CANDIDATES, autotune
+    monkeypatch.setenv("TPCF_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    wl, cd, cr, ref = cfg1
+    try:
+        res = autotune(ctx, [(tp.DR, cd, cr, 0, 2048)], wl.edges_deg, tp.FP32_CHORD)
+        assert not res["cached"]
+        assert all(res["tuning"][k] in v for k, v in CANDIDATES.items())
+        again = autotune(ctx, [(tp.DR, cd, cr, 0, 2048)], wl.edges_deg, tp.FP32_CHORD)
+        assert again["cached"] and again["tuning"] == res["tuning"]
+        assert np.array_equal(ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr), ref["DR"])
+    finally:
+        ctx.set_tuning()

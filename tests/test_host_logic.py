@@ -274,3 +274,56 @@ def test_open_without_gpu_fails_cleanly():
         pytest.skip("a GPU is present")
     with pytest.raises(tp.TpcfError):
         tp.Context(0)
+
+
+@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
+                                   np.array([0.0, 1e-5, 0.5, 60.0, 90.0, 120.0, 179.0, 180.0])])
+def test_matrix_band_is_safe_for_any_rounding(edges):
+    """The matrix-core band: whatever order or fusion the matrix cores use,
+    their e is within ~2e-15 of 1 - d.  Pairs at theta = e_k (1 +- 10^-s) get
+    e = 1 - d (rounded up, down, or moved by up to 2e-15 either way); every
+    decision the band calls certain must equal the oracle's."""
+    g = np.random.default_rng(11)
+    lo, hi = tp.compile_band64(edges)
+    er = edges * DEG
+    thetas = []
+    for e in er:
+        if 0.0 < e < math.pi:
+            for s in range(6, 16):
+                for sign in (-1.0, 1.0):
+                    thetas.append(np.full(20, e * (1.0 + sign * 10.0 ** -s)))
+    theta = np.clip(np.concatenate(thetas), 0.0, math.pi)
+    a, b = _pairs_at(g, theta)
+    d = _dot64(a, b)
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    base = 1.0 - d
+    for shift in (-2e-15, -1e-15, 0.0, 1e-15, 2e-15):
+        e = base + shift
+        for k in range(edges.size):
+            past = truth >= k + 1
+            assert np.all(past[e >= hi[k]]), (k, shift)
+            assert not np.any(past[e < lo[k]]), (k, shift)
+    # the band is narrow: a few times 2^-48 around 1 - D_k
+    D, _, _ = tp.compile_edges(edges)
+    fin = np.isfinite(D)
+    assert np.all(hi[fin] - lo[fin] < 2 ** -45)
+
+
+def test_matrix_cells_are_consistent_with_the_band():
+    edges = synthcat.log_edges(0.0005, 30.0, 40)
+    lo, hi = tp.compile_band64(edges)
+    shift, clo, chi, cells, _ = tp.compile_cells(edges, tp.FP64_MATRIX)
+    g = np.random.default_rng(12)
+    # e values spread over the whole range in log space, plus the band edges
+    e = np.concatenate([10.0 ** g.uniform(-12, 0.3, 200000), lo[np.isfinite(lo)], hi[np.isfinite(hi)],
+                        np.nextafter(lo[np.isfinite(lo)], -1), np.nextafter(hi[np.isfinite(hi)], 3)])
+    key = (e.view(np.uint64) >> np.uint64(32)).astype(np.uint32).view(np.int32).astype(np.int64) >> shift
+    ent = cells[np.clip(key, clo, chi) - clo].astype(np.int64)
+    certain = ent < 0x8000
+    smin = np.array([np.sum(x >= hi) for x in e])
+    smax = np.array([np.sum(x >= lo) for x in e])
+    assert np.all(ent[certain] == smin[certain])
+    assert np.all(smin[certain] == smax[certain])
+    med = (ent >= 0x8000) & (ent != 0xFFFF)
+    k = ent[med] & 0x7FFF
+    assert np.all(smin[med] >= k) and np.all(smax[med] <= k + 1)
