@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0,
                     help="catalog size factor (1.0 = the full workload)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-matrix", action="store_true", help="skip the FP64 matrix-core path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -282,6 +283,12 @@ def main():
         print(f"# fp64: {args.steps} steps in {f64['s']:.3f} s", file=sys.stderr, flush=True)
         if not all(np.array_equal(a, b) for a, b in zip(f32["hist"], f64["hist"])):
             sys.exit("FP32-chord and FP64 histograms differ")
+    fmx = None
+    if not args.no_matrix:
+        fmx = run(tp.FP64_MATRIX, args.steps, args.warmup)
+        print(f"# fp64-matrix: {args.steps} steps in {fmx['s']:.3f} s", file=sys.stderr, flush=True)
+        if not all(np.array_equal(a, b) for a, b in zip(f32["hist"], fmx["hist"])):
+            sys.exit("FP32-chord and FP64-matrix histograms differ")
     if not f32["totals_ok"]:
         sys.exit("slot totals do not match the pair counts")
 
@@ -324,6 +331,13 @@ def main():
                        "flagged_rate": f64["flagged"] / max(1, f64["pairs"]),
                        "exact_rate": f64["exact"] / max(1, f64["pairs"])}
         res["fp32_over_fp64"] = round(value / v64, 3)
+    if fmx is not None:
+        vmx = pairs_step * args.steps / fmx["s"] / 1e9
+        kmx = pairs_step * args.steps / (fmx["kernel_ms"] / 1e3) / 1e9
+        res["fp64_matrix"] = {"gpairs_s": round(vmx, 2), "kernel_gpairs_s": round(kmx, 1),
+                              "ms_per_step": round(fmx["s"] / args.steps * 1e3, 3),
+                              "flagged_rate": fmx["flagged"] / max(1, fmx["pairs"]),
+                              "exact_rate": fmx["exact"] / max(1, fmx["pairs"])}
     if not args.no_cpu_baseline:
         import oracle
         xd = oracle.radec_to_xyz(d.ra, d.dec)

@@ -413,10 +413,11 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Output layout of v_mfma_f64_16x16x4f64 (checked on the device by the
-// layout test): lane l holds rows 4 (l / 16) + r, r = 0..3, of column l % 16.
-// Operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
-__device__ __forceinline__ int mma_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+// Layout of v_mfma_f64_16x16x4f64 on gfx950 (measured with one-hot operands):
+// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; output register r of
+// lane l is D[l / 16 + 4 r][l % 16].  The diagonal masking and the exact
+// re-decision depend on it, so the parity tests check it.
+__device__ __forceinline__ int mma_row(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ __forceinline__ int mma_col(int lane) { return lane & 15; }
 
 template <bool LUT8>
