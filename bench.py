@@ -5,8 +5,9 @@ One step = the whole hot path over the large single-GPU workload (1e6
 clustered data points, 2e6 uniform randoms over the octant, 40 log bins over
 [0.0005, 30] deg): DD, DR and RR histograms on the GPU, copied to the host,
 then Landy-Szalay w(theta).  Catalogs are resident in HBM before the timed
-region starts.  The FP32-chord path is the headline value; the all-FP64 path
-is timed beside it.  Prints one JSON line.
+region starts.  The three exact paths (FP32 chord, FP64 vector, FP64 matrix
+cores) are each tuned on a sample, timed and checked against each other; the
+fastest is the headline value.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -26,6 +27,13 @@ METRIC = "exact-count Gpairs/s, FP32-chord vs FP64 path; p50/p99 job latency"
 # issue slots per second, 4 slots per pair (chord^2 as packed FP32 plus one
 # for the bin decision) -> 9.83e12 pairs/s.
 PEAK_GPAIRS = 256 * 64 * 2.4e9 / 4 / 1e9
+# FP64 matrix-core path: MI355X dense FP64 MFMA peak, and the algorithmic
+# flops of one pair (three products, two sums for the dot, one for 1 - d).
+PEAK_FP64_TFLOPS = 78.6
+FLOPS_PER_PAIR = 6
+PATH_NAMES = {0: "fp32_chord", 1: "fp64", 2: "fp64_matrix"}
+KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)",
+                2: "pairs_kernel<2> (FP64 matrix cores)"}
 
 
 def parse():
@@ -236,14 +244,18 @@ def main():
     cd = ctx.upload_catalog(d.ra, d.dec)
     cr = ctx.upload_catalog(r.ra, r.dec)
     out = torch.zeros((3, nslots), dtype=torch.int64, device=dev)
-    tuning = None
-    if not args.no_autotune:
+    rows = min(nd, 32768)
+    tune_sample = [(tp.DR, cd, cr, 0, rows), (tp.DD, cd, -1, 0, rows)]
+
+    def tune(prec):
+        if args.no_autotune:
+            ctx.set_tuning()
+            return None
         from paper_1204_6630_amd.autotune import autotune
-        rows = min(nd, 32768)
-        sample = [(tp.DR, cd, cr, 0, rows), (tp.DD, cd, -1, 0, rows)]
-        tuning = autotune(ctx, sample, edges, tp.FP32_CHORD)
-        print(f"# tuning: {tuning['tuning']} (cached: {tuning['cached']})", file=sys.stderr,
-              flush=True)
+        t = autotune(ctx, tune_sample, edges, prec)
+        print(f"# tuning {PATH_NAMES[prec]}: {t['tuning']} (cached: {t['cached']})",
+              file=sys.stderr, flush=True)
+        return t["tuning"]
 
     def step(prec):
         ctx.count_async(tp.DD, cd, edges, out[0].data_ptr(), precision=prec)
@@ -254,6 +266,7 @@ def main():
         return h, w
 
     def run(prec, k, w):
+        tuning = tune(prec)
         for _ in range(w):
             h, _ = step(prec)
         torch.cuda.synchronize()
@@ -270,74 +283,79 @@ def main():
         pairs, flagged, exact, rare = ctx.stats(reset=True)
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
+        rows_per_step = ctx.get_tuning()["rows_per_lane"] * (16 if prec == tp.FP64_MATRIX else 64)
+        cols_per_step = 16 if prec == tp.FP64_MATRIX else 2
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
-                "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare}
+                "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,
+                "tuning": tuning, "pairs_per_wave_step": rows_per_step * cols_per_step}
 
     print(f"# workload {wl.name}: N_D={nd} N_R={nr} nbins={edges.size - 1} "
           f"pairs/step={pairs_step:.4e}", file=sys.stderr, flush=True)
-    f32 = run(tp.FP32_CHORD, args.steps, args.warmup)
-    print(f"# fp32-chord: {args.steps} steps in {f32['s']:.3f} s", file=sys.stderr, flush=True)
-    f64 = None
+    paths = [tp.FP32_CHORD]
     if not args.no_fp64:
-        f64 = run(tp.FP64, args.steps, args.warmup)
-        print(f"# fp64: {args.steps} steps in {f64['s']:.3f} s", file=sys.stderr, flush=True)
-        if not all(np.array_equal(a, b) for a, b in zip(f32["hist"], f64["hist"])):
-            sys.exit("FP32-chord and FP64 histograms differ")
-    fmx = None
+        paths.append(tp.FP64)
     if not args.no_matrix:
-        fmx = run(tp.FP64_MATRIX, args.steps, args.warmup)
-        print(f"# fp64-matrix: {args.steps} steps in {fmx['s']:.3f} s", file=sys.stderr, flush=True)
-        if not all(np.array_equal(a, b) for a, b in zip(f32["hist"], fmx["hist"])):
-            sys.exit("FP32-chord and FP64-matrix histograms differ")
-    if not f32["totals_ok"]:
-        sys.exit("slot totals do not match the pair counts")
+        paths.append(tp.FP64_MATRIX)
+    runs = {}
+    for prec in paths:
+        runs[prec] = run(prec, args.steps, args.warmup)
+        print(f"# {PATH_NAMES[prec]}: {args.steps} steps in {runs[prec]['s']:.3f} s",
+              file=sys.stderr, flush=True)
+        if not runs[prec]["totals_ok"]:
+            sys.exit(f"{PATH_NAMES[prec]}: slot totals do not match the pair counts")
+        if not all(np.array_equal(a, b) for a, b in zip(runs[paths[0]]["hist"], runs[prec]["hist"])):
+            sys.exit(f"{PATH_NAMES[paths[0]]} and {PATH_NAMES[prec]} histograms differ")
 
-    ms_step = f32["s"] / args.steps * 1e3
-    value = pairs_step * args.steps / f32["s"] / 1e9
-    k_gpairs = pairs_step * args.steps / (f32["kernel_ms"] / 1e3) / 1e9
+    def summary(prec):
+        r = runs[prec]
+        v = pairs_step * args.steps / r["s"] / 1e9
+        kv = pairs_step * args.steps / (r["kernel_ms"] / 1e3) / 1e9
+        return {"gpairs_s": round(v, 2), "kernel_gpairs_s": round(kv, 1),
+                "ms_per_step": round(r["s"] / args.steps * 1e3, 3),
+                "kernel_ms_per_launch": round(r["kernel_ms"] / max(1, r["launches"]), 3),
+                "tuning": r["tuning"],
+                "flagged_rate": r["flagged"] / max(1, r["pairs"]),
+                "exact_rate": r["exact"] / max(1, r["pairs"]),
+                "rare_step_rate": r["rare"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
+
+    sums = {prec: summary(prec) for prec in paths}
+    head = max(paths, key=lambda p: sums[p]["gpairs_s"])
+    hs = sums[head]
+    kg = hs["kernel_gpairs_s"]
+    if head == tp.FP64_MATRIX:
+        achieved = kg * 1e9 * FLOPS_PER_PAIR / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "flops_per_pair": FLOPS_PER_PAIR}
+    else:
+        roof = {"bound": "alu", "achieved": round(kg, 1), "peak": round(PEAK_GPAIRS, 1),
+                "unit": "Gpairs/s", "frac": round(kg / PEAK_GPAIRS, 4)}
+    roof.update({"traffic": None, "kernel": KERNEL_NAMES[head],
+                 "kernel_ms_per_launch": hs["kernel_ms_per_launch"]})
     res = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": hs["gpairs_s"],
         "unit": "Gpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": hs["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64" if head != tp.FP32_CHORD else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_d": nd, "n_r": nr, "nbins": int(edges.size - 1),
                    "theta_deg": [float(edges[0]), float(edges[-1])],
                    "pairs_per_step": pairs_step, "kinds": "DD+DR+RR+LS",
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "alu", "achieved": round(k_gpairs, 1), "peak": round(PEAK_GPAIRS, 1),
-                     "unit": "Gpairs/s", "frac": round(k_gpairs / PEAK_GPAIRS, 4),
-                     "traffic": None, "kernel": "pairs_kernel<0> (FP32 chord)",
-                     "kernel_ms_per_launch": round(f32["kernel_ms"] / max(1, f32["launches"]), 3)},
-        "tuning": tuning["tuning"] if tuning else None,
-        "fp32_chord": {"gpairs_s": round(value, 2), "kernel_gpairs_s": round(k_gpairs, 1),
-                       "flagged_rate": f32["flagged"] / max(1, f32["pairs"]),
-                       "recheck_rate": f32["exact"] / max(1, f32["pairs"]),
-                       "rare_step_rate": f32["rare"] * 64 * 2 * ctx.get_tuning()["rows_per_lane"]
-                       / max(1, f32["pairs"])},
+        "headline_path": PATH_NAMES[head],
+        "roofline": roof,
     }
-    if f64 is not None:
-        v64 = pairs_step * args.steps / f64["s"] / 1e9
-        k64 = pairs_step * args.steps / (f64["kernel_ms"] / 1e3) / 1e9
-        res["fp64"] = {"gpairs_s": round(v64, 2), "kernel_gpairs_s": round(k64, 1),
-                       "ms_per_step": round(f64["s"] / args.steps * 1e3, 3),
-                       "flagged_rate": f64["flagged"] / max(1, f64["pairs"]),
-                       "exact_rate": f64["exact"] / max(1, f64["pairs"])}
-        res["fp32_over_fp64"] = round(value / v64, 3)
-    if fmx is not None:
-        vmx = pairs_step * args.steps / fmx["s"] / 1e9
-        kmx = pairs_step * args.steps / (fmx["kernel_ms"] / 1e3) / 1e9
-        res["fp64_matrix"] = {"gpairs_s": round(vmx, 2), "kernel_gpairs_s": round(kmx, 1),
-                              "ms_per_step": round(fmx["s"] / args.steps * 1e3, 3),
-                              "flagged_rate": fmx["flagged"] / max(1, fmx["pairs"]),
-                              "exact_rate": fmx["exact"] / max(1, fmx["pairs"])}
+    for prec in paths:
+        res[PATH_NAMES[prec]] = sums[prec]
+    if tp.FP64 in sums:
+        res["fp32_over_fp64"] = round(sums[tp.FP32_CHORD]["gpairs_s"] / sums[tp.FP64]["gpairs_s"], 3)
     if not args.no_cpu_baseline:
         import oracle
         xd = oracle.radec_to_xyz(d.ra, d.dec)

@@ -46,6 +46,7 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef const __attribute__((address_space(4))) float *cfloat_p;
 typedef const __attribute__((address_space(4))) double *cdouble_p;
 typedef const __attribute__((address_space(4))) uint32_t *cword_p;
+typedef const __attribute__((address_space(1))) double *gdouble_p;
 
 // Unit and job descriptors are read-only and wavefront-uniform as well: copy
 // them word by word through the constant address space (scalar loads).
@@ -95,15 +96,15 @@ __device__ __forceinline__ void lds_inc(uint32_t addr) {
     __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Cell entry codes: a slot (certain for the whole cell), flag | k (edge k
+// undecided), or flag | kmask (several edges undecided).  Every test of an
+// entry takes the flag bit from a register (Consts::flag): with literal masks
+// the compiler narrows the tests to 8 or 16 bits and then spends an extra
+// instruction per entry to widen the loaded value again.
 template <bool LUT8>
 struct Code {
     static constexpr uint32_t flag = LUT8 ? 0x80u : 0x8000u;
-    static constexpr uint32_t multi = LUT8 ? 0xFFu : 0xFFFFu;
     static constexpr uint32_t kmask = LUT8 ? 0x7Fu : 0x7FFFu;
-    // true if any entry OR-ed into `any` carries the flag bit
-    __device__ static bool any_flag(uint32_t any) {
-        return LUT8 ? ((int8_t)any < 0) : ((int16_t)any < 0);
-    }
 };
 
 // Number of k with d <= D[k]; D is non-increasing in k.
@@ -189,11 +190,11 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long 
 }
 
 template <bool LUT8>
-__device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Smem &s,
+__device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, uint32_t flag, float q, const Smem &s,
                                                  const PairArgs &a, const JobDev &jb, int i, int j,
                                                  uint32_t &n_exact) {
-    if (ent != Code<LUT8>::multi) {
-        int k = (int)(ent & Code<LUT8>::kmask);
+    if (ent != (flag | Code<LUT8>::kmask)) {
+        int k = (int)(ent ^ flag);
         if (q < s.qlo[k])
             return (uint32_t)k;
         if (q >= s.qhi[k])
@@ -208,11 +209,11 @@ __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, float q, const Sm
 }
 
 template <bool LUT8>
-__device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, double e, double d,
+__device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, uint32_t flag, double e, double d,
                                                  const Smem &s, const PairArgs &a,
                                                  uint32_t &n_exact) {
-    if (ent != Code<LUT8>::multi) {
-        int k = (int)(ent & Code<LUT8>::kmask);
+    if (ent != (flag | Code<LUT8>::kmask)) {
+        int k = (int)(ent ^ flag);
         double Ek = s.E[k];
         if (e > Ek)
             return (uint32_t)(k + 1);
@@ -238,6 +239,7 @@ struct Consts {
     uint32_t lutbias;       // LDS address of cell c is c * entry_bytes + lutbias
     uint32_t rowstep;       // bytes between slots of the histogram
     uint32_t lanebase;      // LDS address of this lane's copy of slot 0
+    uint32_t flag;          // flag bit of the cell entries (VGPR copy)
 };
 
 // One step: JN columns against the P rows of every lane.  All JN * P table
@@ -279,15 +281,15 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
-    if (Code<LUT8>::any_flag(any)) {
+    if (any & k.flag) {
         ++cnt.rare;             // wavefront steps that took the rare path
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                if (ent[t][p] & Code<LUT8>::flag) {
+                if (ent[t][p] & k.flag) {
                     ++cnt.flag;
-                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], q[t][p], s, a, jb, il[p], j + t, cnt.exact);
+                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], k.flag, q[t][p], s, a, jb, il[p], j + t, cnt.exact);
                 }
     }
 #pragma unroll
@@ -337,15 +339,15 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
         for (int p = 0; p < P; ++p)
             any |= ent[t][p];
-    if (Code<LUT8>::any_flag(any)) {
+    if (any & k.flag) {
         ++cnt.rare;             // wavefront steps that took the rare path
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                if (ent[t][p] & Code<LUT8>::flag) {
+                if (ent[t][p] & k.flag) {
                     ++cnt.flag;
-                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], e[t][p], d[t][p], s, a, cnt.exact);
+                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], k.flag, e[t][p], d[t][p], s, a, cnt.exact);
                 }
     }
 #pragma unroll
@@ -421,11 +423,11 @@ __device__ __forceinline__ int mma_row(int lane, int r) { return (lane >> 4) + 4
 __device__ __forceinline__ int mma_col(int lane) { return lane & 15; }
 
 template <bool LUT8>
-__device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, double e, const Smem &s,
+__device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, double e, const Smem &s,
                                                 const PairArgs &a, const JobDev &jb, int i, int j,
                                                 uint32_t &n_exact) {
-    if (ent != Code<LUT8>::multi) {
-        int k = (int)(ent & Code<LUT8>::kmask);
+    if (ent != (flag | Code<LUT8>::kmask)) {
+        int k = (int)(ent ^ flag);
         if (e < s.Tlo[k])
             return (uint32_t)k;
         if (e >= s.Thi[k])
@@ -447,18 +449,27 @@ __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, double e, const Sm
 template <bool LUT8, bool MASKED, int RG>
 __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                          int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
+    const gdouble_p ap = (gdouble_p)jb.apack + lane;
+    const gdouble_p bp = (gdouble_p)jb.bpack + lane;
     double A[RG];
     const int g0 = ib >> 4;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
-        const double v = jb.apack[(size_t)gg * 64 + lane];
+        const double v = ap[(size_t)gg * 64];
         A[g] = lane < 48 ? -v : v;
     }
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     const int jg_end = (j1 + 15) >> 4;
+    const int jg_last = jb.b_groups - 1;
+    // column operands are fetched two groups ahead (clamped to the last group
+    // of the catalog, so the reads never leave it)
+    double b_next = bp[(size_t)min(j0 >> 4, jg_last) * 64];
+    double b_next2 = bp[(size_t)min((j0 >> 4) + 1, jg_last) * 64];
     for (int jg = j0 >> 4; jg < jg_end; ++jg) {
-        const double b = jb.bpack[(size_t)jg * 64 + lane];
+        const double b = b_next;
+        b_next = b_next2;
+        b_next2 = bp[(size_t)min(jg + 2, jg_last) * 64];
         v4d d[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g)
@@ -478,17 +489,17 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 any |= ent[g][r];
-        if (Code<LUT8>::any_flag(any)) {
+        if (any & k.flag) {
             ++cnt.rare;
 #pragma unroll
             for (int g = 0; g < RG; ++g)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (ent[g][r] & Code<LUT8>::flag) {
+                    if (ent[g][r] & k.flag) {
                         ++cnt.flag;
                         const int i = min(ib + 16 * g + mma_row(lane, r), jb.na - 1);
                         const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
-                        ent[g][r] = resolve_mma<LUT8>(ent[g][r], d[g][r], s, a, jb, i, j, cnt.exact);
+                        ent[g][r] = resolve_mma<LUT8>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
                     }
         }
 #pragma unroll
@@ -541,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     k.chi = to_vgpr((uint32_t)a.lut_hi);
     k.lutbias = s.lut_addr - (uint32_t)a.lut_lo * (LUT8 ? 1u : 2u);
     k.rowstep = (uint32_t)a.hist_copies * 4u;
+    k.flag = to_vgpr(Code<LUT8>::flag);
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     Counters cnt;
