@@ -43,8 +43,9 @@ def parse():
                     help="octant: 1e6 x 2e6 DD+DR+RR (default); batched: 64 uneven catalogs "
                          "against one 1e6 random in one launch; serving: Poisson job stream")
     ap.add_argument("--jobs", type=int, default=300, help="serving: number of jobs")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shape instead of tuning on a sample")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune each path's launch shape on a sample first (default: the "
+                         "library's defaults, which are the tuned shapes for this workload)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0,
@@ -120,6 +121,7 @@ def bench_batched(args, tp, torch):
     for _ in range(args.steps):
         for k, (kind, a, b) in enumerate(jobs):
             ctx.count_async(kind, a, e, out[k].data_ptr(), cat_b=b)
+        ctx.synchronize()       # the library's stream, not torch's
         sep = out.cpu().numpy().astype(np.uint64)
     t3 = time.perf_counter()
     if not np.array_equal(sep, ref):
@@ -239,16 +241,16 @@ def main():
     nslots = edges.size + 1
     pairs_step = nd * (nd - 1) // 2 + nd * nr + nr * (nr - 1) // 2
 
-    stream = torch.cuda.current_stream(dev)
-    ctx = tp.Context(0, stream=stream.cuda_stream)
+    ctx = tp.Context(0)
     cd = ctx.upload_catalog(d.ra, d.dec)
     cr = ctx.upload_catalog(r.ra, r.dec)
     out = torch.zeros((3, nslots), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()    # torch's stream is not the context's
     rows = min(nd, 32768)
     tune_sample = [(tp.DR, cd, cr, 0, rows), (tp.DD, cd, -1, 0, rows)]
 
     def tune(prec):
-        if args.no_autotune:
+        if not args.autotune:
             ctx.set_tuning()
             return None
         from paper_1204_6630_amd.autotune import autotune
@@ -261,6 +263,7 @@ def main():
         ctx.count_async(tp.DD, cd, edges, out[0].data_ptr(), precision=prec)
         ctx.count_async(tp.DR, cd, edges, out[1].data_ptr(), cat_b=cr, precision=prec)
         ctx.count_async(tp.RR, cr, edges, out[2].data_ptr(), precision=prec)
+        ctx.synchronize()       # the context's own stream, not torch's
         h = out.cpu().numpy().astype(np.uint64)
         w = tp.landy_szalay(h[0], h[1], h[2], nd, nr)
         return h, w
@@ -283,7 +286,12 @@ def main():
         pairs, flagged, exact, rare = ctx.stats(reset=True)
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
-        rows_per_step = ctx.get_tuning()["rows_per_lane"] * (16 if prec == tp.FP64_MATRIX else 64)
+        t = ctx.get_tuning()
+        rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
+        tuning = {"rows_per_lane": rpl, "hist_copies": t["hist_copies"] or 16,
+                  "max_cols": t["max_cols"] or 4096, "blocks_per_cu": t["blocks_per_cu"],
+                  "autotuned": tuning is not None}
+        rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
         cols_per_step = 16 if prec == tp.FP64_MATRIX else 2
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
                 "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,

@@ -81,8 +81,11 @@ enum {
 };
 
 /* Open a context on HIP device `device`.  hip_stream: a hipStream_t to launch
- * on (borrowed; it must outlive the context), or NULL for a stream owned by
- * the context.  *out receives the context. */
+ * on (borrowed; it must outlive the context), or NULL for a non-blocking
+ * stream owned by the context (the null stream itself cannot be borrowed).
+ * Device buffers that other streams write or read around tpcf_count_async
+ * need an explicit ordering (tpcf_synchronize, or events) with a context
+ * that owns its stream.  *out receives the context. */
 int tpcf_open(int device, void *hip_stream, tpcf_ctx **out);
 
 /* Release every catalog and device buffer of the context, then the context. */
@@ -195,13 +198,17 @@ int tpcf_wait(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64);
 int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
 
 /* Launch shape of later launches (set by the autotuner; defaults are fine).
- * rows_per_lane   2 or 4 rows held in registers per lane (0: 4);
- * hist_copies     LDS histogram copies per wavefront, 4..32 (0: 32, fewer
- *                 for many bins); a value above the default is ignored;
+ * rows_per_lane   vector paths: 2 or 4 rows held in registers per lane;
+ *                 matrix-core path: 2 or 4 groups of 16 rows per wavefront
+ *                 (0: 4 on the vector paths, 2 on the matrix-core path);
+ * hist_copies     LDS histogram copies per wavefront, 4..32 (0: 16); a
+ *                 value above what the slot count allows (32 up to 46
+ *                 slots, 16 up to 94, 8 up to 190, else 4) is lowered;
  * max_cols        largest column range of a work unit, multiple of 256 in
- *                 [256, 65536] (0: 16384);
+ *                 [256, 65536] (0: 4096);
  * blocks_per_cu   grid size per compute unit (0: resident blocks x 4).
- * Results never depend on these. */
+ * Results never depend on these.  tpcf_get_tuning returns the values as
+ * set, 0 standing for the default. */
 int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, int32_t max_cols,
                     int32_t blocks_per_cu);
 int tpcf_get_tuning(tpcf_ctx *ctx, int32_t *rows_per_lane, int32_t *hist_copies, int32_t *max_cols,

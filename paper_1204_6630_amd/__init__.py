@@ -153,7 +153,10 @@ def version() -> str:
 
 class Context:
     """One device context (``tpcf_open``); ``stream`` is an optional
-    ``hipStream_t`` handle (e.g. ``torch.cuda.Stream().cuda_stream``)."""
+    ``hipStream_t`` handle (e.g. ``torch.cuda.Stream().cuda_stream``) to
+    launch on.  None or 0 gives the context a stream of its own (torch's
+    default stream has handle 0 and is not borrowed): then call
+    ``synchronize()`` before torch reads what ``count_async`` wrote."""
 
     def __init__(self, device: int = 0, stream: int | None = None):
         self._h = ctypes.c_void_p()
@@ -206,6 +209,10 @@ class Context:
         if getattr(t, "dtype", None) is None or str(t.dtype) != "torch.float64" or t.dim() != 2 \
                 or t.shape[0] != 3 or not t.is_contiguous() or not t.is_cuda:
             raise ValueError("need a contiguous float64 CUDA tensor of shape (3, n)")
+        # the tensor may still be being written on torch's stream; the
+        # library reads it on its own
+        import torch
+        torch.cuda.current_stream(t.device).synchronize()
         cid = ctypes.c_int32()
         _check(lib().tpcf_attach_catalog(self._h, ctypes.c_void_p(t.data_ptr()), t.shape[1],
                                          ctypes.byref(cid)))

@@ -52,12 +52,22 @@ constexpr double kMatrixTau = 3.552713678800501e-15; // 2^-48, see make_band64
 constexpr int kPoolStreams = 4;
 
 // Launch shape, set by tpcf_set_tuning (the autotuner) or left at defaults.
+// Launch shape.  Zero fields take the defaults, which are the shapes the
+// autotuner picked on the large octant workload: 4 rows per lane on the vector
+// paths, 2 row groups of 16 on the matrix-core path (fewer registers, twice
+// the resident waves), 16 histogram copies, 4096-column units.
 struct Tuning {
-    int rows_per_lane = 4;   // 2 or 4
-    int hist_copies = 0;     // 0: by the number of slots
-    int max_cols = 16384;    // largest column range of a work unit
+    int rows_per_lane = 0;   // 2 or 4
+    int hist_copies = 0;     // 4..32, at most what the slot count allows
+    int max_cols = 0;        // largest column range of a work unit
     int blocks_per_cu = 0;   // 0: resident blocks x 4
 };
+
+int rows_per_lane_of(const Tuning &t, bool matrix) {
+    return t.rows_per_lane ? t.rows_per_lane : (matrix ? 2 : 4);
+}
+
+int max_cols_of(const Tuning &t) { return t.max_cols ? t.max_cols : 4096; }
 
 // Device memory of one context, with an optional budget on the total.
 struct MemAccount {
@@ -501,9 +511,9 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
              bool matrix, Plan **out) {
     // vector paths: 64 lanes x rows_per_lane rows per wavefront; matrix-core
     // path: rows_per_lane groups of 16 rows per wavefront, 16-aligned tiles
-    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * ctx->tune.rows_per_lane;
+    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * rows_per_lane_of(ctx->tune, matrix);
     const int64_t align = matrix ? 16 : 1;
-    const int64_t max_cols = ctx->tune.max_cols;
+    const int64_t max_cols = max_cols_of(ctx->tune);
     char buf[160];
     snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld:%lld:%lld:%lld:%lld", (int)auto_pairs, (long long)na,
              (long long)nb, (long long)rb, (long long)re, (long long)T, (long long)max_cols, (long long)align);
@@ -673,9 +683,10 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.nedges = nbins + 1;
     a.nslots = nbins + 2;
     a.hist_copies = hist_copies_for(nbins + 2);
-    if (ctx->tune.hist_copies > 0 && ctx->tune.hist_copies < a.hist_copies)
-        a.hist_copies = ctx->tune.hist_copies;
-    a.rows_per_lane = ctx->tune.rows_per_lane;
+    const int want_copies = ctx->tune.hist_copies > 0 ? ctx->tune.hist_copies : 16;
+    if (want_copies < a.hist_copies)
+        a.hist_copies = want_copies;
+    a.rows_per_lane = rows_per_lane_of(ctx->tune, cp.precision == TPCF_FP64_MATRIX);
     a.blocks_per_cu = ctx->tune.blocks_per_cu;
     a.stats = stats;
     return a;
@@ -1273,11 +1284,9 @@ int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, i
     if (blocks_per_cu < 0 || blocks_per_cu > 64)
         return fail(TPCF_E_INVALID, "blocks_per_cu must be in [0, 64]");
     Tuning t;
-    if (rows_per_lane)
-        t.rows_per_lane = rows_per_lane;
+    t.rows_per_lane = rows_per_lane;
     t.hist_copies = hist_copies;
-    if (max_cols)
-        t.max_cols = max_cols;
+    t.max_cols = max_cols;
     t.blocks_per_cu = blocks_per_cu;
     ctx->tune = t;
     return TPCF_OK;

@@ -245,6 +245,7 @@ def test_attach_torch_tensor_and_async(ctx, cfg1):
         got = ctx.count(tp.DD, ca, wl.edges_deg, precision=prec)
         assert np.array_equal(got, ref["DD"])
     out = torch.zeros(wl.edges_deg.size + 1, dtype=torch.int64, device="cuda:0")
+    torch.cuda.synchronize()    # the fill runs on torch's stream, the count on the library's
     ctx.count_async(tp.DR, ca, wl.edges_deg, out.data_ptr(), cat_b=cr)
     ctx.synchronize()
     assert np.array_equal(out.cpu().numpy().astype(np.uint64), ref["DR"])
