@@ -286,11 +286,9 @@ def main():
         pairs, flagged, exact, rare = ctx.stats(reset=True)
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
-        t = ctx.get_tuning()
+        t = ctx.get_tuning()     # 0 = the library's default
         rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
-        tuning = {"rows_per_lane": rpl, "hist_copies": t["hist_copies"] or 16,
-                  "max_cols": t["max_cols"] or 4096, "blocks_per_cu": t["blocks_per_cu"],
-                  "autotuned": tuning is not None}
+        tuning = dict(t, rows_per_lane=rpl, autotuned=tuning is not None)
         rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
         cols_per_step = 16 if prec == tp.FP64_MATRIX else 2
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,

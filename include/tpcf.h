@@ -198,21 +198,36 @@ int tpcf_wait(tpcf_ctx *ctx, int64_t job, uint64_t *out_u64);
 int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
 
 /* Launch shape of later launches (set by the autotuner; defaults are fine).
+ * Every field 0 takes the default.
  * rows_per_lane   vector paths: 2 or 4 rows held in registers per lane;
  *                 matrix-core path: 2 or 4 groups of 16 rows per wavefront
- *                 (0: 4 on the vector paths, 2 on the matrix-core path);
- * hist_copies     LDS histogram copies per wavefront, 4..32 (0: 16); a
- *                 value above what the slot count allows (32 up to 46
- *                 slots, 16 up to 94, 8 up to 190, else 4) is lowered;
+ *                 (default: 4 on the vector paths, 2 on the matrix-core path);
+ * hist_copies     LDS histogram copies per wavefront, 4, 8, 16 or 32
+ *                 (default 16); a value above what the slot count allows
+ *                 (32 up to 46 slots, 16 up to 94, 8 up to 190, else 4) is
+ *                 lowered;
  * max_cols        largest column range of a work unit, multiple of 256 in
- *                 [256, 65536] (0: 4096);
- * blocks_per_cu   grid size per compute unit (0: resident blocks x 4).
- * Results never depend on these.  tpcf_get_tuning returns the values as
- * set, 0 standing for the default. */
-int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, int32_t max_cols,
-                    int32_t blocks_per_cu);
-int tpcf_get_tuning(tpcf_ctx *ctx, int32_t *rows_per_lane, int32_t *hist_copies, int32_t *max_cols,
-                    int32_t *blocks_per_cu);
+ *                 [256, 65536] (default 4096);
+ * blocks_per_cu   grid size per compute unit, <= 64 (default: resident
+ *                 blocks x 4);
+ * lut_bytes       largest cell table held in LDS, 4096..33792 bytes
+ *                 (default 33792 for direct FP32 tables, else 24576);
+ * lut_clamped     1: FP32 byte tables start at the first edge and clamp the
+ *                 key into range (finer cells, two more instructions per
+ *                 pair) instead of the direct layout that starts at cell 0.
+ * Results never depend on these.  tpcf_get_tuning returns the fields as set
+ * (0 standing for the default); NULL to tpcf_set_tuning restores defaults. */
+typedef struct tpcf_tuning {
+    int32_t rows_per_lane;
+    int32_t hist_copies;
+    int32_t max_cols;
+    int32_t blocks_per_cu;
+    int32_t lut_bytes;
+    int32_t lut_clamped;
+} tpcf_tuning;
+
+int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning);
+int tpcf_get_tuning(tpcf_ctx *ctx, tpcf_tuning *out);
 
 /* HBM budget for everything the context allocates (catalogs, tables, plans,
  * workspaces); 0 = unlimited.  An allocation that would exceed it fails with
@@ -266,16 +281,20 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
 
 /* Cell table of the pair kernels for the given edges (host only, for CPU
  * tests of the host logic).  precision selects the key: TPCF_FP32_CHORD uses
- * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 the high 32 bits of
- * e = fl64(1 - d) as a signed integer.  A key maps to cell
+ * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 and TPCF_FP64_MATRIX the high
+ * 32 bits of e = 1 - d as a signed integer.  A key maps to cell
  * clamp(key >> shift, lo, hi); entry cells[cell - lo] is a slot (< 0x8000),
  * 0x8000 | k when only edge k is undecided in the cell, or 0xFFFF when
- * several edges are.  out_cells must hold max_cells entries (16..24576;
- * the kernels use 24576 cells for up to 125 bins, 12288 beyond);
+ * several edges are.  direct = 1 (TPCF_FP32_CHORD only) asks for the direct
+ * layout the kernels use for byte tables: lo = 0 and no key the kernel can
+ * produce for norms within delta_max exceeds hi, so the clamp never acts;
+ * it fails with TPCF_E_INVALID if that table would not fit.  out_cells must
+ * hold max_cells entries (16..33792; the kernels use up to 33792 cells for
+ * direct tables, 24576 for other byte tables, 12288 beyond 125 bins);
  * out_E (nbins+1 doubles, may be NULL) receives fl(1 - D_k). */
 int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
-                       int32_t max_cells, int32_t *out_shift, int32_t *out_lo, int32_t *out_hi,
-                       uint16_t *out_cells, double *out_E);
+                       int32_t max_cells, int32_t direct, int32_t *out_shift, int32_t *out_lo,
+                       int32_t *out_hi, uint16_t *out_cells, double *out_E);
 
 /* Matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
  * doubles each) such that e >= out_hi[k] implies d <= D_k and e < out_lo[k]

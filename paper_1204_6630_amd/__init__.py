@@ -19,7 +19,7 @@ import numpy as np
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
     "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
-    "BATCH_GRAPH",
+    "BATCH_GRAPH", "Tuning",
 ]
 
 DD, DR, RR = 0, 1, 2
@@ -56,6 +56,13 @@ class JobDesc(ctypes.Structure):
 
 
 BATCH_GRAPH = 1
+
+
+class Tuning(ctypes.Structure):
+    """struct tpcf_tuning"""
+    _fields_ = [("rows_per_lane", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
+                ("max_cols", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lut_bytes", ctypes.c_int32), ("lut_clamped", ctypes.c_int32)]
 
 
 class TpcfError(RuntimeError):
@@ -110,8 +117,8 @@ def lib():
         "tpcf_poll": ([P, i64, P, P], cint),
         "tpcf_wait": ([P, i64, P], cint),
         "tpcf_cancel": ([P, i64], cint),
-        "tpcf_set_tuning": ([P, i32, i32, i32, i32], cint),
-        "tpcf_get_tuning": ([P, P, P, P, P], cint),
+        "tpcf_set_tuning": ([P, P], cint),
+        "tpcf_get_tuning": ([P, P], cint),
         "tpcf_set_hbm_budget": ([P, i64], cint),
         "tpcf_hbm_usage": ([P, P, P], cint),
         "tpcf_synchronize": ([P], cint),
@@ -119,7 +126,7 @@ def lib():
         "tpcf_kernel_time": ([P, P, P, cint], cint),
         "tpcf_stats": ([P, P, P, P, P, cint], cint),
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
-        "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, P, P, P, P, P], cint),
+        "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
         "tpcf_compile_band64": ([P, i32, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_last_error": ([], ctypes.c_char_p),
@@ -295,14 +302,15 @@ class Context:
         _check(lib().tpcf_cancel(self._h, job))
 
     def set_tuning(self, rows_per_lane: int = 0, hist_copies: int = 0, max_cols: int = 0,
-                   blocks_per_cu: int = 0):
-        _check(lib().tpcf_set_tuning(self._h, rows_per_lane, hist_copies, max_cols, blocks_per_cu))
+                   blocks_per_cu: int = 0, lut_bytes: int = 0, lut_clamped: int = 0):
+        t = Tuning(rows_per_lane, hist_copies, max_cols, blocks_per_cu, lut_bytes, lut_clamped)
+        _check(lib().tpcf_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
-        v = [ctypes.c_int32() for _ in range(4)]
-        _check(lib().tpcf_get_tuning(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(("rows_per_lane", "hist_copies", "max_cols", "blocks_per_cu"),
-                        (x.value for x in v)))
+        """The launch shape as set (0: default)."""
+        t = Tuning()
+        _check(lib().tpcf_get_tuning(self._h, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in Tuning._fields_}
 
     def set_hbm_budget(self, nbytes: int):
         _check(lib().tpcf_set_hbm_budget(self._h, int(nbytes)))
@@ -362,16 +370,20 @@ def compile_band64(edges_deg):
     return lo, hi
 
 
-def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None):
-    """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the table
-    size the kernels use for this many bins."""
+def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None,
+                  direct: bool | None = None):
+    """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the layout
+    and table size the kernels use for this many bins."""
     e = _f64(edges_deg)
+    byte_table = e.size + 1 <= 127
+    if direct is None:
+        direct = precision == FP32_CHORD and byte_table
     if max_cells is None:
-        max_cells = 24576 if e.size + 1 <= 127 else 12288
+        max_cells = 33792 if direct else 24576 if byte_table else 12288
     cells = np.zeros(max_cells, np.uint16)
     E = np.empty(e.size, np.float64)
     sh, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().tpcf_compile_cells(_p(e), e.size - 1, precision, delta_max, max_cells,
+    _check(lib().tpcf_compile_cells(_p(e), e.size - 1, precision, delta_max, max_cells, int(direct),
                                     ctypes.byref(sh), ctypes.byref(lo), ctypes.byref(hi),
                                     _p(cells), _p(E)))
     return sh.value, lo.value, hi.value, cells[:hi.value - lo.value + 1].copy(), E

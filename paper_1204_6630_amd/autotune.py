@@ -1,27 +1,33 @@
 """Autotuner for the pair kernels' launch shape.
 
-Candidates: rows held per lane (2 or 4), LDS histogram copies per wavefront
-(32 or 16), the largest column range of a work unit, and the grid size.  Each
-candidate is timed on a sample of the caller's workload (a block of rows
-against the full column catalog) with the library's HIP-event kernel timer;
-the fastest is applied to the context and cached on disk, keyed by device,
-HIP runtime, precision and bin count.  Counts never depend on the choice.
+Knobs: rows held per lane (or row groups of 16 on the matrix-core path), LDS
+histogram copies per wavefront, the largest column range of a work unit, the
+grid size, the cell-table budget and, for FP32 byte tables, the direct or the
+clamped table layout.  The search is a coordinate descent from the library's
+defaults: each knob in turn is swept over its candidates with the others held
+at the best values so far, on a sample of the caller's workload (a block of
+rows against the full column catalog) timed with the library's HIP-event
+kernel timer.  The best shape is applied to the context and cached on disk,
+keyed by device, HIP runtime, precision and bin count.  Counts never depend
+on the choice.
 """
 
 from __future__ import annotations
 
-import itertools
 import json
 import os
 import time
 
 from . import FP32_CHORD, Context
 
+# 0 is the library's default for every knob
 CANDIDATES = {
-    "rows_per_lane": (2, 4),
-    "hist_copies": (32, 16),
-    "max_cols": (4096, 16384),
+    "rows_per_lane": (0, 2, 4),
+    "hist_copies": (0, 32, 8),
+    "max_cols": (0, 16384),
     "blocks_per_cu": (0, 12),
+    "lut_clamped": (0, 1),
+    "lut_bytes": (0, 16896),
 }
 
 
@@ -37,7 +43,7 @@ def _device_key(precision: int, nbins: int) -> str:
         hip = getattr(torch.version, "hip", "") or ""
     except Exception:  # pragma: no cover
         name, hip = "unknown", ""
-    return f"{name}|hip{hip}|prec{precision}|nbins{nbins}"
+    return f"v2|{name}|hip{hip}|prec{precision}|nbins{nbins}"
 
 
 def _load_cache() -> dict:
@@ -87,20 +93,29 @@ def autotune(ctx: Context, sample, edges, precision: int = FP32_CHORD, use_cache
         ctx.set_tuning(**t)
         return {"tuning": t, "timings_ms": cache[key].get("timings_ms", {}), "cached": True}
     cand = candidates or CANDIDATES
-    names = list(cand)
     timings = {}
     t0 = time.perf_counter()
     # warm the tables and plans once with the defaults
     ctx.set_tuning()
     time_sample(ctx, sample, edges, precision, repeats=1)
-    best, best_ms = None, float("inf")
-    for values in itertools.product(*(cand[n] for n in names)):
-        t = dict(zip(names, values))
-        ctx.set_tuning(**t)
-        ms = time_sample(ctx, sample, edges, precision)
-        timings[json.dumps(t, sort_keys=True)] = round(ms, 3)
-        if ms < best_ms:
-            best, best_ms = t, ms
+
+    def measure(t):
+        tk = json.dumps(t, sort_keys=True)
+        if tk not in timings:
+            ctx.set_tuning(**t)
+            timings[tk] = round(time_sample(ctx, sample, edges, precision), 3)
+        return timings[tk]
+
+    best = {name: 0 for name in cand}
+    best_ms = measure(best)
+    for name, values in cand.items():
+        for v in values:
+            if v == best[name]:
+                continue
+            t = dict(best, **{name: v})
+            ms = measure(t)
+            if ms < 0.99 * best_ms:       # keep a change only for a clear gain
+                best, best_ms = t, ms
     ctx.set_tuning(**best)
     if use_cache:
         cache[key] = {"tuning": best, "timings_ms": timings,

@@ -55,12 +55,15 @@ constexpr int kPoolStreams = 4;
 // Launch shape.  Zero fields take the defaults, which are the shapes the
 // autotuner picked on the large octant workload: 4 rows per lane on the vector
 // paths, 2 row groups of 16 on the matrix-core path (fewer registers, twice
-// the resident waves), 16 histogram copies, 4096-column units.
+// the resident waves), 16 histogram copies, 4096-column units, and direct
+// FP32 byte tables of up to 33 KB.
 struct Tuning {
     int rows_per_lane = 0;   // 2 or 4
     int hist_copies = 0;     // 4..32, at most what the slot count allows
     int max_cols = 0;        // largest column range of a work unit
     int blocks_per_cu = 0;   // 0: resident blocks x 4
+    int lut_bytes = 0;       // largest cell table
+    int lut_clamped = 0;     // 1: FP32 byte tables in the clamped layout
 };
 
 int rows_per_lane_of(const Tuning &t, bool matrix) {
@@ -373,11 +376,13 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
     return TPCF_OK;
 }
 
-std::string edges_key(const double *edges, int nbins, int precision, double delta) {
+std::string edges_key(const double *edges, int nbins, int precision, double delta, const Tuning &t) {
     std::string k((const char *)edges, sizeof(double) * (size_t)(nbins + 1));
     k.append((const char *)&precision, sizeof precision);
     if (precision == TPCF_FP32_CHORD)
         k.append((const char *)&delta, sizeof delta);
+    k.append((const char *)&t.lut_bytes, sizeof t.lut_bytes);
+    k.append((const char *)&t.lut_clamped, sizeof t.lut_clamped);
     return k;
 }
 
@@ -401,7 +406,7 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
 
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta,
                  Compiled **out) {
-    std::string key = edges_key(edges, nbins, precision, delta);
+    std::string key = edges_key(edges, nbins, precision, delta, ctx->tune);
     auto it = ctx->compiled.find(key);
     if (it != ctx->compiled.end()) {
         *out = it->second.get();
@@ -422,12 +427,17 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     c->delta = delta;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    const int max_cells = kMaxLutBytes / c->entry_bytes;
+    const int table_bytes = ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxLutBytes;
+    const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     std::vector<float> qlo(c->edges.D.size(), 0.0f), qhi(c->edges.D.size(), 0.0f);
     std::vector<double> tlo = c->edges.E, thi = c->edges.E;
     if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
-        c->cells = make_cells32(c->edges, c->band, delta, max_cells);
+        if (c->entry_bytes == 1 && !ctx->tune.lut_clamped)
+            c->cells = make_cells32_direct(c->edges, c->band, delta,
+                                           ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxDirectLutBytes);
+        if (c->cells.cells.empty())
+            c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
     } else if (precision == TPCF_FP64_MATRIX) {
@@ -674,6 +684,7 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.lut_shift = cp.cells.shift;
     a.lut_lo = cp.cells.lo;
     a.lut_hi = cp.cells.hi;
+    a.lut_direct = cp.cells.direct ? 1 : 0;
     a.qlo = (const float *)cp.dqlo.p;
     a.qhi = (const float *)cp.dqhi.p;
     a.E = (const double *)cp.dE.p;
@@ -1271,35 +1282,46 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job) {
     return TPCF_OK;
 }
 
-int tpcf_set_tuning(tpcf_ctx *ctx, int32_t rows_per_lane, int32_t hist_copies, int32_t max_cols,
-                    int32_t blocks_per_cu) {
+int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
-    if (rows_per_lane != 0 && rows_per_lane != 2 && rows_per_lane != 4)
+    tpcf_tuning t;
+    memset(&t, 0, sizeof t);
+    if (tuning)
+        t = *tuning;
+    if (t.rows_per_lane != 0 && t.rows_per_lane != 2 && t.rows_per_lane != 4)
         return fail(TPCF_E_INVALID, "rows_per_lane must be 0 (default), 2 or 4");
-    if (hist_copies != 0 && hist_copies != 4 && hist_copies != 8 && hist_copies != 16 && hist_copies != 32)
-        return fail(TPCF_E_INVALID, "hist_copies must be 0 (by bins), 4, 8, 16 or 32");
-    if (max_cols != 0 && (max_cols < 256 || max_cols > 65536 || max_cols % 256))
+    if (t.hist_copies != 0 && t.hist_copies != 4 && t.hist_copies != 8 && t.hist_copies != 16 &&
+        t.hist_copies != 32)
+        return fail(TPCF_E_INVALID, "hist_copies must be 0 (default), 4, 8, 16 or 32");
+    if (t.max_cols != 0 && (t.max_cols < 256 || t.max_cols > 65536 || t.max_cols % 256))
         return fail(TPCF_E_INVALID, "max_cols must be 0 (default) or a multiple of 256 in [256, 65536]");
-    if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64)
         return fail(TPCF_E_INVALID, "blocks_per_cu must be in [0, 64]");
-    Tuning t;
-    t.rows_per_lane = rows_per_lane;
-    t.hist_copies = hist_copies;
-    t.max_cols = max_cols;
-    t.blocks_per_cu = blocks_per_cu;
-    ctx->tune = t;
+    if (t.lut_bytes != 0 && (t.lut_bytes < 4096 || t.lut_bytes > kMaxDirectLutBytes))
+        return fail(TPCF_E_INVALID, "lut_bytes must be 0 (default) or in [4096, 33792]");
+    if (t.lut_clamped != 0 && t.lut_clamped != 1)
+        return fail(TPCF_E_INVALID, "lut_clamped must be 0 or 1");
+    Tuning u;
+    u.rows_per_lane = t.rows_per_lane;
+    u.hist_copies = t.hist_copies;
+    u.max_cols = t.max_cols;
+    u.blocks_per_cu = t.blocks_per_cu;
+    u.lut_bytes = t.lut_bytes;
+    u.lut_clamped = t.lut_clamped;
+    ctx->tune = u;
     return TPCF_OK;
 }
 
-int tpcf_get_tuning(tpcf_ctx *ctx, int32_t *rows_per_lane, int32_t *hist_copies, int32_t *max_cols,
-                    int32_t *blocks_per_cu) {
-    if (!ctx || !rows_per_lane || !hist_copies || !max_cols || !blocks_per_cu)
+int tpcf_get_tuning(tpcf_ctx *ctx, tpcf_tuning *out) {
+    if (!ctx || !out)
         return fail(TPCF_E_INVALID, "NULL argument");
-    *rows_per_lane = ctx->tune.rows_per_lane;
-    *hist_copies = ctx->tune.hist_copies;
-    *max_cols = ctx->tune.max_cols;
-    *blocks_per_cu = ctx->tune.blocks_per_cu;
+    out->rows_per_lane = ctx->tune.rows_per_lane;
+    out->hist_copies = ctx->tune.hist_copies;
+    out->max_cols = ctx->tune.max_cols;
+    out->blocks_per_cu = ctx->tune.blocks_per_cu;
+    out->lut_bytes = ctx->tune.lut_bytes;
+    out->lut_clamped = ctx->tune.lut_clamped;
     return TPCF_OK;
 }
 
@@ -1423,23 +1445,33 @@ int tpcf_landy_szalay(const uint64_t *dd, const uint64_t *dr, const uint64_t *rr
 }
 
 int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
-                       int32_t max_cells, int32_t *out_shift, int32_t *out_lo, int32_t *out_hi,
-                       uint16_t *out_cells, double *out_E) {
+                       int32_t max_cells, int32_t direct, int32_t *out_shift, int32_t *out_lo,
+                       int32_t *out_hi, uint16_t *out_cells, double *out_E) {
     if (!out_shift || !out_lo || !out_hi || !out_cells)
         return fail(TPCF_E_INVALID, "NULL argument");
     if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64 && precision != TPCF_FP64_MATRIX)
         return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX");
     if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
         return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
-    if (max_cells < 16 || max_cells > kMaxLutCells)
-        return fail(TPCF_E_INVALID, "max_cells must be in [16, 24576]");
+    if (max_cells < 16 || max_cells > kMaxDirectLutBytes)
+        return fail(TPCF_E_INVALID, "max_cells must be in [16, 33792]");
+    if (direct != 0 && (direct != 1 || precision != TPCF_FP32_CHORD))
+        return fail(TPCF_E_INVALID, "direct must be 0, or 1 with TPCF_FP32_CHORD");
     EdgeTables t;
     std::string err;
     if (!compile_edges(bin_edges_deg, nbins, &t, &err))
         return fail(TPCF_E_INVALID, err);
-    CellTable c = precision == TPCF_FP32_CHORD ? make_cells32(t, make_band32(t, delta_max), delta_max, max_cells)
-                  : precision == TPCF_FP64_MATRIX ? make_cells64_band(make_band64(t, kMatrixTau), max_cells)
-                                                   : make_cells64(t, max_cells);
+    CellTable c;
+    if (direct) {
+        c = make_cells32_direct(t, make_band32(t, delta_max), delta_max, max_cells);
+        if (c.cells.empty())
+            return fail(TPCF_E_INVALID, "no direct table fits in max_cells");
+    } else {
+        const int m = std::min<int>(max_cells, kMaxLutCells);
+        c = precision == TPCF_FP32_CHORD ? make_cells32(t, make_band32(t, delta_max), delta_max, m)
+            : precision == TPCF_FP64_MATRIX ? make_cells64_band(make_band64(t, kMatrixTau), m)
+                                             : make_cells64(t, m);
+    }
     *out_shift = c.shift;
     *out_lo = c.lo;
     *out_hi = c.hi;

@@ -264,11 +264,61 @@ Band32 make_band32(const EdgeTables &t, double delta) {
 
 // FP32 cells: key = bits(q) >> shift for q >= 0.  The bottom cell also holds
 // every q below its range and the top cell every q above.
+namespace {
+
+// Largest q = fl32(|f_i - f_j|^2) the kernel can produce: |f_i - f_j| <=
+// 2 sqrt(1 + delta) + a few FP32 ulps, and the rounding of q is far below the
+// 1e-4 margin.
+uint32_t qtop_key(double delta) {
+    const double qtop_d = pow(2.0 * sqrt(1.0 + delta) + 4.0 * ldexp(1.0, -24), 2.0) * 1.0001;
+    return fbits(round_up32(qtop_d));
+}
+
+// Entries of FP32 cells [lo, hi] (bit patterns c << shift .. ((c+1) << shift) - 1);
+// the bottom cell reaches down to 0 and the top one up to +inf (a clamp sends
+// every key outside the table there).
+void fill_cells32(const Band32 &b, int ne, CellTable *ct) {
+    const int n = ct->hi - ct->lo + 1;
+    ct->cells.resize(n);
+    for (int c = ct->lo; c <= ct->hi; ++c) {
+        float lo = c == ct->lo ? 0.0f : ffrom((uint32_t)c << ct->shift);
+        float hi = c == ct->hi ? HUGE_VALF : ffrom((((uint32_t)c + 1u) << ct->shift) - 1u);
+        int s_min = 0, s_max = 0;
+        for (int k = 0; k < ne; ++k) {
+            if (lo >= b.qhi[k])
+                ++s_min;
+            if (hi >= b.qlo[k])
+                ++s_max;
+        }
+        ct->cells[c - ct->lo] = encode(s_min, s_max);
+    }
+    tally(ct);
+}
+
+}  // namespace
+
+CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta, int max_cells) {
+    CellTable ct;
+    if (!(delta <= ldexp(1.0, -10)))
+        return ct;
+    const uint32_t ktop = qtop_key(delta);
+    for (int shift = 12; shift <= 23; ++shift) {
+        if ((int64_t)(ktop >> shift) + 1 <= max_cells) {
+            ct.shift = shift;
+            ct.lo = 0;
+            ct.hi = (int32_t)(ktop >> shift);
+            ct.direct = true;
+            // keys never exceed ktop, so the open top cell changes no decision
+            fill_cells32(b, (int)t.D.size(), &ct);
+            return ct;
+        }
+    }
+    return ct;
+}
+
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells) {
     const int ne = (int)t.D.size();
-    // largest possible q: |f_i - f_j| <= 2 sqrt(1 + delta) + a, then rounding
-    const double qtop_d = pow(2.0 * sqrt(1.0 + delta) + 4.0 * ldexp(1.0, -24), 2.0) * 1.0001;
-    const uint32_t ktop = fbits(round_up32(qtop_d));
+    const uint32_t ktop = qtop_key(delta);
     // smallest positive finite threshold
     float tmin = HUGE_VALF;
     for (int k = 0; k < ne; ++k) {
@@ -292,21 +342,7 @@ CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int m
             break;
         }
     }
-    const int n = ct.hi - ct.lo + 1;
-    ct.cells.resize(n);
-    for (int c = ct.lo; c <= ct.hi; ++c) {
-        float lo = c == ct.lo ? 0.0f : ffrom((uint32_t)c << ct.shift);
-        float hi = c == ct.hi ? HUGE_VALF : ffrom((((uint32_t)c + 1u) << ct.shift) - 1u);
-        int s_min = 0, s_max = 0;
-        for (int k = 0; k < ne; ++k) {
-            if (lo >= b.qhi[k])
-                ++s_min;
-            if (hi >= b.qlo[k])
-                ++s_max;
-        }
-        ct.cells[c - ct.lo] = encode(s_min, s_max);
-    }
-    tally(&ct);
+    fill_cells32(b, ne, &ct);
     return ct;
 }
 

@@ -32,6 +32,7 @@ struct Band64 {
 struct CellTable {
     int shift = 0;                  // cell = key >> shift
     int32_t lo = 0, hi = 0;         // clamp range of cells (inclusive)
+    bool direct = false;            // lo = 0 and no reachable key exceeds hi: no clamp needed
     std::vector<uint16_t> cells;    // hi - lo + 1 entries
     int n_certain = 0, n_medium = 0, n_multi = 0;
 };
@@ -48,6 +49,11 @@ Band32 make_band32(const EdgeTables &t, double delta);
 // Cell tables.  FP32: key = bits of q (q >= 0).  FP64: key = high 32 bits of
 // e = fl(1 - d) read as a signed integer.
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
+// Direct FP32 table: cells 0 .. bits(qtop) >> shift, where qtop bounds every
+// q the kernel can compute for norms within delta; the smallest shift whose
+// table has at most max_cells entries.  Returns a table with no cells if
+// delta is too large for the bound (above 2^-10) or none fits.
+CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
 CellTable make_cells64(const EdgeTables &t, int max_cells);
 
 Band64 make_band64(const EdgeTables &t, double tau);

@@ -15,6 +15,9 @@ constexpr int kBlock = kWaves * kWaveSize;
 // edge index fits in 7 bits, else two bytes.
 constexpr int kMaxLutBytes = 24576;
 constexpr int kMaxLutCells = kMaxLutBytes;        // with one-byte entries
+// Direct-indexed FP32 tables (cell = bits(q) >> shift from cell 0, no clamp):
+// the largest table, and the smallest table the default shape asks for.
+constexpr int kMaxDirectLutBytes = 33792;
 // Histogram copies in global memory (u64), indexed by work unit.
 constexpr int kGlobalCopies = 64;
 // Largest number of output slots (nbins <= 256 -> nbins + 2 slots).
@@ -71,6 +74,8 @@ struct PairArgs {
     int32_t lut_entry_bytes;     // 1 or 2
     int32_t lut_shift;           // cell = key >> shift
     int32_t lut_lo, lut_hi;      // clamp range of cells
+    int32_t lut_direct;          // 1: FP32 table indexed from cell 0 without a clamp
+                                 // (every reachable key lies inside it)
 
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each

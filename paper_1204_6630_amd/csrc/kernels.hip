@@ -143,17 +143,21 @@ struct Smem {
     uint32_t lut_addr;   // LDS byte address of lut
 };
 
+// LDS layout: the cell table first (at the start of the block's LDS, so a
+// direct table is indexed by the cell itself), then the histograms and the
+// edge thresholds.
 __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     Smem s;
+    const int lut_bytes = (a.lut_cells * a.lut_entry_bytes + 15) & ~15;
     int hist_words = kWaves * (a.nslots + 1) * a.hist_copies;
-    s.hist = reinterpret_cast<uint32_t *>(base);
-    s.D = reinterpret_cast<double *>(base + hist_words * 4);
+    s.lut = base;
+    s.hist = reinterpret_cast<uint32_t *>(base + lut_bytes);
+    s.D = reinterpret_cast<double *>(base + lut_bytes + hist_words * 4);
     s.E = s.D + a.nedges;
     s.Tlo = s.E + a.nedges;
     s.Thi = s.Tlo + a.nedges;
     s.qlo = reinterpret_cast<float *>(s.Thi + a.nedges);
     s.qhi = s.qlo + a.nedges;
-    s.lut = reinterpret_cast<unsigned char *>(s.qhi + a.nedges);
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
     s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
     return s;
@@ -245,7 +249,7 @@ struct Consts {
 // One step: JN columns against the P rows of every lane.  All JN * P table
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
-template <bool LUT8, bool MASKED, int P, int JN>
+template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT>
 __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
@@ -271,8 +275,17 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             v = __fmaf_rn(dy, dy, v);
             v = __fmaf_rn(dz, dz, v);
             q[t][p] = v;
-            uint32_t c = med3_u32(__float_as_uint(v) >> k.shift, k.clo, k.chi);
-            ent[t][p] = lds_read_entry<LUT8>(c * (LUT8 ? 1u : 2u) + k.lutbias);
+            uint32_t addr;
+            if (DIRECT) {
+                // byte table from cell 0 at LDS address 0 (the kernel has no
+                // static LDS, so its dynamic LDS starts there); every key the
+                // kernel can produce lies inside it (checked on the host)
+                addr = __float_as_uint(v) >> k.shift;
+            } else {
+                uint32_t c = med3_u32(__float_as_uint(v) >> k.shift, k.clo, k.chi);
+                addr = c * (LUT8 ? 1u : 2u) + k.lutbias;
+            }
+            ent[t][p] = lds_read_entry<LUT8>(addr);
         }
     }
     uint32_t any = 0;
@@ -364,7 +377,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 }
 
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
-template <bool LUT8, bool MASKED, int P>
+template <bool LUT8, bool MASKED, int P, bool DIRECT>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
@@ -383,10 +396,10 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
     cfloat_p bz = (cfloat_p)jb.bz32;
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp32<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz,
-                                                 cnt);
+        step_fp32<LUT8, MASKED, P, kColsPerStep, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by,
+                                                         bz, cnt);
     for (; j < j1; ++j)
-        step_fp32<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, cnt);
+        step_fp32<LUT8, MASKED, P, 1, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, cnt);
 }
 
 template <bool LUT8, bool MASKED, int P>
@@ -518,8 +531,10 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
     }
 }
 
-// P: rows per lane of the vector paths (a wavefront covers P * 64 rows of a
-// unit) or row groups of 16 of the matrix-core path (P * 16 rows).
+// PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
+// table, 1 FP64 vector, 2 FP64 matrix cores.  P: rows per lane of the vector
+// paths (a wavefront covers P * 64 rows of a unit) or row groups of 16 of the
+// matrix-core path (P * 16 rows).
 template <int PREC, bool LUT8, int P>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     constexpr int kRowsPerWave = PREC == 2 ? P * 16 : P * kWaveSize;
@@ -577,11 +592,11 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                     rows_mma<LUT8, true, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
                 else
                     rows_mma<LUT8, false, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
-            } else if (PREC == 0) {
+            } else if (PREC == 0 || PREC == 3) {
                 if (masked)
-                    rows_fp32<LUT8, true, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, true, P, PREC == 3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp32<LUT8, false, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, false, P, PREC == 3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             } else {
                 if (masked)
                     rows_fp64<LUT8, true, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
@@ -717,7 +732,9 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
     if (P != 2 && P != 4)
         return (int)hipErrorInvalidValue;
     if (precision == 0) {
-        if (b8) {
+        if (b8 && args->lut_direct) {
+            if (P == 2) TPCF_LAUNCH(3, true, 2); else TPCF_LAUNCH(3, true, 4);
+        } else if (b8) {
             if (P == 2) TPCF_LAUNCH(0, true, 2); else TPCF_LAUNCH(0, true, 4);
         } else {
             if (P == 2) TPCF_LAUNCH(0, false, 2); else TPCF_LAUNCH(0, false, 4);

@@ -302,18 +302,25 @@ def test_gpu_error_paths(ctx, cfg1):
     with pytest.raises(tp.TpcfError) as ei:
         ctx.release_catalog(9999)
     assert ei.value.code == -4
+    for bad in ({"rows_per_lane": 3}, {"hist_copies": 12}, {"max_cols": 300}, {"blocks_per_cu": -1},
+                {"lut_bytes": 100}, {"lut_bytes": 40000}, {"lut_clamped": 2}):
+        with pytest.raises(tp.TpcfError):
+            ctx.set_tuning(**bad)
+    assert ctx.get_tuning() == {k: 0 for k in ctx.get_tuning()}
 
 
 def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
     """Race detector: every tuning choice (rows per lane, histogram copies,
-    unit width, grid size) gives bit-identical counts."""
+    unit width, grid size, table layout and size) gives bit-identical counts."""
     wl, cd, cr, ref = cfg1
     e = wl.edges_deg
     try:
         for rpl in (2, 4):
             for hc in (32, 16, 8, 4):
-                for mc, bpc in ((256, 1), (16384, 0), (4096, 3)):
-                    ctx.set_tuning(rows_per_lane=rpl, hist_copies=hc, max_cols=mc, blocks_per_cu=bpc)
+                for mc, bpc, lb, lc in ((256, 1, 0, 0), (16384, 0, 4096, 1), (4096, 3, 4096, 0),
+                                        (4096, 0, 33792, 1)):
+                    ctx.set_tuning(rows_per_lane=rpl, hist_copies=hc, max_cols=mc, blocks_per_cu=bpc,
+                                   lut_bytes=lb, lut_clamped=lc)
                     for prec in PRECS:
                         assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), ref["DD"])
                         assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),

@@ -161,14 +161,16 @@ def test_fp32_band_adversary(edges):
     assert np.all(in_band[rel < 0.1 * half])
 
 
-def _emulate(a, b, edges, precision, delta):
+def _emulate(a, b, edges, precision, delta, direct=None):
     """Numpy transcription of the kernels' per-pair classification."""
     D, qlo, qhi = tp.compile_edges(edges, delta_max=delta)
-    shift, lo, hi, cells, E = tp.compile_cells(edges, precision, delta_max=delta)
+    shift, lo, hi, cells, E = tp.compile_cells(edges, precision, delta_max=delta, direct=direct)
     d = _dot64(a, b)
     if precision == tp.FP32_CHORD:
         q = _q32(a, b)
         key = q.view(np.uint32) >> np.uint32(shift)
+        # the direct layout (lo = 0) must hold every key without the clamp
+        assert lo > 0 or key.max() <= hi
         c = np.clip(key.astype(np.int64), lo, hi) - lo
     else:
         e = 1.0 - d
@@ -205,9 +207,10 @@ def _emulate(a, b, edges, precision, delta):
     return slot, flag, exact
 
 
-@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64])
+@pytest.mark.parametrize("precision,direct", [(tp.FP32_CHORD, True), (tp.FP32_CHORD, False),
+                                              (tp.FP64, False)])
 @pytest.mark.parametrize("cfg", [1, 2, 3])
-def test_emulated_classification_matches_oracle(cfg, precision):
+def test_emulated_classification_matches_oracle(cfg, precision, direct):
     wl = synthcat.CONFIGS[cfg](scale={1: 0.06, 2: 0.006, 3: 0.0006}[cfg])
     d = wl.data[0]
     r = wl.randoms[0]
@@ -217,7 +220,7 @@ def test_emulated_classification_matches_oracle(cfg, precision):
     a = np.concatenate([xa[ia], xa[:, None, :].repeat(xb.shape[0], 1).reshape(-1, 3)])
     b = np.concatenate([xa[ib], np.tile(xb, (xa.shape[0], 1))])
     delta = 4.5e-16
-    slot, flag, exact = _emulate(a, b, wl.edges_deg, precision, delta)
+    slot, flag, exact = _emulate(a, b, wl.edges_deg, precision, delta, direct)
     truth = oracle.pair_slots(a.T, b.T, wl.edges_deg)
     assert np.array_equal(slot, truth)
     assert flag.mean() < 0.05
@@ -236,11 +239,11 @@ def test_emulation_on_exact_dot_probes():
     b = np.stack([ds, np.sqrt(1.0 - ds * ds), np.zeros_like(ds)], axis=1)
     assert np.array_equal(_dot64(a, b), ds)
     truth = oracle.pair_slots(a.T, b.T, edges)
-    for prec in (tp.FP32_CHORD, tp.FP64):
+    for prec, direct in ((tp.FP32_CHORD, True), (tp.FP32_CHORD, False), (tp.FP64, False)):
         # the probe vectors' norms deviate from 1 by a few ulps
         n2 = np.sum(b * b, axis=1)
         delta = float(np.max(np.abs(n2 - 1.0))) + 4 * 2.0 ** -53
-        slot, _, _ = _emulate(a, b, edges, prec, delta)
+        slot, _, _ = _emulate(a, b, edges, prec, delta, direct)
         assert np.array_equal(slot, truth)
 
 
