@@ -211,10 +211,11 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * blocks_per_cu   grid size per compute unit, <= 64 (default: resident
  *                 blocks x 4);
  * lut_bytes       largest cell table held in LDS, 4096..33792 bytes
- *                 (default 33792 for direct FP32 tables, else 24576);
- * lut_clamped     1: FP32 byte tables start at the first edge and clamp the
- *                 key into range (finer cells, two more instructions per
- *                 pair) instead of the direct layout that starts at cell 0.
+ *                 (default 24576, or 33792 for direct tables);
+ * lut_direct      1: FP32 byte tables in the direct layout, indexed from
+ *                 cell 0 without a clamp (one instruction per pair instead
+ *                 of three, coarser cells, a larger table); 0 (default): the
+ *                 table starts at the first edge and the key is clamped.
  * Results never depend on these.  tpcf_get_tuning returns the fields as set
  * (0 standing for the default); NULL to tpcf_set_tuning restores defaults. */
 typedef struct tpcf_tuning {
@@ -223,7 +224,7 @@ typedef struct tpcf_tuning {
     int32_t max_cols;
     int32_t blocks_per_cu;
     int32_t lut_bytes;
-    int32_t lut_clamped;
+    int32_t lut_direct;
 } tpcf_tuning;
 
 int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning);
@@ -248,11 +249,13 @@ int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int r
 
 /* Work statistics since the last reset: pairs evaluated, pairs that left the
  * table-driven path for a threshold comparison, pairs re-decided with the
- * exact FP64 rule (FP32_CHORD band pairs, or FP64 ties), and wavefront steps
- * (64 lanes x a few pairs each) that took the rare path.  Waits for all of
- * the context's streams.  Any output pointer may be NULL. */
+ * exact FP64 rule (FP32_CHORD band pairs, or FP64 ties), wavefront steps
+ * (64 lanes x a few pairs each) that took the rare path, and wavefront steps
+ * whose pairs all lay certainly beyond the last edge and were counted in
+ * registers without table lookups.  Waits for all of the context's streams.
+ * Any output pointer may be NULL. */
 int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
-               uint64_t *out_rare_steps, int reset);
+               uint64_t *out_rare_steps, uint64_t *out_beyond_steps, int reset);
 
 /* Landy-Szalay estimator (Eq. 1), host FP64; no context needed.
  * dd, dr, rr  histograms of nbins+2 slots as returned by tpcf_count (DD and

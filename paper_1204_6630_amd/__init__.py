@@ -62,7 +62,7 @@ class Tuning(ctypes.Structure):
     """struct tpcf_tuning"""
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("max_cols", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lut_bytes", ctypes.c_int32), ("lut_clamped", ctypes.c_int32)]
+                ("lut_bytes", ctypes.c_int32), ("lut_direct", ctypes.c_int32)]
 
 
 class TpcfError(RuntimeError):
@@ -124,7 +124,7 @@ def lib():
         "tpcf_synchronize": ([P], cint),
         "tpcf_set_timing": ([P, cint], cint),
         "tpcf_kernel_time": ([P, P, P, cint], cint),
-        "tpcf_stats": ([P, P, P, P, P, cint], cint),
+        "tpcf_stats": ([P, P, P, P, P, P, cint], cint),
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
         "tpcf_compile_band64": ([P, i32, P, P], cint),
@@ -302,8 +302,8 @@ class Context:
         _check(lib().tpcf_cancel(self._h, job))
 
     def set_tuning(self, rows_per_lane: int = 0, hist_copies: int = 0, max_cols: int = 0,
-                   blocks_per_cu: int = 0, lut_bytes: int = 0, lut_clamped: int = 0):
-        t = Tuning(rows_per_lane, hist_copies, max_cols, blocks_per_cu, lut_bytes, lut_clamped)
+                   blocks_per_cu: int = 0, lut_bytes: int = 0, lut_direct: int = 0):
+        t = Tuning(rows_per_lane, hist_copies, max_cols, blocks_per_cu, lut_bytes, lut_direct)
         _check(lib().tpcf_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -332,8 +332,8 @@ class Context:
         return ms.value, n.value
 
     def stats(self, reset: bool = False):
-        """(pairs, flagged, exact, rare_steps) since the last reset."""
-        v = [ctypes.c_uint64() for _ in range(4)]
+        """(pairs, flagged, exact, rare_steps, beyond_steps) since the last reset."""
+        v = [ctypes.c_uint64() for _ in range(5)]
         _check(lib().tpcf_stats(self._h, *[ctypes.byref(x) for x in v], 1 if reset else 0))
         return tuple(x.value for x in v)
 
@@ -371,13 +371,11 @@ def compile_band64(edges_deg):
 
 
 def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None,
-                  direct: bool | None = None):
-    """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the layout
-    and table size the kernels use for this many bins."""
+                  direct: bool = False):
+    """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the table
+    size the kernels use for this many bins and layout."""
     e = _f64(edges_deg)
     byte_table = e.size + 1 <= 127
-    if direct is None:
-        direct = precision == FP32_CHORD and byte_table
     if max_cells is None:
         max_cells = 33792 if direct else 24576 if byte_table else 12288
     cells = np.zeros(max_cells, np.uint16)

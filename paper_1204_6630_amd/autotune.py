@@ -26,7 +26,7 @@ CANDIDATES = {
     "hist_copies": (0, 32, 8),
     "max_cols": (0, 16384),
     "blocks_per_cu": (0, 12),
-    "lut_clamped": (0, 1),
+    "lut_direct": (0, 1),
     "lut_bytes": (0, 16896),
 }
 

@@ -55,15 +55,15 @@ constexpr int kPoolStreams = 4;
 // Launch shape.  Zero fields take the defaults, which are the shapes the
 // autotuner picked on the large octant workload: 4 rows per lane on the vector
 // paths, 2 row groups of 16 on the matrix-core path (fewer registers, twice
-// the resident waves), 16 histogram copies, 4096-column units, and direct
-// FP32 byte tables of up to 33 KB.
+// the resident waves), 16 histogram copies, 4096-column units, and clamped
+// cell tables of up to 24 KB.
 struct Tuning {
     int rows_per_lane = 0;   // 2 or 4
     int hist_copies = 0;     // 4..32, at most what the slot count allows
     int max_cols = 0;        // largest column range of a work unit
     int blocks_per_cu = 0;   // 0: resident blocks x 4
     int lut_bytes = 0;       // largest cell table
-    int lut_clamped = 0;     // 1: FP32 byte tables in the clamped layout
+    int lut_direct = 0;      // 1: FP32 byte tables in the direct layout
 };
 
 int rows_per_lane_of(const Tuning &t, bool matrix) {
@@ -141,6 +141,7 @@ struct Compiled {
     int precision = 0;
     int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
     double delta = 0;
+    std::vector<double> thi;   // matrix-core band upper ends (host copy)
 };
 
 struct Plan {
@@ -382,7 +383,7 @@ std::string edges_key(const double *edges, int nbins, int precision, double delt
     if (precision == TPCF_FP32_CHORD)
         k.append((const char *)&delta, sizeof delta);
     k.append((const char *)&t.lut_bytes, sizeof t.lut_bytes);
-    k.append((const char *)&t.lut_clamped, sizeof t.lut_clamped);
+    k.append((const char *)&t.lut_direct, sizeof t.lut_direct);
     return k;
 }
 
@@ -433,7 +434,7 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     std::vector<double> tlo = c->edges.E, thi = c->edges.E;
     if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
-        if (c->entry_bytes == 1 && !ctx->tune.lut_clamped)
+        if (c->entry_bytes == 1 && ctx->tune.lut_direct)
             c->cells = make_cells32_direct(c->edges, c->band, delta,
                                            ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxDirectLutBytes);
         if (c->cells.cells.empty())
@@ -445,6 +446,7 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         c->cells = make_cells64_band(b, max_cells);
         tlo = b.lo;
         thi = b.hi;
+        c->thi = b.hi;
     } else {
         c->cells = make_cells64(c->edges, max_cells);
     }
@@ -495,21 +497,41 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
         bj = max_cols;
     if (bj < 256)
         bj = 256;
-    // row tiles start on multiples of `align` (valid rows from row_lo = rb)
-    for (int64_t i0 = rb - rb % align; i0 < re; i0 += T) {
-        const int64_t i1 = i0 + T < re ? i0 + T : re;
-        const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
-        if (auto_pairs) {
-            int64_t dend = i0 + T < na ? i0 + T : na;
+    // Row tiles start on multiples of `align` (valid rows from row_lo = rb).
+    // Column chunks lie on a common grid of multiples of bj, so units of
+    // different row tiles cover the same column ranges; the list is ordered
+    // column chunk first, so the units in flight at any time (a grid-stride
+    // window of consecutive units) share their columns and the column data
+    // stays in each XCD's L2.
+    const int64_t i_first = rb - rb % align;
+    if (auto_pairs) {
+        for (int64_t i0 = i_first; i0 < re; i0 += T) {
+            const int64_t i1 = i0 + T < re ? i0 + T : re;
+            const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
+            const int64_t dend = i0 + T < na ? i0 + T : na;
             if (lo + 1 < dend)
                 p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend, 0, lo, 0, 0});
-            for (int64_t j0 = dend; j0 < na; j0 += bj) {
-                int64_t j1 = j0 + bj < na ? j0 + bj : na;
+            int64_t j0 = dend;
+            while (j0 < na) {
+                // up to the next multiple of bj; a short first piece joins the next chunk
+                int64_t j1 = (j0 / bj + 1) * bj;
+                if (j1 - j0 < 256)
+                    j1 += bj;
+                if (j1 > na)
+                    j1 = na;
                 p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
+                j0 = j1;
             }
-        } else {
-            for (int64_t j0 = 0; j0 < nb; j0 += bj) {
-                int64_t j1 = j0 + bj < nb ? j0 + bj : nb;
+        }
+        std::sort(p.units.begin(), p.units.end(), [](const Unit &x, const Unit &y) {
+            return x.j1 != y.j1 ? x.j1 < y.j1 : x.i0 < y.i0;
+        });
+    } else {
+        for (int64_t j0 = 0; j0 < nb; j0 += bj) {
+            const int64_t j1 = j0 + bj < nb ? j0 + bj : nb;
+            for (int64_t i0 = i_first; i0 < re; i0 += T) {
+                const int64_t i1 = i0 + T < re ? i0 + T : re;
+                const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
                 p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
             }
         }
@@ -685,6 +707,17 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.lut_lo = cp.cells.lo;
     a.lut_hi = cp.cells.hi;
     a.lut_direct = cp.cells.direct ? 1 : 0;
+    // key of the last edge's certain side (see PairArgs::beyond_key)
+    const size_t last = cp.edges.D.size() - 1;
+    if (cp.precision == TPCF_FP32_CHORD) {
+        float qh = cp.band.qhi[last];
+        memcpy(&a.beyond_key, &qh, sizeof qh);
+    } else {
+        const double t = cp.precision == TPCF_FP64_MATRIX ? cp.thi[last] : cp.edges.E[last];
+        uint64_t b;
+        memcpy(&b, &t, sizeof b);
+        a.beyond_key = (uint32_t)(b >> 32);
+    }
     a.qlo = (const float *)cp.dqlo.p;
     a.qhi = (const float *)cp.dqhi.p;
     a.E = (const double *)cp.dE.p;
@@ -1300,15 +1333,15 @@ int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning) {
         return fail(TPCF_E_INVALID, "blocks_per_cu must be in [0, 64]");
     if (t.lut_bytes != 0 && (t.lut_bytes < 4096 || t.lut_bytes > kMaxDirectLutBytes))
         return fail(TPCF_E_INVALID, "lut_bytes must be 0 (default) or in [4096, 33792]");
-    if (t.lut_clamped != 0 && t.lut_clamped != 1)
-        return fail(TPCF_E_INVALID, "lut_clamped must be 0 or 1");
+    if (t.lut_direct != 0 && t.lut_direct != 1)
+        return fail(TPCF_E_INVALID, "lut_direct must be 0 or 1");
     Tuning u;
     u.rows_per_lane = t.rows_per_lane;
     u.hist_copies = t.hist_copies;
     u.max_cols = t.max_cols;
     u.blocks_per_cu = t.blocks_per_cu;
     u.lut_bytes = t.lut_bytes;
-    u.lut_clamped = t.lut_clamped;
+    u.lut_direct = t.lut_direct;
     ctx->tune = u;
     return TPCF_OK;
 }
@@ -1321,7 +1354,7 @@ int tpcf_get_tuning(tpcf_ctx *ctx, tpcf_tuning *out) {
     out->max_cols = ctx->tune.max_cols;
     out->blocks_per_cu = ctx->tune.blocks_per_cu;
     out->lut_bytes = ctx->tune.lut_bytes;
-    out->lut_clamped = ctx->tune.lut_clamped;
+    out->lut_direct = ctx->tune.lut_direct;
     return TPCF_OK;
 }
 
@@ -1378,7 +1411,7 @@ int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int r
 }
 
 int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
-               uint64_t *out_rare_steps, int reset) {
+               uint64_t *out_rare_steps, uint64_t *out_beyond_steps, int reset) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     TRY(set_device(ctx));
@@ -1405,6 +1438,8 @@ int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64
         *out_exact = tot[2];
     if (out_rare_steps)
         *out_rare_steps = tot[4];
+    if (out_beyond_steps)
+        *out_beyond_steps = tot[5];
     if (reset)
         ctx->pairs_since_reset = 0;
     return TPCF_OK;

@@ -76,6 +76,11 @@ struct PairArgs {
     int32_t lut_lo, lut_hi;      // clamp range of cells
     int32_t lut_direct;          // 1: FP32 table indexed from cell 0 without a clamp
                                  // (every reachable key lies inside it)
+    // Pairs certainly beyond the last edge: FP32 path, bits(q) >= beyond_key
+    // (the bits of the last edge's qhi); FP64 paths, high word of e = 1 - d
+    // above beyond_key as signed integers (e > E_last on the vector path,
+    // e >= the band's upper end on the matrix-core path).
+    uint32_t beyond_key;
 
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
@@ -90,7 +95,8 @@ struct PairArgs {
     int32_t rows_per_lane;       // 2 or 4: a unit spans kWaves * 64 * rows_per_lane rows
     int32_t blocks_per_cu;       // grid = CUs x this (0: resident blocks x 4)
 
-    unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps, -, -, -]
+    unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps,
+                                 //  steps counted beyond the last edge, -, -]
 };
 
 // LDS bytes used by one block for the given table sizes.

@@ -92,6 +92,15 @@ __device__ __forceinline__ uint32_t lds_read_entry(uint32_t addr) {
     return *(const lds_u16 *)(uintptr_t)addr;
 }
 
+__device__ __forceinline__ void lds_add(uint32_t addr, uint32_t v) {
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// True when `pred` holds on every lane of the (fully active) wavefront.
+__device__ __forceinline__ bool wave_all(bool pred) {
+    return __builtin_amdgcn_ballot_w64(pred) == ~0ull;
+}
+
 __device__ __forceinline__ void lds_inc(uint32_t addr) {
     __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -234,6 +243,8 @@ __device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, uint32_t flag, do
 // by the exact FP64 rule, and (wavefront-uniform) steps that took the rare path.
 struct Counters {
     uint32_t flag = 0, exact = 0, rare = 0;
+    uint32_t beyond = 0;        // this lane's pairs counted beyond the last edge (per unit)
+    uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
 };
 
 // Loop constants of one wavefront.
@@ -244,6 +255,7 @@ struct Consts {
     uint32_t rowstep;       // bytes between slots of the histogram
     uint32_t lanebase;      // LDS address of this lane's copy of slot 0
     uint32_t flag;          // flag bit of the cell entries (VGPR copy)
+    uint32_t beyond;        // PairArgs::beyond_key
 };
 
 // One step: JN columns against the P rows of every lane.  All JN * P table
@@ -275,6 +287,28 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             v = __fmaf_rn(dy, dy, v);
             v = __fmaf_rn(dz, dz, v);
             q[t][p] = v;
+        }
+    }
+    if (!MASKED) {
+        // every pair of the step certainly beyond the last edge (q >= 0, so the
+        // bit patterns order like the values): count them in a register
+        uint32_t m = __float_as_uint(q[0][0]);
+#pragma unroll
+        for (int t = 0; t < JN; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                m = min(m, __float_as_uint(q[t][p]));
+        if (wave_all(m >= k.beyond)) {
+            cnt.beyond += JN * P;
+            ++cnt.beyond_steps;
+            return;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const float v = q[t][p];
             uint32_t addr;
             if (DIRECT) {
                 // byte table from cell 0 at LDS address 0 (the kernel has no
@@ -338,9 +372,29 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             double dd = exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
-            double ee = 1.0 - dd;
             d[t][p] = dd;
-            e[t][p] = ee;
+            e[t][p] = 1.0 - dd;
+        }
+    }
+    if (!MASKED) {
+        // high word of e above that of E_last implies e > E_last for every pair
+        int32_t m = __double2hiint(e[0][0]);
+#pragma unroll
+        for (int t = 0; t < JN; ++t)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                m = min(m, __double2hiint(e[t][p]));
+        if (wave_all(m > (int32_t)k.beyond)) {
+            cnt.beyond += JN * P;
+            ++cnt.beyond_steps;
+            return;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < JN; ++t) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double ee = e[t][p];
             // arithmetic shift: e < 0 (d > 1 from rounding) lands in the bottom cell
             int32_t c = med3_i32(__double2hiint(ee) >> (int)k.shift, (int32_t)k.clo, (int32_t)k.chi);
             ent[t][p] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
@@ -487,6 +541,21 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
 #pragma unroll
         for (int g = 0; g < RG; ++g)
             d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
+        if (!MASKED) {
+            // every pair of the tile certainly beyond the last edge: high word
+            // of e above that of the band's upper end
+            int32_t m = __double2hiint(d[0][0]);
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    m = min(m, __double2hiint(d[g][r]));
+            if (wave_all(m > (int32_t)k.beyond)) {
+                cnt.beyond += RG * 4;
+                ++cnt.beyond_steps;
+                continue;
+            }
+        }
         uint32_t ent[RG][4];
         uint32_t any = 0;
 #pragma unroll
@@ -568,6 +637,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     k.lutbias = s.lut_addr - (uint32_t)a.lut_lo * (LUT8 ? 1u : 2u);
     k.rowstep = (uint32_t)a.hist_copies * 4u;
     k.flag = to_vgpr(Code<LUT8>::flag);
+    k.beyond = a.beyond_key;
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     Counters cnt;
@@ -603,7 +673,13 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                 else
                     rows_fp64<LUT8, false, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             }
-            // the wave's own LDS region only: no block barrier needed
+            // pairs counted beyond the last edge go to this lane's copy of the
+            // overflow slot; then the wave's own LDS region is flushed (no
+            // block barrier needed)
+            if (cnt.beyond) {
+                lds_add(__umul24((uint32_t)(a.nslots - 1), k.rowstep) + k.lanebase, cnt.beyond);
+                cnt.beyond = 0;
+            }
             flush_wave(a, s, jb.hist, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
         }
     }
@@ -618,6 +694,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[3], (unsigned long long)n_skip);
         if (cnt.rare)
             atomicAdd(&a.stats[4], (unsigned long long)cnt.rare);
+        if (cnt.beyond_steps)
+            atomicAdd(&a.stats[5], (unsigned long long)cnt.beyond_steps);
     }
 }
 

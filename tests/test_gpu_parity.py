@@ -261,12 +261,15 @@ def test_timing_and_stats(ctx, cfg1):
     ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
     ms, n = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    pairs, flagged, exact, rare = ctx.stats(reset=True)
+    pairs, flagged, exact, rare, beyond = ctx.stats(reset=True)
     assert n == 1 and ms > 0
     assert pairs == wl.data[0].n * wl.randoms[0].n
     assert exact <= flagged <= pairs
     assert rare <= flagged
     assert flagged < 0.2 * pairs
+    # a 30 x 30 deg patch against edges up to 10 deg: many wavefront steps
+    # (4 rows x 2 columns per lane) lie wholly beyond the last edge
+    assert 0 < beyond * 512 < pairs
 
 
 def test_repeatable(ctx, cfg1):
@@ -303,7 +306,7 @@ def test_gpu_error_paths(ctx, cfg1):
         ctx.release_catalog(9999)
     assert ei.value.code == -4
     for bad in ({"rows_per_lane": 3}, {"hist_copies": 12}, {"max_cols": 300}, {"blocks_per_cu": -1},
-                {"lut_bytes": 100}, {"lut_bytes": 40000}, {"lut_clamped": 2}):
+                {"lut_bytes": 100}, {"lut_bytes": 40000}, {"lut_direct": 2}):
         with pytest.raises(tp.TpcfError):
             ctx.set_tuning(**bad)
     assert ctx.get_tuning() == {k: 0 for k in ctx.get_tuning()}
@@ -320,7 +323,7 @@ def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
                 for mc, bpc, lb, lc in ((256, 1, 0, 0), (16384, 0, 4096, 1), (4096, 3, 4096, 0),
                                         (4096, 0, 33792, 1)):
                     ctx.set_tuning(rows_per_lane=rpl, hist_copies=hc, max_cols=mc, blocks_per_cu=bpc,
-                                   lut_bytes=lb, lut_clamped=lc)
+                                   lut_bytes=lb, lut_direct=lc)
                     for prec in PRECS:
                         assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), ref["DD"])
                         assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
