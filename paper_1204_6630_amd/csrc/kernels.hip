@@ -508,11 +508,82 @@ __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, dou
     return count_le(d, s.D, a.nedges);
 }
 
+// Bin the 16 x (RG x 16) pairs of one column group whose e = 1 - d the matrix
+// cores left in d (row group g, output register r of this lane: row
+// ib + 16 g + mma_row(lane, r), column 16 jg + mma_col(lane)).
+template <bool LUT8, bool MASKED, int RG>
+__device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, const Smem &s,
+                                         const Consts &k, const v4d (&d)[RG], int ib, int rlo, int ie,
+                                         int jg, int j1, int lane, Counters &cnt) {
+    if (!MASKED) {
+        // every pair of the tile certainly beyond the last edge: high word of
+        // e above that of the band's upper end
+        int32_t m = __double2hiint(d[0][0]);
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                m = min(m, __double2hiint(d[g][r]));
+        if (wave_all(m > (int32_t)k.beyond)) {
+            cnt.beyond += RG * 4;
+            ++cnt.beyond_steps;
+            return;
+        }
+    }
+    uint32_t ent[RG][4];
+    uint32_t any = 0;
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t c = med3_i32(__double2hiint(d[g][r]) >> (int)k.shift, (int32_t)k.clo,
+                                       (int32_t)k.chi);
+            ent[g][r] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
+        }
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            any |= ent[g][r];
+    if (any & k.flag) {
+        ++cnt.rare;
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (ent[g][r] & k.flag) {
+                    ++cnt.flag;
+                    int i = min(ib + 16 * g + mma_row(lane, r), jb.na - 1);
+                    // opaque here, so the row addresses of this rare path are
+                    // formed on demand and do not occupy registers in the loop
+                    asm volatile("" : "+v"(i));
+                    const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
+                    ent[g][r] = resolve_mma<LUT8>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
+                }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t v = ent[g][r];
+            if (MASKED) {
+                const int i = ib + 16 * g + mma_row(lane, r);
+                const int j = 16 * jg + mma_col(lane);
+                bool ok = i >= rlo && i < ie && j < j1 && (!jb.auto_pairs || j > i);
+                v = ok ? v : (uint32_t)a.nslots;
+            }
+            lds_inc(__umul24(v, k.rowstep) + k.lanebase);
+        }
+}
+
 // Matrix-core path, one wavefront: RG groups of 16 rows starting at ib
 // (valid rows [rlo, ie)) against the column groups of [j0, j1).  For every
 // 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
 // (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
 // then binned exactly as on the vector path, against the matrix-core band.
+// The loop is software-pipelined: the products of the next column group are
+// issued before the current group is binned, so the matrix cores work while
+// the wavefront does its lookups.
 template <bool LUT8, bool MASKED, int RG>
 __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                          int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
@@ -527,76 +598,44 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
         A[g] = lane < 48 ? -v : v;
     }
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    const int jg0 = j0 >> 4;
     const int jg_end = (j1 + 15) >> 4;
     const int jg_last = jb.b_groups - 1;
-    // column operands are fetched two groups ahead (clamped to the last group
-    // of the catalog, so the reads never leave it)
-    double b_next = bp[(size_t)min(j0 >> 4, jg_last) * 64];
-    double b_next2 = bp[(size_t)min((j0 >> 4) + 1, jg_last) * 64];
-    for (int jg = j0 >> 4; jg < jg_end; ++jg) {
-        const double b = b_next;
-        b_next = b_next2;
-        b_next2 = bp[(size_t)min(jg + 2, jg_last) * 64];
-        v4d d[RG];
+    // column operands are fetched two groups ahead of their products
+    // (clamped to the last group of the catalog, so the reads never leave it)
+    double bq0 = bp[(size_t)min(jg0, jg_last) * 64];
+    double bq1 = bp[(size_t)min(jg0 + 1, jg_last) * 64];
+    v4d d0[RG], d1[RG];
+    {
+        const double b = bq0;
+        bq0 = bq1;
+        bq1 = bp[(size_t)min(jg0 + 2, jg_last) * 64];
 #pragma unroll
         for (int g = 0; g < RG; ++g)
-            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
-        if (!MASKED) {
-            // every pair of the tile certainly beyond the last edge: high word
-            // of e above that of the band's upper end
-            int32_t m = __double2hiint(d[0][0]);
+            d0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
+    }
+    for (int jg = jg0; jg < jg_end; jg += 2) {
+        const bool has1 = jg + 1 < jg_end;
+        if (has1) {
+            const double b = bq0;
+            bq0 = bq1;
+            bq1 = bp[(size_t)min(jg + 3, jg_last) * 64];
 #pragma unroll
             for (int g = 0; g < RG; ++g)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    m = min(m, __double2hiint(d[g][r]));
-            if (wave_all(m > (int32_t)k.beyond)) {
-                cnt.beyond += RG * 4;
-                ++cnt.beyond_steps;
-                continue;
-            }
+                d1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
         }
-        uint32_t ent[RG][4];
-        uint32_t any = 0;
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int32_t c = med3_i32(__double2hiint(d[g][r]) >> (int)k.shift, (int32_t)k.clo,
-                                           (int32_t)k.chi);
-                ent[g][r] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
-            }
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                any |= ent[g][r];
-        if (any & k.flag) {
-            ++cnt.rare;
+        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d0, ib, rlo, ie, jg, j1, lane, cnt);
+        if (!has1)
+            break;
+        if (jg + 2 < jg_end) {
+            const double b = bq0;
+            bq0 = bq1;
+            bq1 = bp[(size_t)min(jg + 4, jg_last) * 64];
 #pragma unroll
             for (int g = 0; g < RG; ++g)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (ent[g][r] & k.flag) {
-                        ++cnt.flag;
-                        const int i = min(ib + 16 * g + mma_row(lane, r), jb.na - 1);
-                        const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
-                        ent[g][r] = resolve_mma<LUT8>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
-                    }
+                d0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
         }
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                uint32_t v = ent[g][r];
-                if (MASKED) {
-                    const int i = ib + 16 * g + mma_row(lane, r);
-                    const int j = 16 * jg + mma_col(lane);
-                    bool ok = i >= rlo && i < ie && j < j1 && (!jb.auto_pairs || j > i);
-                    v = ok ? v : (uint32_t)a.nslots;
-                }
-                lds_inc(__umul24(v, k.rowstep) + k.lanebase);
-            }
+        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d1, ib, rlo, ie, jg + 1, j1, lane, cnt);
     }
 }
 
