@@ -208,8 +208,8 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  *                 lowered;
  * max_cols        largest column range of a work unit, multiple of 256 in
  *                 [256, 65536] (default 4096);
- * blocks_per_cu   grid size per compute unit, <= 64 (default: resident
- *                 blocks x 4);
+ * blocks_per_cu   grid size per compute unit, <= 64 (default: the blocks
+ *                 that fit at once; wavefronts take work from a queue);
  * lut_bytes       largest cell table held in LDS, 4096..33792 bytes
  *                 (default 24576, or 33792 for direct tables);
  * lut_direct      1: FP32 byte tables in the direct layout, indexed from

@@ -61,7 +61,7 @@ struct Tuning {
     int rows_per_lane = 0;   // 2 or 4
     int hist_copies = 0;     // 4..32, at most what the slot count allows
     int max_cols = 0;        // largest column range of a work unit
-    int blocks_per_cu = 0;   // 0: resident blocks x 4
+    int blocks_per_cu = 0;   // 0: the blocks that fit at once
     int lut_bytes = 0;       // largest cell table
     int lut_direct = 0;      // 1: FP32 byte tables in the direct layout
 };
@@ -760,14 +760,16 @@ int record_stop(tpcf_ctx *ctx, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
 int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long *d_out,
                const int *cancel) {
     const int nslots = r.nbins + 2;
-    TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * kGlobalCopies * kMaxSlots));
+    // the histogram copies, then the work-queue counter, zeroed together
+    TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * ((size_t)kGlobalCopies * kMaxSlots + 1)));
     unsigned long long *copies = (unsigned long long *)w.copies.p;
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots, w.stream));
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots + 1, w.stream));
     PairArgs a = args_of(ctx, *r.cp, r.nbins, (unsigned long long *)w.stats.p);
     a.jobs = nullptr;
     a.job0 = job_of(r, copies, cancel);
     a.units = (const Unit *)r.plan->dunits.p;
     a.n_units = (int32_t)r.plan->units.size();
+    a.queue = (unsigned int *)(copies + (size_t)kGlobalCopies * nslots);
     hipEvent_t e0, e1;
     if (a.n_units > 0)
         TRY(record_start(ctx, w.stream, &e0, &e1));
@@ -1106,7 +1108,8 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
         TRY(prepare(ctx, jobs[k], delta, &reqs[k]));
     const int nslots = nbins + 2;
     const int prec = jobs[0].precision;
-    const size_t copies_bytes = sizeof(unsigned long long) * (size_t)njobs * kGlobalCopies * nslots;
+    // every job's histogram copies, then the work-queue counter
+    const size_t copies_bytes = sizeof(unsigned long long) * ((size_t)njobs * kGlobalCopies * nslots + 1);
     const size_t out_bytes = sizeof(unsigned long long) * (size_t)njobs * nslots;
     hipStream_t st = ctx->main.stream;
     const bool use_graph = (flags & TPCF_BATCH_GRAPH) != 0;
@@ -1156,6 +1159,7 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
         a.jobs = (const JobDev *)g->jobs.p;
         a.units = (const Unit *)g->units.p;
         a.n_units = (int32_t)hu.size();
+        a.queue = (unsigned int *)((unsigned long long *)g->copies.p + (size_t)njobs * kGlobalCopies * nslots);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (use_graph) {
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -1164,7 +1168,8 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
                 return fail(TPCF_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
             }
         }
-        int lrc = tpcf_launch_zero_u64((unsigned long long *)g->copies.p, (int64_t)njobs * kGlobalCopies * nslots, st);
+        int lrc = tpcf_launch_zero_u64((unsigned long long *)g->copies.p,
+                                       (int64_t)njobs * kGlobalCopies * nslots + 1, st);
         if (!lrc && !use_graph)
             rc = record_start(ctx, st, &e0, &e1);
         if (!lrc && !rc)

@@ -67,6 +67,10 @@ struct PairArgs {
     JobDev job0;                 // the job of a single-job launch (passed by value)
     const Unit *units;           // device
     int32_t n_units;
+    // Work queue: item q is wavefront part q % kWaves of unit q / kWaves;
+    // wavefronts take items in order with an atomic add on *queue (zeroed
+    // before the launch) until they pass n_units * kWaves.
+    unsigned int *queue;
 
     // Cell table (device, copied into LDS by every block).
     const void *lut;
@@ -93,7 +97,7 @@ struct PairArgs {
     // Per-wave LDS histogram copies (layout [slot][copy]).
     int32_t hist_copies;         // 32, 16, 8 or 4
     int32_t rows_per_lane;       // 2 or 4: a unit spans kWaves * 64 * rows_per_lane rows
-    int32_t blocks_per_cu;       // grid = CUs x this (0: resident blocks x 4)
+    int32_t blocks_per_cu;       // grid = CUs x this (0: the blocks that fit at once)
 
     unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps,
                                  //  steps counted beyond the last edge, -, -]

@@ -682,10 +682,23 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     Counters cnt;
 
     uint32_t n_skip = 0;
-    for (int u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+    // Each wavefront takes work items in order from the queue, so the items in
+    // flight are always a window of consecutive units that share their column
+    // range (the plan orders units column chunk first) and the column data
+    // stays in L2.  Every wavefront leaves once the queue is exhausted.
+    const uint32_t n_items = (uint32_t)a.n_units * kWaves;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0)
+            item = atomicAdd(a.queue, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items)
+            break;
+        const int u = (int)(item / kWaves);
+        const int part = (int)(item % kWaves);
         const Unit un = load_uniform(a.units + u);
         const JobDev jb = a.jobs ? load_uniform(a.jobs + un.job) : a.job0;
-        const int ib = un.i0 + wave * kRowsPerWave;
+        const int ib = un.i0 + part * kRowsPerWave;
         if (ib < un.i1) {
             // a cancelled job skips its remaining units (the flag lives in host memory)
             if (jb.cancel && __hip_atomic_load(jb.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
@@ -719,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                 lds_add(__umul24((uint32_t)(a.nslots - 1), k.rowstep) + k.lanebase, cnt.beyond);
                 cnt.beyond = 0;
             }
-            flush_wave(a, s, jb.hist, wave, lane, (u * kWaves + wave) & (kGlobalCopies - 1));
+            flush_wave(a, s, jb.hist, wave, lane, (int)(item & (kGlobalCopies - 1)));
         }
     }
     uint32_t f = wave_sum(cnt.flag);
@@ -824,8 +837,9 @@ int grid_for(int n_units, int lds, int blocks_per_cu) {
         per_cu = 1;
     if (per_cu > 8)
         per_cu = 8;
-    // resident blocks x 4 by default; blocks_per_cu > 0 overrides
-    long long g = blocks_per_cu > 0 ? (long long)cus * blocks_per_cu : (long long)cus * per_cu * 4;
+    // the resident blocks by default (the work queue balances them);
+    // blocks_per_cu > 0 overrides
+    long long g = blocks_per_cu > 0 ? (long long)cus * blocks_per_cu : (long long)cus * per_cu;
     if (g > n_units)
         g = n_units;
     if (g < 1)
