@@ -23,10 +23,17 @@ import time
 import numpy as np
 
 METRIC = "exact-count Gpairs/s, FP32-chord vs FP64 path; p50/p99 job latency"
-# FP32-VALU pair roofline: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 VALU lane
-# issue slots per second, 4 slots per pair (chord^2 as packed FP32 plus one
-# for the bin decision) -> 9.83e12 pairs/s.
-PEAK_GPAIRS = 256 * 64 * 2.4e9 / 4 / 1e9
+# ALU roofline of the FP32-chord path: 256 CUs x 4 SIMDs x 32 FP32 lanes x
+# 2.4 GHz = 78.6e12 FP32 lane operations per second (157.3 TFLOP/s counting an
+# FMA as two), and a pair needs at least 7 of them: 3 subtractions, one
+# multiply and two FMAs for the squared chord, one shift for the table key.
+FP32_LANE_OPS = 256 * 4 * 32 * 2.4e9
+OPS_PER_PAIR_FP32 = 7
+PEAK_GPAIRS = FP32_LANE_OPS / OPS_PER_PAIR_FP32 / 1e9
+# FP64 vector path: 78.6e12 FP64 lane operations per second; a pair needs 6
+# (three products, two sums, 1 - d) plus the key.
+FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9
+OPS_PER_PAIR_FP64 = 7
 # FP64 matrix-core path: MI355X dense FP64 MFMA peak, and the algorithmic
 # flops of one pair (three products, two sums for the dot, one for 1 - d).
 PEAK_FP64_TFLOPS = 78.6
@@ -34,6 +41,46 @@ FLOPS_PER_PAIR = 6
 PATH_NAMES = {0: "fp32_chord", 1: "fp64", 2: "fp64_matrix"}
 KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)",
                 2: "pairs_kernel<2> (FP64 matrix cores)"}
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_octant_1e6x2e6.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(HERE, "paper_1204_6630_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path: str):
+    """HBM bytes per launch of a pair kernel on the octant workload, from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
+    kernel sources changed since those counters were taken."""
+    try:
+        rows = dict(line.split()[:2] for line in open(TRAFFIC_FILE)
+                    if line.strip() and not line.startswith("#"))
+    except (OSError, ValueError):
+        return None
+    if rows.get("kernels_sha256") != kernel_source_hash() or path not in rows:
+        return None
+    return int(float(rows[path]))
+
+
+def roofline(prec: int, kernel_gpairs: float, ms_per_launch: float, traffic=None) -> dict:
+    if prec == 2:
+        achieved = kernel_gpairs * 1e9 * FLOPS_PER_PAIR / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "flops_per_pair": FLOPS_PER_PAIR}
+    else:
+        peak = PEAK_GPAIRS if prec == 0 else FP64_LANE_OPS / OPS_PER_PAIR_FP64 / 1e9
+        roof = {"bound": "alu", "achieved": round(kernel_gpairs, 1), "peak": round(peak, 1),
+                "unit": "Gpairs/s", "frac": round(kernel_gpairs / peak, 4)}
+    roof.update({"traffic": traffic, "kernel": KERNEL_NAMES[prec],
+                 "kernel_ms_per_launch": round(ms_per_launch, 3)})
+    return roof
 
 
 def parse():
@@ -138,9 +185,7 @@ def bench_batched(args, tp, torch):
         "config": {"workload": wl.name, "catalogs": len(cats), "n_random": r.n,
                    "nbins": int(e.size - 1), "pairs_per_step": pairs, "jobs": len(jobs),
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "alu", "achieved": round(kg, 1), "peak": round(PEAK_GPAIRS, 1),
-                     "unit": "Gpairs/s", "frac": round(kg / PEAK_GPAIRS, 4), "traffic": None,
-                     "kernel": "pairs_kernel<0> (FP32 chord), one launch per batch"},
+        "roofline": roofline(tp.FP32_CHORD, kg, kms / max(1, launches)),
         "separate_launches_gpairs_s": round(sep_value, 2),
         "batched_over_separate": round(value / sep_value, 3),
     }
@@ -329,17 +374,8 @@ def main():
     sums = {prec: summary(prec) for prec in paths}
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
-    kg = hs["kernel_gpairs_s"]
-    if head == tp.FP64_MATRIX:
-        achieved = kg * 1e9 * FLOPS_PER_PAIR / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "flops_per_pair": FLOPS_PER_PAIR}
-    else:
-        roof = {"bound": "alu", "achieved": round(kg, 1), "peak": round(PEAK_GPAIRS, 1),
-                "unit": "Gpairs/s", "frac": round(kg / PEAK_GPAIRS, 4)}
-    roof.update({"traffic": None, "kernel": KERNEL_NAMES[head],
-                 "kernel_ms_per_launch": hs["kernel_ms_per_launch"]})
+    roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
+                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 else None)
     res = {
         "metric": METRIC,
         "value": hs["gpairs_s"],
