@@ -255,7 +255,7 @@ struct Consts {
     uint32_t rowstep;       // bytes between slots of the histogram
     uint32_t lanebase;      // LDS address of this lane's copy of slot 0
     uint32_t flag;          // flag bit of the cell entries (VGPR copy)
-    uint32_t beyond;        // PairArgs::beyond_key
+    uint32_t beyond;        // PairArgs::beyond_key (VGPR copy)
 };
 
 // One step: JN columns against the P rows of every lane.  All JN * P table
@@ -265,15 +265,8 @@ template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT>
 __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
-                                          const int (&il)[P], int ie, int j, cfloat_p bx,
-                                          cfloat_p by, cfloat_p bz, Counters &cnt) {
-    float xj[JN], yj[JN], zj[JN];
-#pragma unroll
-    for (int t = 0; t < JN; ++t) {
-        xj[t] = bx[j + t];
-        yj[t] = by[j + t];
-        zj[t] = bz[j + t];
-    }
+                                          const int (&il)[P], int ie, int j, const float (&xj)[JN],
+                                          const float (&yj)[JN], const float (&zj)[JN], Counters &cnt) {
     float q[JN][P];
     uint32_t ent[JN][P];
 #pragma unroll
@@ -448,12 +441,43 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
     cfloat_p bz = (cfloat_p)jb.bz32;
+    constexpr int JN = kColsPerStep;
     int j = j0;
-    for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp32<LUT8, MASKED, P, kColsPerStep, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by,
-                                                         bz, cnt);
-    for (; j < j1; ++j)
-        step_fp32<LUT8, MASKED, P, 1, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, bx, by, bz, cnt);
+    if (j + JN <= j1) {
+        // the columns of the next step are read (through the scalar unit)
+        // while the current step computes; the last prefetch re-reads the
+        // current columns, so no read leaves [j0, j1)
+        float xj[JN], yj[JN], zj[JN];
+#pragma unroll
+        for (int t = 0; t < JN; ++t) {
+            xj[t] = bx[j + t];
+            yj[t] = by[j + t];
+            zj[t] = bz[j + t];
+        }
+        for (; j + JN <= j1; j += JN) {
+            const int jn = j + 2 * JN <= j1 ? j + JN : j;
+            float xn[JN], yn[JN], zn[JN];
+#pragma unroll
+            for (int t = 0; t < JN; ++t) {
+                xn[t] = bx[jn + t];
+                yn[t] = by[jn + t];
+                zn[t] = bz[jn + t];
+            }
+            // keep the prefetch at the top of the step
+            __builtin_amdgcn_sched_barrier(0);
+            step_fp32<LUT8, MASKED, P, JN, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+#pragma unroll
+            for (int t = 0; t < JN; ++t) {
+                xj[t] = xn[t];
+                yj[t] = yn[t];
+                zj[t] = zn[t];
+            }
+        }
+    }
+    for (; j < j1; ++j) {
+        const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
+        step_fp32<LUT8, MASKED, P, 1, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+    }
 }
 
 template <bool LUT8, bool MASKED, int P>
@@ -676,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     k.lutbias = s.lut_addr - (uint32_t)a.lut_lo * (LUT8 ? 1u : 2u);
     k.rowstep = (uint32_t)a.hist_copies * 4u;
     k.flag = to_vgpr(Code<LUT8>::flag);
-    k.beyond = a.beyond_key;
+    k.beyond = to_vgpr(a.beyond_key);
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     Counters cnt;
