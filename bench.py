@@ -328,17 +328,17 @@ def main():
         t1 = time.perf_counter()
         ctx.set_timing(False)
         kms, launches = ctx.kernel_time(reset=True)
-        pairs, flagged, exact, rare, beyond = ctx.stats(reset=True)
+        pairs, flagged, exact, rare, beyond, one_slot = ctx.stats(reset=True)
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
         t = ctx.get_tuning()     # 0 = the library's default
-        rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
+        rpl = t["rows_per_lane"] or 4
         tuning = dict(t, rows_per_lane=rpl, autotuned=tuning is not None)
         rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
         cols_per_step = 16 if prec == tp.FP64_MATRIX else 2
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
                 "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,
-                "beyond": beyond,
+                "beyond": beyond, "one_slot": one_slot,
                 "tuning": tuning, "pairs_per_wave_step": rows_per_step * cols_per_step}
 
     print(f"# workload {wl.name}: N_D={nd} N_R={nr} nbins={edges.size - 1} "
@@ -369,7 +369,8 @@ def main():
                 "flagged_rate": r["flagged"] / max(1, r["pairs"]),
                 "exact_rate": r["exact"] / max(1, r["pairs"]),
                 "rare_step_rate": r["rare"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
-                "beyond_last_edge_rate": r["beyond"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
+                "beyond_last_edge_rate": r["beyond"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
+                "one_slot_rate": r["one_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
 
     sums = {prec: summary(prec) for prec in paths}
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])

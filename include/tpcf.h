@@ -201,7 +201,7 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * Every field 0 takes the default.
  * rows_per_lane   vector paths: 2 or 4 rows held in registers per lane;
  *                 matrix-core path: 2 or 4 groups of 16 rows per wavefront
- *                 (default: 4 on the vector paths, 2 on the matrix-core path);
+ *                 (default 4);
  * hist_copies     LDS histogram copies per wavefront, 4, 8, 16 or 32
  *                 (default 16); a value above what the slot count allows
  *                 (32 up to 46 slots, 16 up to 94, 8 up to 190, else 4) is
@@ -247,15 +247,23 @@ int tpcf_synchronize(tpcf_ctx *ctx);
 int tpcf_set_timing(tpcf_ctx *ctx, int on);
 int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int reset);
 
-/* Work statistics since the last reset: pairs evaluated, pairs that left the
- * table-driven path for a threshold comparison, pairs re-decided with the
- * exact FP64 rule (FP32_CHORD band pairs, or FP64 ties), wavefront steps
- * (64 lanes x a few pairs each) that took the rare path, and wavefront steps
- * whose pairs all lay certainly beyond the last edge and were counted in
- * registers without table lookups.  Waits for all of the context's streams.
- * Any output pointer may be NULL. */
-int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
-               uint64_t *out_rare_steps, uint64_t *out_beyond_steps, int reset);
+/* Work statistics since the last reset. */
+typedef struct tpcf_counters {
+    uint64_t pairs;           /* pairs evaluated */
+    uint64_t flagged;         /* pairs that left the table-driven path for a threshold comparison */
+    uint64_t exact;           /* pairs re-decided with the exact FP64 rule (FP32_CHORD band
+                                 pairs, FP64 ties, matrix-core band pairs) */
+    uint64_t rare_steps;      /* wavefront steps (64 lanes x a few pairs each) that took the
+                                 rare path */
+    uint64_t beyond_steps;    /* steps whose pairs all lay certainly beyond the last edge,
+                                 counted in registers without table lookups */
+    uint64_t one_slot_steps;  /* steps where each lane's pairs all fell in one certain slot,
+                                 added with one LDS atomic per lane */
+} tpcf_counters;
+
+/* Copy the statistics to *out (may be NULL) and, with reset = 1, clear
+ * them.  Waits for all of the context's streams. */
+int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset);
 
 /* Landy-Szalay estimator (Eq. 1), host FP64; no context needed.
  * dd, dr, rr  histograms of nbins+2 slots as returned by tpcf_count (DD and

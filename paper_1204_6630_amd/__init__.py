@@ -11,6 +11,7 @@ fallback.
 
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 
@@ -19,7 +20,7 @@ import numpy as np
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
     "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
-    "BATCH_GRAPH", "Tuning",
+    "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
 DD, DR, RR = 0, 1, 2
@@ -56,6 +57,15 @@ class JobDesc(ctypes.Structure):
 
 
 BATCH_GRAPH = 1
+
+
+class Counters(ctypes.Structure):
+    """struct tpcf_counters"""
+    _fields_ = [(n, ctypes.c_uint64) for n in ("pairs", "flagged", "exact", "rare_steps",
+                                               "beyond_steps", "one_slot_steps")]
+
+
+Stats = collections.namedtuple("Stats", [n for n, _ in Counters._fields_])
 
 
 class Tuning(ctypes.Structure):
@@ -124,7 +134,7 @@ def lib():
         "tpcf_synchronize": ([P], cint),
         "tpcf_set_timing": ([P, cint], cint),
         "tpcf_kernel_time": ([P, P, P, cint], cint),
-        "tpcf_stats": ([P, P, P, P, P, P, cint], cint),
+        "tpcf_stats": ([P, P, cint], cint),
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
         "tpcf_compile_band64": ([P, i32, P, P], cint),
@@ -331,11 +341,11 @@ class Context:
         _check(lib().tpcf_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
         return ms.value, n.value
 
-    def stats(self, reset: bool = False):
-        """(pairs, flagged, exact, rare_steps, beyond_steps) since the last reset."""
-        v = [ctypes.c_uint64() for _ in range(5)]
-        _check(lib().tpcf_stats(self._h, *[ctypes.byref(x) for x in v], 1 if reset else 0))
-        return tuple(x.value for x in v)
+    def stats(self, reset: bool = False) -> "Stats":
+        """Work statistics since the last reset (``tpcf_counters``)."""
+        c = Counters()
+        _check(lib().tpcf_stats(self._h, ctypes.byref(c), 1 if reset else 0))
+        return Stats(*(getattr(c, n) for n, _ in Counters._fields_))
 
 
 def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:

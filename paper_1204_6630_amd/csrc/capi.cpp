@@ -54,9 +54,8 @@ constexpr int kPoolStreams = 4;
 // Launch shape, set by tpcf_set_tuning (the autotuner) or left at defaults.
 // Launch shape.  Zero fields take the defaults, which are the shapes the
 // autotuner picked on the large octant workload: 4 rows per lane on the vector
-// paths, 2 row groups of 16 on the matrix-core path (fewer registers, twice
-// the resident waves), 16 histogram copies, 4096-column units, and clamped
-// cell tables of up to 24 KB.
+// paths and 4 row groups of 16 on the matrix-core path, 16 histogram copies,
+// 4096-column units, and clamped cell tables of up to 24 KB.
 struct Tuning {
     int rows_per_lane = 0;   // 2 or 4
     int hist_copies = 0;     // 4..32, at most what the slot count allows
@@ -66,8 +65,8 @@ struct Tuning {
     int lut_direct = 0;      // 1: FP32 byte tables in the direct layout
 };
 
-int rows_per_lane_of(const Tuning &t, bool matrix) {
-    return t.rows_per_lane ? t.rows_per_lane : (matrix ? 2 : 4);
+int rows_per_lane_of(const Tuning &t, bool) {
+    return t.rows_per_lane ? t.rows_per_lane : 4;
 }
 
 int max_cols_of(const Tuning &t) { return t.max_cols ? t.max_cols : 4096; }
@@ -1415,8 +1414,7 @@ int tpcf_kernel_time(tpcf_ctx *ctx, double *out_ms, int64_t *out_launches, int r
     return TPCF_OK;
 }
 
-int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64_t *out_exact,
-               uint64_t *out_rare_steps, uint64_t *out_beyond_steps, int reset) {
+int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     TRY(set_device(ctx));
@@ -1435,16 +1433,14 @@ int tpcf_stats(tpcf_ctx *ctx, uint64_t *out_pairs, uint64_t *out_flagged, uint64
     }
     if (reset)
         TRY(sync_all(ctx));
-    if (out_pairs)
-        *out_pairs = ctx->pairs_since_reset;
-    if (out_flagged)
-        *out_flagged = tot[1];
-    if (out_exact)
-        *out_exact = tot[2];
-    if (out_rare_steps)
-        *out_rare_steps = tot[4];
-    if (out_beyond_steps)
-        *out_beyond_steps = tot[5];
+    if (out) {
+        out->pairs = ctx->pairs_since_reset;
+        out->flagged = tot[1];
+        out->exact = tot[2];
+        out->rare_steps = tot[4];
+        out->beyond_steps = tot[5];
+        out->one_slot_steps = tot[6];
+    }
     if (reset)
         ctx->pairs_since_reset = 0;
     return TPCF_OK;

@@ -100,7 +100,7 @@ struct PairArgs {
     int32_t blocks_per_cu;       // grid = CUs x this (0: the blocks that fit at once)
 
     unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps,
-                                 //  steps counted beyond the last edge, -, -]
+                                 //  steps counted beyond the last edge, one-slot steps, -]
 };
 
 // LDS bytes used by one block for the given table sizes.

@@ -245,6 +245,7 @@ struct Counters {
     uint32_t flag = 0, exact = 0, rare = 0;
     uint32_t beyond = 0;        // this lane's pairs counted beyond the last edge (per unit)
     uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
+    uint32_t one_slot_steps = 0;  // steps binned with one atomic per lane (uniform)
 };
 
 // Loop constants of one wavefront.
@@ -257,6 +258,43 @@ struct Consts {
     uint32_t flag;          // flag bit of the cell entries (VGPR copy)
     uint32_t beyond;        // PairArgs::beyond_key (VGPR copy)
 };
+
+// LDS address of the cell-table entry of an FP32 key (the bit pattern of q)
+// and of an FP64 key (the high word of e; arithmetic shift, so e < 0 lands
+// in the bottom cell).
+template <bool LUT8, bool DIRECT>
+__device__ __forceinline__ uint32_t addr32(uint32_t bits, const Consts &k) {
+    if (DIRECT) {
+        // byte table from cell 0 at LDS address 0 (the kernel has no static
+        // LDS, so its dynamic LDS starts there); every key the kernel can
+        // produce lies inside it (checked on the host)
+        return bits >> k.shift;
+    }
+    return med3_u32(bits >> k.shift, k.clo, k.chi) * (LUT8 ? 1u : 2u) + k.lutbias;
+}
+
+template <bool LUT8>
+__device__ __forceinline__ uint32_t addr64(int32_t hi, const Consts &k) {
+    const int32_t c = med3_i32(hi >> (int)k.shift, (int32_t)k.clo, (int32_t)k.chi);
+    return (uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias;
+}
+
+// One slot for all of a lane's pairs: slots never decrease as the key grows
+// (keys below the table share its bottom cell), so if the cells of the
+// smallest and largest key hold the same certain slot, every key between
+// them maps to it.  When that holds on every lane the step adds its pairs
+// with one LDS atomic per lane instead of a lookup and an atomic per pair.
+// Used on the matrix-core path, whose tiles are compact (16 rows x 16
+// columns); on the vector paths a lane's rows lie 64 apart, the test succeeds
+// less often and its two dependent lookups cost more than they save.
+__device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint32_t n, const Consts &k,
+                                              Counters &cnt) {
+    if (!wave_all(e_lo == e_hi && !(e_lo & k.flag)))
+        return false;
+    lds_add(__umul24(e_lo, k.rowstep) + k.lanebase, n);
+    ++cnt.one_slot_steps;
+    return true;
+}
 
 // One step: JN columns against the P rows of every lane.  All JN * P table
 // lookups are issued first; one test sends the wavefront to the rare path if
@@ -301,18 +339,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const float v = q[t][p];
-            uint32_t addr;
-            if (DIRECT) {
-                // byte table from cell 0 at LDS address 0 (the kernel has no
-                // static LDS, so its dynamic LDS starts there); every key the
-                // kernel can produce lies inside it (checked on the host)
-                addr = __float_as_uint(v) >> k.shift;
-            } else {
-                uint32_t c = med3_u32(__float_as_uint(v) >> k.shift, k.clo, k.chi);
-                addr = c * (LUT8 ? 1u : 2u) + k.lutbias;
-            }
-            ent[t][p] = lds_read_entry<LUT8>(addr);
+            ent[t][p] = lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(__float_as_uint(q[t][p]), k));
         }
     }
     uint32_t any = 0;
@@ -387,10 +414,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const double ee = e[t][p];
-            // arithmetic shift: e < 0 (d > 1 from rounding) lands in the bottom cell
-            int32_t c = med3_i32(__double2hiint(ee) >> (int)k.shift, (int32_t)k.clo, (int32_t)k.chi);
-            ent[t][p] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
+            ent[t][p] = lds_read_entry<LUT8>(addr64<LUT8>(__double2hiint(e[t][p]), k));
         }
     }
     uint32_t any = 0;
@@ -553,17 +577,23 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
             ++cnt.beyond_steps;
             return;
         }
+        int32_t mx = __double2hiint(d[0][0]);
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                mx = max(mx, __double2hiint(d[g][r]));
+        if (one_slot_step(lds_read_entry<LUT8>(addr64<LUT8>(m, k)), lds_read_entry<LUT8>(addr64<LUT8>(mx, k)),
+                          RG * 4, k, cnt))
+            return;
     }
     uint32_t ent[RG][4];
     uint32_t any = 0;
 #pragma unroll
     for (int g = 0; g < RG; ++g)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t c = med3_i32(__double2hiint(d[g][r]) >> (int)k.shift, (int32_t)k.clo,
-                                       (int32_t)k.chi);
-            ent[g][r] = lds_read_entry<LUT8>((uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias);
-        }
+        for (int r = 0; r < 4; ++r)
+            ent[g][r] = lds_read_entry<LUT8>(addr64<LUT8>(__double2hiint(d[g][r]), k));
 #pragma unroll
     for (int g = 0; g < RG; ++g)
 #pragma unroll
@@ -772,6 +802,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[4], (unsigned long long)cnt.rare);
         if (cnt.beyond_steps)
             atomicAdd(&a.stats[5], (unsigned long long)cnt.beyond_steps);
+        if (cnt.one_slot_steps)
+            atomicAdd(&a.stats[6], (unsigned long long)cnt.one_slot_steps);
     }
 }
 

@@ -261,7 +261,7 @@ def test_timing_and_stats(ctx, cfg1):
     ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
     ms, n = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    pairs, flagged, exact, rare, beyond = ctx.stats(reset=True)
+    pairs, flagged, exact, rare, beyond, one_slot = ctx.stats(reset=True)
     assert n == 1 and ms > 0
     assert pairs == wl.data[0].n * wl.randoms[0].n
     assert exact <= flagged <= pairs
@@ -270,6 +270,33 @@ def test_timing_and_stats(ctx, cfg1):
     # a 30 x 30 deg patch against edges up to 10 deg: many wavefront steps
     # (4 rows x 2 columns per lane) lie wholly beyond the last edge
     assert 0 < beyond * 512 < pairs
+    assert (beyond + one_slot + rare) * 512 <= pairs
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_dense_patch_wide_bins_takes_every_branch(ctx, prec):
+    """A dense 3 x 3 deg patch with four wide bins: many wavefront steps lie
+    wholly beyond the last edge, on the matrix-core path many have each lane's
+    pairs in one slot, the rest go through the per-pair lookups; the counts
+    equal the oracle's."""
+    g = synthcat.rng_for(97, 0)
+    patch = (10.0, 13.0, 20.0, 23.0)
+    d = synthcat.uniform_patch(20_000, patch, g)
+    r = synthcat.uniform_patch(20_000, patch, g)
+    e = synthcat.log_edges(0.01, 1.0, 4)
+    cd = ctx.upload_catalog(*d)
+    cr = ctx.upload_catalog(*r)
+    xd = oracle.radec_to_xyz(*d)
+    xr = oracle.radec_to_xyz(*r)
+    ctx.stats(reset=True)
+    assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), oracle.count(oracle.DD, xd, e))
+    assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
+                          oracle.count(oracle.DR, xd, e, xr))
+    st = ctx.stats(reset=True)
+    assert st.beyond_steps > 0
+    assert (st.one_slot_steps > 0) == (prec == tp.FP64_MATRIX)
+    ctx.release_catalog(cd)
+    ctx.release_catalog(cr)
 
 
 def test_repeatable(ctx, cfg1):
