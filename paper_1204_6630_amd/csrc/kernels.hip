@@ -356,7 +356,11 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & k.flag) {
                     ++cnt.flag;
-                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], k.flag, q[t][p], s, a, jb, il[p], j + t, cnt.exact);
+                    int i = il[p];
+                    // opaque here, so the row addresses of this rare path are
+                    // formed on demand and do not occupy registers in the loop
+                    asm volatile("" : "+v"(i));
+                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], k.flag, q[t][p], s, a, jb, i, j + t, cnt.exact);
                 }
     }
 #pragma unroll
