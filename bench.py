@@ -99,6 +99,8 @@ def parse():
                     help="catalog size factor (1.0 = the full workload)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-matrix", action="store_true", help="skip the FP64 matrix-core path")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="skip the extra run with exact tile pruning (never the headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -339,7 +341,7 @@ def main():
         t1 = time.perf_counter()
         ctx.set_timing(False)
         kms, launches = ctx.kernel_time(reset=True)
-        pairs, flagged, exact, rare, beyond, one_slot = ctx.stats(reset=True)
+        pairs, flagged, exact, rare, beyond, one_slot, pruned = ctx.stats(reset=True)
         # per kind: one more launch of each, timed alone with HIP events
         per_kind = {}
         for name, kind, a, b, npairs in (("DD", tp.DD, cd, -1, nd * (nd - 1) // 2),
@@ -397,6 +399,33 @@ def main():
                 "one_slot_rate": r["one_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
 
     sums = {prec: summary(prec) for prec in paths}
+    pruned = None
+    if not args.no_prune:
+        # exact tile pruning (FP32 chord): whole blocks are binned without
+        # evaluating their pairs, so this is not the brute-force rate and is
+        # never the headline; same histograms required
+        ctx.set_tuning(prune=1)
+        step(tp.FP32_CHORD)
+        torch.cuda.synchronize()
+        ctx.stats(reset=True)
+        ctx.kernel_time(reset=True)
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            hp, _ = step(tp.FP32_CHORD)
+        t1 = time.perf_counter()
+        ctx.set_timing(False)
+        kms, _ = ctx.kernel_time(reset=True)
+        st = ctx.stats(reset=True)
+        ctx.set_tuning()
+        if not all(np.array_equal(a, b) for a, b in zip(runs[paths[0]]["hist"], hp)):
+            sys.exit("pruned and brute-force histograms differ")
+        pruned = {"gpairs_s_algorithmic": round(pairs_step * args.steps / (t1 - t0) / 1e9, 2),
+                  "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
+                  "kernel_ms_per_step": round(kms / args.steps, 3),
+                  "pruned_fraction": round(st.pruned_pairs / max(1, st.pairs), 4),
+                  "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
+                          "blocks are not evaluated, so not comparable to value"}
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
@@ -427,6 +456,8 @@ def main():
     }
     for prec in paths:
         res[PATH_NAMES[prec]] = sums[prec]
+    if pruned is not None:
+        res["fp32_chord_pruned"] = pruned
     if tp.FP64 in sums:
         res["fp32_over_fp64"] = round(sums[tp.FP32_CHORD]["gpairs_s"] / sums[tp.FP64]["gpairs_s"], 3)
     if not args.no_cpu_baseline:

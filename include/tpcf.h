@@ -215,7 +215,15 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * lut_direct      1: FP32 byte tables in the direct layout, indexed from
  *                 cell 0 without a clamp (one instruction per pair instead
  *                 of three, coarser cells, a larger table); 0 (default): the
- *                 table starts at the first edge and the key is clamped.
+ *                 table starts at the first edge and the key is clamped;
+ * prune           1: exact tile pruning.  Bounding caps of the column
+ *                 catalog's aligned 64-point groups (built on first use,
+ *                 4 doubles per group) and of each wavefront's rows bound the
+ *                 angles of a row block x 64-column block; when that interval,
+ *                 widened by 1e-6 rad and at least 1e-5 rad from 0 and pi,
+ *                 contains no edge, all of the block's pairs go to that slot
+ *                 without being evaluated.  Counts are unchanged; 0 (default)
+ *                 evaluates every pair.
  * Results never depend on these.  tpcf_get_tuning returns the fields as set
  * (0 standing for the default); NULL to tpcf_set_tuning restores defaults. */
 typedef struct tpcf_tuning {
@@ -225,6 +233,7 @@ typedef struct tpcf_tuning {
     int32_t blocks_per_cu;
     int32_t lut_bytes;
     int32_t lut_direct;
+    int32_t prune;
 } tpcf_tuning;
 
 int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning);
@@ -259,6 +268,8 @@ typedef struct tpcf_counters {
                                  counted in registers without table lookups */
     uint64_t one_slot_steps;  /* steps where each lane's pairs all fell in one certain slot,
                                  added with one LDS atomic per lane */
+    uint64_t pruned_pairs;    /* pairs binned by pruned blocks without being evaluated
+                                 (tuning field prune) */
 } tpcf_counters;
 
 /* Copy the statistics to *out (may be NULL) and, with reset = 1, clear

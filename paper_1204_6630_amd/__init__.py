@@ -62,7 +62,7 @@ BATCH_GRAPH = 1
 class Counters(ctypes.Structure):
     """struct tpcf_counters"""
     _fields_ = [(n, ctypes.c_uint64) for n in ("pairs", "flagged", "exact", "rare_steps",
-                                               "beyond_steps", "one_slot_steps")]
+                                               "beyond_steps", "one_slot_steps", "pruned_pairs")]
 
 
 Stats = collections.namedtuple("Stats", [n for n, _ in Counters._fields_])
@@ -72,7 +72,8 @@ class Tuning(ctypes.Structure):
     """struct tpcf_tuning"""
     _fields_ = [("rows_per_lane", ctypes.c_int32), ("hist_copies", ctypes.c_int32),
                 ("max_cols", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lut_bytes", ctypes.c_int32), ("lut_direct", ctypes.c_int32)]
+                ("lut_bytes", ctypes.c_int32), ("lut_direct", ctypes.c_int32),
+                ("prune", ctypes.c_int32)]
 
 
 class TpcfError(RuntimeError):
@@ -312,8 +313,8 @@ class Context:
         _check(lib().tpcf_cancel(self._h, job))
 
     def set_tuning(self, rows_per_lane: int = 0, hist_copies: int = 0, max_cols: int = 0,
-                   blocks_per_cu: int = 0, lut_bytes: int = 0, lut_direct: int = 0):
-        t = Tuning(rows_per_lane, hist_copies, max_cols, blocks_per_cu, lut_bytes, lut_direct)
+                   blocks_per_cu: int = 0, lut_bytes: int = 0, lut_direct: int = 0, prune: int = 0):
+        t = Tuning(rows_per_lane, hist_copies, max_cols, blocks_per_cu, lut_bytes, lut_direct, prune)
         _check(lib().tpcf_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:

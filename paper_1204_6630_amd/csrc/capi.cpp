@@ -63,6 +63,7 @@ struct Tuning {
     int blocks_per_cu = 0;   // 0: the blocks that fit at once
     int lut_bytes = 0;       // largest cell table
     int lut_direct = 0;      // 1: FP32 byte tables in the direct layout
+    int prune = 0;           // 1: exact tile pruning
 };
 
 int rows_per_lane_of(const Tuning &t, bool) {
@@ -130,11 +131,13 @@ struct Catalog {
     std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
     double *dpack = nullptr;    // matrix-core operand pack, built on first use
     size_t bytes_pack = 0;
+    double *dcaps = nullptr;    // bounding caps of aligned 64-point groups, built on first use
+    size_t bytes_caps = 0;
 };
 
 struct Compiled {
     EdgeTables edges;
-    DevBuf dD, dE, dqlo, dqhi, dlut, dTlo, dThi;
+    DevBuf dD, dE, dqlo, dqhi, dlut, dTlo, dThi, dErad;
     CellTable cells;
     Band32 band;
     int precision = 0;
@@ -402,6 +405,7 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
     c.dlut.release(ctx->mem);
     c.dTlo.release(ctx->mem);
     c.dThi.release(ctx->mem);
+    c.dErad.release(ctx->mem);
 }
 
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta,
@@ -464,7 +468,8 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     if ((rc = upload_blocking(ctx->mem, c->dD, c->edges.D)) || (rc = upload_blocking(ctx->mem, c->dE, c->edges.E)) ||
         (rc = upload_blocking(ctx->mem, c->dqlo, qlo)) || (rc = upload_blocking(ctx->mem, c->dqhi, qhi)) ||
         (rc = upload_blocking(ctx->mem, c->dlut, packed)) || (rc = upload_blocking(ctx->mem, c->dTlo, tlo)) ||
-        (rc = upload_blocking(ctx->mem, c->dThi, thi))) {
+        (rc = upload_blocking(ctx->mem, c->dThi, thi)) ||
+        (rc = upload_blocking(ctx->mem, c->dErad, c->edges.edge_rad))) {
         free_compiled(ctx, *c);
         return rc;
     }
@@ -610,6 +615,27 @@ int ensure_pack(tpcf_ctx *ctx, Catalog &c) {
     return TPCF_OK;
 }
 
+// Bounding caps of a catalog's aligned 64-point groups, built on the device on
+// first use (pruning).
+int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
+    if (c.dcaps)
+        return TPCF_OK;
+    const int64_t groups = (c.n + 63) / 64 > 0 ? (c.n + 63) / 64 : 1;
+    c.bytes_caps = sizeof(double) * 4 * (size_t)groups;
+    TRY(dev_alloc(ctx->mem, (void **)&c.dcaps, c.bytes_caps));
+    hipError_t e = hipSuccess;
+    if (c.n > 0)
+        e = (hipError_t)tpcf_launch_caps64(c.d64, c.n, c.dcaps, ctx->main.stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->main.stream);
+    if (e != hipSuccess) {
+        dev_free(ctx->mem, c.dcaps, c.bytes_caps);
+        c.dcaps = nullptr;
+        return fail(TPCF_E_HIP, std::string("bounding caps: ") + hipGetErrorString(e));
+    }
+    return TPCF_OK;
+}
+
 // Validate one request.  delta_override >= 0 compiles the FP32 band for that
 // norm bound (shared by every job of a batch) instead of the request's own.
 int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r) {
@@ -660,6 +686,8 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->A)));
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->B)));
     }
+    if (ctx->tune.prune)
+        TRY(ensure_caps(ctx, const_cast<Catalog &>(*r->B)));
     TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, matrix, &r->plan));
     r->pairs = r->plan->pairs;
     r->cache_key.clear();
@@ -688,6 +716,7 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
     j.bpack = r.B->dpack;
     j.a_groups = (int32_t)((r.A->n + 15) / 16);
     j.b_groups = (int32_t)((r.B->n + 15) / 16);
+    j.bcaps = r.B->dcaps;
     j.hist = hist;
     j.cancel = cancel;
     j.auto_pairs = r.auto_pairs ? 1 : 0;
@@ -706,6 +735,8 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.lut_lo = cp.cells.lo;
     a.lut_hi = cp.cells.hi;
     a.lut_direct = cp.cells.direct ? 1 : 0;
+    a.prune = ctx->tune.prune ? 1 : 0;
+    a.erad = (const double *)cp.dErad.p;
     // key of the last edge's certain side (see PairArgs::beyond_key)
     const size_t last = cp.edges.D.size() - 1;
     if (cp.precision == TPCF_FP32_CHORD) {
@@ -887,6 +918,7 @@ int tpcf_close(tpcf_ctx *ctx) {
             dev_free(ctx->mem, kv.second.d64, kv.second.bytes64);
         dev_free(ctx->mem, kv.second.d32, kv.second.bytes32);
         dev_free(ctx->mem, kv.second.dpack, kv.second.bytes_pack);
+        dev_free(ctx->mem, kv.second.dcaps, kv.second.bytes_caps);
     }
     for (auto &kv : ctx->compiled)
         free_compiled(ctx, *kv.second);
@@ -1032,6 +1064,7 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat) {
         dev_free(ctx->mem, it->second.d64, it->second.bytes64);
     dev_free(ctx->mem, it->second.d32, it->second.bytes32);
     dev_free(ctx->mem, it->second.dpack, it->second.bytes_pack);
+    dev_free(ctx->mem, it->second.dcaps, it->second.bytes_caps);
     ctx->cats.erase(it);
     return TPCF_OK;
 }
@@ -1339,6 +1372,8 @@ int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning) {
         return fail(TPCF_E_INVALID, "lut_bytes must be 0 (default) or in [4096, 33792]");
     if (t.lut_direct != 0 && t.lut_direct != 1)
         return fail(TPCF_E_INVALID, "lut_direct must be 0 or 1");
+    if (t.prune != 0 && t.prune != 1)
+        return fail(TPCF_E_INVALID, "prune must be 0 or 1");
     Tuning u;
     u.rows_per_lane = t.rows_per_lane;
     u.hist_copies = t.hist_copies;
@@ -1346,6 +1381,7 @@ int tpcf_set_tuning(tpcf_ctx *ctx, const tpcf_tuning *tuning) {
     u.blocks_per_cu = t.blocks_per_cu;
     u.lut_bytes = t.lut_bytes;
     u.lut_direct = t.lut_direct;
+    u.prune = t.prune;
     ctx->tune = u;
     return TPCF_OK;
 }
@@ -1359,6 +1395,7 @@ int tpcf_get_tuning(tpcf_ctx *ctx, tpcf_tuning *out) {
     out->blocks_per_cu = ctx->tune.blocks_per_cu;
     out->lut_bytes = ctx->tune.lut_bytes;
     out->lut_direct = ctx->tune.lut_direct;
+    out->prune = ctx->tune.prune;
     return TPCF_OK;
 }
 
@@ -1440,6 +1477,7 @@ int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset) {
         out->rare_steps = tot[4];
         out->beyond_steps = tot[5];
         out->one_slot_steps = tot[6];
+        out->pruned_pairs = tot[7];
     }
     if (reset)
         ctx->pairs_since_reset = 0;

@@ -55,6 +55,10 @@ struct JobDev {
     // is 1), zero-padded to whole groups.
     const double *apack, *bpack;
     int32_t a_groups, b_groups;
+    // Bounding caps of the column catalog's aligned 64-point groups (stored
+    // order): centre x, y, z and an upper bound of the angular radius; null
+    // unless pruning is on.
+    const double *bcaps;
     unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
     const int *cancel;           // host-visible flag (non-zero: skip the rest), or null
     int32_t auto_pairs;          // 1: DD/RR (count j > i only), 0: DR
@@ -86,6 +90,12 @@ struct PairArgs {
     // e >= the band's upper end on the matrix-core path).
     uint32_t beyond_key;
 
+    // Exact tile pruning: 1 = a wavefront bins a whole aligned 64-column
+    // block at once when the bounding caps put every pair of the block
+    // strictly inside one slot (edges in radians, nedges, in erad).
+    int32_t prune;
+    const double *erad;
+
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
     const double *E;             // fl(1 - D_k), nedges
@@ -100,16 +110,25 @@ struct PairArgs {
     int32_t blocks_per_cu;       // grid = CUs x this (0: the blocks that fit at once)
 
     unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps,
-                                 //  steps counted beyond the last edge, one-slot steps, -]
+                                 //  steps counted beyond the last edge, one-slot steps,
+                                 //  pairs binned by pruned blocks]
 };
 
 // LDS bytes used by one block for the given table sizes.
 inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_bytes, int nedges) {
     int hist = kWaves * (nslots + 1) * hist_copies * 4;      // +1: discard row
     int lut = ((lut_cells * lut_entry_bytes) + 15) & ~15;
-    int thr = nedges * (4 + 4 + 8 + 8 + 8 + 8);
+    int thr = nedges * (4 + 4 + 8 + 8 + 8 + 8 + 8);
     return hist + lut + thr;
 }
+
+// Margin (radians) of the pruning test: covers the FP32 copies of the rows
+// (<= 1.2e-7 rad), the arithmetic of the caps and the counting rule's own
+// rounding of the angle away from 0 and pi.
+constexpr double kPruneMargin = 1e-6;
+// Pruning is never applied when a block's angles may come within this of 0
+// or pi, where the rule's acos is ill-conditioned.
+constexpr double kPruneGuard = 1e-5;
 
 }  // namespace tpcf
 
@@ -125,4 +144,7 @@ int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
                          double *maxdev_out, void *stream);
 // Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack).
 int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream);
+// Bounding caps of the aligned 64-point groups of an FP64 SoA catalog
+// (see JobDev::bcaps): 4 doubles per group.
+int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, void *stream);
 }

@@ -147,6 +147,7 @@ struct Smem {
     double *Tlo, *Thi;
     float *qlo;
     float *qhi;
+    double *erad;        // edges in radians (pruning)
     unsigned char *lut;
     uint32_t hist_addr;  // LDS byte address of hist
     uint32_t lut_addr;   // LDS byte address of lut
@@ -165,7 +166,8 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     s.E = s.D + a.nedges;
     s.Tlo = s.E + a.nedges;
     s.Thi = s.Tlo + a.nedges;
-    s.qlo = reinterpret_cast<float *>(s.Thi + a.nedges);
+    s.erad = s.Thi + a.nedges;
+    s.qlo = reinterpret_cast<float *>(s.erad + a.nedges);
     s.qhi = s.qlo + a.nedges;
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
     s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
@@ -246,6 +248,7 @@ struct Counters {
     uint32_t beyond = 0;        // this lane's pairs counted beyond the last edge (per unit)
     uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
     uint32_t one_slot_steps = 0;  // steps binned with one atomic per lane (uniform)
+    unsigned long long pruned = 0;  // pairs binned by pruned blocks (uniform)
 };
 
 // Loop constants of one wavefront.
@@ -294,6 +297,110 @@ __device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint
     lds_add(__umul24(e_lo, k.rowstep) + k.lanebase, n);
     ++cnt.one_slot_steps;
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// Exact tile pruning.  A bounding cap (unit centre c, angular radius rho) of
+// the wavefront's rows and one of an aligned 64-column block bound the angle
+// of every pair of the block to [acos(c_r . c_b) - rho_r - rho_b,
+// acos(c_r . c_b) + rho_r + rho_b].  Widened by kPruneMargin (which covers
+// the FP32 row copies, the cap arithmetic and the counting rule's rounding of
+// the angle) and kept away from 0 and pi, an interval that contains no edge
+// puts every pair of the block in one slot: the wavefront adds the block's
+// pairs to that slot without evaluating them.
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, kWaveSize);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmin(v, __shfl_xor(v, off, kWaveSize));
+    return v;
+}
+
+struct Cap {
+    double x, y, z, rho;
+};
+
+// Cap of the points (x, y, z) held by the lanes (every lane contributes n
+// points; duplicates are harmless).  Identical on every lane.
+template <int N>
+__device__ __forceinline__ Cap cap_of(const double (&x)[N], const double (&y)[N], const double (&z)[N]) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        sx += x[p];
+        sy += y[p];
+        sz += z[p];
+    }
+    sx = wave_sum_d(sx);
+    sy = wave_sum_d(sy);
+    sz = wave_sum_d(sz);
+    const double norm = sqrt(sx * sx + sy * sy + sz * sz);
+    Cap c;
+    if (!(norm > 1e-3)) {       // points spread over the sphere: no useful cap
+        c.x = 1.0;
+        c.y = c.z = 0.0;
+        c.rho = M_PI;
+        return c;
+    }
+    c.x = sx / norm;
+    c.y = sy / norm;
+    c.z = sz / norm;
+    double m = 1.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        const double len = sqrt(x[p] * x[p] + y[p] * y[p] + z[p] * z[p]);
+        m = fmin(m, (c.x * x[p] + c.y * y[p] + c.z * z[p]) / len);
+    }
+    m = wave_min_d(m);
+    c.rho = acos(fmin(fmax(m, -1.0), 1.0)) + 1e-12;
+    return c;
+}
+
+// Number of edges <= t (edges increasing, in LDS).
+__device__ __forceinline__ int edges_le(const double *erad, int n, double t) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (erad[mid] <= t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// The slot of every pair between the row cap and the column block's cap, or
+// -1 when the test cannot prove one.  Wavefront-uniform.
+__device__ __forceinline__ int prune_slot(const Cap &r, const double *bcap, const Smem &s, int nedges) {
+    const cdouble_p bc = (cdouble_p)bcap;
+    const double d = fmin(fmax(r.x * bc[0] + r.y * bc[1] + r.z * bc[2], -1.0), 1.0);
+    const double th = acos(d);
+    const double spread = r.rho + bc[3] + kPruneMargin;
+    const double lo = th - spread, hi = th + spread;
+    int slot = -1;
+    if (lo >= kPruneGuard && hi <= M_PI - kPruneGuard) {
+        const int a = edges_le(s.erad, nedges, lo);
+        if (a == edges_le(s.erad, nedges, hi))
+            slot = a;
+    }
+    return __builtin_amdgcn_readfirstlane(slot);
+}
+
+// Add n pairs of this lane to `slot` (the overflow slot through the register
+// counter).
+__device__ __forceinline__ void bin_block(int slot, uint32_t n, const PairArgs &a, const Consts &k,
+                                          Counters &cnt) {
+    if (slot == a.nslots - 1)
+        cnt.beyond += n;
+    else
+        lds_add(__umul24((uint32_t)slot, k.rowstep) + k.lanebase, n);
 }
 
 // One step: JN columns against the P rows of every lane.  All JN * P table
@@ -451,21 +558,12 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
         }
 }
 
-// One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
+// Columns [j0, j1) against the P rows of every lane (FP32 path).
 template <bool LUT8, bool MASKED, int P, bool DIRECT>
-__device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
-                          int j0, int j1, int lane, Counters &cnt) {
-    float xi[P], yi[P], zi[P];
-    int ii[P], il[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        int i = ib + p * kWaveSize + lane;
-        ii[p] = i;
-        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
-        xi[p] = jb.ax32[il[p]];
-        yi[p] = jb.ay32[il[p]];
-        zi[p] = jb.az32[il[p]];
-    }
+__device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                                          const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
+                                          const int (&ii)[P], const int (&il)[P], int ie, int j0, int j1,
+                                          Counters &cnt) {
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
     cfloat_p bz = (cfloat_p)jb.bz32;
@@ -508,7 +606,67 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
     }
 }
 
+
+// One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE>
+__device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
+                          int j0, int j1, int lane, Counters &cnt) {
+    float xi[P], yi[P], zi[P];
+    int ii[P], il[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        int i = ib + p * kWaveSize + lane;
+        ii[p] = i;
+        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
+        xi[p] = jb.ax32[il[p]];
+        yi[p] = jb.ay32[il[p]];
+        zi[p] = jb.az32[il[p]];
+    }
+    if (PRUNE && !MASKED && jb.bcaps) {
+        double xd[P], yd[P], zd[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            xd[p] = xi[p];
+            yd[p] = yi[p];
+            zd[p] = zi[p];
+        }
+        const Cap rc = cap_of<P>(xd, yd, zd);
+        for (int j = j0; j < j1;) {
+            const int jn = min(j1, (j & ~63) + 64);
+            if ((j & 63) == 0 && jn - j == 64) {
+                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                if (slot >= 0) {
+                    bin_block(slot, P * 64, a, k, cnt);
+                    cnt.pruned += (unsigned long long)P * kWaveSize * 64;
+                    j = jn;
+                    continue;
+                }
+            }
+            cols_fp32<LUT8, MASKED, P, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
+            j = jn;
+        }
+        return;
+    }
+    cols_fp32<LUT8, MASKED, P, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
+}
+
+// Columns [j0, j1) against the P rows of every lane (FP64 vector path).
 template <bool LUT8, bool MASKED, int P>
+__device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                                          const double (&xi)[P], const double (&yi)[P],
+                                          const double (&zi)[P], const int (&ii)[P], int ie, int j0, int j1,
+                                          Counters &cnt) {
+    cdouble_p bx = (cdouble_p)jb.bx64;
+    cdouble_p by = (cdouble_p)jb.by64;
+    cdouble_p bz = (cdouble_p)jb.bz64;
+    int j = j0;
+    for (; j + kColsPerStep <= j1; j += kColsPerStep)
+        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+    for (; j < j1; ++j)
+        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+}
+
+template <bool LUT8, bool MASKED, int P, bool PRUNE>
 __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     double xi[P], yi[P], zi[P];
@@ -522,14 +680,25 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
         yi[p] = jb.ay64[il];
         zi[p] = jb.az64[il];
     }
-    cdouble_p bx = (cdouble_p)jb.bx64;
-    cdouble_p by = (cdouble_p)jb.by64;
-    cdouble_p bz = (cdouble_p)jb.bz64;
-    int j = j0;
-    for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
-    for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+    if (PRUNE && !MASKED && jb.bcaps) {
+        const Cap rc = cap_of<P>(xi, yi, zi);
+        for (int j = j0; j < j1;) {
+            const int jn = min(j1, (j & ~63) + 64);
+            if ((j & 63) == 0 && jn - j == 64) {
+                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                if (slot >= 0) {
+                    bin_block(slot, P * 64, a, k, cnt);
+                    cnt.pruned += (unsigned long long)P * kWaveSize * 64;
+                    j = jn;
+                    continue;
+                }
+            }
+            cols_fp64<LUT8, MASKED, P>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
+            j = jn;
+        }
+        return;
+    }
+    cols_fp64<LUT8, MASKED, P>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -634,27 +803,11 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
         }
 }
 
-// Matrix-core path, one wavefront: RG groups of 16 rows starting at ib
-// (valid rows [rlo, ie)) against the column groups of [j0, j1).  For every
-// 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
-// (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
-// then binned exactly as on the vector path, against the matrix-core band.
-// The loop is software-pipelined: the products of the next column group are
-// issued before the current group is binned, so the matrix cores work while
-// the wavefront does its lookups.
 template <bool LUT8, bool MASKED, int RG>
-__device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                         int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
-    const gdouble_p ap = (gdouble_p)jb.apack + lane;
+__device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                                         const double (&A)[RG], int ib, int rlo, int ie, int j0, int j1,
+                                         int lane, Counters &cnt) {
     const gdouble_p bp = (gdouble_p)jb.bpack + lane;
-    double A[RG];
-    const int g0 = ib >> 4;
-#pragma unroll
-    for (int g = 0; g < RG; ++g) {
-        const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
-        const double v = ap[(size_t)gg * 64];
-        A[g] = lane < 48 ? -v : v;
-    }
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     const int jg0 = j0 >> 4;
     const int jg_end = (j1 + 15) >> 4;
@@ -697,11 +850,55 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
     }
 }
 
+// Matrix-core path, one wavefront: RG groups of 16 rows starting at ib
+// (valid rows [rlo, ie)) against the column groups of [j0, j1).  For every
+// 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
+// (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
+// then binned exactly as on the vector path, against the matrix-core band.
+// The loop is software-pipelined: the products of the next column group are
+// issued before the current group is binned, so the matrix cores work while
+// the wavefront does its lookups.
+template <bool LUT8, bool MASKED, int RG, bool PRUNE>
+__device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                         int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
+    const gdouble_p ap = (gdouble_p)jb.apack + lane;
+    double A[RG];
+    const int g0 = ib >> 4;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
+        const double v = ap[(size_t)gg * 64];
+        A[g] = lane < 48 ? -v : v;
+    }
+    if (PRUNE && !MASKED && jb.bcaps) {
+        // unmasked: rows [ib, ib + 16 RG) are all valid; lane l takes one
+        const int i = ib + lane % (16 * RG);
+        const double xr[1] = {jb.ax64[i]}, yr[1] = {jb.ay64[i]}, zr[1] = {jb.az64[i]};
+        const Cap rc = cap_of<1>(xr, yr, zr);
+        for (int j = j0; j < j1;) {
+            const int jn = min(j1, (j & ~63) + 64);
+            if ((j & 63) == 0 && jn - j == 64) {
+                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                if (slot >= 0) {
+                    bin_block(slot, 16 * RG, a, k, cnt);
+                    cnt.pruned += (unsigned long long)16 * RG * 64;
+                    j = jn;
+                    continue;
+                }
+            }
+            cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j, jn, lane, cnt);
+            j = jn;
+        }
+        return;
+    }
+    cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j0, j1, lane, cnt);
+}
+
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
 // table, 1 FP64 vector, 2 FP64 matrix cores.  P: rows per lane of the vector
 // paths (a wavefront covers P * 64 rows of a unit) or row groups of 16 of the
 // matrix-core path (P * 16 rows).
-template <int PREC, bool LUT8, int P>
+template <int PREC, bool LUT8, int P, bool PRUNE>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     constexpr int kRowsPerWave = PREC == 2 ? P * 16 : P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -724,6 +921,7 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
         s.Thi[e] = a.Thi[e];
         s.qlo[e] = a.qlo[e];
         s.qhi[e] = a.qhi[e];
+        s.erad[e] = a.erad ? a.erad[e] : 0.0;
     }
     __syncthreads();
 
@@ -769,19 +967,19 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             if (PREC == 2) {
                 masked = masked || (un.j1 & 15) != 0;
                 if (masked)
-                    rows_mma<LUT8, true, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
+                    rows_mma<LUT8, true, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_mma<LUT8, false, P>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
+                    rows_mma<LUT8, false, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
             } else if (PREC == 0 || PREC == 3) {
                 if (masked)
-                    rows_fp32<LUT8, true, P, PREC == 3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, true, P, PREC == 3, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp32<LUT8, false, P, PREC == 3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, false, P, PREC == 3, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             } else {
                 if (masked)
-                    rows_fp64<LUT8, true, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp64<LUT8, true, P, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp64<LUT8, false, P>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp64<LUT8, false, P, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             }
             // pairs counted beyond the last edge go to this lane's copy of the
             // overflow slot; then the wave's own LDS region is flushed (no
@@ -808,6 +1006,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[5], (unsigned long long)cnt.beyond_steps);
         if (cnt.one_slot_steps)
             atomicAdd(&a.stats[6], (unsigned long long)cnt.one_slot_steps);
+        if (cnt.pruned)
+            atomicAdd(&a.stats[7], cnt.pruned);
     }
 }
 
@@ -877,6 +1077,26 @@ __global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_
     }
 }
 
+// Bounding cap of every aligned group of 64 stored points: one wavefront per
+// group (4 doubles: unit centre, angular radius).
+__global__ __launch_bounds__(256) void caps64_kernel(const double *xyz, int64_t n, double *caps,
+                                                     int64_t groups) {
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = threadIdx.x >> 6;
+    for (int64_t g = (int64_t)blockIdx.x * kWaves + wave; g < groups; g += (int64_t)gridDim.x * kWaves) {
+        // lanes past the catalog repeat the group's first point
+        const int64_t p = g * 64 + lane < n ? g * 64 + lane : g * 64;
+        const double x[1] = {xyz[p]}, y[1] = {xyz[n + p]}, z[1] = {xyz[2 * n + p]};
+        const Cap c = cap_of<1>(x, y, z);
+        if (lane == 0) {
+            caps[4 * g] = c.x;
+            caps[4 * g + 1] = c.y;
+            caps[4 * g + 2] = c.z;
+            caps[4 * g + 3] = c.rho;
+        }
+    }
+}
+
 int grid_for(int n_units, int lds, int blocks_per_cu) {
     static int cus = 0, lds_per_cu = 0;
     if (!cus) {
@@ -907,6 +1127,21 @@ int grid_for(int n_units, int lds, int blocks_per_cu) {
     return (int)g;
 }
 
+template <int PR, bool B8>
+void launch_pairs(int P, bool prune, int grid, int lds, hipStream_t st, const PairArgs &a) {
+    if (prune) {
+        if (P == 2)
+            hipLaunchKernelGGL((pairs_kernel<PR, B8, 2, true>), dim3(grid), dim3(kBlock), lds, st, a);
+        else
+            hipLaunchKernelGGL((pairs_kernel<PR, B8, 4, true>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else {
+        if (P == 2)
+            hipLaunchKernelGGL((pairs_kernel<PR, B8, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
+        else
+            hipLaunchKernelGGL((pairs_kernel<PR, B8, 4, false>), dim3(grid), dim3(kBlock), lds, st, a);
+    }
+}
+
 }  // namespace
 
 extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stream) {
@@ -918,34 +1153,29 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
     hipStream_t st = (hipStream_t)stream;
     const bool b8 = args->lut_entry_bytes == 1;
     const int P = args->rows_per_lane;
-#define TPCF_LAUNCH(PR, B8, PP) \
-    hipLaunchKernelGGL((pairs_kernel<PR, B8, PP>), dim3(grid), dim3(kBlock), lds, st, *args)
     if (P != 2 && P != 4)
         return (int)hipErrorInvalidValue;
+    const bool prune = args->prune != 0;
     if (precision == 0) {
-        if (b8 && args->lut_direct) {
-            if (P == 2) TPCF_LAUNCH(3, true, 2); else TPCF_LAUNCH(3, true, 4);
-        } else if (b8) {
-            if (P == 2) TPCF_LAUNCH(0, true, 2); else TPCF_LAUNCH(0, true, 4);
-        } else {
-            if (P == 2) TPCF_LAUNCH(0, false, 2); else TPCF_LAUNCH(0, false, 4);
-        }
+        if (b8 && args->lut_direct)
+            launch_pairs<3, true>(P, prune, grid, lds, st, *args);
+        else if (b8)
+            launch_pairs<0, true>(P, prune, grid, lds, st, *args);
+        else
+            launch_pairs<0, false>(P, prune, grid, lds, st, *args);
     } else if (precision == 1) {
-        if (b8) {
-            if (P == 2) TPCF_LAUNCH(1, true, 2); else TPCF_LAUNCH(1, true, 4);
-        } else {
-            if (P == 2) TPCF_LAUNCH(1, false, 2); else TPCF_LAUNCH(1, false, 4);
-        }
+        if (b8)
+            launch_pairs<1, true>(P, prune, grid, lds, st, *args);
+        else
+            launch_pairs<1, false>(P, prune, grid, lds, st, *args);
     } else if (precision == 2) {
-        if (b8) {
-            if (P == 2) TPCF_LAUNCH(2, true, 2); else TPCF_LAUNCH(2, true, 4);
-        } else {
-            if (P == 2) TPCF_LAUNCH(2, false, 2); else TPCF_LAUNCH(2, false, 4);
-        }
+        if (b8)
+            launch_pairs<2, true>(P, prune, grid, lds, st, *args);
+        else
+            launch_pairs<2, false>(P, prune, grid, lds, st, *args);
     } else {
         return (int)hipErrorInvalidValue;
     }
-#undef TPCF_LAUNCH
     return (int)hipGetLastError();
 }
 
@@ -958,6 +1188,18 @@ extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, 
         blocks = 4096;
     hipLaunchKernelGGL(pack16_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
                        pack, total);
+    return (int)hipGetLastError();
+}
+
+extern "C" int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, void *stream) {
+    const int64_t groups = (n + 63) / 64;
+    if (groups <= 0)
+        return 0;
+    int64_t blocks = (groups + kWaves - 1) / kWaves;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(caps64_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
+                       caps, groups);
     return (int)hipGetLastError();
 }
 

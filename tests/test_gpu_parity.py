@@ -200,6 +200,13 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
     for p in PRECS[1:]:
         for a, b in zip(full[PRECS[0]], full[p]):
             assert np.array_equal(a, b), p
+    try:    # exact tile pruning on the full catalogs
+        ctx.set_tuning(prune=1)
+        pruned = (ctx.count(tp.DD, cd, e), ctx.count(tp.DR, cd, e, cat_b=cr), ctx.count(tp.RR, cr, e))
+    finally:
+        ctx.set_tuning()
+    for a, b in zip(full[PRECS[0]], pruned):
+        assert np.array_equal(a, b)
     xd, xr = _stored(ctx, cd, _xyz(d)), _stored(ctx, cr, _xyz(r))
     size = 200 if cfg == 2 else 150
     for rb, re in _sample_blocks(d.n, 2, size, 11 + cfg):
@@ -261,7 +268,7 @@ def test_timing_and_stats(ctx, cfg1):
     ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
     ms, n = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    pairs, flagged, exact, rare, beyond, one_slot = ctx.stats(reset=True)
+    pairs, flagged, exact, rare, beyond, one_slot, pruned = ctx.stats(reset=True)
     assert n == 1 and ms > 0
     assert pairs == wl.data[0].n * wl.randoms[0].n
     assert exact <= flagged <= pairs
@@ -271,6 +278,29 @@ def test_timing_and_stats(ctx, cfg1):
     # (4 rows x 2 columns per lane) lie wholly beyond the last edge
     assert 0 < beyond * 512 < pairs
     assert (beyond + one_slot + rare) * 512 <= pairs
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_pruning_keeps_counts_exact(ctx, cfg1, prec):
+    """Exact tile pruning on config 1: the same counts as the oracle, with
+    some blocks binned whole, including row ranges (unaligned row tiles)."""
+    wl, cd, cr, ref = cfg1
+    e = wl.edges_deg
+    try:
+        ctx.set_tuning(prune=1)
+        ctx.stats(reset=True)
+        assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), ref["DD"])
+        assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec), ref["DR"])
+        assert np.array_equal(ctx.count(tp.RR, cr, e, precision=prec), ref["RR"])
+        st = ctx.stats(reset=True)
+        assert 0 < st.pruned_pairs < st.pairs
+        ctx.set_tuning()
+        part = ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec, row_begin=333, row_end=7777)
+        ctx.set_tuning(prune=1)
+        assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec, row_begin=333,
+                                        row_end=7777), part)
+    finally:
+        ctx.set_tuning()
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -289,12 +319,20 @@ def test_dense_patch_wide_bins_takes_every_branch(ctx, prec):
     xd = oracle.radec_to_xyz(*d)
     xr = oracle.radec_to_xyz(*r)
     ctx.stats(reset=True)
-    assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), oracle.count(oracle.DD, xd, e))
-    assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
-                          oracle.count(oracle.DR, xd, e, xr))
+    dd_ref, dr_ref = oracle.count(oracle.DD, xd, e), oracle.count(oracle.DR, xd, e, xr)
+    assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), dd_ref)
+    assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec), dr_ref)
     st = ctx.stats(reset=True)
     assert st.beyond_steps > 0
     assert (st.one_slot_steps > 0) == (prec == tp.FP64_MATRIX)
+    # pruning bins whole blocks inside the wide bins and beyond the last edge
+    try:
+        ctx.set_tuning(prune=1)
+        assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), dd_ref)
+        assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec), dr_ref)
+        assert ctx.stats(reset=True).pruned_pairs > 0
+    finally:
+        ctx.set_tuning()
     ctx.release_catalog(cd)
     ctx.release_catalog(cr)
 
@@ -333,7 +371,7 @@ def test_gpu_error_paths(ctx, cfg1):
         ctx.release_catalog(9999)
     assert ei.value.code == -4
     for bad in ({"rows_per_lane": 3}, {"hist_copies": 12}, {"max_cols": 300}, {"blocks_per_cu": -1},
-                {"lut_bytes": 100}, {"lut_bytes": 40000}, {"lut_direct": 2}):
+                {"lut_bytes": 100}, {"lut_bytes": 40000}, {"lut_direct": 2}, {"prune": 3}):
         with pytest.raises(tp.TpcfError):
             ctx.set_tuning(**bad)
     assert ctx.get_tuning() == {k: 0 for k in ctx.get_tuning()}
@@ -347,10 +385,10 @@ def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
     try:
         for rpl in (2, 4):
             for hc in (32, 16, 8, 4):
-                for mc, bpc, lb, lc in ((256, 1, 0, 0), (16384, 0, 4096, 1), (4096, 3, 4096, 0),
-                                        (4096, 0, 33792, 1)):
+                for mc, bpc, lb, lc, pr in ((256, 1, 0, 0, 1), (16384, 0, 4096, 1, 0),
+                                            (4096, 3, 4096, 0, 1), (4096, 0, 33792, 1, 0)):
                     ctx.set_tuning(rows_per_lane=rpl, hist_copies=hc, max_cols=mc, blocks_per_cu=bpc,
-                                   lut_bytes=lb, lut_direct=lc)
+                                   lut_bytes=lb, lut_direct=lc, prune=pr)
                     for prec in PRECS:
                         assert np.array_equal(ctx.count(tp.DD, cd, e, precision=prec), ref["DD"])
                         assert np.array_equal(ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec),
