@@ -9,6 +9,9 @@ Contents
     wrappers over ``tpcf_oracle.c`` (plain FP64 double loops, libm acos).
   * ``landy_szalay``: the Landy-Szalay estimator (paper Eq. 1) written out in
     FP64 numpy.
+  * ``count_regions``: counts plus, per jackknife region, the pairs with a
+    member in it; ``jackknife``: delete-one jackknife of w by recounting the
+    catalogs with each region removed.
   * ``tiny``: a pure-Python loop version of the counting for small inputs.
 
 Every function is pinned by ``tests/test_oracle_pins.py`` against closed forms,
@@ -61,6 +64,9 @@ def _load():
         lib.oracle_pair_slots.restype = ctypes.c_int
         lib.oracle_pair_angles.argtypes = [i64, P, P, P, P, P, P, P]
         lib.oracle_pair_angles.restype = ctypes.c_int
+        lib.oracle_count_regions.argtypes = [ctypes.c_int, i64, P, P, P, P, i64, P, P, P, P,
+                                             ctypes.c_int32, P, ctypes.c_int32, P, P]
+        lib.oracle_count_regions.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -183,3 +189,53 @@ def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:
         else:
             raise ValueError("form must be 0 or 1")
     return w
+
+
+def count_regions(kind: int, a_xyz, a_region, edges_deg, nreg: int, b_xyz=None, b_region=None):
+    """(total, touch): total as ``count``; touch[r] counts the pairs with at
+    least one member in region r (once for a pair inside one region)."""
+    edges = _f64(edges_deg)
+    nbins = edges.size - 1
+    ax, ay, az = (_f64(c) for c in a_xyz)
+    ra = np.ascontiguousarray(a_region, dtype=np.int32)
+    if kind == DR:
+        bx, by, bz = (_f64(c) for c in b_xyz)
+        rb = np.ascontiguousarray(b_region, dtype=np.int32)
+        cross = 1
+    else:
+        bx, by, bz, rb = ax, ay, az, ra
+        cross = 0
+    total = np.zeros(nbins + 2, dtype=np.uint64)
+    touch = np.zeros((nreg, nbins + 2), dtype=np.uint64)
+    rc = _load().oracle_count_regions(cross, ax.size, _ptr(ax), _ptr(ay), _ptr(az), _ptr(ra),
+                                      bx.size, _ptr(bx), _ptr(by), _ptr(bz), _ptr(rb), nbins,
+                                      _ptr(edges), nreg, _ptr(total), _ptr(touch))
+    if rc != 0:
+        raise ValueError("oracle_count_regions rejected its arguments")
+    return total, touch
+
+
+def jackknife(d_xyz, d_region, r_xyz, r_region, edges_deg, nreg: int, form: int = 0):
+    """Delete-one jackknife of the Landy-Szalay w: for every region r, w from
+    the catalogs with region r removed (recounted), then
+    cov = (K - 1) / K sum_r (w_r - mean)(w_r - mean)^T with K = nreg.
+    Returns (samples [K, nbins], mean [nbins], cov [nbins, nbins])."""
+    dx = [_f64(c) for c in d_xyz]
+    rx = [_f64(c) for c in r_xyz]
+    dreg = np.asarray(d_region)
+    rreg = np.asarray(r_region)
+    samples = []
+    for r in range(nreg):
+        kd = dreg != r
+        kr = rreg != r
+        d = [c[kd] for c in dx]
+        rr_ = [c[kr] for c in rx]
+        dd = count(DD, d, edges_deg)
+        dr = count(DR, d, edges_deg, b_xyz=rr_)
+        rr = count(RR, rr_, edges_deg)
+        samples.append(landy_szalay(dd[1:-1], dr[1:-1], rr[1:-1], int(kd.sum()), int(kr.sum()), form))
+    samples = np.array(samples)
+    mean = samples.mean(axis=0)
+    dev = samples - mean
+    cov = (nreg - 1.0) / nreg * (dev.T @ dev)
+    return samples, mean, cov

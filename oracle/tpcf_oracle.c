@@ -182,6 +182,60 @@ int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
     return 0;
 }
 
+/*
+ * Pair counts with jackknife regions: every point carries a region label in
+ * [0, nreg).  out_total (nbins+2 slots) is the histogram of oracle_count over
+ * all pairs; out_touch (nreg x (nbins+2)) row r counts the pairs with at
+ * least one member in region r (a pair whose members share a region counts
+ * once there).  Removing region r from both catalogs removes exactly the
+ * pairs of row r, so the delete-one jackknife histograms are
+ * out_total - out_touch[r].  Single-threaded; returns 0, or -1 on bad
+ * arguments (a label out of range included).
+ */
+int oracle_count_regions(int cross, int64_t na, const double *ax, const double *ay,
+                         const double *az, const int32_t *ra, int64_t nb, const double *bx,
+                         const double *by, const double *bz, const int32_t *rb, int32_t nbins,
+                         const double *edges_deg, int32_t nreg, uint64_t *out_total,
+                         uint64_t *out_touch)
+{
+    if (nbins < 1 || nreg < 1 || na < 0 || (cross && nb < 0) || !out_total || !out_touch)
+        return -1;
+    for (int64_t i = 0; i < na; ++i)
+        if (ra[i] < 0 || ra[i] >= nreg)
+            return -1;
+    if (cross)
+        for (int64_t j = 0; j < nb; ++j)
+            if (rb[j] < 0 || rb[j] >= nreg)
+                return -1;
+    const double deg = M_PI / 180.0;
+    const int nedges = nbins + 1;
+    const int nslots = nbins + 2;
+    double *edge_rad = (double *)malloc(sizeof(double) * (size_t)nedges);
+    if (!edge_rad)
+        return -1;
+    for (int k = 0; k < nedges; ++k)
+        edge_rad[k] = edges_deg[k] * deg;
+    memset(out_total, 0, sizeof(uint64_t) * (size_t)nslots);
+    memset(out_touch, 0, sizeof(uint64_t) * (size_t)nreg * (size_t)nslots);
+    for (int64_t i = 0; i < na; ++i) {
+        const int64_t j0 = cross ? 0 : i + 1;
+        const int64_t jn = cross ? nb : na;
+        for (int64_t j = j0; j < jn; ++j) {
+            const double xj = cross ? bx[j] : ax[j];
+            const double yj = cross ? by[j] : ay[j];
+            const double zj = cross ? bz[j] : az[j];
+            const int32_t rj = cross ? rb[j] : ra[j];
+            const int s = slot_of(pair_angle(ax[i], ay[i], az[i], xj, yj, zj), edge_rad, nedges);
+            out_total[s] += 1;
+            out_touch[(size_t)ra[i] * (size_t)nslots + (size_t)s] += 1;
+            if (rj != ra[i])
+                out_touch[(size_t)rj * (size_t)nslots + (size_t)s] += 1;
+        }
+    }
+    free(edge_rad);
+    return 0;
+}
+
 /* Slot of each listed pair (i-th entry pairs point a_i with point b_i);
  * used for probes placed next to bin edges. */
 int oracle_pair_slots(int64_t n, const double *ax, const double *ay, const double *az,

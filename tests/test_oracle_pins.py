@@ -368,3 +368,93 @@ def test_landy_szalay_random_vs_random_is_zero():
     ratio = nr / nd
     naive = 1 + ratio ** 2 * dd / rr - 2 * ratio * dr / rr
     assert np.all(np.abs(naive + 2.0) < 0.2)
+
+
+# --- jackknife regions (count_regions, jackknife) -----------------------------
+
+def _regions_case(seed, n_d=400, n_r=500, nreg=5):
+    g = synthcat.rng_for(93, seed)
+    patch = (0.0, 20.0, 0.0, 20.0)
+    ra_d, dec_d = synthcat.uniform_patch(n_d, patch, g)
+    ra_r, dec_r = synthcat.uniform_patch(n_r, patch, g)
+    # regions: RA stripes of 4 deg (a typical jackknife split)
+    reg_d = np.minimum((ra_d // 4).astype(np.int32), nreg - 1)
+    reg_r = np.minimum((ra_r // 4).astype(np.int32), nreg - 1)
+    return _xyz(ra_d, dec_d), reg_d, _xyz(ra_r, dec_r), reg_r, nreg
+
+
+def test_region_totals_equal_plain_counts_and_one_region_touches_all():
+    d, rd, r, rr_, nreg = _regions_case(0)
+    e = synthcat.log_edges(0.1, 10.0, 12)
+    for kind, b, rb in ((oracle.DD, None, None), (oracle.DR, r, rr_)):
+        total, touch = oracle.count_regions(kind, d, rd, e, nreg, b_xyz=b, b_region=rb)
+        assert np.array_equal(total, oracle.count(kind, d, e, b_xyz=b))
+        one_a = np.zeros_like(rd)
+        one_b = None if rb is None else np.zeros_like(rb)
+        t1, touch1 = oracle.count_regions(kind, d, one_a, e, 1, b_xyz=b, b_region=one_b)
+        assert np.array_equal(touch1[0], t1)
+
+
+def test_removing_a_region_removes_exactly_its_touch_row():
+    """Deletion identity against recounts of the reduced catalogs: a planted
+    double count of same-region pairs, a missing second region, or swapped
+    DR labels would each break it."""
+    d, rd, r, rr_, nreg = _regions_case(1)
+    e = synthcat.log_edges(0.1, 10.0, 12)
+    dd_t, dd_touch = oracle.count_regions(oracle.DD, d, rd, e, nreg)
+    dr_t, dr_touch = oracle.count_regions(oracle.DR, d, rd, e, nreg, b_xyz=r, b_region=rr_)
+    for k in range(nreg):
+        kd, kr = rd != k, rr_ != k
+        dsub = [c[kd] for c in d]
+        rsub = [c[kr] for c in r]
+        assert np.array_equal(dd_t - dd_touch[k], oracle.count(oracle.DD, dsub, e))
+        assert np.array_equal(dr_t - dr_touch[k], oracle.count(oracle.DR, dsub, e, b_xyz=rsub))
+
+
+def test_region_counts_match_pure_python():
+    d, rd, r, rr_, nreg = _regions_case(2, n_d=60, n_r=70, nreg=3)
+    e = synthcat.log_edges(0.5, 12.0, 6)
+    er = [x * (math.pi / 180.0) for x in e]
+    pa = list(zip(*d))
+    pb = list(zip(*r))
+    for kind in (oracle.DD, oracle.DR):
+        total = np.zeros(e.size + 1, np.uint64)
+        touch = np.zeros((nreg, e.size + 1), np.uint64)
+        if kind == oracle.DD:
+            pairs = [(pa[i], pa[j], rd[i], rd[j]) for i in range(len(pa)) for j in range(i + 1, len(pa))]
+        else:
+            pairs = [(pa[i], pb[j], rd[i], rr_[j]) for i in range(len(pa)) for j in range(len(pb))]
+        for p, q, ri, rj in pairs:
+            s = tiny.slot(tiny.angle(p, q), er)
+            total[s] += 1
+            touch[ri, s] += 1
+            if rj != ri:
+                touch[rj, s] += 1
+        got_t, got_touch = oracle.count_regions(kind, d, rd, e, nreg,
+                                                b_xyz=None if kind == oracle.DD else r,
+                                                b_region=None if kind == oracle.DD else rr_)
+        assert np.array_equal(got_t, total) and np.array_equal(got_touch, touch)
+
+
+def test_jackknife_samples_and_covariance():
+    """Samples by recount equal Landy-Szalay of (total - touch) with the
+    region's points removed from N_D and N_R; the covariance equals
+    (K-1)^2/K times numpy's unbiased sample covariance."""
+    d, rd, r, rr_, nreg = _regions_case(3)
+    e = synthcat.log_edges(0.5, 10.0, 6)
+    samples, mean, cov = oracle.jackknife(d, rd, r, rr_, e, nreg)
+    dd_t, dd_touch = oracle.count_regions(oracle.DD, d, rd, e, nreg)
+    dr_t, dr_touch = oracle.count_regions(oracle.DR, d, rd, e, nreg, b_xyz=r, b_region=rr_)
+    rr_t, rr_touch = oracle.count_regions(oracle.RR, r, rr_, e, nreg)
+    for k in range(nreg):
+        nd = int((rd != k).sum())
+        nr = int((rr_ != k).sum())
+        w = oracle.landy_szalay((dd_t - dd_touch[k])[1:-1], (dr_t - dr_touch[k])[1:-1],
+                                (rr_t - rr_touch[k])[1:-1], nd, nr)
+        assert np.array_equal(np.isnan(w), np.isnan(samples[k]))
+        fin = np.isfinite(w)
+        assert np.allclose(w[fin], samples[k][fin], rtol=0, atol=1e-13)
+    fin = np.all(np.isfinite(samples), axis=0)
+    ref = (nreg - 1) ** 2 / nreg * np.cov(samples[:, fin].T, ddof=1)
+    assert np.allclose(cov[np.ix_(fin, fin)], ref, rtol=1e-12, atol=1e-15)
+    assert np.allclose(mean, samples.mean(axis=0), equal_nan=True)
