@@ -127,6 +127,39 @@ int tpcf_catalog_size(tpcf_ctx *ctx, int32_t cat, int64_t *out_n);
 /* Release a catalog id and the device memory the library owns for it. */
 int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat);
 
+/* Jackknife regions.  The paper judges its residuals against the statistical
+ * error of a sky with few independent fields (Section 4, discussion of the
+ * w(theta) residuals); a delete-one jackknife over sky regions estimates that
+ * error from one pass of counting.  Regions are labels chosen by the caller
+ * (contiguous patches of sky, typically). */
+#define TPCF_MAX_REGIONS 1024
+
+/* tpcf_upload_catalog with a region label per object: region (host, n int32)
+ * holds values in [0, nreg), 1 <= nreg <= TPCF_MAX_REGIONS; NULL region
+ * uploads an unlabelled catalog (nreg ignored).  Objects are stored grouped
+ * by region (each region a contiguous run of rows, in label order), Morton
+ * order within a region; tpcf_catalog_order returns the order.
+ * TPCF_E_INVALID for a label out of range. */
+int tpcf_upload_catalog_regions(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg,
+                                int64_t n, const int32_t *region, int32_t nreg,
+                                int32_t *out_cat);
+
+/* Region count of a catalog in *out_nreg (0 if unlabelled) and, when
+ * out_counts (host, nreg int64) is not NULL, the objects per region. */
+int tpcf_catalog_regions(tpcf_ctx *ctx, int32_t cat, int32_t *out_nreg, int64_t *out_counts);
+
+/* Counts of a whole-catalog request split by region (synchronous): the
+ * pairs as tpcf_count with row_begin = row_end = -1 into out_total (nbins+2
+ * slots), and into out_touch (host, nreg x (nbins+2) u64, region-major) for
+ * every region r the pairs with at least one member in r (a pair inside one
+ * region is counted once there).  The counts with region r deleted are then
+ * out_total - out_touch[r], exactly.  Both catalogs (cat_b = -1 for DD/RR)
+ * must carry labels with the same nreg.  Same kinds, edges and precisions as
+ * tpcf_count; results are not cached. */
+int tpcf_count_regions(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
+                       const double *bin_edges_deg, int32_t nbins, int precision,
+                       uint64_t *out_total, uint64_t *out_touch);
+
 /* Count pairs (synchronous).
  * kind       TPCF_DD or TPCF_RR: unordered pairs i < j of cat_a, cat_b must be
  *            -1; TPCF_DR: every pair (i in cat_a, j in cat_b).
@@ -288,6 +321,23 @@ int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset);
  * out_w       host array of nbins doubles; NaN where RR_k = 0. */
 int tpcf_landy_szalay(const uint64_t *dd, const uint64_t *dr, const uint64_t *rr,
                       int32_t nbins, int64_t n_d, int64_t n_r, int form, double *out_w);
+
+/* Delete-one jackknife of the Landy-Szalay w over nreg regions, host FP64; no
+ * context needed.  dd, dr, rr: whole-catalog histograms (nbins+2 slots);
+ * dd_touch, dr_touch, rr_touch: the matching tpcf_count_regions outputs
+ * (nreg x (nbins+2)); n_d, n_r: catalog sizes; nd_reg, nr_reg: objects per
+ * region (tpcf_catalog_regions).  For each region r, sample r is
+ * tpcf_landy_szalay (same form) of the counts total - touch[r] with sizes
+ * n_d - nd_reg[r], n_r - nr_reg[r].  Outputs (host): out_samples nreg x nbins
+ * (region-major), out_mean nbins (may be NULL), out_cov nbins x nbins (may
+ * be NULL), cov = (nreg-1)/nreg * sum_r (w_r - mean)(w_r - mean)^T.
+ * 2 <= nreg <= TPCF_MAX_REGIONS; TPCF_E_INVALID as tpcf_landy_szalay for a
+ * deleted catalog with fewer than 2 objects. */
+int tpcf_jackknife(const uint64_t *dd, const uint64_t *dd_touch, const uint64_t *dr,
+                   const uint64_t *dr_touch, const uint64_t *rr, const uint64_t *rr_touch,
+                   int32_t nbins, int32_t nreg, int64_t n_d, const int64_t *nd_reg, int64_t n_r,
+                   const int64_t *nr_reg, int form, double *out_samples, double *out_mean,
+                   double *out_cov);
 
 /* Host-side edge compilation, exposed for inspection and CPU tests of the
  * host logic (no device work).  For nbins+1 edges in degrees it writes:

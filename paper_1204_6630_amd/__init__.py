@@ -19,12 +19,13 @@ import numpy as np
 
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
-    "landy_szalay", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
+    "landy_szalay", "jackknife", "MAX_REGIONS", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
 DD, DR, RR = 0, 1, 2
 FP32_CHORD, FP64, FP64_MATRIX = 0, 1, 2
+MAX_REGIONS = 1024
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libtpcf.so")
@@ -33,7 +34,8 @@ _lib = None
 # every symbol declared in include/tpcf.h
 EXPORTED_SYMBOLS = (
     "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
-    "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog", "tpcf_count",
+    "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog",
+    "tpcf_upload_catalog_regions", "tpcf_catalog_regions", "tpcf_count_regions", "tpcf_jackknife", "tpcf_count",
     "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
@@ -121,6 +123,10 @@ def lib():
         "tpcf_catalog_order": ([P, i32, P], cint),
         "tpcf_catalog_size": ([P, i32, P], cint),
         "tpcf_release_catalog": ([P, i32], cint),
+        "tpcf_upload_catalog_regions": ([P, P, P, i64, P, i32, P], cint),
+        "tpcf_catalog_regions": ([P, i32, P, P], cint),
+        "tpcf_count_regions": ([P, cint, i32, i32, P, i32, cint, P, P], cint),
+        "tpcf_jackknife": ([P, P, P, P, P, P, i32, i32, i64, P, i64, P, cint, P, P, P], cint),
         "tpcf_count": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
         "tpcf_count_async": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
         "tpcf_count_batch": ([P, P, i32, cint, P], cint),
@@ -211,6 +217,25 @@ class Context:
         _check(lib().tpcf_upload_catalog(self._h, _p(ra), _p(dec), ra.size, ctypes.byref(cid)))
         return cid.value
 
+    def upload_catalog_regions(self, ra_deg, dec_deg, region, nreg: int) -> int:
+        """Upload with a jackknife region label in [0, nreg) per object."""
+        ra, dec = _f64(ra_deg), _f64(dec_deg)
+        reg = np.ascontiguousarray(region, dtype=np.int32)
+        if ra.shape != dec.shape or ra.ndim != 1 or reg.shape != ra.shape:
+            raise ValueError("ra, dec and region must be 1-D arrays of the same length")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_upload_catalog_regions(self._h, _p(ra), _p(dec), ra.size, _p(reg), nreg,
+                                                 ctypes.byref(cid)))
+        return cid.value
+
+    def catalog_regions(self, cat: int) -> np.ndarray:
+        """Objects per region (empty for an unlabelled catalog)."""
+        nreg = ctypes.c_int32()
+        _check(lib().tpcf_catalog_regions(self._h, cat, ctypes.byref(nreg), None))
+        out = np.zeros(nreg.value, dtype=np.int64)
+        _check(lib().tpcf_catalog_regions(self._h, cat, ctypes.byref(nreg), _p(out)))
+        return out
+
     def upload_catalog_xyz(self, x, y, z) -> int:
         x, y, z = _f64(x), _f64(y), _f64(z)
         if not (x.shape == y.shape == z.shape) or x.ndim != 1:
@@ -258,6 +283,18 @@ class Context:
         _check(lib().tpcf_count(self._h, kind, cat_a, cat_b, _p(e), e.size - 1, precision,
                                 row_begin, row_end, _p(out)))
         return out
+
+    def count_regions(self, kind: int, cat_a: int, edges_deg, cat_b: int = -1,
+                      precision: int = FP32_CHORD):
+        """(total, touch): total as ``count``; touch[r] the pairs with a member
+        in region r (tpcf_count_regions)."""
+        e = _f64(edges_deg)
+        nreg = len(self.catalog_regions(cat_a))
+        total = np.zeros(e.size + 1, dtype=np.uint64)
+        touch = np.zeros((max(nreg, 1), e.size + 1), dtype=np.uint64)
+        _check(lib().tpcf_count_regions(self._h, kind, cat_a, cat_b, _p(e), e.size - 1, precision,
+                                        _p(total), _p(touch)))
+        return total, touch[:nreg]
 
     def count_async(self, kind: int, cat_a: int, edges_deg, out_device_ptr: int, cat_b: int = -1,
                     precision: int = FP32_CHORD, row_begin: int = -1, row_end: int = -1):
@@ -360,6 +397,29 @@ def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:
     w = np.empty(nbins, dtype=np.float64)
     _check(lib().tpcf_landy_szalay(_p(dd), _p(dr), _p(rr), nbins, n_d, n_r, form, _p(w)))
     return w
+
+
+def jackknife(dd, dd_touch, dr, dr_touch, rr, rr_touch, n_d: int, nd_reg, n_r: int, nr_reg,
+              form: int = 0):
+    """Delete-one jackknife of w (tpcf_jackknife): (samples [nreg, nbins],
+    mean [nbins], cov [nbins, nbins])."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (dd, dd_touch, dr, dr_touch, rr, rr_touch)]
+    ndr = np.ascontiguousarray(nd_reg, dtype=np.int64)
+    nrr = np.ascontiguousarray(nr_reg, dtype=np.int64)
+    nslots = arrs[0].size
+    nreg = ndr.size
+    if arrs[0].ndim != 1 or nslots < 3 or nrr.size != nreg:
+        raise ValueError("need nbins+2-slot totals and one size per region")
+    for t, touch in zip(arrs[0::2], arrs[1::2]):
+        if t.shape != (nslots,) or touch.shape != (nreg, nslots):
+            raise ValueError("totals must have nbins+2 slots and touch arrays shape (nreg, nbins+2)")
+    nbins = nslots - 2
+    samples = np.empty((nreg, nbins), dtype=np.float64)
+    mean = np.empty(nbins, dtype=np.float64)
+    cov = np.empty((nbins, nbins), dtype=np.float64)
+    _check(lib().tpcf_jackknife(*(_p(a) for a in arrs), nbins, nreg, n_d, _p(ndr), n_r, _p(nrr), form,
+                                _p(samples), _p(mean), _p(cov)))
+    return samples, mean, cov
 
 
 def compile_edges(edges_deg, delta_max: float = 0.0):

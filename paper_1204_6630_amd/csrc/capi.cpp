@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "edges.h"
@@ -133,6 +134,9 @@ struct Catalog {
     size_t bytes_pack = 0;
     double *dcaps = nullptr;    // bounding caps of aligned 64-point groups, built on first use
     size_t bytes_caps = 0;
+    // jackknife regions: stored rows of region r are [reg_start[r], reg_start[r+1])
+    int32_t nreg = 0;
+    std::vector<int64_t> reg_start;
 };
 
 struct Compiled {
@@ -160,6 +164,8 @@ struct Workspace {
     DevBuf copies;   // kGlobalCopies x nslots u64
     DevBuf out;      // kMaxSlots u64
     DevBuf stats;    // 8 u64
+    DevBuf touch;    // nreg x kGlobalCopies x nslots u64 (jackknife regions)
+    DevBuf tout;     // nreg x nslots u64
     int inflight = 0;
 };
 
@@ -244,6 +250,8 @@ int init_workspace(tpcf_ctx *ctx, Workspace &w, hipStream_t borrowed) {
 
 void free_workspace(tpcf_ctx *ctx, Workspace &w) {
     w.copies.release(ctx->mem);
+    w.touch.release(ctx->mem);
+    w.tout.release(ctx->mem);
     w.out.release(ctx->mem);
     w.stats.release(ctx->mem);
     if (w.own && w.stream)
@@ -314,19 +322,24 @@ uint64_t quant21(double c) {
     return (uint64_t)t;
 }
 
-std::vector<int64_t> morton_order(const double *x, const double *y, const double *z, int64_t n) {
-    std::vector<std::pair<uint64_t, int64_t>> k((size_t)n);
+// Stored order: Morton order of the unit vectors, grouped by region first
+// when labels are given (so each region is a contiguous range of rows).
+std::vector<int64_t> morton_order(const double *x, const double *y, const double *z, int64_t n,
+                                  const int32_t *region = nullptr) {
+    std::vector<std::tuple<int32_t, uint64_t, int64_t>> k((size_t)n);
     for (int64_t i = 0; i < n; ++i)
-        k[i] = {spread3(quant21(x[i])) | spread3(quant21(y[i])) << 1 | spread3(quant21(z[i])) << 2, i};
+        k[i] = std::make_tuple(region ? region[i] : 0,
+                               spread3(quant21(x[i])) | spread3(quant21(y[i])) << 1 | spread3(quant21(z[i])) << 2,
+                               i);
     std::sort(k.begin(), k.end());
     std::vector<int64_t> order((size_t)n);
     for (int64_t i = 0; i < n; ++i)
-        order[i] = k[i].second;
+        order[i] = std::get<2>(k[i]);
     return order;
 }
 
 int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
-                int32_t *out_cat) {
+                int32_t *out_cat, const int32_t *region = nullptr, int32_t nreg = 0) {
     if (!out_cat)
         return fail(TPCF_E_INVALID, "out_cat is NULL");
     if (n < 0 || n > (int64_t)0x7fffffff - 1024)
@@ -343,7 +356,15 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
     Catalog c;
     c.n = n;
     c.delta = delta;
-    c.order = morton_order(x, y, z, n);
+    c.order = morton_order(x, y, z, n, region);
+    if (region) {
+        c.nreg = nreg;
+        c.reg_start.assign((size_t)nreg + 1, 0);
+        for (int64_t i = 0; i < n; ++i)
+            ++c.reg_start[(size_t)region[i] + 1];
+        for (int32_t r = 0; r < nreg; ++r)
+            c.reg_start[(size_t)r + 1] += c.reg_start[(size_t)r];
+    }
     size_t alloc_n = (size_t)(n > 0 ? n : 1);
     std::vector<double> h64(3 * alloc_n, 0.0);
     std::vector<float> h32(3 * alloc_n, 0.0f);
@@ -481,6 +502,21 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
 // Work units.  DR: every row tile against column chunks of the B catalog.
 // DD/RR: every row tile [i0, i1) against j in [i0, n): one masked unit for the
 // diagonal block [i0, i0 + T), then unmasked chunks from i0 + T on.
+Unit mk_unit(int64_t i0, int64_t i1, int64_t j0, int64_t j1, int64_t row_lo, int64_t col_lo, int32_t reg_a,
+             int32_t reg_b) {
+    Unit u;
+    memset(&u, 0, sizeof u);
+    u.i0 = (int32_t)i0;
+    u.i1 = (int32_t)i1;
+    u.j0 = (int32_t)j0;
+    u.j1 = (int32_t)j1;
+    u.row_lo = (int32_t)row_lo;
+    u.col_lo = (int32_t)col_lo;
+    u.reg_a = reg_a;
+    u.reg_b = reg_b;
+    return u;
+}
+
 Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, int64_t T,
                int64_t max_cols, int64_t align) {
     Plan p;
@@ -514,7 +550,7 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
             const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
             const int64_t dend = i0 + T < na ? i0 + T : na;
             if (lo + 1 < dend)
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)i0, (int32_t)dend, 0, lo, 0, 0});
+                p.units.push_back(mk_unit(i0, i1, i0, dend, lo, i0, -1, -1));
             int64_t j0 = dend;
             while (j0 < na) {
                 // up to the next multiple of bj; a short first piece joins the next chunk
@@ -523,7 +559,7 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
                     j1 += bj;
                 if (j1 > na)
                     j1 = na;
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
+                p.units.push_back(mk_unit(i0, i1, j0, j1, lo, j0, -1, -1));
                 j0 = j1;
             }
         }
@@ -536,8 +572,73 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
             for (int64_t i0 = i_first; i0 < re; i0 += T) {
                 const int64_t i1 = i0 + T < re ? i0 + T : re;
                 const int32_t lo = (int32_t)(i0 > rb ? i0 : rb);
-                p.units.push_back(Unit{(int32_t)i0, (int32_t)i1, (int32_t)j0, (int32_t)j1, 0, lo, 0, 0});
+                p.units.push_back(mk_unit(i0, i1, j0, j1, lo, j0, -1, -1));
             }
+        }
+    }
+    return p;
+}
+
+// Work units of a whole-catalog request with jackknife regions: no unit
+// crosses a region boundary on either side, and each carries its two region
+// ids.  Row tiles are cut at region ends (and start on multiples of `align`,
+// valid rows from the region start); columns are cut on the bj grid and at
+// region starts (matrix-core units start on multiples of 16, valid columns
+// from col_lo).  Auto-pairs: per row tile a diagonal unit over the tile's
+// own columns, then the columns after it.  Ordered column chunk first.
+Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64_t max_cols, int64_t align,
+                       const std::vector<int64_t> &sa, const std::vector<int64_t> &sb) {
+    Plan p;
+    p.pairs = auto_pairs ? (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2 : (uint64_t)na * (uint64_t)nb;
+    double per_unit = (double)p.pairs / 4096.0 / (double)T;
+    int64_t bj = (int64_t)per_unit;
+    bj = (bj + 255) / 256 * 256;
+    if (bj > max_cols)
+        bj = max_cols;
+    if (bj < 256)
+        bj = 256;
+    const int nra = (int)sa.size() - 1, nrb = (int)sb.size() - 1;
+    auto region_of = [](const std::vector<int64_t> &st, int64_t j) {
+        return (int32_t)(std::upper_bound(st.begin(), st.end(), j) - st.begin() - 1);
+    };
+    // the column pieces [c0, c1) after column j: bj grid and region starts
+    auto next_cut = [&](const std::vector<int64_t> &st, int64_t j, int64_t n) {
+        int64_t c = (j / bj + 1) * bj;
+        const auto it = std::upper_bound(st.begin(), st.end(), j);
+        if (it != st.end() && *it < c)
+            c = *it;
+        return c < n ? c : n;
+    };
+    struct Tile { int64_t i0, i1, lo; int32_t reg; };
+    std::vector<Tile> tiles;
+    for (int r = 0; r < nra; ++r) {
+        const int64_t s0 = sa[(size_t)r], s1 = sa[(size_t)r + 1];
+        if (s0 == s1)
+            continue;   // empty region
+        for (int64_t i0 = s0 - s0 % align; i0 < s1; i0 += T)
+            tiles.push_back(Tile{i0, i0 + T < s1 ? i0 + T : s1, i0 > s0 ? i0 : s0, (int32_t)r});
+    }
+    if (auto_pairs) {
+        for (const Tile &t : tiles) {
+            if (t.lo + 1 < t.i1)
+                p.units.push_back(mk_unit(t.i0, t.i1, t.i0, t.i1, t.lo, t.i0, t.reg, t.reg));
+            for (int64_t j = t.i1; j < na;) {
+                const int64_t c1 = next_cut(sa, j, na);
+                p.units.push_back(mk_unit(t.i0, t.i1, j - j % align, c1, t.lo, j, t.reg, region_of(sa, j)));
+                j = c1;
+            }
+        }
+        std::sort(p.units.begin(), p.units.end(), [](const Unit &x, const Unit &y) {
+            return x.j1 != y.j1 ? x.j1 < y.j1 : x.i0 < y.i0;
+        });
+    } else {
+        (void)nrb;
+        for (int64_t j = 0; j < nb;) {
+            const int64_t c1 = next_cut(sb, j, nb);
+            const int32_t rj = region_of(sb, j);
+            for (const Tile &t : tiles)
+                p.units.push_back(mk_unit(t.i0, t.i1, j - j % align, c1, t.lo, j, t.reg, rj));
+            j = c1;
         }
     }
     return p;
@@ -566,6 +667,38 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
         ctx->plans.clear();
     }
     auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re, T, max_cols, align));
+    TRY(upload_blocking(ctx->mem, p->dunits, p->units));
+    *out = p.get();
+    ctx->plans[buf] = std::move(p);
+    return TPCF_OK;
+}
+
+// Plan of a whole-catalog request with jackknife regions (cached like get_plan,
+// keyed by the catalog ids, which are never reused).
+int get_plan_regions(tpcf_ctx *ctx, bool auto_pairs, int32_t cat_a, int32_t cat_b, const Catalog &A,
+                     const Catalog &B, bool matrix, Plan **out) {
+    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * rows_per_lane_of(ctx->tune, matrix);
+    const int64_t align = matrix ? 16 : 1;
+    const int64_t max_cols = max_cols_of(ctx->tune);
+    char buf[160];
+    snprintf(buf, sizeof buf, "R%d:%d:%d:%lld:%lld:%lld", (int)auto_pairs, (int)cat_a, (int)cat_b, (long long)T,
+             (long long)max_cols, (long long)align);
+    auto it = ctx->plans.find(buf);
+    if (it != ctx->plans.end()) {
+        *out = it->second.get();
+        return TPCF_OK;
+    }
+    if (ctx->plans.size() >= 256) {
+        TRY(sync_all(ctx));
+        drop_graphs(ctx);
+        for (auto &kv : ctx->plans)
+            kv.second->dunits.release(ctx->mem);
+        ctx->plans.clear();
+    }
+    auto p = std::make_unique<Plan>(
+        make_plan_regions(auto_pairs, A.n, B.n, T, max_cols, align, A.reg_start, B.reg_start));
+    if (p->units.size() > (size_t)0x7fffffff / kWaves)
+        return fail(TPCF_E_INVALID, "too many work units (region boundaries split the work too finely)");
     TRY(upload_blocking(ctx->mem, p->dunits, p->units));
     *out = p.get();
     ctx->plans[buf] = std::move(p);
@@ -638,7 +771,7 @@ int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
 
 // Validate one request.  delta_override >= 0 compiles the FP32 band for that
 // norm bound (shared by every job of a batch) instead of the request's own.
-int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r) {
+int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r, bool regions = false) {
     if (d.kind != TPCF_DD && d.kind != TPCF_DR && d.kind != TPCF_RR)
         return fail(TPCF_E_INVALID, "kind must be TPCF_DD, TPCF_DR or TPCF_RR");
     if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64 && d.precision != TPCF_FP64_MATRIX)
@@ -688,9 +821,19 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
     }
     if (ctx->tune.prune)
         TRY(ensure_caps(ctx, const_cast<Catalog &>(*r->B)));
+    r->cache_key.clear();
+    if (regions) {
+        if (rb != 0 || re != r->A->n)
+            return fail(TPCF_E_INVALID, "region counts cover whole catalogs");
+        if (r->A->nreg < 1 || r->B->nreg != r->A->nreg)
+            return fail(TPCF_E_INVALID, "both catalogs need region labels with the same number of regions");
+        TRY(get_plan_regions(ctx, r->auto_pairs, r->cat_a, r->auto_pairs ? r->cat_a : r->cat_b, *r->A, *r->B,
+                             matrix, &r->plan));
+        r->pairs = r->plan->pairs;
+        return TPCF_OK;
+    }
     TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, matrix, &r->plan));
     r->pairs = r->plan->pairs;
-    r->cache_key.clear();
     if (d.kind == TPCF_RR)
         r->cache_key = cache_key(d.cat_a, d.bin_edges_deg, d.nbins, d.precision, rb, re);
     return TPCF_OK;
@@ -787,9 +930,18 @@ int record_stop(tpcf_ctx *ctx, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
 // Enqueue one request on a workspace: zero its histogram copies, count, and
 // reduce into d_out (nslots u64).  Every argument travels by value in the
 // kernel arguments, so nothing on the host must outlive the call.
+// With regions (nreg > 0), every unit's counts also go to the copies of its
+// two regions in w.touch, reduced into d_touch (nreg x nslots u64).
 int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long *d_out,
-               const int *cancel) {
+               const int *cancel, int32_t nreg = 0, unsigned long long *d_touch = nullptr) {
     const int nslots = r.nbins + 2;
+    unsigned long long *touch = nullptr;
+    if (nreg > 0) {
+        const size_t per = (size_t)kGlobalCopies * (size_t)nslots;
+        TRY(w.touch.ensure(ctx->mem, sizeof(unsigned long long) * per * (size_t)nreg));
+        touch = (unsigned long long *)w.touch.p;
+        HIP_TRY((hipError_t)tpcf_launch_zero_u64(touch, (int64_t)(per * (size_t)nreg), w.stream));
+    }
     // the histogram copies, then the work-queue counter, zeroed together
     TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * ((size_t)kGlobalCopies * kMaxSlots + 1)));
     unsigned long long *copies = (unsigned long long *)w.copies.p;
@@ -797,6 +949,7 @@ int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long
     PairArgs a = args_of(ctx, *r.cp, r.nbins, (unsigned long long *)w.stats.p);
     a.jobs = nullptr;
     a.job0 = job_of(r, copies, cancel);
+    a.job0.touch = touch;
     a.units = (const Unit *)r.plan->dunits.p;
     a.n_units = (int32_t)r.plan->units.size();
     a.queue = (unsigned int *)(copies + (size_t)kGlobalCopies * nslots);
@@ -810,6 +963,8 @@ int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long
         return fail(TPCF_E_HIP, std::string("pair kernel launch: ") + hipGetErrorString((hipError_t)lrc));
     TRY(record_stop(ctx, w.stream, e0, e1));
     lrc = tpcf_launch_reduce_copies(copies, nslots, 1, d_out, w.stream);
+    if (lrc == 0 && touch)
+        lrc = tpcf_launch_reduce_copies(touch, nslots, nreg, d_touch, w.stream);
     if (lrc)
         return fail(TPCF_E_HIP, std::string("reduce launch: ") + hipGetErrorString((hipError_t)lrc));
     ctx->pairs_since_reset += r.pairs;
@@ -935,14 +1090,21 @@ int tpcf_close(tpcf_ctx *ctx) {
     return TPCF_OK;
 }
 
-int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg, int64_t n,
-                        int32_t *out_cat) {
+int tpcf_upload_catalog_regions(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg, int64_t n,
+                                const int32_t *region, int32_t nreg, int32_t *out_cat) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     if (n < 0)
         return fail(TPCF_E_INVALID, "n must be >= 0");
     if (n > 0 && (!ra_deg || !dec_deg))
         return fail(TPCF_E_INVALID, "ra_deg/dec_deg is NULL");
+    if (region) {
+        if (nreg < 1 || nreg > TPCF_MAX_REGIONS)
+            return fail(TPCF_E_INVALID, "nreg must be in [1, TPCF_MAX_REGIONS]");
+        for (int64_t i = 0; i < n; ++i)
+            if (region[i] < 0 || region[i] >= nreg)
+                return fail(TPCF_E_INVALID, "region labels must lie in [0, nreg)");
+    }
     const double deg = M_PI / 180.0;
     std::vector<double> x((size_t)n), y((size_t)n), z((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
@@ -954,7 +1116,26 @@ int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_d
         y[i] = cos(b) * sin(a);
         z[i] = sin(b);
     }
-    return add_catalog(ctx, x.data(), y.data(), z.data(), n, out_cat);
+    return add_catalog(ctx, x.data(), y.data(), z.data(), n, out_cat, region, region ? nreg : 0);
+}
+
+int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_deg, int64_t n,
+                        int32_t *out_cat) {
+    return tpcf_upload_catalog_regions(ctx, ra_deg, dec_deg, n, nullptr, 0, out_cat);
+}
+
+int tpcf_catalog_regions(tpcf_ctx *ctx, int32_t cat, int32_t *out_nreg, int64_t *out_counts) {
+    if (!ctx || !out_nreg)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    auto it = ctx->cats.find(cat);
+    if (it == ctx->cats.end())
+        return fail(TPCF_E_BADID, "unknown catalog id");
+    const Catalog &c = it->second;
+    *out_nreg = c.nreg;
+    if (out_counts)
+        for (int32_t r = 0; r < c.nreg; ++r)
+            out_counts[r] = c.reg_start[(size_t)r + 1] - c.reg_start[(size_t)r];
+    return TPCF_OK;
 }
 
 int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y, const double *z,
@@ -1095,6 +1276,43 @@ int tpcf_count(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const doub
     if (!r.cache_key.empty())
         ctx->result_cache[r.cache_key] = h;
     memcpy(out_u64, h.data(), sizeof(uint64_t) * h.size());
+    return TPCF_OK;
+}
+
+int tpcf_count_regions(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const double *bin_edges_deg,
+                       int32_t nbins, int precision, uint64_t *out_total, uint64_t *out_touch) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    if (!out_total || !out_touch)
+        return fail(TPCF_E_INVALID, "out_total/out_touch is NULL");
+    Request r;
+    TRY(prepare(ctx, desc_of(kind, cat_a, cat_b, bin_edges_deg, nbins, precision, -1, -1), -1, &r, true));
+    const int nslots = nbins + 2;
+    const int32_t nreg = r.A->nreg;
+    Workspace &w = ctx->main;
+    TRY(w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots));
+    TRY(w.tout.ensure(ctx->mem, sizeof(unsigned long long) * (size_t)kMaxSlots * (size_t)nreg));
+    TRY(launch_one(ctx, w, r, (unsigned long long *)w.out.p, nullptr, nreg, (unsigned long long *)w.tout.p));
+    std::vector<uint64_t> h((size_t)nslots), t((size_t)nslots * (size_t)nreg);
+    HIP_TRY(hipMemcpyAsync(h.data(), w.out.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, w.stream));
+    HIP_TRY(hipMemcpyAsync(t.data(), w.tout.p, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost, w.stream));
+    HIP_TRY(hipStreamSynchronize(w.stream));
+    TRY(check_total(h.data(), nslots, r.pairs));
+    // every pair touches one or two regions: the touch sums lie between the
+    // total and twice the total, slot by slot, and no region exceeds the total
+    for (int s = 0; s < nslots; ++s) {
+        uint64_t sum = 0;
+        for (int32_t g = 0; g < nreg; ++g) {
+            const uint64_t v = t[(size_t)g * nslots + s];
+            if (v > h[(size_t)s])
+                return fail(TPCF_E_INTERNAL, "a region count exceeds the total");
+            sum += v;
+        }
+        if (sum < h[(size_t)s] || sum > 2 * h[(size_t)s])
+            return fail(TPCF_E_INTERNAL, "region counts do not cover the total");
+    }
+    memcpy(out_total, h.data(), sizeof(uint64_t) * h.size());
+    memcpy(out_touch, t.data(), sizeof(uint64_t) * t.size());
     return TPCF_OK;
 }
 
@@ -1515,6 +1733,52 @@ int tpcf_landy_szalay(const uint64_t *dd, const uint64_t *dr, const uint64_t *rr
         }
     }
     memcpy(out_w, w.data(), sizeof(double) * (size_t)nbins);
+    return TPCF_OK;
+}
+
+int tpcf_jackknife(const uint64_t *dd, const uint64_t *dd_touch, const uint64_t *dr, const uint64_t *dr_touch,
+                   const uint64_t *rr, const uint64_t *rr_touch, int32_t nbins, int32_t nreg, int64_t n_d,
+                   const int64_t *nd_reg, int64_t n_r, const int64_t *nr_reg, int form, double *out_samples,
+                   double *out_mean, double *out_cov) {
+    if (!dd || !dd_touch || !dr || !dr_touch || !rr || !rr_touch || !nd_reg || !nr_reg || !out_samples)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    if (nbins < 1 || nbins > 256)
+        return fail(TPCF_E_INVALID, "nbins must be in [1, 256]");
+    if (nreg < 2 || nreg > TPCF_MAX_REGIONS)
+        return fail(TPCF_E_INVALID, "nreg must be in [2, TPCF_MAX_REGIONS]");
+    const size_t ns = (size_t)nbins + 2, K = (size_t)nreg, nb = (size_t)nbins;
+    std::vector<uint64_t> d1(ns), d2(ns), d3(ns);
+    for (size_t r = 0; r < K; ++r) {
+        // region r deleted: the pairs that touch it leave every count
+        for (size_t s = 0; s < ns; ++s) {
+            if (dd_touch[r * ns + s] > dd[s] || dr_touch[r * ns + s] > dr[s] || rr_touch[r * ns + s] > rr[s])
+                return fail(TPCF_E_INVALID, "a region count exceeds its total");
+            d1[s] = dd[s] - dd_touch[r * ns + s];
+            d2[s] = dr[s] - dr_touch[r * ns + s];
+            d3[s] = rr[s] - rr_touch[r * ns + s];
+        }
+        TRY(tpcf_landy_szalay(d1.data(), d2.data(), d3.data(), nbins, n_d - nd_reg[r], n_r - nr_reg[r], form,
+                              out_samples + r * nb));
+    }
+    std::vector<double> mean(nb, 0.0);
+    for (size_t k = 0; k < nb; ++k) {
+        double acc = 0.0;
+        for (size_t r = 0; r < K; ++r)
+            acc += out_samples[r * nb + k];
+        mean[k] = acc / (double)K;
+    }
+    if (out_mean)
+        memcpy(out_mean, mean.data(), sizeof(double) * nb);
+    if (out_cov) {
+        const double f = ((double)K - 1.0) / (double)K;
+        for (size_t a = 0; a < nb; ++a)
+            for (size_t b = 0; b < nb; ++b) {
+                double acc = 0.0;
+                for (size_t r = 0; r < K; ++r)
+                    acc += (out_samples[r * nb + a] - mean[a]) * (out_samples[r * nb + b] - mean[b]);
+                out_cov[a * nb + b] = f * acc;
+            }
+    }
     return TPCF_OK;
 }
 

@@ -34,13 +34,16 @@ constexpr uint16_t kMulti = 0xFFFF;
 constexpr int kMaxSlots8 = 127;
 
 // One work unit: the row tile starting at i0 with valid rows [row_lo, i1),
-// against columns j in [j0, j1), of job `job`.  A unit needs per-pair masking
-// when its valid rows do not fill the tile, when j1 cuts a column group short
-// (matrix-core path), or, for auto-pairs, when its columns overlap its rows
-// (the j <= i diagonal).  Matrix-core units start i0 and j0 on multiples of 16.
+// against columns j in [j0, j1) with valid columns from col_lo, of job `job`.
+// A unit needs per-pair masking when its valid rows do not fill the tile,
+// when j1 cuts a column group short or col_lo > j0 (matrix-core path: units
+// start i0 and j0 on multiples of 16; on the vector paths col_lo == j0), or,
+// for auto-pairs, when its columns overlap its rows (the j <= i diagonal).
+// reg_a / reg_b: jackknife regions of the unit's rows and columns (-1: none).
 struct Unit {
     int32_t i0, i1, j0, j1;
-    int32_t job, row_lo, pad1, pad2;
+    int32_t job, row_lo, col_lo, reg_a;
+    int32_t reg_b, pad0, pad1, pad2;
 };
 
 // One counting job of a launch: catalogs A (rows i) and B (columns j) as
@@ -60,6 +63,10 @@ struct JobDev {
     // unless pruning is on.
     const double *bcaps;
     unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
+    // jackknife regions: nreg x kGlobalCopies x nslots, zeroed before; the
+    // histogram of a unit also goes to its rows' and columns' regions (once
+    // when they coincide).  Null without regions.
+    unsigned long long *touch;
     const int *cancel;           // host-visible flag (non-zero: skip the rest), or null
     int32_t auto_pairs;          // 1: DD/RR (count j > i only), 0: DR
     int32_t na, nb;              // catalog sizes

@@ -181,12 +181,13 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Sum one wavefront's LDS histogram into a global copy and clear it.
-__device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long *hist, int wave,
-                           int lane, int copy) {
+// Sum one wavefront's LDS histogram into a global copy and clear it; with
+// region copies (r0, r1 non-null) the sums also go there.
+__device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long *hist, unsigned long long *r0,
+                           unsigned long long *r1, int wave, int lane, int copy) {
     const int C = a.hist_copies;
     uint32_t *h = s.hist + wave * (a.nslots + 1) * C;
-    unsigned long long *g = hist + (size_t)copy * a.nslots;
+    const size_t off = (size_t)copy * a.nslots;
     for (int s0 = 0; s0 < a.nslots; s0 += kWaveSize) {
         int slot = s0 + lane;
         if (slot < a.nslots) {
@@ -198,8 +199,13 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long 
                 acc += row[cc];
                 row[cc] = 0;
             }
-            if (acc)
-                atomicAdd(&g[slot], (unsigned long long)acc);
+            if (acc) {
+                atomicAdd(&hist[off + slot], (unsigned long long)acc);
+                if (r0)
+                    atomicAdd(&r0[off + slot], (unsigned long long)acc);
+                if (r1)
+                    atomicAdd(&r1[off + slot], (unsigned long long)acc);
+            }
         }
     }
 }
@@ -735,7 +741,7 @@ __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, dou
 template <bool LUT8, bool MASKED, int RG>
 __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, const Smem &s,
                                          const Consts &k, const v4d (&d)[RG], int ib, int rlo, int ie,
-                                         int jg, int j1, int lane, Counters &cnt) {
+                                         int jg, int clo, int j1, int lane, Counters &cnt) {
     if (!MASKED) {
         // every pair of the tile certainly beyond the last edge: high word of
         // e above that of the band's upper end
@@ -796,7 +802,7 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
             if (MASKED) {
                 const int i = ib + 16 * g + mma_row(lane, r);
                 const int j = 16 * jg + mma_col(lane);
-                bool ok = i >= rlo && i < ie && j < j1 && (!jb.auto_pairs || j > i);
+                bool ok = i >= rlo && i < ie && j >= clo && j < j1 && (!jb.auto_pairs || j > i);
                 v = ok ? v : (uint32_t)a.nslots;
             }
             lds_inc(__umul24(v, k.rowstep) + k.lanebase);
@@ -805,8 +811,8 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
 
 template <bool LUT8, bool MASKED, int RG>
 __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                                         const double (&A)[RG], int ib, int rlo, int ie, int j0, int j1,
-                                         int lane, Counters &cnt) {
+                                         const double (&A)[RG], int ib, int rlo, int ie, int j0, int clo,
+                                         int j1, int lane, Counters &cnt) {
     const gdouble_p bp = (gdouble_p)jb.bpack + lane;
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     const int jg0 = j0 >> 4;
@@ -835,7 +841,7 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
             for (int g = 0; g < RG; ++g)
                 d1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
         }
-        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d0, ib, rlo, ie, jg, j1, lane, cnt);
+        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d0, ib, rlo, ie, jg, clo, j1, lane, cnt);
         if (!has1)
             break;
         if (jg + 2 < jg_end) {
@@ -846,7 +852,7 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
             for (int g = 0; g < RG; ++g)
                 d0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
         }
-        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d1, ib, rlo, ie, jg + 1, j1, lane, cnt);
+        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d1, ib, rlo, ie, jg + 1, clo, j1, lane, cnt);
     }
 }
 
@@ -860,7 +866,7 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
 // the wavefront does its lookups.
 template <bool LUT8, bool MASKED, int RG, bool PRUNE>
 __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                         int ib, int rlo, int ie, int j0, int j1, int lane, Counters &cnt) {
+                         int ib, int rlo, int ie, int j0, int clo, int j1, int lane, Counters &cnt) {
     const gdouble_p ap = (gdouble_p)jb.apack + lane;
     double A[RG];
     const int g0 = ib >> 4;
@@ -886,12 +892,12 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
                     continue;
                 }
             }
-            cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j, jn, lane, cnt);
+            cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j, j, jn, lane, cnt);
             j = jn;
         }
         return;
     }
-    cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j0, j1, lane, cnt);
+    cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j0, clo, j1, lane, cnt);
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
@@ -963,13 +969,17 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             }
             const int ie = min(un.i1, ib + kRowsPerWave);
             const int rlo = max(un.row_lo, ib);
-            bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib;
+            // col_lo > j0 occurs on the matrix-core path only (vector plans start
+            // every unit at its first valid column)
+            bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib ||
+                          un.col_lo > un.j0;
             if (PREC == 2) {
                 masked = masked || (un.j1 & 15) != 0;
                 if (masked)
-                    rows_mma<LUT8, true, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
+                    rows_mma<LUT8, true, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane, cnt);
                 else
-                    rows_mma<LUT8, false, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.j1, lane, cnt);
+                    rows_mma<LUT8, false, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
+                                                    cnt);
             } else if (PREC == 0 || PREC == 3) {
                 if (masked)
                     rows_fp32<LUT8, true, P, PREC == 3, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
@@ -988,7 +998,15 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                 lds_add(__umul24((uint32_t)(a.nslots - 1), k.rowstep) + k.lanebase, cnt.beyond);
                 cnt.beyond = 0;
             }
-            flush_wave(a, s, jb.hist, wave, lane, (int)(item & (kGlobalCopies - 1)));
+            unsigned long long *r0 = nullptr, *r1 = nullptr;
+            if (jb.touch) {
+                const size_t per_region = (size_t)kGlobalCopies * a.nslots;
+                if (un.reg_a >= 0)
+                    r0 = jb.touch + (size_t)un.reg_a * per_region;
+                if (un.reg_b >= 0 && un.reg_b != un.reg_a)
+                    r1 = jb.touch + (size_t)un.reg_b * per_region;
+            }
+            flush_wave(a, s, jb.hist, r0, r1, wave, lane, (int)(item & (kGlobalCopies - 1)));
         }
     }
     uint32_t f = wave_sum(cnt.flag);

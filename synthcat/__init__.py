@@ -109,6 +109,16 @@ def clustered(n: int, n_centres: int, sigma_deg: float, footprint,
     return ra, dec
 
 
+def grid_regions(ra, dec, footprint, n_ra: int, n_dec: int) -> np.ndarray:
+    """Jackknife region labels (int32): the footprint cut into an n_ra x n_dec
+    grid of equal RA and Dec steps, label = dec_cell * n_ra + ra_cell.  Points
+    on or past the far edges fall into the last cell of each axis."""
+    ra0, ra1, de0, de1 = footprint
+    ia = np.clip(((np.asarray(ra) - ra0) / (ra1 - ra0) * n_ra).astype(np.int64), 0, n_ra - 1)
+    idc = np.clip(((np.asarray(dec) - de0) / (de1 - de0) * n_dec).astype(np.int64), 0, n_dec - 1)
+    return (idc * n_ra + ia).astype(np.int32)
+
+
 @dataclass
 class Catalog:
     ra: np.ndarray

@@ -330,3 +330,49 @@ def test_matrix_cells_are_consistent_with_the_band():
     med = (ent >= 0x8000) & (ent != 0xFFFF)
     k = ent[med] & 0x7FFF
     assert np.all(smin[med] >= k) and np.all(smax[med] <= k + 1)
+
+
+# --- host jackknife (tpcf_jackknife) -----------------------------------------
+
+def test_host_jackknife_equals_oracle_recount():
+    """tpcf_jackknife on oracle region counts against the oracle's delete-one
+    jackknife by recount of the reduced catalogs (an independent route:
+    removing points and counting again)."""
+    g = synthcat.rng_for(94, 0)
+    patch = (0.0, 16.0, 0.0, 16.0)
+    ra_d, dec_d = synthcat.uniform_patch(350, patch, g)
+    ra_r, dec_r = synthcat.uniform_patch(420, patch, g)
+    nreg = 6
+    reg_d = synthcat.grid_regions(ra_d, dec_d, patch, 3, 2)
+    reg_r = synthcat.grid_regions(ra_r, dec_r, patch, 3, 2)
+    d = oracle.radec_to_xyz(ra_d, dec_d)
+    r = oracle.radec_to_xyz(ra_r, dec_r)
+    e = synthcat.log_edges(0.5, 10.0, 7)
+    dd = oracle.count_regions(oracle.DD, d, reg_d, e, nreg)
+    dr = oracle.count_regions(oracle.DR, d, reg_d, e, nreg, b_xyz=r, b_region=reg_r)
+    rr = oracle.count_regions(oracle.RR, r, reg_r, e, nreg)
+    nd_reg = np.bincount(reg_d, minlength=nreg)
+    nr_reg = np.bincount(reg_r, minlength=nreg)
+    for form in (0, 1):
+        s, m, c = tp.jackknife(dd[0], dd[1], dr[0], dr[1], rr[0], rr[1], 350, nd_reg, 420, nr_reg, form)
+        so, mo, co = oracle.jackknife(d, reg_d, r, reg_r, e, nreg, form)
+        assert np.array_equal(np.isnan(s), np.isnan(so))
+        np.testing.assert_allclose(s, so, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(m, mo, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(c, co, rtol=1e-10, atol=1e-18)
+
+
+def test_host_jackknife_argument_errors():
+    z = np.zeros(5, np.uint64)
+    t = np.zeros((3, 5), np.uint64)
+    n = np.ones(3, np.int64)
+    with pytest.raises(ValueError):
+        tp.jackknife(z, t, z, t, z, t, 10, np.ones(2, np.int64), 10, n)
+    with pytest.raises(tp.TpcfError):
+        tp.jackknife(z, t, z, t, z, t, 10, n, 10, n, form=2)
+    one = np.zeros((1, 5), np.uint64)
+    with pytest.raises(tp.TpcfError):   # a single region has no jackknife
+        tp.jackknife(z, one, z, one, z, one, 10, np.ones(1, np.int64), 10, np.ones(1, np.int64))
+    big = np.ones((3, 5), np.uint64)
+    with pytest.raises(tp.TpcfError):   # a region count above its total
+        tp.jackknife(z, big, z, t, z, t, 10, n, 10, n)
