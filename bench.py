@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--no-matrix", action="store_true", help="skip the FP64 matrix-core path")
     ap.add_argument("--no-prune", action="store_true",
                     help="skip the extra run with exact tile pruning (never the headline)")
+    ap.add_argument("--no-jackknife", action="store_true",
+                    help="skip the jackknife-region step (8 x 8 regions over the octant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -426,6 +428,45 @@ def main():
                   "pruned_fraction": round(st.pruned_pairs / max(1, st.pairs), 4),
                   "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
                           "blocks are not evaluated, so not comparable to value"}
+    jack = None
+    if not args.no_jackknife:
+        # jackknife regions: the same catalogs labelled with an 8 x 8 RA/Dec
+        # grid (64 regions); one step = DD, DR, RR with per-region counts
+        # (FP32 chord path) and the host delete-one jackknife of w
+        nreg = 64
+        lab_d = synthcat.grid_regions(d.ra, d.dec, synthcat.OCTANT, 8, 8)
+        lab_r = synthcat.grid_regions(r.ra, r.dec, synthcat.OCTANT, 8, 8)
+        jd = ctx.upload_catalog_regions(d.ra, d.dec, lab_d, nreg)
+        jr = ctx.upload_catalog_regions(r.ra, r.dec, lab_r, nreg)
+        nd_reg, nr_reg = ctx.catalog_regions(jd), ctx.catalog_regions(jr)
+
+        def jstep():
+            a = ctx.count_regions(tp.DD, jd, edges)
+            b = ctx.count_regions(tp.DR, jd, edges, cat_b=jr)
+            c = ctx.count_regions(tp.RR, jr, edges)
+            tp.jackknife(a[0], a[1], b[0], b[1], c[0], c[1], nd, nd_reg, nr, nr_reg)
+            return a, b, c
+
+        jstep()
+        ctx.kernel_time(reset=True)
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ja, jb_, jc = jstep()
+        t1 = time.perf_counter()
+        ctx.set_timing(False)
+        kms, _ = ctx.kernel_time(reset=True)
+        ctx.stats(reset=True)
+        if not all(np.array_equal(x[0], y) for x, y in zip((ja, jb_, jc), runs[paths[0]]["hist"])):
+            sys.exit("jackknife-region totals and brute-force histograms differ")
+        ms = (t1 - t0) / args.steps * 1e3
+        jack = {"nreg": nreg, "gpairs_s": round(pairs_step * args.steps / (t1 - t0) / 1e9, 2),
+                "ms_per_step": round(ms, 3), "kernel_ms_per_step": round(kms / args.steps, 3),
+                "over_plain_step": round(ms / sums[tp.FP32_CHORD]["ms_per_step"], 3),
+                "note": "DD+DR+RR with per-region counts (FP32 chord) + host jackknife of w; "
+                        "same totals as the plain step"}
+        ctx.release_catalog(jd)
+        ctx.release_catalog(jr)
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
@@ -458,6 +499,8 @@ def main():
         res[PATH_NAMES[prec]] = sums[prec]
     if pruned is not None:
         res["fp32_chord_pruned"] = pruned
+    if jack is not None:
+        res["jackknife_regions"] = jack
     if tp.FP64 in sums:
         res["fp32_over_fp64"] = round(sums[tp.FP32_CHORD]["gpairs_s"] / sums[tp.FP64]["gpairs_s"], 3)
     if not args.no_cpu_baseline:
