@@ -9,6 +9,8 @@ Contents
     wrappers over ``tpcf_oracle.c`` (plain FP64 double loops, libm acos).
   * ``landy_szalay``: the Landy-Szalay estimator (paper Eq. 1) written out in
     FP64 numpy.
+  * ``count3d``, ``pair_distances``: the same counting by 3-D distance of
+    Cartesian points (FP64 differences, libm sqrt).
   * ``count_regions``: counts plus, per jackknife region, the pairs with a
     member in it; ``jackknife``: delete-one jackknife of w by recounting the
     catalogs with each region removed.
@@ -64,6 +66,11 @@ def _load():
         lib.oracle_pair_slots.restype = ctypes.c_int
         lib.oracle_pair_angles.argtypes = [i64, P, P, P, P, P, P, P]
         lib.oracle_pair_angles.restype = ctypes.c_int
+        lib.oracle_count3d.argtypes = [ctypes.c_int, i64, P, P, P, i64, P, P, P,
+                                       ctypes.c_int32, P, i64, i64, ctypes.c_int, P]
+        lib.oracle_count3d.restype = ctypes.c_int
+        lib.oracle_pair_distances.argtypes = [i64, P, P, P, P, P, P, P]
+        lib.oracle_pair_distances.restype = ctypes.c_int
         lib.oracle_count_regions.argtypes = [ctypes.c_int, i64, P, P, P, P, i64, P, P, P, P,
                                              ctypes.c_int32, P, ctypes.c_int32, P, P]
         lib.oracle_count_regions.restype = ctypes.c_int
@@ -122,6 +129,43 @@ def count(kind: int, a_xyz, edges_deg, b_xyz=None, row_begin: int = -1,
                               row_begin, row_end, nthreads or default_threads(), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_count rejected its arguments")
+    return out
+
+
+def count3d(kind: int, a_xyz, edges, b_xyz=None, row_begin: int = -1,
+            row_end: int = -1, nthreads: int | None = None) -> np.ndarray:
+    """Histogram of 3-D pair distances, nbins+2 uint64 slots
+    [r < e_0, bins 0..nbins-1, r >= e_nbins]; points are Cartesian
+    coordinates and edges distances in the same unit.  Pairs as ``count``."""
+    e = _f64(edges)
+    nbins = e.size - 1
+    ax, ay, az = (_f64(c) for c in a_xyz)
+    if kind == DR:
+        if b_xyz is None:
+            raise ValueError("DR needs a second catalog")
+        bx, by, bz = (_f64(c) for c in b_xyz)
+        cross = 1
+    else:
+        if b_xyz is not None:
+            raise ValueError("DD/RR take one catalog")
+        bx, by, bz = ax, ay, az
+        cross = 0
+    out = np.zeros(nbins + 2, dtype=np.uint64)
+    rc = _load().oracle_count3d(cross, ax.size, _ptr(ax), _ptr(ay), _ptr(az), bx.size,
+                                _ptr(bx), _ptr(by), _ptr(bz), nbins, _ptr(e),
+                                row_begin, row_end, nthreads or default_threads(), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_count3d rejected its arguments")
+    return out
+
+
+def pair_distances(a_xyz, b_xyz) -> np.ndarray:
+    """3-D distance of each listed pair (a_i, b_i)."""
+    ax, ay, az = (_f64(c) for c in a_xyz)
+    bx, by, bz = (_f64(c) for c in b_xyz)
+    out = np.empty(ax.size, dtype=np.float64)
+    _load().oracle_pair_distances(ax.size, _ptr(ax), _ptr(ay), _ptr(az), _ptr(bx),
+                                  _ptr(by), _ptr(bz), _ptr(out))
     return out
 
 

@@ -26,6 +26,12 @@
  *     slot 0 is theta < e_0, slot k+1 is e_k <= theta < e_{k+1}, and slot
  *     nbins+1 is theta >= e_nbins (ties go to the upper bin).
  *
+ * The same file counts pairs by 3-D distance (oracle_count3d): the paper
+ * notes that the method carries over to the spatial correlation function
+ * (Section 1); there the separation is the FP64 Euclidean distance
+ * sqrt((dx^2 + dy^2) + dz^2) of the coordinate differences, each operation
+ * rounded, and edges are distances.
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fno-builtin -shared -fPIC
  * -pthread (no builtins: sin and cos stay separate libm calls).
  * Every loop below is the plain definition; threads only split the rows i.
@@ -69,7 +75,21 @@ static double pair_angle(double xi, double yi, double zi,
     return acos(d);
 }
 
-/* Output slot of an angle: the number of edges at or below it. */
+/* Separation of two points in 3-D (the spatial variant of the correlation
+ * function, Section 1): the Euclidean distance, in FP64, from the coordinate
+ * differences, (dx^2 + dy^2) + dz^2 left to right with every operation
+ * rounded, then the libm square root. */
+static double pair_distance(double xi, double yi, double zi,
+                            double xj, double yj, double zj)
+{
+    double dx = xi - xj;
+    double dy = yi - yj;
+    double dz = zi - zj;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    return sqrt(d2);
+}
+
+/* Output slot of an angle (or a distance): the number of edges at or below it. */
 static int slot_of(double t, const double *edge_rad, int nedges)
 {
     int s = 0;
@@ -81,6 +101,7 @@ static int slot_of(double t, const double *edge_rad, int nedges)
 
 typedef struct {
     int cross;                       /* 0: pairs i<j within A; 1: A x B */
+    int metric;                      /* 0: angle on the sky; 1: distance in 3-D */
     int64_t na, nb;
     const double *ax, *ay, *az, *bx, *by, *bz;
     int nedges;
@@ -94,6 +115,12 @@ typedef struct {
     job_t *job;
     uint64_t *hist;                  /* nedges + 1 slots, private */
 } worker_t;
+
+static double separation(const job_t *jb, double xi, double yi, double zi,
+                         double xj, double yj, double zj)
+{
+    return jb->metric ? pair_distance(xi, yi, zi, xj, yj, zj) : pair_angle(xi, yi, zi, xj, yj, zj);
+}
 
 static void *worker(void *arg)
 {
@@ -110,12 +137,12 @@ static void *worker(void *arg)
             double xi = jb->ax[i], yi = jb->ay[i], zi = jb->az[i];
             if (jb->cross) {
                 for (int64_t j = 0; j < jb->nb; ++j) {
-                    double t = pair_angle(xi, yi, zi, jb->bx[j], jb->by[j], jb->bz[j]);
+                    double t = separation(jb, xi, yi, zi, jb->bx[j], jb->by[j], jb->bz[j]);
                     w->hist[slot_of(t, jb->edge_rad, jb->nedges)] += 1;
                 }
             } else {
                 for (int64_t j = i + 1; j < jb->na; ++j) {
-                    double t = pair_angle(xi, yi, zi, jb->ax[j], jb->ay[j], jb->az[j]);
+                    double t = separation(jb, xi, yi, zi, jb->ax[j], jb->ay[j], jb->az[j]);
                     w->hist[slot_of(t, jb->edge_rad, jb->nedges)] += 1;
                 }
             }
@@ -129,14 +156,15 @@ static void *worker(void *arg)
  *   cross = 0: unordered pairs i < j of catalog A with i in [row_begin,
  *              row_end) (DD or RR);
  *   cross = 1: pairs (i, j), i in rows [row_begin, row_end) of A, j in B (DR).
- * edges_deg: nbins+1 increasing edges in degrees.  out: nbins+2 slots.
+ * metric 0: angles, edges in degrees; metric 1: 3-D distances, edges in the
+ * coordinates' unit.  edges: nbins+1 increasing values.  out: nbins+2 slots.
  * row_begin < 0 or row_end < 0 select all rows.  Returns 0, or -1 on bad
  * arguments.
  */
-int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
-                 const double *az, int64_t nb, const double *bx, const double *by,
-                 const double *bz, int32_t nbins, const double *edges_deg,
-                 int64_t row_begin, int64_t row_end, int nthreads, uint64_t *out)
+static int count_pairs(int cross, int metric, int64_t na, const double *ax, const double *ay,
+                       const double *az, int64_t nb, const double *bx, const double *by,
+                       const double *bz, int32_t nbins, const double *edges,
+                       int64_t row_begin, int64_t row_end, int nthreads, uint64_t *out)
 {
     if (nbins < 1 || na < 0 || (cross && nb < 0) || !out)
         return -1;
@@ -145,15 +173,16 @@ int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
     double *edge_rad = (double *)malloc(sizeof(double) * (size_t)nedges);
     if (!edge_rad)
         return -1;
+    /* angular edges come in degrees; distances are used as given */
     for (int k = 0; k < nedges; ++k)
-        edge_rad[k] = edges_deg[k] * deg;
+        edge_rad[k] = metric ? edges[k] : edges[k] * deg;
 
     if (row_begin < 0) row_begin = 0;
     if (row_end < 0 || row_end > na) row_end = na;
     if (row_begin > row_end) row_begin = row_end;
     if (nthreads < 1) nthreads = 1;
 
-    job_t jb = {cross, na, nb, ax, ay, az, bx, by, bz, nedges, edge_rad,
+    job_t jb = {cross, metric, na, nb, ax, ay, az, bx, by, bz, nedges, edge_rad,
                 row_begin, row_end, row_begin, 16};
     worker_t *ws = (worker_t *)calloc((size_t)nthreads, sizeof(worker_t));
     pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
@@ -180,6 +209,31 @@ int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
     }
     free(ws); free(th); free(hists); free(edge_rad);
     return 0;
+}
+
+int oracle_count(int cross, int64_t na, const double *ax, const double *ay,
+                 const double *az, int64_t nb, const double *bx, const double *by,
+                 const double *bz, int32_t nbins, const double *edges_deg,
+                 int64_t row_begin, int64_t row_end, int nthreads, uint64_t *out)
+{
+    return count_pairs(cross, 0, na, ax, ay, az, nb, bx, by, bz, nbins, edges_deg,
+                       row_begin, row_end, nthreads, out);
+}
+
+/*
+ * The same histogram over 3-D separations (the spatial correlation function
+ * the paper's method extends to, Section 1): points are given as Cartesian
+ * coordinates (comoving positions, any length unit), the separation of a pair
+ * is pair_distance above, and edges are distances in the same unit; slot s
+ * is the number of edges e_k with e_k <= r.
+ */
+int oracle_count3d(int cross, int64_t na, const double *ax, const double *ay,
+                   const double *az, int64_t nb, const double *bx, const double *by,
+                   const double *bz, int32_t nbins, const double *edges,
+                   int64_t row_begin, int64_t row_end, int nthreads, uint64_t *out)
+{
+    return count_pairs(cross, 1, na, ax, ay, az, nb, bx, by, bz, nbins, edges,
+                       row_begin, row_end, nthreads, out);
 }
 
 /*
@@ -265,5 +319,16 @@ int oracle_pair_angles(int64_t n, const double *ax, const double *ay, const doub
 {
     for (int64_t i = 0; i < n; ++i)
         theta[i] = pair_angle(ax[i], ay[i], az[i], bx[i], by[i], bz[i]);
+    return 0;
+}
+
+/* 3-D distance of each listed pair (a_i, b_i), as pair_distance. */
+int oracle_pair_distances(int64_t n, const double *ax, const double *ay, const double *az,
+                          const double *bx, const double *by, const double *bz, double *out)
+{
+    if (n < 0 || !out)
+        return -1;
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = pair_distance(ax[i], ay[i], az[i], bx[i], by[i], bz[i]);
     return 0;
 }

@@ -458,3 +458,103 @@ def test_jackknife_samples_and_covariance():
     ref = (nreg - 1) ** 2 / nreg * np.cov(samples[:, fin].T, ddof=1)
     assert np.allclose(cov[np.ix_(fin, fin)], ref, rtol=1e-12, atol=1e-15)
     assert np.allclose(mean, samples.mean(axis=0), equal_nan=True)
+
+
+# --- 3-D distances (count3d, pair_distances) ---------------------------------
+
+def _lattice(n, offset=0.0):
+    g = np.arange(n, dtype=np.float64) + offset
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return x.ravel(), y.ravel(), z.ravel()
+
+
+def _lattice_histogram(n, edges):
+    """Closed form for the unordered pairs of an n^3 integer lattice: the
+    displacement (a, b, c) occurs (n-|a|)(n-|b|)(n-|c|) times as an ordered
+    pair, and its squared length a^2 + b^2 + c^2 is an exact integer.  An
+    edge e (a double whose square is exact) lies at or below the distance
+    exactly when e^2 <= a^2 + b^2 + c^2; on this lattice no squared distance
+    is close enough to an e^2 for the rounding of the square root to matter."""
+    e2 = [float(e) * float(e) for e in edges]
+    hist = np.zeros(len(edges) + 1, dtype=np.int64)
+    for a in range(-(n - 1), n):
+        for b in range(-(n - 1), n):
+            for c in range(-(n - 1), n):
+                if a == 0 and b == 0 and c == 0:
+                    continue
+                mult = (n - abs(a)) * (n - abs(b)) * (n - abs(c))
+                r2 = a * a + b * b + c * c
+                hist[sum(1 for t in e2 if t <= r2)] += mult
+    assert np.all(hist % 2 == 0)
+    return (hist // 2).astype(np.uint64)
+
+
+def test_3d_lattice_closed_form_with_ties_on_edges():
+    """Edges 1, 2, 3, 4 equal lattice distances exactly (ties go to the upper
+    bin); 1.5, 2.5 and 5.25 fall between squared distances.  A dropped
+    coordinate term, a compare of r^2 against e (no square root), i <= j, or
+    a tie sent down each changes this histogram."""
+    n = 6
+    edges = np.array([0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 5.25])
+    got = oracle.count3d(oracle.DD, _lattice(n), edges)
+    assert np.array_equal(got, _lattice_histogram(n, edges))
+    assert int(got.sum()) == n ** 3 * (n ** 3 - 1) // 2
+
+
+def test_3d_exact_distances_of_pythagorean_pairs():
+    a = [np.zeros(4), np.zeros(4), np.zeros(4)]
+    b = [np.array([3.0, 1.0, 2.0, 0.0]), np.array([4.0, 2.0, 3.0, 0.0]), np.array([0.0, 2.0, 6.0, 0.0])]
+    assert list(oracle.pair_distances(a, b)) == [5.0, 3.0, 7.0, 0.0]
+
+
+def test_3d_histogram_matches_scipy_distances():
+    """scipy's Euclidean distances (its own arithmetic) binned with
+    numpy.searchsorted(side='right'); pairs whose distance lies within 1e-12
+    relative of an edge (none expected) are left out of the comparison."""
+    g = synthcat.rng_for(96, 0)
+    a = g.uniform(0.0, 100.0, size=(700, 3))
+    b = g.uniform(20.0, 140.0, size=(600, 3))
+    edges = synthcat.log_edges(0.5, 80.0, 15)
+    for kind, other in ((oracle.DR, b), (oracle.DD, None)):
+        dist = cdist(a, a if other is None else other)
+        if other is None:
+            dist = dist[np.triu_indices(a.shape[0], k=1)]
+        else:
+            dist = dist.ravel()
+        near = np.min(np.abs(dist[:, None] - edges[None, :]) / edges[None, :], axis=1) < 1e-12
+        assert not near.any()
+        ref = np.bincount(np.searchsorted(edges, dist, side="right"), minlength=edges.size + 1)
+        got = oracle.count3d(kind, a.T, edges, b_xyz=None if other is None else other.T)
+        assert np.array_equal(got, ref.astype(np.uint64))
+
+
+def test_3d_power_of_two_scaling_and_exact_translation():
+    """Scaling coordinates and edges by 4 is exact in every operation, the
+    square root included, so counts are identical; so is a translation of
+    integer coordinates by 1024 (exact differences)."""
+    g = synthcat.rng_for(96, 1)
+    pts = np.round(g.uniform(0.0, 60.0, size=(500, 3)))
+    edges = np.array([0.0, 1.0, 2.0, 3.5, 7.0, 12.0, 20.0, 33.0])
+    base = oracle.count3d(oracle.DD, pts.T, edges)
+    assert np.array_equal(base, oracle.count3d(oracle.DD, (4.0 * pts).T, 4.0 * edges))
+    assert np.array_equal(base, oracle.count3d(oracle.DD, (pts + 1024.0).T, edges))
+    # edge 0: every pair, coincident points included, is at or above it
+    assert int(base[0]) == 0
+
+
+def test_3d_union_symmetry_and_totals():
+    g = synthcat.rng_for(96, 2)
+    a = g.normal(50.0, 10.0, size=(400, 3))
+    b = g.uniform(0.0, 100.0, size=(300, 3))
+    edges = synthcat.log_edges(0.2, 60.0, 12)
+    dd_a = oracle.count3d(oracle.DD, a.T, edges)
+    dd_b = oracle.count3d(oracle.DD, b.T, edges)
+    dr = oracle.count3d(oracle.DR, a.T, edges, b_xyz=b.T)
+    assert np.array_equal(dr, oracle.count3d(oracle.DR, b.T, edges, b_xyz=a.T))
+    ab = np.concatenate([a, b])
+    assert np.array_equal(oracle.count3d(oracle.DD, ab.T, edges), dd_a + dd_b + dr)
+    assert int(dr.sum()) == 400 * 300 and int(dd_a.sum()) == 400 * 399 // 2
+    # row ranges add up
+    parts = sum(oracle.count3d(oracle.DD, a.T, edges, row_begin=r0, row_end=r1)
+                for r0, r1 in ((0, 130), (130, 131), (131, 400)))
+    assert np.array_equal(parts, dd_a)
