@@ -108,6 +108,30 @@ int tpcf_upload_catalog(tpcf_ctx *ctx, const double *ra_deg, const double *dec_d
 int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
                             const double *z, int64_t n, int32_t *out_cat);
 
+/* 3-D catalog: Cartesian positions (comoving coordinates, any length unit;
+ * host FP64 arrays of n finite values with |x|, |y|, |z| <= 2^50).  The paper
+ * notes that its method carries over from w(theta) to the spatial
+ * correlation function xi(r) (Section 1).  Pairs of a 3-D catalog are binned
+ * by their Euclidean distance r under the 3-D counting rule:
+ *   squared distance  r2 = (dx*dx + dy*dy) + dz*dz, dx = x_i - x_j etc.,
+ *                     FP64, no fused multiply-add, left to right;
+ *   distance          r = sqrt(r2) (host libm, correctly rounded);
+ *   slot              number of edges e_k <= r (edges in the coordinates'
+ *                     unit, finite, strictly increasing, within [0, 1e150]).
+ * Every counting call (tpcf_count, _async, _batch, tpcf_submit) takes 3-D
+ * catalogs in place of sky catalogs; bin_edges_deg then holds distances.
+ * Both catalogs of a DR count must be 3-D, and so must every catalog of a
+ * batch.  Precisions: TPCF_FP32_CHORD (FP32 squared distances of FP32 copies
+ * against a proven band, band pairs re-decided with the exact rule) and
+ * TPCF_FP64 (the rule's r2 against S_k = the smallest double whose square
+ * root reaches e_k); TPCF_FP64_MATRIX and pruning are angular only
+ * (TPCF_E_INVALID, resp. no pruning).  The FP32 band widens with the largest
+ * norm R of the catalogs (about 2^-23 R in r), so coordinates centred on the
+ * survey keep fewer pairs on the exact path.  Rows are stored in Morton order
+ * of the bounding box; tpcf_catalog_order returns it. */
+int tpcf_upload_catalog_3d(tpcf_ctx *ctx, const double *x, const double *y,
+                           const double *z, int64_t n, int32_t *out_cat);
+
 /* Zero-copy attach of caller-owned device memory: d_xyz64 points to 3*n
  * doubles on the context's device laid out as x[0..n), y[0..n), z[0..n)
  * (unit vectors, same norm limit as above).  The caller keeps the memory
@@ -372,6 +396,18 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
  * doubles each) such that e >= out_hi[k] implies d <= D_k and e < out_lo[k]
  * implies d > D_k whenever e is within 2^-48 of 1 - d. */
 int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_lo, double *out_hi);
+
+/* 3-D edge compilation (host only, for CPU tests): for nbins+1 distance
+ * edges (as tpcf_upload_catalog_3d) and points of FP64 norm at most rmax
+ * (0 <= rmax <= 2^51):
+ *   out_S    nbins+1 doubles: S_k = smallest double s with sqrt(s) >= e_k
+ *            (-inf when e_k == 0: every pair is at or past it);
+ *   out_qlo, out_qhi  nbins+1 floats: the FP32 band, q < qlo_k implies
+ *            r2 < S_k and q >= qhi_k implies r2 >= S_k for the kernel's
+ *            q = fl32 |f_i - f_j|^2 of the FP32 copies;
+ * any output pointer may be NULL. */
+int tpcf_compile_edges_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_S,
+                          float *out_qlo, float *out_qhi);
 
 /* Message describing the last failed call on the calling thread ("" if none).
  * Valid until the next call on the same thread. */

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
-    "landy_szalay", "jackknife", "MAX_REGIONS", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
+    "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_band64",
-    "tpcf_compile_edges",
+    "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_compile_edges_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -119,6 +119,8 @@ def lib():
         "tpcf_close": ([P], cint),
         "tpcf_upload_catalog": ([P, P, P, i64, P], cint),
         "tpcf_upload_catalog_xyz": ([P, P, P, P, i64, P], cint),
+        "tpcf_upload_catalog_3d": ([P, P, P, P, i64, P], cint),
+        "tpcf_compile_edges_3d": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_attach_catalog": ([P, P, i64, P], cint),
         "tpcf_catalog_order": ([P, i32, P], cint),
         "tpcf_catalog_size": ([P, i32, P], cint),
@@ -235,6 +237,16 @@ class Context:
         out = np.zeros(nreg.value, dtype=np.int64)
         _check(lib().tpcf_catalog_regions(self._h, cat, ctypes.byref(nreg), _p(out)))
         return out
+
+    def upload_catalog_3d(self, x, y, z) -> int:
+        """3-D catalog of Cartesian points; counts of it bin pairs by
+        Euclidean distance, with edges in the coordinates' unit."""
+        x, y, z = _f64(x), _f64(y), _f64(z)
+        if not (x.shape == y.shape == z.shape) or x.ndim != 1:
+            raise ValueError("x, y, z must be 1-D arrays of the same length")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_upload_catalog_3d(self._h, _p(x), _p(y), _p(z), x.size, ctypes.byref(cid)))
+        return cid.value
 
     def upload_catalog_xyz(self, x, y, z) -> int:
         x, y, z = _f64(x), _f64(y), _f64(z)
@@ -430,6 +442,16 @@ def compile_edges(edges_deg, delta_max: float = 0.0):
     qhi = np.empty(e.size, np.float32)
     _check(lib().tpcf_compile_edges(_p(e), e.size - 1, delta_max, _p(D), _p(qlo), _p(qhi)))
     return D, qlo, qhi
+
+
+def compile_edges_3d(edges, rmax: float):
+    """(S, qlo, qhi) of tpcf_compile_edges_3d."""
+    e = _f64(edges)
+    S = np.empty(e.size, dtype=np.float64)
+    qlo = np.empty(e.size, dtype=np.float32)
+    qhi = np.empty(e.size, dtype=np.float32)
+    _check(lib().tpcf_compile_edges_3d(_p(e), e.size - 1, rmax, _p(S), _p(qlo), _p(qhi)))
+    return S, qlo, qhi
 
 
 def compile_band64(edges_deg):

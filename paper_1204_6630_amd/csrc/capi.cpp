@@ -50,6 +50,7 @@ int fail(int code, const std::string &msg) {
 
 constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
 constexpr double kMatrixTau = 3.552713678800501e-15; // 2^-48, see make_band64
+constexpr double kMaxCoord3d = 1125899906842624.0;    // 2^50: largest |coordinate| of a 3-D catalog
 constexpr int kPoolStreams = 4;
 
 // Launch shape, set by tpcf_set_tuning (the autotuner) or left at defaults.
@@ -137,6 +138,11 @@ struct Catalog {
     // jackknife regions: stored rows of region r are [reg_start[r], reg_start[r+1])
     int32_t nreg = 0;
     std::vector<int64_t> reg_start;
+    // 0: unit vectors on the sky; 1: Cartesian points in 3-D (rmax bounds
+    // their FP64 norms, for the FP32 band)
+    int metric = 0;
+    double rmax = 0;
+    double band_param() const { return metric ? rmax : delta; }
 };
 
 struct Compiled {
@@ -146,7 +152,8 @@ struct Compiled {
     Band32 band;
     int precision = 0;
     int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
-    double delta = 0;
+    double delta = 0;      // norm bound of the band (3-D: rmax)
+    int metric = 0;
     std::vector<double> thi;   // matrix-core band upper ends (host copy)
 };
 
@@ -180,6 +187,7 @@ struct Request {
     Compiled *cp = nullptr;
     Plan *plan = nullptr;
     uint64_t pairs = 0;
+    int metric = 0;
     std::string cache_key;   // RR requests: key of the result cache
 };
 
@@ -313,8 +321,8 @@ uint64_t spread3(uint64_t v) {
     return v;
 }
 
-uint64_t quant21(double c) {
-    double t = (c + 1.0) * 0.5 * 2097151.0;
+uint64_t quant21(double c, double lo = -1.0, double hi = 1.0) {
+    double t = (c - lo) / (hi - lo) * 2097151.0;
     if (!(t > 0.0))
         return 0;
     if (t > 2097151.0)
@@ -325,11 +333,12 @@ uint64_t quant21(double c) {
 // Stored order: Morton order of the unit vectors, grouped by region first
 // when labels are given (so each region is a contiguous range of rows).
 std::vector<int64_t> morton_order(const double *x, const double *y, const double *z, int64_t n,
-                                  const int32_t *region = nullptr) {
+                                  const int32_t *region = nullptr, double lo = -1.0, double hi = 1.0) {
     std::vector<std::tuple<int32_t, uint64_t, int64_t>> k((size_t)n);
     for (int64_t i = 0; i < n; ++i)
         k[i] = std::make_tuple(region ? region[i] : 0,
-                               spread3(quant21(x[i])) | spread3(quant21(y[i])) << 1 | spread3(quant21(z[i])) << 2,
+                               spread3(quant21(x[i], lo, hi)) | spread3(quant21(y[i], lo, hi)) << 1 |
+                                   spread3(quant21(z[i], lo, hi)) << 2,
                                i);
     std::sort(k.begin(), k.end());
     std::vector<int64_t> order((size_t)n);
@@ -339,24 +348,49 @@ std::vector<int64_t> morton_order(const double *x, const double *y, const double
 }
 
 int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
-                int32_t *out_cat, const int32_t *region = nullptr, int32_t nreg = 0) {
+                int32_t *out_cat, const int32_t *region = nullptr, int32_t nreg = 0, int metric = 0) {
     if (!out_cat)
         return fail(TPCF_E_INVALID, "out_cat is NULL");
     if (n < 0 || n > (int64_t)0x7fffffff - 1024)
         return fail(TPCF_E_INVALID, "catalog size out of range");
     if (n > 0 && (!x || !y || !z))
         return fail(TPCF_E_INVALID, "coordinate array is NULL");
-    bool finite = true;
-    double delta = n > 0 ? norm_bound(x, y, z, n, &finite) : 0.0;
-    if (!finite)
-        return fail(TPCF_E_INVALID, "coordinates must be finite");
-    if (delta > kMaxDelta)
-        return fail(TPCF_E_INVALID, "unit vectors must satisfy | |v|^2 - 1 | <= 2^-20");
-    TRY(set_device(ctx));
     Catalog c;
     c.n = n;
-    c.delta = delta;
-    c.order = morton_order(x, y, z, n, region);
+    c.metric = metric;
+    double lo = -1.0, hi = 1.0;
+    if (metric == 0) {
+        bool finite = true;
+        double delta = n > 0 ? norm_bound(x, y, z, n, &finite) : 0.0;
+        if (!finite)
+            return fail(TPCF_E_INVALID, "coordinates must be finite");
+        if (delta > kMaxDelta)
+            return fail(TPCF_E_INVALID, "unit vectors must satisfy | |v|^2 - 1 | <= 2^-20");
+        c.delta = delta;
+    } else {
+        // 3-D: finite coordinates within 2^50; rmax bounds every FP64 norm
+        // (the square root of the largest squared norm, widened)
+        double r2 = 0.0;
+        lo = HUGE_VAL;
+        hi = -HUGE_VAL;
+        for (int64_t i = 0; i < n; ++i) {
+            const double v[3] = {x[i], y[i], z[i]};
+            for (double w : v) {
+                if (!isfinite(w) || fabs(w) > kMaxCoord3d)
+                    return fail(TPCF_E_INVALID, "3-D coordinates must be finite with |c| <= 2^50");
+                lo = std::min(lo, w);
+                hi = std::max(hi, w);
+            }
+            r2 = std::max(r2, (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        }
+        c.rmax = sqrt(r2) * (1.0 + ldexp(1.0, -40)) + ldexp(1.0, -1000);
+        if (!(hi > lo)) {
+            lo = n > 0 ? lo - 1.0 : -1.0;
+            hi = lo + 2.0;
+        }
+    }
+    TRY(set_device(ctx));
+    c.order = morton_order(x, y, z, n, region, lo, hi);
     if (region) {
         c.nreg = nreg;
         c.reg_start.assign((size_t)nreg + 1, 0);
@@ -400,10 +434,12 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
     return TPCF_OK;
 }
 
-std::string edges_key(const double *edges, int nbins, int precision, double delta, const Tuning &t) {
+std::string edges_key(const double *edges, int nbins, int precision, double delta, int metric,
+                      const Tuning &t) {
     std::string k((const char *)edges, sizeof(double) * (size_t)(nbins + 1));
     k.append((const char *)&precision, sizeof precision);
-    if (precision == TPCF_FP32_CHORD)
+    k.append((const char *)&metric, sizeof metric);
+    if (precision == TPCF_FP32_CHORD || metric)
         k.append((const char *)&delta, sizeof delta);
     k.append((const char *)&t.lut_bytes, sizeof t.lut_bytes);
     k.append((const char *)&t.lut_direct, sizeof t.lut_direct);
@@ -429,9 +465,9 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
     c.dErad.release(ctx->mem);
 }
 
-int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta,
+int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta, int metric,
                  Compiled **out) {
-    std::string key = edges_key(edges, nbins, precision, delta, ctx->tune);
+    std::string key = edges_key(edges, nbins, precision, delta, metric, ctx->tune);
     auto it = ctx->compiled.find(key);
     if (it != ctx->compiled.end()) {
         *out = it->second.get();
@@ -446,17 +482,26 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     }
     auto c = std::make_unique<Compiled>();
     std::string err;
-    if (!compile_edges(edges, nbins, &c->edges, &err))
+    if (!(metric ? compile_edges_3d(edges, nbins, &c->edges, &err) : compile_edges(edges, nbins, &c->edges, &err)))
         return fail(TPCF_E_INVALID, err);
     c->precision = precision;
     c->delta = delta;
+    c->metric = metric;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
     const int table_bytes = ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxLutBytes;
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     std::vector<float> qlo(c->edges.D.size(), 0.0f), qhi(c->edges.D.size(), 0.0f);
     std::vector<double> tlo = c->edges.E, thi = c->edges.E;
-    if (precision == TPCF_FP32_CHORD) {
+    if (metric && precision == TPCF_FP32_CHORD) {
+        c->band = make_band32_3d(c->edges, delta);
+        c->cells = make_cells32_top(c->edges, c->band, qtop_key_3d(delta), max_cells);
+        qlo = c->band.qlo;
+        qhi = c->band.qhi;
+    } else if (metric) {
+        const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
+        c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
+    } else if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
         if (c->entry_bytes == 1 && ctx->tune.lut_direct)
             c->cells = make_cells32_direct(c->edges, c->band, delta,
@@ -810,16 +855,20 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
         return fail(TPCF_E_INVALID, "row range must satisfy 0 <= row_begin <= row_end <= n");
     r->rb = rb;
     r->re = re;
+    r->metric = r->A->metric;
+    if (r->B->metric != r->metric)
+        return fail(TPCF_E_INVALID, "a sky catalog and a 3-D catalog cannot be paired");
+    if (r->metric && d.precision == TPCF_FP64_MATRIX)
+        return fail(TPCF_E_INVALID, "3-D catalogs count with TPCF_FP32_CHORD or TPCF_FP64");
     TRY(set_device(ctx));
-    const double delta = delta_override >= 0 ? delta_override
-                                             : (r->A->delta > r->B->delta ? r->A->delta : r->B->delta);
-    TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, &r->cp));
+    const double delta = delta_override >= 0 ? delta_override : std::max(r->A->band_param(), r->B->band_param());
+    TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, r->metric, &r->cp));
     const bool matrix = d.precision == TPCF_FP64_MATRIX;
     if (matrix) {
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->A)));
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->B)));
     }
-    if (ctx->tune.prune)
+    if (ctx->tune.prune && !r->metric)
         TRY(ensure_caps(ctx, const_cast<Catalog &>(*r->B)));
     r->cache_key.clear();
     if (regions) {
@@ -878,7 +927,8 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.lut_lo = cp.cells.lo;
     a.lut_hi = cp.cells.hi;
     a.lut_direct = cp.cells.direct ? 1 : 0;
-    a.prune = ctx->tune.prune ? 1 : 0;
+    a.metric = cp.metric;
+    a.prune = ctx->tune.prune && !cp.metric ? 1 : 0;   // the caps are angular
     a.erad = (const double *)cp.dErad.p;
     // key of the last edge's certain side (see PairArgs::beyond_key)
     const size_t last = cp.edges.D.size() - 1;
@@ -1138,6 +1188,13 @@ int tpcf_catalog_regions(tpcf_ctx *ctx, int32_t cat, int32_t *out_nreg, int64_t 
     return TPCF_OK;
 }
 
+int tpcf_upload_catalog_3d(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
+                           int32_t *out_cat) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    return add_catalog(ctx, x, y, z, n, out_cat, nullptr, 0, 1);
+}
+
 int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y, const double *z,
                             int64_t n, int32_t *out_cat) {
     if (!ctx)
@@ -1348,14 +1405,17 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
     for (int32_t k = 0; k < njobs; ++k) {
         auto a = ctx->cats.find(jobs[k].cat_a);
         if (a != ctx->cats.end())
-            delta = std::max(delta, a->second.delta);
+            delta = std::max(delta, a->second.band_param());
         auto b = ctx->cats.find(jobs[k].cat_b);
         if (b != ctx->cats.end())
-            delta = std::max(delta, b->second.delta);
+            delta = std::max(delta, b->second.band_param());
     }
     std::vector<Request> reqs((size_t)njobs);
-    for (int32_t k = 0; k < njobs; ++k)
+    for (int32_t k = 0; k < njobs; ++k) {
         TRY(prepare(ctx, jobs[k], delta, &reqs[k]));
+        if (reqs[k].metric != reqs[0].metric)
+            return fail(TPCF_E_INVALID, "a batch cannot mix sky and 3-D catalogs");
+    }
     const int nslots = nbins + 2;
     const int prec = jobs[0].precision;
     // every job's histogram copies, then the work-queue counter
@@ -1847,6 +1907,26 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
     for (int k = 0; k <= nbins; ++k) {
         if (out_D)
             out_D[k] = t.D[k];
+        if (out_qlo)
+            out_qlo[k] = b.qlo[k];
+        if (out_qhi)
+            out_qhi[k] = b.qhi[k];
+    }
+    return TPCF_OK;
+}
+
+int tpcf_compile_edges_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_S, float *out_qlo,
+                          float *out_qhi) {
+    if (!(rmax >= 0.0) || rmax > 2.0 * kMaxCoord3d)
+        return fail(TPCF_E_INVALID, "rmax must be in [0, 2^51]");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges_3d(bin_edges, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    Band32 b = make_band32_3d(t, rmax);
+    for (int k = 0; k <= nbins; ++k) {
+        if (out_S)
+            out_S[k] = t.E[k];   // -inf for a zero edge
         if (out_qlo)
             out_qlo[k] = b.qlo[k];
         if (out_qhi)

@@ -262,6 +262,142 @@ Band32 make_band32(const EdgeTables &t, double delta) {
     return b;
 }
 
+// 3-D edges.  The counting rule bins a pair by r = sqrt(r2), r2 the FP64
+// sum (dx^2 + dy^2) + dz^2 of the coordinate differences.  sqrt is
+// non-decreasing (and correctly rounded), so r >= e_k <=> r2 >= S_k with S_k
+// the smallest double whose square root is >= e_k, found by bisection over the
+// ordered non-negative doubles with the same libm sqrt.  A window of doubles
+// around S_k is checked exhaustively.
+namespace {
+
+inline bool reaches3(double s, double e) { return sqrt(s) >= e; }
+
+double threshold3_of(double e) {
+    int64_t lo = okey(0.0), hi = okey(1e300);    // reaches3(lo) false (e > 0), reaches3(hi) true
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (reaches3(from_okey(mid), e))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return from_okey(hi);
+}
+
+bool verify_threshold3(double e, double S, std::string *why) {
+    const int64_t k = okey(S);
+    for (int64_t t = std::max(okey(0.0), k - 256); t <= k + 256; ++t) {
+        if (reaches3(from_okey(t), e) != (t >= k)) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "sqrt not monotone around threshold %.17g for edge %.17g", S, e);
+            *why = buf;
+            return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+bool compile_edges_3d(const double *edges, int nbins, EdgeTables *out, std::string *err) {
+    if (nbins < 1 || nbins > 256) {
+        *err = "nbins must be in [1, 256]";
+        return false;
+    }
+    if (!edges) {
+        *err = "bin edges are NULL";
+        return false;
+    }
+    for (int k = 0; k <= nbins; ++k) {
+        double v = edges[k];
+        if (!isfinite(v) || v < 0.0 || v > 1e150) {
+            *err = "3-D bin edges must be finite and within [0, 1e150]";
+            return false;
+        }
+        if (k > 0 && !(v > edges[k - 1])) {
+            *err = "bin edges must be strictly increasing";
+            return false;
+        }
+    }
+    EdgeTables t;
+    t.nbins = nbins;
+    t.metric = 1;
+    t.edge_rad.assign(edges, edges + nbins + 1);
+    t.D.resize(nbins + 1);
+    t.E.resize(nbins + 1);
+    for (int k = 0; k <= nbins; ++k) {
+        const double e = edges[k];
+        if (!(e > 0.0)) {              // every distance reaches 0
+            t.D[k] = HUGE_VAL;
+            t.E[k] = -HUGE_VAL;
+            continue;
+        }
+        const double S = threshold3_of(e);
+        std::string why;
+        if (!verify_threshold3(e, S, &why)) {
+            *err = why;
+            return false;
+        }
+        t.D[k] = -S;
+        t.E[k] = S;
+    }
+    *out = std::move(t);
+    return true;
+}
+
+// Band of 3-D edge k for points v (FP64, |v| <= R) and their FP32 copies f.
+//  * The rule's r2 is within the factors (1 -+ U)^5 of c_v^2 = |v_i - v_j|^2
+//    (U = 2^-53: one rounding for each difference, counted twice in the
+//    square, the square and the two additions; every term is non-negative),
+//    plus tau64 for gradual underflow.  So
+//      c_v >= C+ = sqrt((S_k + tau64) / (1 - U)^5)  =>  r2 >= S_k,
+//      c_v <  C- = sqrt((S_k - tau64)_+ / (1 + U)^5) =>  r2 <  S_k.
+//  * |f - v| <= u |v| + 2^-149 per component (u = 2^-24), so
+//    |c_f - c_v| <= a = 2 (u R + 2^-148).
+//  * The kernel's q (differences of the FP32 copies, squares and sums, fused
+//    or not) satisfies (1-u)^5 c_f^2 - tau <= q <= (1+u)^5 c_f^2 + tau.
+//  Hence, as for angles, q >= qhi_k => r2 >= S_k and q < qlo_k => r2 < S_k:
+//      qhi_k = RU32(((C+ + a)^2 (1+u)^5 + tau) s),
+//      qlo_k = RD32((((C- - a)_+)^2 (1-u)^5 - tau) / s),   s = 1 + 2^-20.
+Band32 make_band32_3d(const EdgeTables &t, double rmax) {
+    const double U = ldexp(1.0, -53), u = ldexp(1.0, -24);
+    const double a = 2.0 * (u * rmax + ldexp(1.0, -148));
+    const double grow = pow(1.0 + u, 5.0), shrink = pow(1.0 - u, 5.0);
+    const double grow64 = pow(1.0 + U, 5.0), shrink64 = pow(1.0 - U, 5.0);
+    const double tau = ldexp(1.0, -120), tau64 = ldexp(1.0, -1020);
+    const double s = 1.0 + ldexp(1.0, -20);
+    Band32 b;
+    b.delta = rmax;
+    const int ne = (int)t.D.size();
+    b.qlo.resize(ne);
+    b.qhi.resize(ne);
+    for (int k = 0; k < ne; ++k) {
+        const double S = t.E[k];
+        if (S == -HUGE_VAL) {
+            b.qlo[k] = b.qhi[k] = -HUGE_VALF;
+            continue;
+        }
+        const double cp = sqrt((S + tau64) / shrink64);
+        const double hi = ((cp + a) * (cp + a) * grow + tau) * s;
+        b.qhi[k] = round_up32(hi);     // +inf above the FP32 range: never certain
+        const double cm = sqrt(std::max(0.0, S - tau64) / grow64) - a;
+        if (cm <= 0.0) {
+            b.qlo[k] = 0.0f;
+        } else {
+            const double v = (cm * cm * shrink - tau) / s;
+            b.qlo[k] = v <= 0.0 ? 0.0f : round_down32(v);
+        }
+    }
+    return b;
+}
+
+uint32_t qtop_key_3d(double rmax) {
+    const double u = ldexp(1.0, -24);
+    const double c = 2.0 * rmax * (1.0 + 2.0 * u) + ldexp(1.0, -140);
+    const double q = c * c * pow(1.0 + u, 5.0) * 1.0001 + ldexp(1.0, -120);
+    return fbits(q < 3.0e38 ? round_up32(q) : 3.0e38f);
+}
+
 // FP32 cells: key = bits(q) >> shift for q >= 0.  The bottom cell also holds
 // every q below its range and the top cell every q above.
 namespace {
@@ -317,8 +453,11 @@ CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta
 }
 
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells) {
+    return make_cells32_top(t, b, qtop_key(delta), max_cells);
+}
+
+CellTable make_cells32_top(const EdgeTables &t, const Band32 &b, uint32_t ktop, int max_cells) {
     const int ne = (int)t.D.size();
-    const uint32_t ktop = qtop_key(delta);
     // smallest positive finite threshold
     float tmin = HUGE_VALF;
     for (int k = 0; k < ne; ++k) {
@@ -349,9 +488,9 @@ CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int m
 // FP64 cells: key = (int32) high word of e = fl(1 - d), arithmetic shift.
 // e < 0 (d > 1 from rounding) falls into the bottom cell, whose range is
 // taken to start at -inf.
-CellTable make_cells64(const EdgeTables &t, int max_cells) {
+CellTable make_cells64(const EdgeTables &t, int max_cells, double etop) {
     const int ne = (int)t.E.size();
-    const int32_t ktop = dhi(2.0 + ldexp(1.0, -18));
+    const int32_t ktop = dhi(etop);
     double tmin = HUGE_VAL;
     for (int k = 0; k < ne; ++k)
         if (isfinite(t.E[k]) && t.E[k] > 0.0)

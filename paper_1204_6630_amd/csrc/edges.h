@@ -9,11 +9,16 @@
 
 namespace tpcf {
 
+// Angular edges: a pair lies at or past edge k when its dot product d
+// satisfies d <= D_k.  3-D edges (compile_edges_3d): the same form with
+// d = -r^2 and D_k = -S_k, S_k the smallest double whose square root reaches
+// e_k, and E_k = S_k (the FP64 path keys on r^2 itself).
 struct EdgeTables {
     int nbins = 0;
-    std::vector<double> edge_rad;   // e_k = edge_deg[k] * (pi / 180)
-    std::vector<double> D;          // largest d with acos(d) >= e_k (+-inf at the ends)
-    std::vector<double> E;          // fl(1 - D_k); -inf where D_k = +inf, +inf where D_k = -inf
+    int metric = 0;                 // 0: angles on the sky, 1: 3-D distances
+    std::vector<double> edge_rad;   // e_k = edge_deg[k] * (pi / 180); 3-D: e_k itself
+    std::vector<double> D;          // largest d with acos(d) >= e_k (+-inf at the ends); 3-D: -S_k
+    std::vector<double> E;          // fl(1 - D_k); -inf where D_k = +inf, +inf where D_k = -inf; 3-D: S_k
 };
 
 struct Band32 {
@@ -46,15 +51,33 @@ bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::str
 // deviate from 1 by at most delta.
 Band32 make_band32(const EdgeTables &t, double delta);
 
+// 3-D edges: finite, strictly increasing, within [0, 1e150] (same length
+// unit as the coordinates), 1 <= nbins <= 256.  False with a message on
+// invalid input.
+bool compile_edges_3d(const double *edges, int nbins, EdgeTables *out, std::string *err);
+
+// FP32 band of every 3-D edge for squared distances q of FP32 copies of
+// points whose FP64 norms are at most rmax.
+Band32 make_band32_3d(const EdgeTables &t, double rmax);
+
+// Bit pattern of an upper bound of every q the FP32 kernel computes for
+// points of norm at most rmax (3-D).
+uint32_t qtop_key_3d(double rmax);
+
 // Cell tables.  FP32: key = bits of q (q >= 0).  FP64: key = high 32 bits of
 // e = fl(1 - d) read as a signed integer.
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
+// The same with the top key given (every q above it goes to the top cell).
+CellTable make_cells32_top(const EdgeTables &t, const Band32 &b, uint32_t ktop, int max_cells);
 // Direct FP32 table: cells 0 .. bits(qtop) >> shift, where qtop bounds every
 // q the kernel can compute for norms within delta; the smallest shift whose
 // table has at most max_cells entries.  Returns a table with no cells if
 // delta is too large for the bound (above 2^-10) or none fits.
 CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
-CellTable make_cells64(const EdgeTables &t, int max_cells);
+// etop bounds the keyed value from above (cells above it are not built; a
+// larger value falls into the top cell): 2 for e = 1 - d, the largest
+// squared distance for 3-D.
+CellTable make_cells64(const EdgeTables &t, int max_cells, double etop = 2.0 + 1.0 / 262144.0);
 
 Band64 make_band64(const EdgeTables &t, double tau);
 // Cells over the high word of e (as make_cells64) against a Band64.

@@ -103,6 +103,11 @@ struct PairArgs {
     int32_t prune;
     const double *erad;
 
+    // 0: angles on the sky (dot products against D_k); 1: 3-D distances
+    // (squared distances of Cartesian points, D_k = -S_k, E_k = S_k); no
+    // pruning and no matrix-core path for 3-D.
+    int32_t metric;
+
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
     const double *E;             // fl(1 - D_k), nedges

@@ -140,6 +140,29 @@ __device__ __forceinline__ double exact_dot(double xi, double yi, double zi,
     return s + v;
 }
 
+// 3-D: squared distance of the counting rule, (dx^2 + dy^2) + dz^2 of the
+// FP64 coordinate differences, every operation rounded.
+__device__ __forceinline__ double exact_d2(double xi, double yi, double zi,
+                                           double xj, double yj, double zj) {
+    double dx = xi - xj;
+    double dy = yi - yj;
+    double dz = zi - zj;
+    double t = dx * dx;
+    double u = dy * dy;
+    double s = t + u;
+    double v = dz * dz;
+    return s + v;
+}
+
+// The value the thresholds D_k are compared with (past edge k when
+// value <= D_k): the dot product for angles, minus the squared distance in
+// 3-D (where D_k = -S_k).
+template <bool M3>
+__device__ __forceinline__ double rule_value(double xi, double yi, double zi,
+                                             double xj, double yj, double zj) {
+    return M3 ? -exact_d2(xi, yi, zi, xj, yj, zj) : exact_dot(xi, yi, zi, xj, yj, zj);
+}
+
 struct Smem {
     uint32_t *hist;      // kWaves x (nslots + 1) x copies
     double *D;
@@ -210,7 +233,7 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long 
     }
 }
 
-template <bool LUT8>
+template <bool LUT8, bool M3>
 __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, uint32_t flag, float q, const Smem &s,
                                                  const PairArgs &a, const JobDev &jb, int i, int j,
                                                  uint32_t &n_exact) {
@@ -221,11 +244,11 @@ __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, uint32_t flag, fl
         if (q >= s.qhi[k])
             return (uint32_t)(k + 1);
         ++n_exact;
-        double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+        double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
         return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
     }
     ++n_exact;
-    double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+    double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
     return count_le(d, s.D, a.nedges);
 }
 
@@ -412,7 +435,7 @@ __device__ __forceinline__ void bin_block(int slot, uint32_t n, const PairArgs &
 // One step: JN columns against the P rows of every lane.  All JN * P table
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
-template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT>
+template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT, bool M3>
 __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
@@ -473,7 +496,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
                     // opaque here, so the row addresses of this rare path are
                     // formed on demand and do not occupy registers in the loop
                     asm volatile("" : "+v"(i));
-                    ent[t][p] = resolve_fp32<LUT8>(ent[t][p], k.flag, q[t][p], s, a, jb, i, j + t, cnt.exact);
+                    ent[t][p] = resolve_fp32<LUT8, M3>(ent[t][p], k.flag, q[t][p], s, a, jb, i, j + t, cnt.exact);
                 }
     }
 #pragma unroll
@@ -489,7 +512,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
         }
 }
 
-template <bool LUT8, bool MASKED, int P, int JN>
+template <bool LUT8, bool MASKED, int P, int JN, bool M3>
 __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie,
@@ -508,9 +531,16 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            double dd = exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
-            d[t][p] = dd;
-            e[t][p] = 1.0 - dd;
+            if (M3) {
+                // key on the squared distance itself; d = -r^2 for the thresholds
+                const double r2 = exact_d2(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
+                d[t][p] = -r2;
+                e[t][p] = r2;
+            } else {
+                double dd = exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
+                d[t][p] = dd;
+                e[t][p] = 1.0 - dd;
+            }
         }
     }
     if (!MASKED) {
@@ -565,7 +595,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP32 path).
-template <bool LUT8, bool MASKED, int P, bool DIRECT>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
                                           const int (&ii)[P], const int (&il)[P], int ie, int j0, int j1,
@@ -597,7 +627,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
-            step_fp32<LUT8, MASKED, P, JN, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
@@ -608,13 +638,13 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     }
     for (; j < j1; ++j) {
         const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
-        step_fp32<LUT8, MASKED, P, 1, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
     }
 }
 
 
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
@@ -648,16 +678,16 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp32<LUT8, MASKED, P, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
+            cols_fp32<LUT8, MASKED, P, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp32<LUT8, MASKED, P, DIRECT>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
+    cols_fp32<LUT8, MASKED, P, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
-template <bool LUT8, bool MASKED, int P>
+template <bool LUT8, bool MASKED, int P, bool M3>
 __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie, int j0, int j1,
@@ -667,12 +697,12 @@ __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, c
     cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
     for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp64<LUT8, MASKED, P, kColsPerStep>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        step_fp64<LUT8, MASKED, P, kColsPerStep, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
     for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        step_fp64<LUT8, MASKED, P, 1, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
 }
 
-template <bool LUT8, bool MASKED, int P, bool PRUNE>
+template <bool LUT8, bool MASKED, int P, bool PRUNE, bool M3>
 __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     double xi[P], yi[P], zi[P];
@@ -699,12 +729,12 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp64<LUT8, MASKED, P>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
+            cols_fp64<LUT8, MASKED, P, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp64<LUT8, MASKED, P>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
+    cols_fp64<LUT8, MASKED, P, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -901,7 +931,8 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
-// table, 1 FP64 vector, 2 FP64 matrix cores.  P: rows per lane of the vector
+// table, 1 FP64 vector, 2 FP64 matrix cores; 3-D distances: 5 FP32 squared
+// distance with a clamped table, 4 FP64 vector.  P: rows per lane of the vector
 // paths (a wavefront covers P * 64 rows of a unit) or row groups of 16 of the
 // matrix-core path (P * 16 rows).
 template <int PREC, bool LUT8, int P, bool PRUNE>
@@ -980,16 +1011,18 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
                 else
                     rows_mma<LUT8, false, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
                                                     cnt);
-            } else if (PREC == 0 || PREC == 3) {
+            } else if (PREC == 0 || PREC == 3 || PREC == 5) {
+                constexpr bool M3 = PREC == 5;
                 if (masked)
-                    rows_fp32<LUT8, true, P, PREC == 3, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, true, P, PREC == 3, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp32<LUT8, false, P, PREC == 3, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, false, P, PREC == 3, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             } else {
+                constexpr bool M3 = PREC == 4;
                 if (masked)
-                    rows_fp64<LUT8, true, P, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp64<LUT8, true, P, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp64<LUT8, false, P, PRUNE>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp64<LUT8, false, P, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             }
             // pairs counted beyond the last edge go to this lane's copy of the
             // overflow slot; then the wave's own LDS region is flushed (no
@@ -1160,6 +1193,15 @@ void launch_pairs(int P, bool prune, int grid, int lds, hipStream_t st, const Pa
     }
 }
 
+// 3-D distances: no pruning (the bounding caps are angular).
+template <int PR, bool B8>
+void launch_pairs3(int P, int grid, int lds, hipStream_t st, const PairArgs &a) {
+    if (P == 2)
+        hipLaunchKernelGGL((pairs_kernel<PR, B8, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL((pairs_kernel<PR, B8, 4, false>), dim3(grid), dim3(kBlock), lds, st, a);
+}
+
 }  // namespace
 
 extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stream) {
@@ -1174,6 +1216,21 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
     if (P != 2 && P != 4)
         return (int)hipErrorInvalidValue;
     const bool prune = args->prune != 0;
+    if (args->metric == 1) {
+        if (prune)
+            return (int)hipErrorInvalidValue;
+        if (precision == 0 && b8)
+            launch_pairs3<5, true>(P, grid, lds, st, *args);
+        else if (precision == 0)
+            launch_pairs3<5, false>(P, grid, lds, st, *args);
+        else if (precision == 1 && b8)
+            launch_pairs3<4, true>(P, grid, lds, st, *args);
+        else if (precision == 1)
+            launch_pairs3<4, false>(P, grid, lds, st, *args);
+        else
+            return (int)hipErrorInvalidValue;
+        return (int)hipGetLastError();
+    }
     if (precision == 0) {
         if (b8 && args->lut_direct)
             launch_pairs<3, true>(P, prune, grid, lds, st, *args);

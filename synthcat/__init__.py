@@ -229,4 +229,67 @@ def config5_randoms(n: int = 2_000_000):
     return [Catalog(*uniform_patch(n, OCTANT, rng_for(5, 100 + r))) for r in range(3)]
 
 
+# --- 3-D boxes (the spatial variant xi(r)) ----------------------------------
+
+@dataclass
+class Box:
+    """Cartesian points (comoving coordinates, e.g. Mpc/h), float64."""
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.x.size)
+
+    def xyz(self):
+        return self.x, self.y, self.z
+
+
+def box_uniform(n: int, side: float, rng: np.random.Generator, origin: float = 0.0) -> Box:
+    """n points uniform in the cube [origin, origin + side)^3."""
+    p = rng.uniform(origin, origin + side, size=(3, n))
+    return Box(p[0].copy(), p[1].copy(), p[2].copy())
+
+
+def box_clustered(n: int, n_centres: int, sigma: float, side: float, rng: np.random.Generator,
+                  origin: float = 0.0) -> Box:
+    """n points in isotropic Gaussian blobs (per-axis sigma) around uniform
+    centres in the cube; points outside the cube are redrawn."""
+    c = rng.uniform(origin, origin + side, size=(n_centres, 3))
+    out = np.empty((n, 3), dtype=np.float64)
+    todo = np.arange(n)
+    while todo.size:
+        pick = rng.integers(0, n_centres, size=todo.size)
+        p = c[pick] + rng.normal(0.0, sigma, size=(todo.size, 3))
+        ok = np.all((p >= origin) & (p < origin + side), axis=1)
+        out[todo[ok]] = p[ok]
+        todo = todo[~ok]
+    return Box(out[:, 0].copy(), out[:, 1].copy(), out[:, 2].copy())
+
+
+@dataclass
+class Workload3d:
+    name: str
+    data: Box
+    randoms: Box
+    edges: np.ndarray
+
+
+def config3d(scale: float = 1.0, side: float = 1000.0) -> Workload3d:
+    """3-D analogue of config 3: 1e6 data points (70% in blobs around 20000
+    centres with per-axis sigma 2, 30% uniform) and 2e6 uniform randoms in a
+    box of side 1000 (Mpc/h); 30 log bins over [0.5, 150]."""
+    nd = max(2, int(round(1_000_000 * scale)))
+    nr = max(2, int(round(2_000_000 * scale)))
+    g = rng_for(30, 0)
+    ncl = int(round(0.7 * nd))
+    a = box_clustered(ncl, max(1, int(round(20000 * scale))), 2.0, side, g)
+    b = box_uniform(nd - ncl, side, g)
+    perm = g.permutation(nd)
+    d = Box(*(np.concatenate([u, v])[perm] for u, v in zip(a.xyz(), b.xyz())))
+    r = box_uniform(nr, side, rng_for(30, 1))
+    return Workload3d(f"box{int(side)}_{nd:.0e}x{nr:.0e}".replace("+0", ""), d, r, log_edges(0.5, 150.0, 30))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}

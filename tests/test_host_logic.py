@@ -376,3 +376,82 @@ def test_host_jackknife_argument_errors():
     big = np.ones((3, 5), np.uint64)
     with pytest.raises(tp.TpcfError):   # a region count above its total
         tp.jackknife(z, big, z, t, z, t, 10, n, 10, n)
+
+
+# --- 3-D distances: thresholds S_k and the FP32 band ---------------------------
+
+@pytest.mark.parametrize("edges", [
+    synthcat.log_edges(0.5, 150.0, 40),
+    np.array([0.0, 1e-9, 0.3, 1.0, 2.0, 7.5, 1e6, 3e40, 1e120]),
+])
+def test_3d_thresholds_bracket_sqrt(edges):
+    S, _, _ = tp.compile_edges_3d(edges, rmax=1000.0)
+    for k, e in enumerate(edges):
+        if e == 0.0:
+            assert S[k] == -np.inf
+            continue
+        assert math.sqrt(S[k]) >= e
+        assert math.sqrt(_next(S[k], -1)) < e
+        for s in range(1, 40):
+            assert math.sqrt(_next(S[k], s)) >= e
+            lo = _next(S[k], -s)
+            if lo >= 0.0:
+                assert math.sqrt(lo) < e
+    assert np.all(np.diff(S[np.isfinite(S)]) > 0)
+
+
+def test_3d_edges_validation():
+    for bad in ([1.0, 1.0, 2.0], [2.0, 1.0], [-1.0, 1.0], [1.0, np.inf], [1.0, 2e150], [1.0]):
+        with pytest.raises(tp.TpcfError):
+            tp.compile_edges_3d(bad, rmax=1.0)
+    with pytest.raises(tp.TpcfError):
+        tp.compile_edges_3d([1.0, 2.0], rmax=-1.0)
+
+
+def _pairs_at_distance(g, r, rmax):
+    """Pairs (a, b) with |a - b| = r (to FP64 rounding), a random direction,
+    and both points within the ball of radius rmax."""
+    n = r.size
+    u = g.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    base = g.uniform(-1.0, 1.0, size=(n, 3)) * (0.3 * rmax)
+    return base, base + r[:, None] * u
+
+
+@pytest.mark.parametrize("rmax", [1.0, 1000.0, 3.0e5])
+def test_3d_fp32_band_adversary(rmax):
+    """Pairs at r = e_k (1 +- 10^-s), s = 2..9, for every edge: each FP32
+    decision the band calls certain agrees with the oracle's distance rule,
+    and the band is no wider than its error analysis allows."""
+    g = np.random.default_rng(11)
+    edges = synthcat.log_edges(1e-3 * rmax, 0.3 * rmax, 24)
+    S, qlo, qhi = tp.compile_edges_3d(edges, rmax=rmax)
+    rs, rel, edge_of = [], [], []
+    for k, e in enumerate(edges):
+        for s in range(2, 10):
+            for sign in (-1.0, 1.0):
+                rs.append(np.full(50, e * (1.0 + sign * 10.0 ** -s)))
+                rel.append(np.full(50, 10.0 ** -s))
+                edge_of.append(np.full(50, k))
+    r = np.concatenate(rs)
+    rel = np.concatenate(rel)
+    edge_of = np.concatenate(edge_of)
+    a, b = _pairs_at_distance(g, r, rmax)
+    assert np.all(np.linalg.norm(a, axis=1) <= rmax) and np.all(np.linalg.norm(b, axis=1) <= rmax)
+    q = _q32(a, b)
+    dist = oracle.pair_distances(a.T, b.T)
+    d = a - b
+    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    in_band = np.zeros(r.size, bool)
+    for k in range(edges.size):
+        past = dist >= edges[k]
+        assert np.array_equal(past, r2 >= S[k]), k
+        above = q >= qhi[k]
+        below = q < qlo[k]
+        assert np.all(past[above]), k
+        assert not np.any(past[below]), k
+        in_band |= ~above & ~below & (edge_of == k)
+    # half-width in r: a = 2^-23 rmax from the FP32 copies plus ~3 ulp of q
+    half = 2.0 ** -23 * rmax / edges[edge_of] + 4e-7
+    assert not np.any(in_band & (rel > 3.0 * half))
+    assert np.all(in_band[rel < 0.1 * half])
