@@ -103,6 +103,8 @@ def parse():
                     help="skip the extra run with exact tile pruning (never the headline)")
     ap.add_argument("--no-jackknife", action="store_true",
                     help="skip the jackknife-region step (8 x 8 regions over the octant)")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3-D xi(r) step (1e6 x 2e6 points in a box of side 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -467,6 +469,54 @@ def main():
                         "same totals as the plain step"}
         ctx.release_catalog(jd)
         ctx.release_catalog(jr)
+    xi3d = None
+    if not args.no_3d:
+        # the 3-D variant xi(r): same kernels keyed on squared distances; one
+        # step = DD + DR + RR + Landy-Szalay on a 1e6 x 2e6 box workload
+        w3 = synthcat.config3d(scale=args.scale)
+        b_d = ctx.upload_catalog_3d(*w3.data.xyz())
+        b_r = ctx.upload_catalog_3d(*w3.randoms.xyz())
+        n3d, n3r = w3.data.n, w3.randoms.n
+        pairs3 = n3d * (n3d - 1) // 2 + n3d * n3r + n3r * (n3r - 1) // 2
+        out3 = torch.zeros((3, w3.edges.size + 1), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        xi3d = {"workload": w3.name, "n_d": n3d, "n_r": n3r, "nbins": int(w3.edges.size - 1),
+                "r_range": [float(w3.edges[0]), float(w3.edges[-1])], "pairs_per_step": pairs3}
+        hist3 = {}
+        for prec in (tp.FP32_CHORD, tp.FP64):
+            def step3():
+                ctx.count_async(tp.DD, b_d, w3.edges, out3[0].data_ptr(), precision=prec)
+                ctx.count_async(tp.DR, b_d, w3.edges, out3[1].data_ptr(), cat_b=b_r, precision=prec)
+                ctx.count_async(tp.RR, b_r, w3.edges, out3[2].data_ptr(), precision=prec)
+                ctx.synchronize()
+                h = out3.cpu().numpy().astype(np.uint64)
+                tp.landy_szalay(h[0], h[1], h[2], n3d, n3r)
+                return h
+            step3()
+            ctx.kernel_time(reset=True)
+            ctx.stats(reset=True)
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                h3 = step3()
+            t1 = time.perf_counter()
+            ctx.set_timing(False)
+            kms, nl = ctx.kernel_time(reset=True)
+            st = ctx.stats(reset=True)
+            if [int(x.sum()) for x in h3] != [n3d * (n3d - 1) // 2, n3d * n3r, n3r * (n3r - 1) // 2]:
+                sys.exit("3-D slot totals do not match the pair counts")
+            hist3[prec] = h3
+            xi3d[PATH_NAMES[prec]] = {
+                "gpairs_s": round(pairs3 * args.steps / (t1 - t0) / 1e9, 2),
+                "kernel_gpairs_s": round(pairs3 * args.steps / (kms / 1e3) / 1e9, 1),
+                "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
+                "kernel_ms_per_launch": round(kms / max(1, nl), 3),
+                "exact_rate": st.exact / max(1, st.pairs)}
+        if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[tp.FP64])):
+            sys.exit("3-D FP32 and FP64 histograms differ")
+        ctx.release_catalog(b_d)
+        ctx.release_catalog(b_r)
+        del out3
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
@@ -501,6 +551,8 @@ def main():
         res["fp32_chord_pruned"] = pruned
     if jack is not None:
         res["jackknife_regions"] = jack
+    if xi3d is not None:
+        res["xi_r_3d"] = xi3d
     if tp.FP64 in sums:
         res["fp32_over_fp64"] = round(sums[tp.FP32_CHORD]["gpairs_s"] / sums[tp.FP64]["gpairs_s"], 3)
     if not args.no_cpu_baseline:
