@@ -361,7 +361,7 @@ def main():
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
         t = ctx.get_tuning()     # 0 = the library's default
-        rpl = t["rows_per_lane"] or 4
+        rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
         tuning = dict(t, rows_per_lane=rpl, autotuned=tuning is not None)
         rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
         cols_per_step = 16 if prec == tp.FP64_MATRIX else 2

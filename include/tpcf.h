@@ -258,7 +258,7 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * Every field 0 takes the default.
  * rows_per_lane   vector paths: 2 or 4 rows held in registers per lane;
  *                 matrix-core path: 2 or 4 groups of 16 rows per wavefront
- *                 (default 4);
+ *                 (default 4 on the vector paths, 2 on the matrix-core path);
  * hist_copies     LDS histogram copies per wavefront, 4, 8, 16 or 32
  *                 (default 16); a value above what the slot count allows
  *                 (32 up to 46 slots, 16 up to 94, 8 up to 190, else 4) is

@@ -68,8 +68,11 @@ struct Tuning {
     int prune = 0;           // 1: exact tile pruning
 };
 
-int rows_per_lane_of(const Tuning &t, bool) {
-    return t.rows_per_lane ? t.rows_per_lane : 4;
+// Default: 4 rows per lane on the vector paths, 2 row groups of 16 on the
+// matrix-core path (fewer registers, more wavefronts to overlap the matrix
+// cores with the binning).
+int rows_per_lane_of(const Tuning &t, bool matrix) {
+    return t.rows_per_lane ? t.rows_per_lane : matrix ? 2 : 4;
 }
 
 int max_cols_of(const Tuning &t) { return t.max_cols ? t.max_cols : 4096; }

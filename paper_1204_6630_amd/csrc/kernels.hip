@@ -839,6 +839,13 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
         }
 }
 
+// Column groups of [j0, j1) against the RG row groups of this wavefront: RG
+// matrix-core products per 16-column group, then the binning of their pairs.
+// The products of one group are binned before the next group's are issued
+// (no double buffer): that keeps the wavefront near 100 registers, and the
+// other wavefronts of the SIMD keep the matrix cores busy meanwhile.  The
+// column operands are fetched two groups ahead (clamped to the last group of
+// the catalog, so the reads never leave it).
 template <bool LUT8, bool MASKED, int RG>
 __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                          const double (&A)[RG], int ib, int rlo, int ie, int j0, int clo,
@@ -848,41 +855,17 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
     const int jg0 = j0 >> 4;
     const int jg_end = (j1 + 15) >> 4;
     const int jg_last = jb.b_groups - 1;
-    // column operands are fetched two groups ahead of their products
-    // (clamped to the last group of the catalog, so the reads never leave it)
     double bq0 = bp[(size_t)min(jg0, jg_last) * 64];
     double bq1 = bp[(size_t)min(jg0 + 1, jg_last) * 64];
-    v4d d0[RG], d1[RG];
-    {
+    for (int jg = jg0; jg < jg_end; ++jg) {
         const double b = bq0;
         bq0 = bq1;
-        bq1 = bp[(size_t)min(jg0 + 2, jg_last) * 64];
+        bq1 = bp[(size_t)min(jg + 2, jg_last) * 64];
+        v4d d[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g)
-            d0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
-    }
-    for (int jg = jg0; jg < jg_end; jg += 2) {
-        const bool has1 = jg + 1 < jg_end;
-        if (has1) {
-            const double b = bq0;
-            bq0 = bq1;
-            bq1 = bp[(size_t)min(jg + 3, jg_last) * 64];
-#pragma unroll
-            for (int g = 0; g < RG; ++g)
-                d1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
-        }
-        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d0, ib, rlo, ie, jg, clo, j1, lane, cnt);
-        if (!has1)
-            break;
-        if (jg + 2 < jg_end) {
-            const double b = bq0;
-            bq0 = bq1;
-            bq1 = bp[(size_t)min(jg + 4, jg_last) * 64];
-#pragma unroll
-            for (int g = 0; g < RG; ++g)
-                d0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
-        }
-        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d1, ib, rlo, ie, jg + 1, clo, j1, lane, cnt);
+            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
+        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d, ib, rlo, ie, jg, clo, j1, lane, cnt);
     }
 }
 
@@ -891,9 +874,6 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
 // 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
 // (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
 // then binned exactly as on the vector path, against the matrix-core band.
-// The loop is software-pipelined: the products of the next column group are
-// issued before the current group is binned, so the matrix cores work while
-// the wavefront does its lookups.
 template <bool LUT8, bool MASKED, int RG, bool PRUNE>
 __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                          int ib, int rlo, int ie, int j0, int clo, int j1, int lane, Counters &cnt) {
