@@ -1,0 +1,125 @@
+"""GPU parity at the limits of the bin count and on seeded random cases
+(needs an MI355X).
+
+* nbins from 1 to the maximum 256: past 125 bins the cell tables switch from
+  one-byte to two-byte entries and the per-wavefront histogram copies drop
+  from 16 to 8 and then 4, so each of those kernel variants meets the oracle
+  here, for every precision and for 3-D catalogs too;
+* edges that include 0 and 180 degrees exactly, on the full sphere;
+* 16 seeded random cases: catalog sizes, bin counts, edge placements, point
+  distributions (full sphere, clustered patch, duplicated points), kinds,
+  precisions and launch shapes drawn at random, each bit-exact against the
+  oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1204_6630_amd as tp
+import synthcat
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def sphere(ctx):
+    g = synthcat.rng_for(97, 0)
+    ra_a, dec_a = synthcat.uniform_sphere(2500, g)
+    ra_c, dec_c = synthcat.clustered(1500, 40, 2.0, (0.0, 360.0, -90.0, 90.0), g)
+    ra_a = np.concatenate([ra_a, ra_c])
+    dec_a = np.concatenate([dec_a, dec_c])
+    ra_b, dec_b = synthcat.uniform_sphere(1700, g)
+    ca = ctx.upload_catalog(ra_a, dec_a)
+    cb = ctx.upload_catalog(ra_b, dec_b)
+    return ca, cb, oracle.radec_to_xyz(ra_a, dec_a), oracle.radec_to_xyz(ra_b, dec_b)
+
+
+_ref = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("nbins", [1, 125, 126, 200, 256])
+def test_bin_counts_up_to_the_maximum(ctx, sphere, prec, nbins):
+    ca, cb, xa, xb = sphere
+    edges = np.linspace(0.0, 180.0, nbins + 1)          # 0 and 180 exactly
+    if nbins == 200:
+        edges = np.concatenate([[0.0], synthcat.log_edges(1e-3, 180.0, nbins)])[:nbins + 1]
+    if (nbins, "DD") not in _ref:
+        _ref[(nbins, "DD")] = oracle.count(oracle.DD, xa, edges)
+        _ref[(nbins, "DR")] = oracle.count(oracle.DR, xa, edges, b_xyz=xb)
+    assert np.array_equal(ctx.count(tp.DD, ca, edges, precision=prec), _ref[(nbins, "DD")])
+    assert np.array_equal(ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec), _ref[(nbins, "DR")])
+
+
+@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64])
+def test_3d_with_256_bins(ctx, prec):
+    g = synthcat.rng_for(97, 1)
+    a = synthcat.box_clustered(3000, 60, 3.0, 200.0, g)
+    edges = np.linspace(0.0, 120.0, 257)
+    cid = ctx.upload_catalog_3d(*a.xyz())
+    try:
+        ref = _ref.setdefault("3d256", oracle.count3d(oracle.DD, a.xyz(), edges))
+        assert np.array_equal(ctx.count(tp.DD, cid, edges, precision=prec), ref)
+    finally:
+        ctx.release_catalog(cid)
+
+
+def _random_case(seed):
+    g = np.random.default_rng(1000 + seed)
+    na = int(g.choice([1, 2, 17, 64, 65, 1000, 1537, 3000]))
+    nb = int(g.choice([1, 3, 64, 257, 999, 2500]))
+    nbins = int(g.choice([1, 2, 7, 40, 125, 126, 199, 256]))
+    style = g.choice(["sphere", "patch", "dups"])
+    if style == "sphere":
+        ra, dec = synthcat.uniform_sphere(na + nb, g)
+    elif style == "patch":
+        ra, dec = synthcat.clustered(na + nb, max(1, (na + nb) // 30), 0.5, synthcat.PATCH_30, g)
+    else:
+        # a few distinct positions, each repeated: many coincident pairs
+        r0, d0 = synthcat.uniform_patch(max(1, (na + nb) // 8), synthcat.PATCH_30, g)
+        pick = g.integers(0, r0.size, size=na + nb)
+        ra, dec = r0[pick], d0[pick]
+    lo = float(g.choice([0.0, 1e-4, 0.01]))
+    hi = float(g.choice([1.0, 30.0, 180.0]))
+    if g.uniform() < 0.5 and lo > 0.0:
+        edges = synthcat.log_edges(lo, hi, nbins)
+    else:
+        edges = np.linspace(lo, hi, nbins + 1)
+    kind = int(g.choice([tp.DD, tp.DR]))
+    prec = int(g.choice(PRECS))
+    tuning = {"rows_per_lane": int(g.choice([0, 2, 4])), "hist_copies": int(g.choice([0, 4, 8, 32])),
+              "max_cols": int(g.choice([0, 256, 1024]))}
+    return (ra[:na], dec[:na]), (ra[na:], dec[na:]), edges, kind, prec, tuning, style
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_seeded_random_cases(ctx, seed):
+    (ra_a, dec_a), (ra_b, dec_b), edges, kind, prec, tuning, style = _random_case(seed)
+    print(f"case {seed}: na={ra_a.size} nb={ra_b.size} nbins={edges.size - 1} kind={kind} "
+          f"prec={prec} {style} {tuning}", flush=True)
+    ca = ctx.upload_catalog(ra_a, dec_a)
+    cb = ctx.upload_catalog(ra_b, dec_b)
+    ctx.set_tuning(**tuning)
+    try:
+        xa = oracle.radec_to_xyz(ra_a, dec_a)
+        if kind == tp.DD:
+            got = ctx.count(tp.DD, ca, edges, precision=prec)
+            ref = oracle.count(oracle.DD, xa, edges)
+        else:
+            got = ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec)
+            ref = oracle.count(oracle.DR, xa, edges, b_xyz=oracle.radec_to_xyz(ra_b, dec_b))
+        assert np.array_equal(got, ref)
+    finally:
+        ctx.set_tuning()
+        ctx.release_catalog(ca)
+        ctx.release_catalog(cb)
