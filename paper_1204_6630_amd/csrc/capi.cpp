@@ -547,6 +547,25 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     return TPCF_OK;
 }
 
+// Column chunk width of a plan: aim for >= ~4096 units on big requests,
+// within [256, max_cols], but wide enough that the unit list stays below
+// kMaxUnits (about 0.8 GB of units; catalogs of 1e8 points would otherwise
+// need tens of GB of them).
+constexpr double kMaxUnits = 16777216.0;
+
+int64_t chunk_width(uint64_t pairs, int64_t T, int64_t max_cols) {
+    int64_t bj = (int64_t)((double)pairs / 4096.0 / (double)T);
+    bj = (bj + 255) / 256 * 256;
+    if (bj > max_cols)
+        bj = max_cols;
+    if (bj < 256)
+        bj = 256;
+    const double need = (double)pairs / (double)T / kMaxUnits;   // columns per unit for kMaxUnits units
+    if ((double)bj < need)
+        bj = ((int64_t)need + 256) / 256 * 256;
+    return bj;
+}
+
 // Work units.  DR: every row tile against column chunks of the B catalog.
 // DD/RR: every row tile [i0, i1) against j in [i0, n): one masked unit for the
 // diagonal block [i0, i0 + T), then unmasked chunks from i0 + T on.
@@ -577,14 +596,7 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
         pairs = (uint64_t)(re - rb) * (uint64_t)nb;
     }
     p.pairs = pairs;
-    // column chunk: aim for >= ~4096 units on big requests, within [256, max_cols]
-    double per_unit = (double)pairs / 4096.0 / (double)T;
-    int64_t bj = (int64_t)per_unit;
-    bj = (bj + 255) / 256 * 256;
-    if (bj > max_cols)
-        bj = max_cols;
-    if (bj < 256)
-        bj = 256;
+    const int64_t bj = chunk_width(pairs, T, max_cols);
     // Row tiles start on multiples of `align` (valid rows from row_lo = rb).
     // Column chunks lie on a common grid of multiples of bj, so units of
     // different row tiles cover the same column ranges; the list is ordered
@@ -638,13 +650,7 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
                        const std::vector<int64_t> &sa, const std::vector<int64_t> &sb) {
     Plan p;
     p.pairs = auto_pairs ? (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2 : (uint64_t)na * (uint64_t)nb;
-    double per_unit = (double)p.pairs / 4096.0 / (double)T;
-    int64_t bj = (int64_t)per_unit;
-    bj = (bj + 255) / 256 * 256;
-    if (bj > max_cols)
-        bj = max_cols;
-    if (bj < 256)
-        bj = 256;
+    const int64_t bj = chunk_width(p.pairs, T, max_cols);
     const int nra = (int)sa.size() - 1, nrb = (int)sb.size() - 1;
     auto region_of = [](const std::vector<int64_t> &st, int64_t j) {
         return (int32_t)(std::upper_bound(st.begin(), st.end(), j) - st.begin() - 1);
