@@ -123,3 +123,40 @@ def test_seeded_random_cases(ctx, seed):
         ctx.set_tuning()
         ctx.release_catalog(ca)
         ctx.release_catalog(cb)
+
+
+def test_huge_request_uses_wide_units_with_the_same_counts(ctx):
+    """4e7 random points on the device (zero-copy attach) against 1e6 data
+    rows, 2 rows per lane (512-row tiles): 4e13 pairs, beyond what
+    4096-column units can list within the unit budget (16.7M units), so the
+    plan widens its column chunks.  The counts must equal the sum over two
+    halves of the rows, whose plans keep the usual width, and the totals must
+    close."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(1204)
+    nr, nd = 40_000_000, 1_000_000
+
+    def unit_vectors(n):
+        v = torch.randn((3, n), dtype=torch.float64, device="cuda:0", generator=g)
+        v /= torch.linalg.vector_norm(v, dim=0, keepdim=True)
+        return v.contiguous()
+
+    tr = unit_vectors(nr)
+    td = unit_vectors(nd)
+    cr = ctx.attach_catalog(tr)
+    cd = ctx.attach_catalog(td)
+    ctx.set_tuning(rows_per_lane=2)
+    try:
+        edges = synthcat.log_edges(0.01, 1.0, 20)
+        full = ctx.count(tp.DR, cd, edges, cat_b=cr)
+        halves = (ctx.count(tp.DR, cd, edges, cat_b=cr, row_begin=0, row_end=nd // 2)
+                  + ctx.count(tp.DR, cd, edges, cat_b=cr, row_begin=nd // 2, row_end=nd))
+        assert int(full.sum()) == nd * nr
+        assert np.array_equal(full, halves)
+    finally:
+        ctx.set_tuning()
+        ctx.release_catalog(cd)
+        ctx.release_catalog(cr)
+        del tr, td
+        torch.cuda.empty_cache()
