@@ -68,17 +68,21 @@ def measured_traffic(path: str):
     return int(float(rows[path]))
 
 
-def roofline(prec: int, kernel_gpairs: float, ms_per_launch: float, traffic=None) -> dict:
+def roofline(prec: int, kernel_gpairs: float, ms_per_launch: float, traffic=None, kernel=None,
+             ops_per_pair=None) -> dict:
     if prec == 2:
         achieved = kernel_gpairs * 1e9 * FLOPS_PER_PAIR / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "flops_per_pair": FLOPS_PER_PAIR}
     else:
-        peak = PEAK_GPAIRS if prec == 0 else FP64_LANE_OPS / OPS_PER_PAIR_FP64 / 1e9
+        if prec == 0:
+            peak = FP32_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP32) / 1e9
+        else:
+            peak = FP64_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP64) / 1e9
         roof = {"bound": "alu", "achieved": round(kernel_gpairs, 1), "peak": round(peak, 1),
                 "unit": "Gpairs/s", "frac": round(kernel_gpairs / peak, 4)}
-    roof.update({"traffic": traffic, "kernel": KERNEL_NAMES[prec],
+    roof.update({"traffic": traffic, "kernel": kernel or KERNEL_NAMES[prec],
                  "kernel_ms_per_launch": round(ms_per_launch, 3)})
     return roof
 
@@ -424,10 +428,15 @@ def main():
         ctx.set_tuning()
         if not all(np.array_equal(a, b) for a, b in zip(runs[paths[0]]["hist"], hp)):
             sys.exit("pruned and brute-force histograms differ")
+        evaluated = st.pairs - st.pruned_pairs
         pruned = {"gpairs_s_algorithmic": round(pairs_step * args.steps / (t1 - t0) / 1e9, 2),
                   "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
                   "kernel_ms_per_step": round(kms / args.steps, 3),
                   "pruned_fraction": round(st.pruned_pairs / max(1, st.pairs), 4),
+                  # the roofline of the pairs the kernel still evaluated
+                  "roofline_evaluated_pairs": roofline(
+                      tp.FP32_CHORD, evaluated / (kms / 1e3) / 1e9, kms / (3 * args.steps),
+                      kernel="pairs_kernel<0> with pruning (FP32 chord)"),
                   "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
                           "blocks are not evaluated, so not comparable to value"}
     jack = None
@@ -464,6 +473,9 @@ def main():
         ms = (t1 - t0) / args.steps * 1e3
         jack = {"nreg": nreg, "gpairs_s": round(pairs_step * args.steps / (t1 - t0) / 1e9, 2),
                 "ms_per_step": round(ms, 3), "kernel_ms_per_step": round(kms / args.steps, 3),
+                "roofline": roofline(tp.FP32_CHORD, pairs_step * args.steps / (kms / 1e3) / 1e9,
+                                     kms / (3 * args.steps),
+                                     kernel="pairs_kernel<0> with region copies (FP32 chord)"),
                 "over_plain_step": round(ms / sums[tp.FP32_CHORD]["ms_per_step"], 3),
                 "note": "DD+DR+RR with per-region counts (FP32 chord) + host jackknife of w; "
                         "same totals as the plain step"}
@@ -511,7 +523,14 @@ def main():
                 "kernel_gpairs_s": round(pairs3 * args.steps / (kms / 1e3) / 1e9, 1),
                 "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
                 "kernel_ms_per_launch": round(kms / max(1, nl), 3),
-                "exact_rate": st.exact / max(1, st.pairs)}
+                "exact_rate": st.exact / max(1, st.pairs),
+                # FP32: 3 differences, a square, 2 FMAs and the key (as for
+                # angles); FP64: 3 differences, 3 squares, 2 sums (the key is
+                # the high word of r^2)
+                "roofline": roofline(prec, pairs3 * args.steps / (kms / 1e3) / 1e9, kms / max(1, nl),
+                                     kernel=("pairs_kernel<5> (3-D FP32)" if prec == tp.FP32_CHORD
+                                             else "pairs_kernel<4> (3-D FP64)"),
+                                     ops_per_pair=7 if prec == tp.FP32_CHORD else 8)}
         if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[tp.FP64])):
             sys.exit("3-D FP32 and FP64 histograms differ")
         ctx.release_catalog(b_d)
