@@ -368,7 +368,7 @@ def main():
         rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
         tuning = dict(t, rows_per_lane=rpl, autotuned=tuning is not None)
         rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
-        cols_per_step = 16 if prec == tp.FP64_MATRIX else 2
+        cols_per_step = {tp.FP32_CHORD: 4, tp.FP64: 2, tp.FP64_MATRIX: 16}[prec]
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
                 "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,
                 "beyond": beyond, "one_slot": one_slot, "per_kind": per_kind,

@@ -35,7 +35,13 @@ using namespace tpcf;
 
 namespace {
 
-constexpr int kColsPerStep = 2;
+// Columns per step of the vector paths (each lane evaluates P x this many
+// pairs between two wavefront-wide tests).  Measured on the octant workload:
+// 4 columns are 8 % faster than 2 on the FP32 path (fewer tests and loop
+// trips per pair), while the FP64 path, with twice the registers per value,
+// is 12 % slower at 4 than at 2.
+constexpr int kColsPerStepF32 = 4;
+constexpr int kColsPerStepF64 = 2;
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
@@ -603,7 +609,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
     cfloat_p bz = (cfloat_p)jb.bz32;
-    constexpr int JN = kColsPerStep;
+    constexpr int JN = kColsPerStepF32;
     int j = j0;
     if (j + JN <= j1) {
         // the columns of the next step are read (through the scalar unit)
@@ -696,8 +702,8 @@ __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, c
     cdouble_p by = (cdouble_p)jb.by64;
     cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
-    for (; j + kColsPerStep <= j1; j += kColsPerStep)
-        step_fp64<LUT8, MASKED, P, kColsPerStep, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+    for (; j + kColsPerStepF64 <= j1; j += kColsPerStepF64)
+        step_fp64<LUT8, MASKED, P, kColsPerStepF64, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
     for (; j < j1; ++j)
         step_fp64<LUT8, MASKED, P, 1, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
 }
