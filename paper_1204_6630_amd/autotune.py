@@ -43,7 +43,7 @@ def _device_key(precision: int, nbins: int) -> str:
         hip = getattr(torch.version, "hip", "") or ""
     except Exception:  # pragma: no cover
         name, hip = "unknown", ""
-    return f"v2|{name}|hip{hip}|prec{precision}|nbins{nbins}"
+    return f"v3|{name}|hip{hip}|prec{precision}|nbins{nbins}"
 
 
 def _load_cache() -> dict:
