@@ -74,6 +74,8 @@ def _load():
         lib.oracle_count_regions.argtypes = [ctypes.c_int, i64, P, P, P, P, i64, P, P, P, P,
                                              ctypes.c_int32, P, ctypes.c_int32, P, P]
         lib.oracle_count_regions.restype = ctypes.c_int
+        lib.oracle_count_regions3d.argtypes = lib.oracle_count_regions.argtypes
+        lib.oracle_count_regions3d.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -235,9 +237,11 @@ def landy_szalay(dd, dr, rr, n_d: int, n_r: int, form: int = 0) -> np.ndarray:
     return w
 
 
-def count_regions(kind: int, a_xyz, a_region, edges_deg, nreg: int, b_xyz=None, b_region=None):
-    """(total, touch): total as ``count``; touch[r] counts the pairs with at
-    least one member in region r (once for a pair inside one region)."""
+def count_regions(kind: int, a_xyz, a_region, edges_deg, nreg: int, b_xyz=None, b_region=None,
+                  metric: int = 0):
+    """(total, touch): total as ``count`` (``count3d`` with metric 1, edges
+    then distances); touch[r] counts the pairs with at least one member in
+    region r (once for a pair inside one region)."""
     edges = _f64(edges_deg)
     nbins = edges.size - 1
     ax, ay, az = (_f64(c) for c in a_xyz)
@@ -251,15 +255,15 @@ def count_regions(kind: int, a_xyz, a_region, edges_deg, nreg: int, b_xyz=None, 
         cross = 0
     total = np.zeros(nbins + 2, dtype=np.uint64)
     touch = np.zeros((nreg, nbins + 2), dtype=np.uint64)
-    rc = _load().oracle_count_regions(cross, ax.size, _ptr(ax), _ptr(ay), _ptr(az), _ptr(ra),
-                                      bx.size, _ptr(bx), _ptr(by), _ptr(bz), _ptr(rb), nbins,
-                                      _ptr(edges), nreg, _ptr(total), _ptr(touch))
+    fn = _load().oracle_count_regions3d if metric else _load().oracle_count_regions
+    rc = fn(cross, ax.size, _ptr(ax), _ptr(ay), _ptr(az), _ptr(ra), bx.size, _ptr(bx), _ptr(by), _ptr(bz),
+            _ptr(rb), nbins, _ptr(edges), nreg, _ptr(total), _ptr(touch))
     if rc != 0:
         raise ValueError("oracle_count_regions rejected its arguments")
     return total, touch
 
 
-def jackknife(d_xyz, d_region, r_xyz, r_region, edges_deg, nreg: int, form: int = 0):
+def jackknife(d_xyz, d_region, r_xyz, r_region, edges_deg, nreg: int, form: int = 0, metric: int = 0):
     """Delete-one jackknife of the Landy-Szalay w: for every region r, w from
     the catalogs with region r removed (recounted), then
     cov = (K - 1) / K sum_r (w_r - mean)(w_r - mean)^T with K = nreg.
@@ -274,9 +278,10 @@ def jackknife(d_xyz, d_region, r_xyz, r_region, edges_deg, nreg: int, form: int 
         kr = rreg != r
         d = [c[kd] for c in dx]
         rr_ = [c[kr] for c in rx]
-        dd = count(DD, d, edges_deg)
-        dr = count(DR, d, edges_deg, b_xyz=rr_)
-        rr = count(RR, rr_, edges_deg)
+        cnt = count3d if metric else count
+        dd = cnt(DD, d, edges_deg)
+        dr = cnt(DR, d, edges_deg, b_xyz=rr_)
+        rr = cnt(RR, rr_, edges_deg)
         samples.append(landy_szalay(dd[1:-1], dr[1:-1], rr[1:-1], int(kd.sum()), int(kr.sum()), form))
     samples = np.array(samples)
     mean = samples.mean(axis=0)

@@ -246,10 +246,10 @@ int oracle_count3d(int cross, int64_t na, const double *ax, const double *ay,
  * out_total - out_touch[r].  Single-threaded; returns 0, or -1 on bad
  * arguments (a label out of range included).
  */
-int oracle_count_regions(int cross, int64_t na, const double *ax, const double *ay,
+static int count_regions(int cross, int metric, int64_t na, const double *ax, const double *ay,
                          const double *az, const int32_t *ra, int64_t nb, const double *bx,
                          const double *by, const double *bz, const int32_t *rb, int32_t nbins,
-                         const double *edges_deg, int32_t nreg, uint64_t *out_total,
+                         const double *edges, int32_t nreg, uint64_t *out_total,
                          uint64_t *out_touch)
 {
     if (nbins < 1 || nreg < 1 || na < 0 || (cross && nb < 0) || !out_total || !out_touch)
@@ -268,7 +268,7 @@ int oracle_count_regions(int cross, int64_t na, const double *ax, const double *
     if (!edge_rad)
         return -1;
     for (int k = 0; k < nedges; ++k)
-        edge_rad[k] = edges_deg[k] * deg;
+        edge_rad[k] = metric ? edges[k] : edges[k] * deg;
     memset(out_total, 0, sizeof(uint64_t) * (size_t)nslots);
     memset(out_touch, 0, sizeof(uint64_t) * (size_t)nreg * (size_t)nslots);
     for (int64_t i = 0; i < na; ++i) {
@@ -279,7 +279,9 @@ int oracle_count_regions(int cross, int64_t na, const double *ax, const double *
             const double yj = cross ? by[j] : ay[j];
             const double zj = cross ? bz[j] : az[j];
             const int32_t rj = cross ? rb[j] : ra[j];
-            const int s = slot_of(pair_angle(ax[i], ay[i], az[i], xj, yj, zj), edge_rad, nedges);
+            const double t = metric ? pair_distance(ax[i], ay[i], az[i], xj, yj, zj)
+                                    : pair_angle(ax[i], ay[i], az[i], xj, yj, zj);
+            const int s = slot_of(t, edge_rad, nedges);
             out_total[s] += 1;
             out_touch[(size_t)ra[i] * (size_t)nslots + (size_t)s] += 1;
             if (rj != ra[i])
@@ -288,6 +290,28 @@ int oracle_count_regions(int cross, int64_t na, const double *ax, const double *
     }
     free(edge_rad);
     return 0;
+}
+
+int oracle_count_regions(int cross, int64_t na, const double *ax, const double *ay,
+                         const double *az, const int32_t *ra, int64_t nb, const double *bx,
+                         const double *by, const double *bz, const int32_t *rb, int32_t nbins,
+                         const double *edges_deg, int32_t nreg, uint64_t *out_total,
+                         uint64_t *out_touch)
+{
+    return count_regions(cross, 0, na, ax, ay, az, ra, nb, bx, by, bz, rb, nbins, edges_deg, nreg,
+                         out_total, out_touch);
+}
+
+/* The same for 3-D catalogs: separations are the distances of
+ * oracle_count3d, edges distances. */
+int oracle_count_regions3d(int cross, int64_t na, const double *ax, const double *ay,
+                           const double *az, const int32_t *ra, int64_t nb, const double *bx,
+                           const double *by, const double *bz, const int32_t *rb, int32_t nbins,
+                           const double *edges, int32_t nreg, uint64_t *out_total,
+                           uint64_t *out_touch)
+{
+    return count_regions(cross, 1, na, ax, ay, az, ra, nb, bx, by, bz, rb, nbins, edges, nreg,
+                         out_total, out_touch);
 }
 
 /* Slot of each listed pair (i-th entry pairs point a_i with point b_i);
