@@ -132,6 +132,14 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
 int tpcf_upload_catalog_3d(tpcf_ctx *ctx, const double *x, const double *y,
                            const double *z, int64_t n, int32_t *out_cat);
 
+/* tpcf_upload_catalog_3d with jackknife region labels (see
+ * tpcf_upload_catalog_regions): stored grouped by label, Morton order of the
+ * bounding box inside each region; tpcf_count_regions and tpcf_jackknife
+ * then give delete-one errors of xi(r). */
+int tpcf_upload_catalog_3d_regions(tpcf_ctx *ctx, const double *x, const double *y,
+                                   const double *z, int64_t n, const int32_t *region,
+                                   int32_t nreg, int32_t *out_cat);
+
 /* Zero-copy attach of caller-owned device memory: d_xyz64 points to 3*n
  * doubles on the context's device laid out as x[0..n), y[0..n), z[0..n)
  * (unit vectors, same norm limit as above).  The caller keeps the memory

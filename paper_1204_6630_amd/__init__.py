@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_band64",
-    "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_compile_edges_3d",
+    "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -120,6 +120,7 @@ def lib():
         "tpcf_upload_catalog": ([P, P, P, i64, P], cint),
         "tpcf_upload_catalog_xyz": ([P, P, P, P, i64, P], cint),
         "tpcf_upload_catalog_3d": ([P, P, P, P, i64, P], cint),
+        "tpcf_upload_catalog_3d_regions": ([P, P, P, P, i64, P, i32, P], cint),
         "tpcf_compile_edges_3d": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_attach_catalog": ([P, P, i64, P], cint),
         "tpcf_catalog_order": ([P, i32, P], cint),
@@ -246,6 +247,17 @@ class Context:
             raise ValueError("x, y, z must be 1-D arrays of the same length")
         cid = ctypes.c_int32()
         _check(lib().tpcf_upload_catalog_3d(self._h, _p(x), _p(y), _p(z), x.size, ctypes.byref(cid)))
+        return cid.value
+
+    def upload_catalog_3d_regions(self, x, y, z, region, nreg: int) -> int:
+        """3-D catalog with a jackknife region label in [0, nreg) per point."""
+        x, y, z = _f64(x), _f64(y), _f64(z)
+        reg = np.ascontiguousarray(region, dtype=np.int32)
+        if not (x.shape == y.shape == z.shape == reg.shape) or x.ndim != 1:
+            raise ValueError("x, y, z and region must be 1-D arrays of the same length")
+        cid = ctypes.c_int32()
+        _check(lib().tpcf_upload_catalog_3d_regions(self._h, _p(x), _p(y), _p(z), x.size, _p(reg), nreg,
+                                                    ctypes.byref(cid)))
         return cid.value
 
     def upload_catalog_xyz(self, x, y, z) -> int:

@@ -358,6 +358,13 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
         return fail(TPCF_E_INVALID, "catalog size out of range");
     if (n > 0 && (!x || !y || !z))
         return fail(TPCF_E_INVALID, "coordinate array is NULL");
+    if (region) {
+        if (nreg < 1 || nreg > TPCF_MAX_REGIONS)
+            return fail(TPCF_E_INVALID, "nreg must be in [1, TPCF_MAX_REGIONS]");
+        for (int64_t i = 0; i < n; ++i)
+            if (region[i] < 0 || region[i] >= nreg)
+                return fail(TPCF_E_INVALID, "region labels must lie in [0, nreg)");
+    }
     Catalog c;
     c.n = n;
     c.metric = metric;
@@ -651,7 +658,7 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
     Plan p;
     p.pairs = auto_pairs ? (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2 : (uint64_t)na * (uint64_t)nb;
     const int64_t bj = chunk_width(p.pairs, T, max_cols);
-    const int nra = (int)sa.size() - 1, nrb = (int)sb.size() - 1;
+    const int nra = (int)sa.size() - 1;
     auto region_of = [](const std::vector<int64_t> &st, int64_t j) {
         return (int32_t)(std::upper_bound(st.begin(), st.end(), j) - st.begin() - 1);
     };
@@ -686,7 +693,6 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
             return x.j1 != y.j1 ? x.j1 < y.j1 : x.i0 < y.i0;
         });
     } else {
-        (void)nrb;
         for (int64_t j = 0; j < nb;) {
             const int64_t c1 = next_cut(sb, j, nb);
             const int32_t rj = region_of(sb, j);
@@ -1157,13 +1163,6 @@ int tpcf_upload_catalog_regions(tpcf_ctx *ctx, const double *ra_deg, const doubl
         return fail(TPCF_E_INVALID, "n must be >= 0");
     if (n > 0 && (!ra_deg || !dec_deg))
         return fail(TPCF_E_INVALID, "ra_deg/dec_deg is NULL");
-    if (region) {
-        if (nreg < 1 || nreg > TPCF_MAX_REGIONS)
-            return fail(TPCF_E_INVALID, "nreg must be in [1, TPCF_MAX_REGIONS]");
-        for (int64_t i = 0; i < n; ++i)
-            if (region[i] < 0 || region[i] >= nreg)
-                return fail(TPCF_E_INVALID, "region labels must lie in [0, nreg)");
-    }
     const double deg = M_PI / 180.0;
     std::vector<double> x((size_t)n), y((size_t)n), z((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
@@ -1197,11 +1196,16 @@ int tpcf_catalog_regions(tpcf_ctx *ctx, int32_t cat, int32_t *out_nreg, int64_t 
     return TPCF_OK;
 }
 
-int tpcf_upload_catalog_3d(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
-                           int32_t *out_cat) {
+int tpcf_upload_catalog_3d_regions(tpcf_ctx *ctx, const double *x, const double *y, const double *z,
+                                   int64_t n, const int32_t *region, int32_t nreg, int32_t *out_cat) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
-    return add_catalog(ctx, x, y, z, n, out_cat, nullptr, 0, 1);
+    return add_catalog(ctx, x, y, z, n, out_cat, region, region ? nreg : 0, 1);
+}
+
+int tpcf_upload_catalog_3d(tpcf_ctx *ctx, const double *x, const double *y, const double *z, int64_t n,
+                           int32_t *out_cat) {
+    return tpcf_upload_catalog_3d_regions(ctx, x, y, z, n, nullptr, 0, out_cat);
 }
 
 int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y, const double *z,

@@ -200,3 +200,46 @@ def test_full_octant_deleted_region_equals_reduced_catalog_counts(ctx):
     finally:
         ctx.release_catalog(cd)
         ctx.release_catalog(cr)
+
+
+@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64])
+def test_3d_regions_and_jackknife(ctx, prec):
+    """3-D catalogs (a clustered box and uniform randoms) cut into 3 x 3 x 1
+    slabs: totals and touch rows bit-exact against the oracle, the matrix
+    path refused, and the jackknife of xi(r) equal to the oracle's recount."""
+    g = synthcat.rng_for(98, 0)
+    a = synthcat.box_clustered(2500, 60, 2.0, 120.0, g)
+    b = synthcat.box_uniform(3000, 120.0, g)
+    nreg = 9
+
+    def labels(box):
+        ix = np.minimum((box.x // 40).astype(np.int32), 2)
+        iy = np.minimum((box.y // 40).astype(np.int32), 2)
+        return (iy * 3 + ix).astype(np.int32)
+
+    la, lb = labels(a), labels(b)
+    e = synthcat.log_edges(0.5, 50.0, 15)
+    ca = ctx.upload_catalog_3d_regions(*a.xyz(), la, nreg)
+    cb = ctx.upload_catalog_3d_regions(*b.xyz(), lb, nreg)
+    try:
+        ref_dd = _cached("3d_dd", lambda: oracle.count_regions(oracle.DD, a.xyz(), la, e, nreg, metric=1))
+        ref_dr = _cached("3d_dr", lambda: oracle.count_regions(oracle.DR, a.xyz(), la, e, nreg,
+                                                               b_xyz=b.xyz(), b_region=lb, metric=1))
+        ref_rr = _cached("3d_rr", lambda: oracle.count_regions(oracle.RR, b.xyz(), lb, e, nreg, metric=1))
+        dd = ctx.count_regions(tp.DD, ca, e, precision=prec)
+        dr = ctx.count_regions(tp.DR, ca, e, cat_b=cb, precision=prec)
+        rr = ctx.count_regions(tp.RR, cb, e, precision=prec)
+        _check(dd, ref_dd)
+        _check(dr, ref_dr)
+        _check(rr, ref_rr)
+        with pytest.raises(tp.TpcfError):
+            ctx.count_regions(tp.DD, ca, e, precision=tp.FP64_MATRIX)
+        s, m, c = tp.jackknife(dd[0], dd[1], dr[0], dr[1], rr[0], rr[1], a.n, ctx.catalog_regions(ca),
+                               b.n, ctx.catalog_regions(cb))
+        so, mo, co = _cached("3d_jk", lambda: oracle.jackknife(a.xyz(), la, b.xyz(), lb, e, nreg, metric=1))
+        assert np.array_equal(np.isnan(s), np.isnan(so))
+        np.testing.assert_allclose(s, so, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(c, co, rtol=1e-10, atol=1e-18)
+    finally:
+        ctx.release_catalog(ca)
+        ctx.release_catalog(cb)
