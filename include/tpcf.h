@@ -124,8 +124,8 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
  * batch.  Precisions: TPCF_FP32_CHORD (FP32 squared distances of FP32 copies
  * against a proven band, band pairs re-decided with the exact rule) and
  * TPCF_FP64 (the rule's r2 against S_k = the smallest double whose square
- * root reaches e_k); TPCF_FP64_MATRIX and pruning are angular only
- * (TPCF_E_INVALID, resp. no pruning).  The FP32 band widens with the largest
+ * root reaches e_k); TPCF_FP64_MATRIX is angular only (TPCF_E_INVALID).
+ * Pruning (tuning field prune) uses bounding balls.  The FP32 band widens with the largest
  * norm R of the catalogs (about 2^-23 R in r), so coordinates centred on the
  * survey keep fewer pairs on the exact path.  Rows are stored in Morton order
  * of the bounding box; tpcf_catalog_order returns it. */
@@ -287,8 +287,11 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  *                 angles of a row block x 64-column block; when that interval,
  *                 widened by 1e-6 rad and at least 1e-5 rad from 0 and pi,
  *                 contains no edge, all of the block's pairs go to that slot
- *                 without being evaluated.  Counts are unchanged; 0 (default)
- *                 evaluates every pair.
+ *                 without being evaluated.  3-D catalogs: bounding balls
+ *                 (mean and largest distance from it) bound the distances,
+ *                 widened by 2^-22 R (R the largest norm) and 1e-12
+ *                 relative.  Counts are unchanged; 0 (default) evaluates
+ *                 every pair.
  * Results never depend on these.  tpcf_get_tuning returns the fields as set
  * (0 standing for the default); NULL to tpcf_set_tuning restores defaults. */
 typedef struct tpcf_tuning {

@@ -818,7 +818,7 @@ int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
     TRY(dev_alloc(ctx->mem, (void **)&c.dcaps, c.bytes_caps));
     hipError_t e = hipSuccess;
     if (c.n > 0)
-        e = (hipError_t)tpcf_launch_caps64(c.d64, c.n, c.dcaps, ctx->main.stream);
+        e = (hipError_t)tpcf_launch_caps64(c.d64, c.n, c.dcaps, c.metric, ctx->main.stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(ctx->main.stream);
     if (e != hipSuccess) {
@@ -883,7 +883,7 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->A)));
         TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->B)));
     }
-    if (ctx->tune.prune && !r->metric)
+    if (ctx->tune.prune)
         TRY(ensure_caps(ctx, const_cast<Catalog &>(*r->B)));
     r->cache_key.clear();
     if (regions) {
@@ -943,7 +943,10 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.lut_hi = cp.cells.hi;
     a.lut_direct = cp.cells.direct ? 1 : 0;
     a.metric = cp.metric;
-    a.prune = ctx->tune.prune && !cp.metric ? 1 : 0;   // the caps are angular
+    a.prune = ctx->tune.prune ? 1 : 0;
+    // 3-D: the FP32 row copies move each point by at most 2^-24 R per
+    // component (sqrt(3) 2^-24 R in all); cp.delta holds R for 3-D edges
+    a.prune_margin = cp.metric ? ldexp(cp.delta, -22) + 1e-300 : 0.0;
     a.erad = (const double *)cp.dErad.p;
     // key of the last edge's certain side (see PairArgs::beyond_key)
     const size_t last = cp.edges.D.size() - 1;

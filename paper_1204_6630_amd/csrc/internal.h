@@ -59,8 +59,9 @@ struct JobDev {
     const double *apack, *bpack;
     int32_t a_groups, b_groups;
     // Bounding caps of the column catalog's aligned 64-point groups (stored
-    // order): centre x, y, z and an upper bound of the angular radius; null
-    // unless pruning is on.
+    // order): centre x, y, z and an upper bound of the angular radius (3-D:
+    // the points' mean and the largest distance from it); null unless
+    // pruning is on.
     const double *bcaps;
     unsigned long long *hist;    // kGlobalCopies x nslots, zeroed before
     // jackknife regions: nreg x kGlobalCopies x nslots, zeroed before; the
@@ -107,6 +108,9 @@ struct PairArgs {
     // (squared distances of Cartesian points, D_k = -S_k, E_k = S_k); no
     // pruning and no matrix-core path for 3-D.
     int32_t metric;
+    // 3-D pruning: absolute widening of the distance interval of a block
+    // (covers the FP32 copies of the rows, 2^-22 times the largest norm).
+    double prune_margin;
 
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
@@ -157,6 +161,6 @@ int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
 // Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack).
 int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream);
 // Bounding caps of the aligned 64-point groups of an FP64 SoA catalog
-// (see JobDev::bcaps): 4 doubles per group.
-int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, void *stream);
+// (see JobDev::bcaps): 4 doubles per group; metric 1 (3-D): bounding balls.
+int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, int metric, void *stream);
 }

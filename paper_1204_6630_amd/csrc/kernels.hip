@@ -203,6 +203,13 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     return s;
 }
 
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, kWaveSize));
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
@@ -426,6 +433,61 @@ __device__ __forceinline__ int prune_slot(const Cap &r, const double *bcap, cons
             slot = a;
     }
     return __builtin_amdgcn_readfirstlane(slot);
+}
+
+// 3-D: bounding ball of the points held by the lanes (centre = their mean,
+// radius = the largest distance from it, widened by 1e-12 relative).
+// Identical on every lane.
+template <int N>
+__device__ __forceinline__ Cap ball_of(const double (&x)[N], const double (&y)[N], const double (&z)[N]) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        sx += x[p];
+        sy += y[p];
+        sz += z[p];
+    }
+    const double inv = 1.0 / (double)(N * kWaveSize);
+    Cap c;
+    c.x = wave_sum_d(sx) * inv;
+    c.y = wave_sum_d(sy) * inv;
+    c.z = wave_sum_d(sz) * inv;
+    double m = 0.0;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        const double dx = x[p] - c.x, dy = y[p] - c.y, dz = z[p] - c.z;
+        m = fmax(m, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    c.rho = wave_max_d(m) * (1.0 + 1e-12);
+    return c;
+}
+
+// 3-D: the slot of every pair between the row ball and the column block's
+// ball, or -1.  Their distances lie within [|c_r - c_b| -+ (rho_r + rho_b)],
+// widened by margin (the FP32 copies of the rows, at most 2^-22 R) and by
+// 1e-12 relative (the rule's and this arithmetic's rounding).
+__device__ __forceinline__ int prune_slot3(const Cap &r, const double *bcap, const Smem &s, int nedges,
+                                           double margin) {
+    const cdouble_p bc = (cdouble_p)bcap;
+    const double dx = r.x - bc[0], dy = r.y - bc[1], dz = r.z - bc[2];
+    const double dc = sqrt(dx * dx + dy * dy + dz * dz);
+    const double spread = r.rho + bc[3];
+    const double w = margin + 1e-12 * (dc + spread);
+    const double lo = dc - spread - w, hi = dc + spread + w;
+    const int a = edges_le(s.erad, nedges, lo);
+    const int slot = a == edges_le(s.erad, nedges, hi) ? a : -1;
+    return __builtin_amdgcn_readfirstlane(slot);
+}
+
+// Block cap and block slot for either metric.
+template <bool M3, int N>
+__device__ __forceinline__ Cap block_cap(const double (&x)[N], const double (&y)[N], const double (&z)[N]) {
+    return M3 ? ball_of<N>(x, y, z) : cap_of<N>(x, y, z);
+}
+
+template <bool M3>
+__device__ __forceinline__ int block_slot(const Cap &r, const double *bcap, const Smem &s, const PairArgs &a) {
+    return M3 ? prune_slot3(r, bcap, s, a.nedges, a.prune_margin) : prune_slot(r, bcap, s, a.nedges);
 }
 
 // Add n pairs of this lane to `slot` (the overflow slot through the register
@@ -672,11 +734,11 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
             yd[p] = yi[p];
             zd[p] = zi[p];
         }
-        const Cap rc = cap_of<P>(xd, yd, zd);
+        const Cap rc = block_cap<M3, P>(xd, yd, zd);
         for (int j = j0; j < j1;) {
             const int jn = min(j1, (j & ~63) + 64);
             if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
                 if (slot >= 0) {
                     bin_block(slot, P * 64, a, k, cnt);
                     cnt.pruned += (unsigned long long)P * kWaveSize * 64;
@@ -723,11 +785,11 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
         zi[p] = jb.az64[il];
     }
     if (PRUNE && !MASKED && jb.bcaps) {
-        const Cap rc = cap_of<P>(xi, yi, zi);
+        const Cap rc = block_cap<M3, P>(xi, yi, zi);
         for (int j = j0; j < j1;) {
             const int jn = min(j1, (j & ~63) + 64);
             if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
                 if (slot >= 0) {
                     bin_block(slot, P * 64, a, k, cnt);
                     cnt.pruned += (unsigned long long)P * kWaveSize * 64;
@@ -1117,14 +1179,14 @@ __global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_
 // Bounding cap of every aligned group of 64 stored points: one wavefront per
 // group (4 doubles: unit centre, angular radius).
 __global__ __launch_bounds__(256) void caps64_kernel(const double *xyz, int64_t n, double *caps,
-                                                     int64_t groups) {
+                                                     int64_t groups, int metric) {
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x >> 6;
     for (int64_t g = (int64_t)blockIdx.x * kWaves + wave; g < groups; g += (int64_t)gridDim.x * kWaves) {
         // lanes past the catalog repeat the group's first point
         const int64_t p = g * 64 + lane < n ? g * 64 + lane : g * 64;
         const double x[1] = {xyz[p]}, y[1] = {xyz[n + p]}, z[1] = {xyz[2 * n + p]};
-        const Cap c = cap_of<1>(x, y, z);
+        const Cap c = metric ? ball_of<1>(x, y, z) : cap_of<1>(x, y, z);
         if (lane == 0) {
             caps[4 * g] = c.x;
             caps[4 * g + 1] = c.y;
@@ -1179,14 +1241,6 @@ void launch_pairs(int P, bool prune, int grid, int lds, hipStream_t st, const Pa
     }
 }
 
-// 3-D distances: no pruning (the bounding caps are angular).
-template <int PR, bool B8>
-void launch_pairs3(int P, int grid, int lds, hipStream_t st, const PairArgs &a) {
-    if (P == 2)
-        hipLaunchKernelGGL((pairs_kernel<PR, B8, 2, false>), dim3(grid), dim3(kBlock), lds, st, a);
-    else
-        hipLaunchKernelGGL((pairs_kernel<PR, B8, 4, false>), dim3(grid), dim3(kBlock), lds, st, a);
-}
 
 }  // namespace
 
@@ -1203,16 +1257,14 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
         return (int)hipErrorInvalidValue;
     const bool prune = args->prune != 0;
     if (args->metric == 1) {
-        if (prune)
-            return (int)hipErrorInvalidValue;
         if (precision == 0 && b8)
-            launch_pairs3<5, true>(P, grid, lds, st, *args);
+            launch_pairs<5, true>(P, prune, grid, lds, st, *args);
         else if (precision == 0)
-            launch_pairs3<5, false>(P, grid, lds, st, *args);
+            launch_pairs<5, false>(P, prune, grid, lds, st, *args);
         else if (precision == 1 && b8)
-            launch_pairs3<4, true>(P, grid, lds, st, *args);
+            launch_pairs<4, true>(P, prune, grid, lds, st, *args);
         else if (precision == 1)
-            launch_pairs3<4, false>(P, grid, lds, st, *args);
+            launch_pairs<4, false>(P, prune, grid, lds, st, *args);
         else
             return (int)hipErrorInvalidValue;
         return (int)hipGetLastError();
@@ -1252,7 +1304,7 @@ extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, 
     return (int)hipGetLastError();
 }
 
-extern "C" int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, void *stream) {
+extern "C" int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, int metric, void *stream) {
     const int64_t groups = (n + 63) / 64;
     if (groups <= 0)
         return 0;
@@ -1260,7 +1312,7 @@ extern "C" int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, 
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(caps64_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
-                       caps, groups);
+                       caps, groups, metric);
     return (int)hipGetLastError();
 }
 

@@ -195,3 +195,50 @@ def test_full_box_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx):
     finally:
         ctx.release_catalog(cd)
         ctx.release_catalog(cr)
+
+
+@pytest.mark.parametrize("prec", PRECS3)
+def test_3d_pruning_keeps_counts_exact(ctx, box, prec):
+    """Exact tile pruning with bounding balls: the box in full equals the
+    oracle; dense blobs with wide bins (whole blocks inside one bin, and
+    beyond the last edge) equal the oracle with pruned blocks counted."""
+    wl, cd, cr, ref = box
+    old = ctx.get_tuning()
+    ctx.set_tuning(prune=1)
+    try:
+        ctx.stats(reset=True)
+        assert np.array_equal(ctx.count(tp.DD, cd, wl.edges, precision=prec), ref["DD"])
+        assert np.array_equal(ctx.count(tp.DR, cd, wl.edges, cat_b=cr, precision=prec), ref["DR"])
+        assert np.array_equal(ctx.count(tp.RR, cr, wl.edges, precision=prec), ref["RR"])
+        g = synthcat.rng_for(31, 77)
+        blobs = synthcat.box_clustered(12000, 12, 0.8, 400.0, g)
+        e = np.array([0.0, 3.0, 40.0, 150.0, 300.0])
+        cb = ctx.upload_catalog_3d(*blobs.xyz())
+        try:
+            ctx.stats(reset=True)
+            got = ctx.count(tp.DD, cb, e, precision=prec)
+            st = ctx.stats(reset=True)
+            assert np.array_equal(got, _cached("blobs", lambda: oracle.count3d(oracle.DD, blobs.xyz(), e)))
+            assert st.pruned_pairs > 0
+        finally:
+            ctx.release_catalog(cb)
+    finally:
+        ctx.set_tuning(**old)
+
+
+def test_3d_pruning_at_full_size_equals_brute_force(ctx):
+    wl = synthcat.config3d()
+    cd = ctx.upload_catalog_3d(*wl.data.xyz())
+    cr = ctx.upload_catalog_3d(*wl.randoms.xyz())
+    try:
+        brute = [ctx.count(tp.DD, cd, wl.edges), ctx.count(tp.DR, cd, wl.edges, cat_b=cr)]
+        ctx.set_tuning(prune=1)
+        ctx.stats(reset=True)
+        pruned = [ctx.count(tp.DD, cd, wl.edges), ctx.count(tp.DR, cd, wl.edges, cat_b=cr)]
+        st = ctx.stats(reset=True)
+        assert all(np.array_equal(a, b) for a, b in zip(brute, pruned))
+        assert st.pruned_pairs > st.pairs // 2
+    finally:
+        ctx.set_tuning()
+        ctx.release_catalog(cd)
+        ctx.release_catalog(cr)
