@@ -533,6 +533,27 @@ def main():
                                      ops_per_pair=7 if prec == tp.FP32_CHORD else 8)}
         if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[tp.FP64])):
             sys.exit("3-D FP32 and FP64 histograms differ")
+        if not args.no_prune:
+            # the same 3-D step with exact tile pruning (bounding balls), FP32
+            ctx.set_tuning(prune=1)
+            prec = tp.FP32_CHORD
+            step3()
+            ctx.kernel_time(reset=True)
+            ctx.stats(reset=True)
+            ctx.set_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                h3p = step3()
+            t1 = time.perf_counter()
+            ctx.set_timing(False)
+            kms, _ = ctx.kernel_time(reset=True)
+            st = ctx.stats(reset=True)
+            ctx.set_tuning()
+            if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], h3p)):
+                sys.exit("3-D pruned and brute-force histograms differ")
+            xi3d["fp32_pruned"] = {"gpairs_s_algorithmic": round(pairs3 * args.steps / (t1 - t0) / 1e9, 2),
+                                   "kernel_ms_per_step": round(kms / args.steps, 3),
+                                   "pruned_fraction": round(st.pruned_pairs / max(1, st.pairs), 4)}
         ctx.release_catalog(b_d)
         ctx.release_catalog(b_r)
         del out3
