@@ -71,10 +71,11 @@ def measured_traffic(path: str):
 def roofline(prec: int, kernel_gpairs: float, ms_per_launch: float, traffic=None, kernel=None,
              ops_per_pair=None) -> dict:
     if prec == 2:
-        achieved = kernel_gpairs * 1e9 * FLOPS_PER_PAIR / 1e12
+        fpp = ops_per_pair or FLOPS_PER_PAIR
+        achieved = kernel_gpairs * 1e9 * fpp / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "flops_per_pair": FLOPS_PER_PAIR}
+                "flops_per_pair": fpp}
     else:
         if prec == 0:
             peak = FP32_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP32) / 1e9
@@ -495,7 +496,7 @@ def main():
         xi3d = {"workload": w3.name, "n_d": n3d, "n_r": n3r, "nbins": int(w3.edges.size - 1),
                 "r_range": [float(w3.edges[0]), float(w3.edges[-1])], "pairs_per_step": pairs3}
         hist3 = {}
-        for prec in (tp.FP32_CHORD, tp.FP64):
+        for prec in (tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX):
             def step3():
                 ctx.count_async(tp.DD, b_d, w3.edges, out3[0].data_ptr(), precision=prec)
                 ctx.count_async(tp.DR, b_d, w3.edges, out3[1].data_ptr(), cat_b=b_r, precision=prec)
@@ -525,14 +526,16 @@ def main():
                 "kernel_ms_per_launch": round(kms / max(1, nl), 3),
                 "exact_rate": st.exact / max(1, st.pairs),
                 # FP32: 3 differences, a square, 2 FMAs and the key (as for
-                # angles); FP64: 3 differences, 3 squares, 2 sums (the key is
-                # the high word of r^2)
+                # angles); FP64 (vector and matrix cores): 3 differences,
+                # 3 squares, 2 sums (the key is the high word of r^2)
                 "roofline": roofline(prec, pairs3 * args.steps / (kms / 1e3) / 1e9, kms / max(1, nl),
-                                     kernel=("pairs_kernel<5> (3-D FP32)" if prec == tp.FP32_CHORD
-                                             else "pairs_kernel<4> (3-D FP64)"),
+                                     kernel={tp.FP32_CHORD: "pairs_kernel<5> (3-D FP32)",
+                                             tp.FP64: "pairs_kernel<4> (3-D FP64)",
+                                             tp.FP64_MATRIX: "pairs_kernel<8> (3-D FP64 matrix cores)"}[prec],
                                      ops_per_pair=7 if prec == tp.FP32_CHORD else 8)}
-        if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[tp.FP64])):
-            sys.exit("3-D FP32 and FP64 histograms differ")
+        for other in (tp.FP64, tp.FP64_MATRIX):
+            if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[other])):
+                sys.exit("3-D histograms differ between precisions")
         if not args.no_prune:
             # the same 3-D step with exact tile pruning (bounding balls), FP32
             ctx.set_tuning(prune=1)

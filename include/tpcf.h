@@ -124,8 +124,10 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
  * batch.  Precisions: TPCF_FP32_CHORD (FP32 squared distances of FP32 copies
  * against a proven band, band pairs re-decided with the exact rule) and
  * TPCF_FP64 (the rule's r2 against S_k = the smallest double whose square
- * root reaches e_k); TPCF_FP64_MATRIX is angular only (TPCF_E_INVALID).
- * Pruning (tuning field prune) uses bounding balls.  The FP32 band widens with the largest
+ * root reaches e_k) and TPCF_FP64_MATRIX (r2 = |a|^2 + |b|^2 - 2 a.b from the
+ * FP64 matrix cores, the squared norms in the operand pack and the
+ * accumulator, against a band of 2^-47 R^2; band pairs re-decided with the
+ * exact rule).  Pruning (tuning field prune) uses bounding balls.  The FP32 band widens with the largest
  * norm R of the catalogs (about 2^-23 R in r), so coordinates centred on the
  * survey keep fewer pairs on the exact path.  Rows are stored in Morton order
  * of the bounding box; tpcf_catalog_order returns it. */
@@ -419,6 +421,14 @@ int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_
  * any output pointer may be NULL. */
 int tpcf_compile_edges_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_S,
                           float *out_qlo, float *out_qhi);
+
+/* 3-D matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
+ * doubles each) such that, for points of norm at most rmax, a matrix-core
+ * r2 >= out_hi[k] implies that the rule's r2 is >= S_k and r2 < out_lo[k]
+ * that it is < S_k, whenever the matrix-core value is within 2^-47 rmax^2 of
+ * the rule's. */
+int tpcf_compile_band64_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_lo,
+                           double *out_hi);
 
 /* Message describing the last failed call on the calling thread ("" if none).
  * Valid until the next call on the same thread. */

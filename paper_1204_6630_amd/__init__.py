@@ -41,6 +41,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_band64",
     "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
+    "tpcf_compile_band64_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -122,6 +123,7 @@ def lib():
         "tpcf_upload_catalog_3d": ([P, P, P, P, i64, P], cint),
         "tpcf_upload_catalog_3d_regions": ([P, P, P, P, i64, P, i32, P], cint),
         "tpcf_compile_edges_3d": ([P, i32, ctypes.c_double, P, P, P], cint),
+        "tpcf_compile_band64_3d": ([P, i32, ctypes.c_double, P, P], cint),
         "tpcf_attach_catalog": ([P, P, i64, P], cint),
         "tpcf_catalog_order": ([P, i32, P], cint),
         "tpcf_catalog_size": ([P, i32, P], cint),
@@ -464,6 +466,15 @@ def compile_edges_3d(edges, rmax: float):
     qhi = np.empty(e.size, dtype=np.float32)
     _check(lib().tpcf_compile_edges_3d(_p(e), e.size - 1, rmax, _p(S), _p(qlo), _p(qhi)))
     return S, qlo, qhi
+
+
+def compile_band64_3d(edges, rmax: float):
+    """(lo, hi) of tpcf_compile_band64_3d."""
+    e = _f64(edges)
+    lo = np.empty(e.size, dtype=np.float64)
+    hi = np.empty(e.size, dtype=np.float64)
+    _check(lib().tpcf_compile_band64_3d(_p(e), e.size - 1, rmax, _p(lo), _p(hi)))
+    return lo, hi
 
 
 def compile_band64(edges_deg):

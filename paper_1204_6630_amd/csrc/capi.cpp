@@ -508,6 +508,13 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         c->cells = make_cells32_top(c->edges, c->band, qtop_key_3d(delta), max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
+    } else if (metric && precision == TPCF_FP64_MATRIX) {
+        const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
+        Band64 b = make_band64_3d(c->edges, delta);
+        c->cells = make_cells64_band(b, max_cells, top > 1e-300 ? top : 1e-300);
+        tlo = b.lo;
+        thi = b.hi;
+        c->thi = b.hi;
     } else if (metric) {
         const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
         c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
@@ -795,7 +802,7 @@ int ensure_pack(tpcf_ctx *ctx, Catalog &c) {
     TRY(dev_alloc(ctx->mem, (void **)&c.dpack, c.bytes_pack));
     hipError_t e = hipSuccess;
     if (c.n > 0)
-        e = (hipError_t)tpcf_launch_pack16(c.d64, c.n, c.dpack, ctx->main.stream);
+        e = (hipError_t)tpcf_launch_pack16(c.d64, c.n, c.dpack, c.metric, ctx->main.stream);
     else
         e = (hipError_t)tpcf_launch_zero_u64((unsigned long long *)c.dpack, (int64_t)(c.bytes_pack / 8), ctx->main.stream);
     if (e == hipSuccess)
@@ -873,8 +880,6 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
     r->metric = r->A->metric;
     if (r->B->metric != r->metric)
         return fail(TPCF_E_INVALID, "a sky catalog and a 3-D catalog cannot be paired");
-    if (r->metric && d.precision == TPCF_FP64_MATRIX)
-        return fail(TPCF_E_INVALID, "3-D catalogs count with TPCF_FP32_CHORD or TPCF_FP64");
     TRY(set_device(ctx));
     const double delta = delta_override >= 0 ? delta_override : std::max(r->A->band_param(), r->B->band_param());
     TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, r->metric, &r->cp));
@@ -1927,6 +1932,24 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
             out_qlo[k] = b.qlo[k];
         if (out_qhi)
             out_qhi[k] = b.qhi[k];
+    }
+    return TPCF_OK;
+}
+
+int tpcf_compile_band64_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_lo,
+                           double *out_hi) {
+    if (!out_lo || !out_hi)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    if (!(rmax >= 0.0) || rmax > 2.0 * kMaxCoord3d)
+        return fail(TPCF_E_INVALID, "rmax must be in [0, 2^51]");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges_3d(bin_edges, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    Band64 b = make_band64_3d(t, rmax);
+    for (int k = 0; k <= nbins; ++k) {
+        out_lo[k] = b.lo[k];
+        out_hi[k] = b.hi[k];
     }
     return TPCF_OK;
 }

@@ -563,9 +563,38 @@ Band64 make_band64(const EdgeTables &t, double tau) {
     return b;
 }
 
-CellTable make_cells64_band(const Band64 &b, int max_cells) {
+// 3-D matrix-core band.  The matrix cores evaluate C + sum_k A_k B_k with
+// A = (-2x_i, -2y_i, -2z_i, 1), B = (x_j, y_j, z_j, q_j) and C = q_i, where q
+// is the squared norm rounded as (x^2 + y^2) + z^2; every term and partial
+// sum is bounded by 4 R^2 (R >= every norm), so at most five roundings, in
+// any order and fused or not, leave the result within 20 U R^2 of
+// q_i + q_j - 2 a.b (U = 2^-53); each q is within 3.0001 U R^2 of the exact
+// squared norm; and the rule's r2 is within 5.0001 U (2R)^2 of the exact
+// squared distance.  Together: within 50 U R^2 < tau = 2^-47 R^2 of the rule's
+// r2, so r2_mma >= hi_k = RU(S_k + tau) gives r2 >= S_k and
+// r2_mma < lo_k = RD(S_k - tau) gives r2 < S_k (RU/RD: one double outward
+// after the rounded sum).
+Band64 make_band64_3d(const EdgeTables &t, double rmax) {
+    Band64 b;
+    b.tau = ldexp(rmax * rmax, -47) + 1e-300;
+    const int ne = (int)t.E.size();
+    b.lo.resize(ne);
+    b.hi.resize(ne);
+    for (int k = 0; k < ne; ++k) {
+        const double S = t.E[k];
+        if (S == -HUGE_VAL) {           // a zero edge: every pair is at or past it
+            b.lo[k] = b.hi[k] = -HUGE_VAL;
+            continue;
+        }
+        b.hi[k] = nextafter(S + b.tau, HUGE_VAL);
+        b.lo[k] = nextafter(S - b.tau, -HUGE_VAL);
+    }
+    return b;
+}
+
+CellTable make_cells64_band(const Band64 &b, int max_cells, double etop) {
     const int ne = (int)b.lo.size();
-    const int32_t ktop = dhi(2.0 + ldexp(1.0, -18));
+    const int32_t ktop = dhi(etop);
     double tmin = HUGE_VAL;
     for (int k = 0; k < ne; ++k) {
         if (isfinite(b.lo[k]) && b.lo[k] > 0.0)

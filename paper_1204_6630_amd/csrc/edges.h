@@ -80,7 +80,12 @@ CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta
 CellTable make_cells64(const EdgeTables &t, int max_cells, double etop = 2.0 + 1.0 / 262144.0);
 
 Band64 make_band64(const EdgeTables &t, double tau);
-// Cells over the high word of e (as make_cells64) against a Band64.
-CellTable make_cells64_band(const Band64 &b, int max_cells);
+// 3-D: band of every edge for r2 computed by the matrix cores as
+// |a|^2 + |b|^2 - 2 a.b for points of norm at most rmax: r2 >= hi_k implies
+// that the rule's r2 reaches S_k, r2 < lo_k that it does not.
+Band64 make_band64_3d(const EdgeTables &t, double rmax);
+// Cells over the high word of e (as make_cells64) against a Band64; etop as
+// for make_cells64.
+CellTable make_cells64_band(const Band64 &b, int max_cells, double etop = 2.0 + 1.0 / 262144.0);
 
 }  // namespace tpcf

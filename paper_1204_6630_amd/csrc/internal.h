@@ -158,8 +158,9 @@ int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots, 
                               unsigned long long *out, void *stream);
 int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
                          double *maxdev_out, void *stream);
-// Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack).
-int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream);
+// Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack);
+// metric 1 (3-D): component 3 holds the squared norm instead of 1.
+int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, int metric, void *stream);
 // Bounding caps of the aligned 64-point groups of an FP64 SoA catalog
 // (see JobDev::bcaps): 4 doubles per group; metric 1 (3-D): bounding balls.
 int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, int metric, void *stream);

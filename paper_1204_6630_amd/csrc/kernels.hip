@@ -814,7 +814,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int mma_row(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ __forceinline__ int mma_col(int lane) { return lane & 15; }
 
-template <bool LUT8>
+template <bool LUT8, bool M3>
 __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, double e, const Smem &s,
                                                 const PairArgs &a, const JobDev &jb, int i, int j,
                                                 uint32_t &n_exact) {
@@ -825,18 +825,18 @@ __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, dou
         if (e >= s.Thi[k])
             return (uint32_t)(k + 1);
         ++n_exact;
-        double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+        double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
         return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
     }
     ++n_exact;
-    double d = exact_dot(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+    double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
     return count_le(d, s.D, a.nedges);
 }
 
 // Bin the 16 x (RG x 16) pairs of one column group whose e = 1 - d the matrix
 // cores left in d (row group g, output register r of this lane: row
 // ib + 16 g + mma_row(lane, r), column 16 jg + mma_col(lane)).
-template <bool LUT8, bool MASKED, int RG>
+template <bool LUT8, bool MASKED, int RG, bool M3>
 __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, const Smem &s,
                                          const Consts &k, const v4d (&d)[RG], int ib, int rlo, int ie,
                                          int jg, int clo, int j1, int lane, Counters &cnt) {
@@ -889,7 +889,7 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
                     // formed on demand and do not occupy registers in the loop
                     asm volatile("" : "+v"(i));
                     const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
-                    ent[g][r] = resolve_mma<LUT8>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
+                    ent[g][r] = resolve_mma<LUT8, M3>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
                 }
     }
 #pragma unroll
@@ -914,10 +914,10 @@ __device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, co
 // other wavefronts of the SIMD keep the matrix cores busy meanwhile.  The
 // column operands are fetched two groups ahead (clamped to the last group of
 // the catalog, so the reads never leave it).
-template <bool LUT8, bool MASKED, int RG>
+template <bool LUT8, bool MASKED, int RG, bool M3>
 __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                                         const double (&A)[RG], int ib, int rlo, int ie, int j0, int clo,
-                                         int j1, int lane, Counters &cnt) {
+                                         const double (&A)[RG], const v4d (&C)[RG], int ib, int rlo, int ie,
+                                         int j0, int clo, int j1, int lane, Counters &cnt) {
     const gdouble_p bp = (gdouble_p)jb.bpack + lane;
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     const int jg0 = j0 >> 4;
@@ -932,8 +932,8 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
         v4d d[RG];
 #pragma unroll
         for (int g = 0; g < RG; ++g)
-            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, zero, 0, 0, 0);
-        bin_tile<LUT8, MASKED, RG>(a, jb, s, k, d, ib, rlo, ie, jg, clo, j1, lane, cnt);
+            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, M3 ? C[g] : zero, 0, 0, 0);
+        bin_tile<LUT8, MASKED, RG, M3>(a, jb, s, k, d, ib, rlo, ie, jg, clo, j1, lane, cnt);
     }
 }
 
@@ -942,27 +942,40 @@ __device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, co
 // 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
 // (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
 // then binned exactly as on the vector path, against the matrix-core band.
-template <bool LUT8, bool MASKED, int RG, bool PRUNE>
+template <bool LUT8, bool MASKED, int RG, bool PRUNE, bool M3>
 __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                          int ib, int rlo, int ie, int j0, int clo, int j1, int lane, Counters &cnt) {
     const gdouble_p ap = (gdouble_p)jb.apack + lane;
     double A[RG];
+    v4d C[RG];
     const int g0 = ib >> 4;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
         const double v = ap[(size_t)gg * 64];
-        A[g] = lane < 48 ? -v : v;
+        if (M3) {
+            // 3-D: A row (-2x, -2y, -2z, 1) against B column (x, y, z, |b|^2),
+            // and the accumulator starts at |a|^2 of the output's row: the
+            // product is |a|^2 + |b|^2 - 2 a.b
+            A[g] = lane < 48 ? -2.0 * v : 1.0;
+            const gdouble_p q = (gdouble_p)jb.apack + (size_t)gg * 64 + 48 + mma_row(lane, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                C[g][r] = q[4 * r];
+        } else {
+            A[g] = lane < 48 ? -v : v;
+            C[g] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
     }
     if (PRUNE && !MASKED && jb.bcaps) {
         // unmasked: rows [ib, ib + 16 RG) are all valid; lane l takes one
         const int i = ib + lane % (16 * RG);
         const double xr[1] = {jb.ax64[i]}, yr[1] = {jb.ay64[i]}, zr[1] = {jb.az64[i]};
-        const Cap rc = cap_of<1>(xr, yr, zr);
+        const Cap rc = block_cap<M3, 1>(xr, yr, zr);
         for (int j = j0; j < j1;) {
             const int jn = min(j1, (j & ~63) + 64);
             if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = prune_slot(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a.nedges);
+                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
                 if (slot >= 0) {
                     bin_block(slot, 16 * RG, a, k, cnt);
                     cnt.pruned += (unsigned long long)16 * RG * 64;
@@ -970,22 +983,23 @@ __device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, con
                     continue;
                 }
             }
-            cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j, j, jn, lane, cnt);
+            cols_mma<LUT8, MASKED, RG, M3>(a, jb, s, k, A, C, ib, rlo, ie, j, j, jn, lane, cnt);
             j = jn;
         }
         return;
     }
-    cols_mma<LUT8, MASKED, RG>(a, jb, s, k, A, ib, rlo, ie, j0, clo, j1, lane, cnt);
+    cols_mma<LUT8, MASKED, RG, M3>(a, jb, s, k, A, C, ib, rlo, ie, j0, clo, j1, lane, cnt);
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
 // table, 1 FP64 vector, 2 FP64 matrix cores; 3-D distances: 5 FP32 squared
-// distance with a clamped table, 4 FP64 vector.  P: rows per lane of the vector
+// distance with a clamped table, 4 FP64 vector, 8 FP64 matrix cores.  P: rows per lane of the vector
 // paths (a wavefront covers P * 64 rows of a unit) or row groups of 16 of the
 // matrix-core path (P * 16 rows).
 template <int PREC, bool LUT8, int P, bool PRUNE>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
-    constexpr int kRowsPerWave = PREC == 2 ? P * 16 : P * kWaveSize;
+    constexpr bool MMA = PREC == 2 || PREC == 8;
+    constexpr int kRowsPerWave = MMA ? P * 16 : P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
     const int tid = threadIdx.x;
@@ -1052,12 +1066,13 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             // every unit at its first valid column)
             bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib ||
                           un.col_lo > un.j0;
-            if (PREC == 2) {
+            if (MMA) {
                 masked = masked || (un.j1 & 15) != 0;
                 if (masked)
-                    rows_mma<LUT8, true, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane, cnt);
+                    rows_mma<LUT8, true, P, PRUNE, PREC == 8>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
+                                                              cnt);
                 else
-                    rows_mma<LUT8, false, P, PRUNE>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
+                    rows_mma<LUT8, false, P, PRUNE, PREC == 8>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
                                                     cnt);
             } else if (PREC == 0 || PREC == 3 || PREC == 5) {
                 constexpr bool M3 = PREC == 5;
@@ -1162,7 +1177,7 @@ __global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsign
 
 // Matrix-core operand pack: pack[64 g + l] = component l / 16 of point
 // 16 g + l % 16 (component 3 is 1), zero past the end of the catalog.
-__global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_t total) {
+__global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_t total, int metric) {
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t g = idx >> 6;
@@ -1170,8 +1185,20 @@ __global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_
         const int64_t p = 16 * g + (l & 15);
         const int c = l >> 4;
         double v = 0.0;
-        if (p < n)
-            v = c < 3 ? xyz[(int64_t)c * n + p] : 1.0;
+        if (p < n) {
+            if (c < 3) {
+                v = xyz[(int64_t)c * n + p];
+            } else if (metric) {
+                // 3-D: the squared norm, (x^2 + y^2) + z^2 rounded per operation
+                const double x = xyz[p], y = xyz[n + p], z = xyz[2 * n + p];
+                const double t = x * x;
+                const double u = y * y;
+                const double w = z * z;
+                v = (t + u) + w;
+            } else {
+                v = 1.0;
+            }
+        }
         pack[idx] = v;
     }
 }
@@ -1265,6 +1292,10 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
             launch_pairs<4, true>(P, prune, grid, lds, st, *args);
         else if (precision == 1)
             launch_pairs<4, false>(P, prune, grid, lds, st, *args);
+        else if (precision == 2 && b8)
+            launch_pairs<8, true>(P, prune, grid, lds, st, *args);
+        else if (precision == 2)
+            launch_pairs<8, false>(P, prune, grid, lds, st, *args);
         else
             return (int)hipErrorInvalidValue;
         return (int)hipGetLastError();
@@ -1292,7 +1323,7 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
     return (int)hipGetLastError();
 }
 
-extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, void *stream) {
+extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, int metric, void *stream) {
     const int64_t total = ((n + 15) / 16) * 64;
     if (total <= 0)
         return 0;
@@ -1300,7 +1331,7 @@ extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, 
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(pack16_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
-                       pack, total);
+                       pack, total, metric);
     return (int)hipGetLastError();
 }
 

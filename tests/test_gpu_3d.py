@@ -6,7 +6,7 @@ function xi(r)).  Counts are integers: bit-exact equality with the oracle's
 fall exactly on edges (ties re-decided with the exact rule), clustered boxes
 in full, ragged sizes around the tile sizes, row ranges, coordinates far
 from the origin (a wide FP32 band), batches and jobs; at the full box size
-(1e6 x 2e6) FP32 equals FP64 and sampled row blocks equal the oracle.
+(1e6 x 2e6) the three precisions agree and sampled row blocks equal the oracle.
 """
 
 import numpy as np
@@ -18,7 +18,7 @@ import synthcat
 
 pytestmark = pytest.mark.gpu
 
-PRECS3 = [tp.FP32_CHORD, tp.FP64]
+PRECS3 = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
 _cache = {}
 
 
@@ -148,8 +148,6 @@ def test_3d_errors(ctx, box):
     wl, cd, cr, _ = box
     sky = ctx.upload_catalog(np.array([1.0, 2.0]), np.array([3.0, 4.0]))
     try:
-        with pytest.raises(tp.TpcfError):      # no matrix-core path in 3-D
-            ctx.count(tp.DD, cd, wl.edges, precision=tp.FP64_MATRIX)
         with pytest.raises(tp.TpcfError):      # a sky catalog against a 3-D one
             ctx.count(tp.DR, cd, wl.edges, cat_b=sky)
         with pytest.raises(tp.TpcfError):      # mixed batch
@@ -183,7 +181,8 @@ def test_full_box_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx):
         for kind, a, b in ((tp.DD, cd, -1), (tp.DR, cd, cr), (tp.RR, cr, -1)):
             f32 = ctx.count(kind, a, wl.edges, cat_b=b, precision=tp.FP32_CHORD)
             f64 = ctx.count(kind, a, wl.edges, cat_b=b, precision=tp.FP64)
-            assert np.array_equal(f32, f64)
+            mma = ctx.count(kind, a, wl.edges, cat_b=b, precision=tp.FP64_MATRIX)
+            assert np.array_equal(f32, f64) and np.array_equal(f32, mma)
         order = ctx.catalog_order(cd)
         xs = tuple(c[order] for c in wl.data.xyz())
         for r0, r1 in _sample_blocks(wl.data.n, 2, 192, 5):

@@ -61,7 +61,7 @@ def test_bin_counts_up_to_the_maximum(ctx, sphere, prec, nbins):
     assert np.array_equal(ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec), _ref[(nbins, "DR")])
 
 
-@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64])
+@pytest.mark.parametrize("prec", PRECS)
 def test_3d_with_256_bins(ctx, prec):
     g = synthcat.rng_for(97, 1)
     a = synthcat.box_clustered(3000, 60, 3.0, 200.0, g)

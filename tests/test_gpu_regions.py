@@ -202,11 +202,11 @@ def test_full_octant_deleted_region_equals_reduced_catalog_counts(ctx):
         ctx.release_catalog(cr)
 
 
-@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64])
+@pytest.mark.parametrize("prec", PRECS)
 def test_3d_regions_and_jackknife(ctx, prec):
     """3-D catalogs (a clustered box and uniform randoms) cut into 3 x 3 x 1
-    slabs: totals and touch rows bit-exact against the oracle, the matrix
-    path refused, and the jackknife of xi(r) equal to the oracle's recount."""
+    slabs: totals and touch rows bit-exact against the oracle for every
+    precision, and the jackknife of xi(r) equal to the oracle's recount."""
     g = synthcat.rng_for(98, 0)
     a = synthcat.box_clustered(2500, 60, 2.0, 120.0, g)
     b = synthcat.box_uniform(3000, 120.0, g)
@@ -232,8 +232,6 @@ def test_3d_regions_and_jackknife(ctx, prec):
         _check(dd, ref_dd)
         _check(dr, ref_dr)
         _check(rr, ref_rr)
-        with pytest.raises(tp.TpcfError):
-            ctx.count_regions(tp.DD, ca, e, precision=tp.FP64_MATRIX)
         s, m, c = tp.jackknife(dd[0], dd[1], dr[0], dr[1], rr[0], rr[1], a.n, ctx.catalog_regions(ca),
                                b.n, ctx.catalog_regions(cb))
         so, mo, co = _cached("3d_jk", lambda: oracle.jackknife(a.xyz(), la, b.xyz(), lb, e, nreg, metric=1))

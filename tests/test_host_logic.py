@@ -455,3 +455,37 @@ def test_3d_fp32_band_adversary(rmax):
     half = 2.0 ** -23 * rmax / edges[edge_of] + 4e-7
     assert not np.any(in_band & (rel > 3.0 * half))
     assert np.all(in_band[rel < 0.1 * half])
+
+
+@pytest.mark.parametrize("rmax", [1.0, 1000.0, 3.0e5])
+def test_3d_matrix_band_is_safe_for_any_rounding(rmax):
+    """The matrix cores' r2 = |a|^2 + |b|^2 - 2 a.b lies within 50 U R^2 of the
+    rule's r2 (the derivation beside make_band64_3d): values perturbed by up
+    to that much, and the products summed in other orders, never cross a band
+    the wrong way; the band is no wider than 2^-46 R^2 plus an ulp."""
+    g = np.random.default_rng(17)
+    edges = synthcat.log_edges(1e-3 * rmax, 0.3 * rmax, 24)
+    S, _, _ = tp.compile_edges_3d(edges, rmax=rmax)
+    lo, hi = tp.compile_band64_3d(edges, rmax=rmax)
+    rs, ks = [], []
+    for k, e in enumerate(edges):
+        for s_ in range(3, 16):
+            for sign in (-1.0, 1.0):
+                rs.append(np.full(40, e * (1.0 + sign * 10.0 ** -s_)))
+    r = np.concatenate(rs)
+    a, b = _pairs_at_distance(g, r, rmax)
+    d = a - b
+    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    qa = (a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1]) + a[:, 2] * a[:, 2]
+    qb = (b[:, 0] * b[:, 0] + b[:, 1] * b[:, 1]) + b[:, 2] * b[:, 2]
+    dot = (a * b).sum(axis=1)
+    forms = [qa + qb - 2.0 * dot,
+             (qb - 2.0 * (a[:, 2] * b[:, 2])) + (qa - 2.0 * (a[:, 0] * b[:, 0] + a[:, 1] * b[:, 1]))]
+    U = 2.0 ** -53
+    for e2 in forms + [r2 + g.uniform(-48.0, 48.0, size=r2.size) * U * rmax * rmax]:
+        assert np.all(np.abs(e2 - r2) <= 50.0 * U * rmax * rmax)
+        for k in range(edges.size):
+            past = r2 >= S[k]
+            assert np.all(past[e2 >= hi[k]]), k
+            assert not np.any(past[e2 < lo[k]]), k
+    assert np.all(hi - lo <= 2.0 ** -46 * rmax * rmax * 1.01 + 4 * np.spacing(hi))
