@@ -147,7 +147,7 @@ def bench_batched(args, tp, torch):
     Timed: the whole batch as one hipGraph-replayed launch, and beside it the
     same jobs as 129 separate launches."""
     import synthcat
-    wl = synthcat.config4(scale=args.scale)
+    wl = synthcat.batched_64(scale=args.scale)
     e = wl.edges_deg
     ctx = tp.Context(0)
     cats = [ctx.upload_catalog(c.ra, c.dec) for c in wl.data]
@@ -212,14 +212,14 @@ def bench_serving(args, tp):
     e = synthcat.log_edges(0.001, 20.0, 30)
     ctx = tp.Context(0)
     n_random = int(round(2_000_000 * args.scale))
-    rnd = [ctx.upload_catalog(c.ra, c.dec) for c in synthcat.config5_randoms(n_random)]
-    spec = synthcat.config5_jobs(n_jobs=args.jobs, size_hi=int(1_000_000 * args.scale))
+    rnd = [ctx.upload_catalog(c.ra, c.dec) for c in synthcat.serving_randoms(n_random)]
+    spec = synthcat.serving_jobs(n_jobs=args.jobs, size_hi=int(1_000_000 * args.scale))
     print(f"# serving: generating {len(spec)} job catalogs", file=sys.stderr, flush=True)
     jobs = []
     for s in spec:
         j = Job(id=s["id"], kind=s["kind"], arrival=0.0, random=s["random"])
         if s["kind"] != "RR":
-            c = synthcat.config5_catalog(s)
+            c = synthcat.serving_catalog(s)
             j.ra, j.dec, j.n = c.ra, c.dec, c.n
         jobs.append(j)
     # sustained rate: one DR of a 1e5 catalog against a resident random
@@ -258,7 +258,7 @@ def bench_serving(args, tp):
         "steps": 1, "warmup": 0, "ms_per_step": round(rep.makespan * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "config5_serving", "jobs": len(jobs), "n_random": n_random,
+        "config": {"workload": "serving_stream", "jobs": len(jobs), "n_random": n_random,
                    "randoms": 3, "nbins": int(e.size - 1), "arrival_rate_per_s": round(lam, 3),
                    "hbm_budget_bytes": 1 << 30, "parallelism": "single-gpu"},
         "latency_ms": {"p50": round(rep.percentile(50) * 1e3, 2),
@@ -272,7 +272,7 @@ def bench_serving(args, tp):
 def main():
     args = parse()
     if args.gpus != 1:
-        sys.exit("bench.py runs on one GPU only: this build has no multi-GPU path "
+        sys.exit("bench.py runs on one GPU only: the library has no multi-GPU path "
                  f"(asked for --gpus {args.gpus})")
     import torch
     import paper_1204_6630_amd as tp
@@ -294,7 +294,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = synthcat.config3(scale=args.scale)
+    wl = synthcat.octant_1e6x2e6(scale=args.scale)
     d, r = wl.data[0], wl.randoms[0]
     nd, nr = d.n, r.n
     edges = wl.edges_deg
@@ -486,7 +486,7 @@ def main():
     if not args.no_3d:
         # the 3-D variant xi(r): same kernels keyed on squared distances; one
         # step = DD + DR + RR + Landy-Szalay on a 1e6 x 2e6 box workload
-        w3 = synthcat.config3d(scale=args.scale)
+        w3 = synthcat.box_1e6x2e6(scale=args.scale)
         b_d = ctx.upload_catalog_3d(*w3.data.xyz())
         b_r = ctx.upload_catalog_3d(*w3.randoms.xyz())
         n3d, n3r = w3.data.n, w3.randoms.n

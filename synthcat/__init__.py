@@ -11,7 +11,7 @@ available here.  The recipes below stand in for them: uniform random catalogs
 over a patch of the sky, and clustered "data" catalogs made of Gaussian blobs
 around uniformly drawn centres, optionally mixed with an unclustered
 background.  Every generator takes a ``numpy.random.Generator`` (PCG64) so a
-(config, stream) seed reproduces the same catalog bit for bit.
+(family, stream) seed reproduces the same catalog bit for bit.
 """
 
 from __future__ import annotations
@@ -29,9 +29,11 @@ PATCH_30 = (0.0, 30.0, 0.0, 30.0)
 OCTANT = (0.0, 90.0, 0.0, 90.0)
 
 
-def rng_for(config: int, stream: int) -> np.random.Generator:
-    """PCG64 generator for one (config, stream) pair."""
-    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * config + stream))
+def rng_for(family: int, stream: int) -> np.random.Generator:
+    """PCG64 generator for one (workload family, stream) pair.  Families are
+    small integers, one per workload below (1 patch, 2 and 3 octant, 4
+    batched, 5 serving, 30 box); tests draw from families of their own."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * family + stream))
 
 
 def log_edges(lo_deg: float, hi_deg: float, nbins: int) -> np.ndarray:
@@ -138,28 +140,28 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
 
-def config1(scale: float = 1.0) -> Workload:
+def patch30_1e4(scale: float = 1.0) -> Workload:
     """Small plain case: 1e4 clustered points (200 centres, sigma 0.5 deg) and
     1e4 uniform randoms on a 30x30 deg patch; 20 log bins over [0.01, 10] deg."""
     n = max(2, int(round(10_000 * scale)))
     g = rng_for(1, 0)
     d = clustered(n, 200, 0.5, PATCH_30, g)
     r = uniform_patch(n, PATCH_30, rng_for(1, 1))
-    return Workload("config1_patch30_1e4", [Catalog(*d)], [Catalog(*r)],
+    return Workload("patch30_1e4", [Catalog(*d)], [Catalog(*r)],
                     log_edges(0.01, 10.0, 20))
 
 
-def config2(scale: float = 1.0) -> Workload:
+def octant_1e5(scale: float = 1.0) -> Workload:
     """1e5 clustered points (2000 centres, sigma 0.3 deg) and 1e5 uniform
     randoms over the octant; 30 log bins over [0.001, 20] deg."""
     n = max(2, int(round(100_000 * scale)))
     d = clustered(n, 2000, 0.3, OCTANT, rng_for(2, 0))
     r = uniform_patch(n, OCTANT, rng_for(2, 1))
-    return Workload("config2_octant_1e5", [Catalog(*d)], [Catalog(*r)],
+    return Workload("octant_1e5", [Catalog(*d)], [Catalog(*r)],
                     log_edges(0.001, 20.0, 30))
 
 
-def config3(scale: float = 1.0) -> Workload:
+def octant_1e6x2e6(scale: float = 1.0) -> Workload:
     """1e6 data points (70% in blobs around 20000 centres with sigma 0.2 deg,
     30% uniform background) and 2e6 uniform randoms over the octant; 40 log
     bins over [0.0005, 30] deg."""
@@ -173,11 +175,11 @@ def config3(scale: float = 1.0) -> Workload:
     dec = np.concatenate([a[1], b[1]])
     perm = g.permutation(nd)
     r = uniform_patch(nr, OCTANT, rng_for(3, 1))
-    return Workload("config3_octant_1e6x2e6", [Catalog(ra[perm], dec[perm])],
+    return Workload("octant_1e6x2e6", [Catalog(ra[perm], dec[perm])],
                     [Catalog(*r)], log_edges(0.0005, 30.0, 40))
 
 
-def config4(n_catalogs: int = 64, scale: float = 1.0) -> Workload:
+def batched_64(n_catalogs: int = 64, scale: float = 1.0) -> Workload:
     """64 data catalogs of log-uniform size in [5e3, 5e5], clustered (50 points
     per centre, sigma 0.3 deg) inside a random 20x20 deg sub-patch of the
     octant each, against one 1e6-point uniform octant random catalog; 30 log
@@ -193,18 +195,18 @@ def config4(n_catalogs: int = 64, scale: float = 1.0) -> Workload:
         data.append(Catalog(*clustered(n, max(1, n // 50), 0.3, fp, g)))
     nr = max(2, int(round(1_000_000 * scale)))
     r = uniform_patch(nr, OCTANT, rng_for(4, 1))
-    return Workload("config4_batched_64", data, [Catalog(*r)],
+    return Workload("batched_64", data, [Catalog(*r)],
                     log_edges(0.001, 20.0, 30))
 
 
-def config5_jobs(n_jobs: int = 2000, size_lo: int = 1000, size_hi: int = 1_000_000,
+def serving_jobs(n_jobs: int = 2000, size_lo: int = 1000, size_hi: int = 1_000_000,
                  seed_stream: int = 0):
     """Job stream for the serving case: kinds DD/DR/RR with mix 40/40/20,
     catalog sizes log-uniform in [size_lo, size_hi], clustered (50 points per
     centre, sigma 0.3 deg) or uniform over the octant with probability 1/2
     each; DR and RR jobs name one of three resident random catalogs.
     Returns a list of dicts; catalogs are generated lazily by
-    :func:`config5_catalog`."""
+    :func:`serving_catalog`."""
     g = rng_for(5, seed_stream)
     jobs = []
     for j in range(n_jobs):
@@ -218,14 +220,14 @@ def config5_jobs(n_jobs: int = 2000, size_lo: int = 1000, size_hi: int = 1_000_0
     return jobs
 
 
-def config5_catalog(job) -> Catalog:
+def serving_catalog(job) -> Catalog:
     g = np.random.Generator(np.random.PCG64(job["seed"]))
     if job["clustered"]:
         return Catalog(*clustered(job["n"], max(1, job["n"] // 50), 0.3, OCTANT, g))
     return Catalog(*uniform_patch(job["n"], OCTANT, g))
 
 
-def config5_randoms(n: int = 2_000_000):
+def serving_randoms(n: int = 2_000_000):
     return [Catalog(*uniform_patch(n, OCTANT, rng_for(5, 100 + r))) for r in range(3)]
 
 
@@ -276,8 +278,8 @@ class Workload3d:
     edges: np.ndarray
 
 
-def config3d(scale: float = 1.0, side: float = 1000.0) -> Workload3d:
-    """3-D analogue of config 3: 1e6 data points (70% in blobs around 20000
+def box_1e6x2e6(scale: float = 1.0, side: float = 1000.0) -> Workload3d:
+    """3-D analogue of the 1e6 x 2e6 octant workload: 1e6 data points (70% in blobs around 20000
     centres with per-axis sigma 2, 30% uniform) and 2e6 uniform randoms in a
     box of side 1000 (Mpc/h); 30 log bins over [0.5, 150]."""
     nd = max(2, int(round(1_000_000 * scale)))
@@ -292,4 +294,5 @@ def config3d(scale: float = 1.0, side: float = 1000.0) -> Workload3d:
     return Workload3d(f"box{int(side)}_{nd:.0e}x{nr:.0e}".replace("+0", ""), d, r, log_edges(0.5, 150.0, 30))
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+WORKLOADS = {"patch30_1e4": patch30_1e4, "octant_1e5": octant_1e5,
+             "octant_1e6x2e6": octant_1e6x2e6, "batched_64": batched_64}

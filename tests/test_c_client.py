@@ -40,7 +40,7 @@ def test_c_client_compiles_and_links(tmp_path):
 @pytest.mark.gpu
 def test_c_client_counts_equal_the_oracle(tmp_path):
     exe = _build(tmp_path)
-    wl = synthcat.config1(scale=0.1)
+    wl = synthcat.patch30_1e4(scale=0.1)
     d = wl.data[0]
     e = wl.edges_deg
     lines = ([str(d.n)] + [f"{float(a)!r} {float(b)!r}" for a, b in zip(d.ra, d.dec)] + [str(e.size - 1)]

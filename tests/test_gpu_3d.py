@@ -60,7 +60,7 @@ def test_lattice_ties_on_edges(ctx, prec, offset):
 
 @pytest.fixture(scope="module")
 def box(ctx):
-    wl = synthcat.config3d(scale=0.01)          # 1e4 data, 2e4 randoms, box 1000
+    wl = synthcat.box_1e6x2e6(scale=0.01)          # 1e4 data, 2e4 randoms, box 1000
     cd = ctx.upload_catalog_3d(*wl.data.xyz())
     cr = ctx.upload_catalog_3d(*wl.randoms.xyz())
     ref = _cached("box", lambda: {
@@ -174,7 +174,7 @@ def _sample_blocks(n, nblocks, size, seed):
 def test_full_box_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx):
     """1e6 data x 2e6 randoms in a box of side 1000: DD, DR, RR agree between
     the precisions; sampled stored row blocks agree with the oracle."""
-    wl = synthcat.config3d()
+    wl = synthcat.box_1e6x2e6()
     cd = ctx.upload_catalog_3d(*wl.data.xyz())
     cr = ctx.upload_catalog_3d(*wl.randoms.xyz())
     try:
@@ -226,7 +226,7 @@ def test_3d_pruning_keeps_counts_exact(ctx, box, prec):
 
 
 def test_3d_pruning_at_full_size_equals_brute_force(ctx):
-    wl = synthcat.config3d()
+    wl = synthcat.box_1e6x2e6()
     cd = ctx.upload_catalog_3d(*wl.data.xyz())
     cr = ctx.upload_catalog_3d(*wl.randoms.xyz())
     try:

@@ -32,7 +32,7 @@ def ctx():
 def small_batch(ctx):
     """Eight catalogs of uneven size in 20 x 20 deg sub-patches (the batched
     workload's recipe, scaled down) and one uniform random catalog."""
-    wl = synthcat.config4(n_catalogs=8, scale=0.02)
+    wl = synthcat.batched_64(n_catalogs=8, scale=0.02)
     cats = [ctx.upload_catalog(c.ra, c.dec) for c in wl.data]
     r = wl.randoms[0]
     cr = ctx.upload_catalog(r.ra, r.dec)

@@ -39,8 +39,8 @@ def _stored(ctx, cid, xyz):
     return tuple(c[order] for c in xyz)
 
 
-def test_config4_full_batch(ctx):
-    wl = synthcat.config4()
+def test_batched_64_full_batch(ctx):
+    wl = synthcat.batched_64()
     e = wl.edges_deg
     cats = [ctx.upload_catalog(c.ra, c.dec) for c in wl.data]
     r = wl.randoms[0]
@@ -71,14 +71,14 @@ def test_config4_full_batch(ctx):
         ctx.release_catalog(cr)
 
 
-def test_config5_jobs_at_full_size(ctx):
+def test_serving_jobs_at_full_size(ctx):
     e = synthcat.log_edges(0.001, 20.0, 30)
-    randoms = synthcat.config5_randoms()
+    randoms = synthcat.serving_randoms()
     rids = [ctx.upload_catalog(c.ra, c.dec) for c in randoms]
-    jobs = synthcat.config5_jobs(n_jobs=6)
+    jobs = synthcat.serving_jobs(n_jobs=6)
     try:
         for job in jobs:
-            cat = randoms[job["random"]] if job["kind"] == "RR" else synthcat.config5_catalog(job)
+            cat = randoms[job["random"]] if job["kind"] == "RR" else synthcat.serving_catalog(job)
             cid = rids[job["random"]] if job["kind"] == "RR" else ctx.upload_catalog(cat.ra, cat.dec)
             kind = {"DD": tp.DD, "DR": tp.DR, "RR": tp.RR}[job["kind"]]
             other = rids[job["random"]] if kind == tp.DR else -1

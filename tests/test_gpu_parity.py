@@ -35,7 +35,7 @@ def _xyz(cat):
 
 def _workload(cfg):
     if cfg not in _cache:
-        _cache[cfg] = synthcat.CONFIGS[cfg]()
+        _cache[cfg] = synthcat.WORKLOADS[cfg]()
     return _cache[cfg]
 
 
@@ -52,8 +52,8 @@ def _oracle(key, fn):
 
 
 @pytest.fixture(scope="module")
-def cfg1(ctx):
-    wl = _workload(1)
+def patch(ctx):
+    wl = _workload("patch30_1e4")
     d, r = wl.data[0], wl.randoms[0]
     cd = ctx.upload_catalog(d.ra, d.dec)
     cr = ctx.upload_catalog(r.ra, r.dec)
@@ -67,8 +67,8 @@ def cfg1(ctx):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_config1_full_bit_exact(ctx, cfg1, prec):
-    wl, cd, cr, ref = cfg1
+def test_patch_full_bit_exact(ctx, patch, prec):
+    wl, cd, cr, ref = patch
     dd = ctx.count(tp.DD, cd, wl.edges_deg, precision=prec)
     dr = ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=prec)
     rr = ctx.count(tp.RR, cr, wl.edges_deg, precision=prec)
@@ -104,8 +104,8 @@ def test_ragged_sizes_and_tails(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_row_ranges(ctx, cfg1, prec):
-    wl, cd, cr, _ = cfg1
+def test_row_ranges(ctx, patch, prec):
+    wl, cd, cr, _ = patch
     xd = _stored(ctx, cd, _xyz(wl.data[0]))
     xr = _xyz(wl.randoms[0])
     n = wl.data[0].n
@@ -181,7 +181,7 @@ def _sample_blocks(n, nblocks, size, seed):
     return [(int(s), int(min(n, s + size))) for s in starts]
 
 
-@pytest.mark.parametrize("cfg", [2, 3])
+@pytest.mark.parametrize("cfg", ["octant_1e5", "octant_1e6x2e6"])
 def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
     wl = _workload(cfg)
     d, r = wl.data[0], wl.randoms[0]
@@ -208,8 +208,8 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
     for a, b in zip(full[PRECS[0]], pruned):
         assert np.array_equal(a, b)
     xd, xr = _stored(ctx, cd, _xyz(d)), _stored(ctx, cr, _xyz(r))
-    size = 200 if cfg == 2 else 150
-    for rb, re in _sample_blocks(d.n, 2, size, 11 + cfg):
+    size = 200 if cfg == "octant_1e5" else 150
+    for rb, re in _sample_blocks(d.n, 2, size, 11 + len(cfg)):
         for prec in PRECS:
             got = ctx.count(tp.DD, cd, e, precision=prec, row_begin=rb, row_end=re)
             ref = _oracle(("DD", cfg, rb), lambda: oracle.count(oracle.DD, xd, e, row_begin=rb, row_end=re))
@@ -217,7 +217,7 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
             got = ctx.count(tp.DR, cd, e, cat_b=cr, precision=prec, row_begin=rb, row_end=re)
             ref = _oracle(("DR", cfg, rb), lambda: oracle.count(oracle.DR, xd, e, b_xyz=xr, row_begin=rb, row_end=re))
             assert np.array_equal(got, ref), ("DR", prec, rb)
-    for rb, re in _sample_blocks(r.n, 1, size, 21 + cfg):
+    for rb, re in _sample_blocks(r.n, 1, size, 21 + len(cfg)):
         for prec in PRECS:
             got = ctx.count(tp.RR, cr, e, precision=prec, row_begin=rb, row_end=re)
             ref = _oracle(("RR", cfg, rb), lambda: oracle.count(oracle.RR, xr, e, row_begin=rb, row_end=re))
@@ -226,9 +226,9 @@ def test_full_size_fp32_equals_fp64_and_sampled_rows_equal_oracle(ctx, cfg):
     ctx.release_catalog(cr)
 
 
-def test_union_invariant_on_gpu(ctx, cfg1):
+def test_union_invariant_on_gpu(ctx, patch):
     """DD(A u B) = DD(A) + DD(B) + DR(A, B) and DR(A, B) = DR(B, A)."""
-    wl, cd, cr, _ = cfg1
+    wl, cd, cr, _ = patch
     d, r = wl.data[0], wl.randoms[0]
     cu = ctx.upload_catalog(np.concatenate([d.ra, r.ra]), np.concatenate([d.dec, r.dec]))
     e = wl.edges_deg
@@ -242,9 +242,9 @@ def test_union_invariant_on_gpu(ctx, cfg1):
     ctx.release_catalog(cu)
 
 
-def test_attach_torch_tensor_and_async(ctx, cfg1):
+def test_attach_torch_tensor_and_async(ctx, patch):
     import torch
-    wl, cd, cr, ref = cfg1
+    wl, cd, cr, ref = patch
     x = np.stack(_xyz(wl.data[0]))
     t = torch.from_numpy(x).to("cuda:0").contiguous()
     ca = ctx.attach_catalog(t)
@@ -260,8 +260,8 @@ def test_attach_torch_tensor_and_async(ctx, cfg1):
     del t
 
 
-def test_timing_and_stats(ctx, cfg1):
-    wl, cd, cr, _ = cfg1
+def test_timing_and_stats(ctx, patch):
+    wl, cd, cr, _ = patch
     ctx.stats(reset=True)
     ctx.kernel_time(reset=True)
     ctx.set_timing(True)
@@ -281,10 +281,10 @@ def test_timing_and_stats(ctx, cfg1):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_pruning_keeps_counts_exact(ctx, cfg1, prec):
-    """Exact tile pruning on config 1: the same counts as the oracle, with
+def test_pruning_keeps_counts_exact(ctx, patch, prec):
+    """Exact tile pruning on the 30 x 30 deg patch: the same counts as the oracle, with
     some blocks binned whole, including row ranges (unaligned row tiles)."""
-    wl, cd, cr, ref = cfg1
+    wl, cd, cr, ref = patch
     e = wl.edges_deg
     try:
         ctx.set_tuning(prune=1)
@@ -337,14 +337,14 @@ def test_dense_patch_wide_bins_takes_every_branch(ctx, prec):
     ctx.release_catalog(cr)
 
 
-def test_repeatable(ctx, cfg1):
-    wl, cd, cr, _ = cfg1
+def test_repeatable(ctx, patch):
+    wl, cd, cr, _ = patch
     a = [ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD) for _ in range(3)]
     assert all(np.array_equal(a[0], x) for x in a[1:])
 
 
-def test_gpu_error_paths(ctx, cfg1):
-    wl, cd, cr, _ = cfg1
+def test_gpu_error_paths(ctx, patch):
+    wl, cd, cr, _ = patch
     e = wl.edges_deg
     with pytest.raises(tp.TpcfError) as ei:
         ctx.count(tp.DD, 9999, e)
@@ -377,10 +377,10 @@ def test_gpu_error_paths(ctx, cfg1):
     assert ctx.get_tuning() == {k: 0 for k in ctx.get_tuning()}
 
 
-def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
+def test_counts_do_not_depend_on_launch_shape(ctx, patch):
     """Race detector: every tuning choice (rows per lane, histogram copies,
     unit width, grid size, table layout and size) gives bit-identical counts."""
-    wl, cd, cr, ref = cfg1
+    wl, cd, cr, ref = patch
     e = wl.edges_deg
     try:
         for rpl in (2, 4):
@@ -397,10 +397,10 @@ def test_counts_do_not_depend_on_launch_shape(ctx, cfg1):
         ctx.set_tuning()
 
 
-def test_autotuner_picks_a_candidate(ctx, cfg1, tmp_path, monkeypatch):
+def test_autotuner_picks_a_candidate(ctx, patch, tmp_path, monkeypatch):
     from paper_1204_6630_amd.autotune import CANDIDATES, autotune
     monkeypatch.setenv("TPCF_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
-    wl, cd, cr, ref = cfg1
+    wl, cd, cr, ref = patch
     try:
         res = autotune(ctx, [(tp.DR, cd, cr, 0, 2048)], wl.edges_deg, tp.FP32_CHORD)
         assert not res["cached"]

@@ -37,8 +37,8 @@ def _cached(key, fn):
 
 @pytest.fixture(scope="module")
 def grid_case(ctx):
-    """config1's catalogs (1e4 + 1e4 on a 30x30 deg patch), 4 x 3 regions."""
-    wl = synthcat.CONFIGS[1]()
+    """patch30_1e4's catalogs (1e4 + 1e4 on a 30x30 deg patch), 4 x 3 regions."""
+    wl = synthcat.patch30_1e4()
     d, r = wl.data[0], wl.randoms[0]
     fp = synthcat.PATCH_30
     nreg = 12
@@ -170,7 +170,7 @@ def test_full_octant_deleted_region_equals_reduced_catalog_counts(ctx):
     """1e6 data x 2e6 randoms over the octant, 8 x 8 regions: for two regions,
     total - touch[r] equals the plain count of the catalogs without region r
     (the plain path is itself checked against the oracle)."""
-    wl = synthcat.CONFIGS[3]()
+    wl = synthcat.octant_1e6x2e6()
     d, r = wl.data[0], wl.randoms[0]
     fp = synthcat.OCTANT
     nreg = 64

@@ -209,9 +209,10 @@ def _emulate(a, b, edges, precision, delta, direct=None):
 
 @pytest.mark.parametrize("precision,direct", [(tp.FP32_CHORD, True), (tp.FP32_CHORD, False),
                                               (tp.FP64, False)])
-@pytest.mark.parametrize("cfg", [1, 2, 3])
-def test_emulated_classification_matches_oracle(cfg, precision, direct):
-    wl = synthcat.CONFIGS[cfg](scale={1: 0.06, 2: 0.006, 3: 0.0006}[cfg])
+@pytest.mark.parametrize("cfg,scale", [("patch30_1e4", 0.06), ("octant_1e5", 0.006),
+                                       ("octant_1e6x2e6", 0.0006)])
+def test_emulated_classification_matches_oracle(cfg, scale, precision, direct):
+    wl = synthcat.WORKLOADS[cfg](scale=scale)
     d = wl.data[0]
     r = wl.randoms[0]
     xa = np.stack(oracle.radec_to_xyz(d.ra, d.dec), axis=1)

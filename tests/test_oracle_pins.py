@@ -105,11 +105,11 @@ def _near_edge(theta, edges_rad, rel=1e-9):
     return np.any(d <= rel * edges_rad[None, :] + 1e-12, axis=-1)
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_histogram_matches_independent_binning(cfg):
+@pytest.mark.parametrize("cfg,scale", [("patch30_1e4", 0.015), ("octant_1e5", 0.0015)])
+def test_histogram_matches_independent_binning(cfg, scale):
     """Per-pair slots and whole histograms against scipy chord distances
     binned with numpy.searchsorted (side='right': theta == e_k goes up)."""
-    wl = synthcat.CONFIGS[cfg](scale=0.015 if cfg == 1 else 0.0015)
+    wl = synthcat.WORKLOADS[cfg](scale=scale)
     d = wl.data[0]
     edges = wl.edges_deg
     er = edges * DEG
