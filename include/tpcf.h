@@ -278,11 +278,17 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * blocks_per_cu   grid size per compute unit, <= 64 (default: the blocks
  *                 that fit at once; wavefronts take work from a queue);
  * lut_bytes       largest cell table held in LDS, 4096..33792 bytes
- *                 (default 24576, or 33792 for direct tables);
- * lut_direct      1: FP32 byte tables in the direct layout, indexed from
- *                 cell 0 without a clamp (one instruction per pair instead
- *                 of three, coarser cells, a larger table); 0 (default): the
- *                 table starts at the first edge and the key is clamped;
+ *                 (default 24576; for wrapped tables 32768, which then also
+ *                 hold the histograms and thresholds);
+ * lut_direct      1: FP32 byte tables in the wrapped layout: the kernel
+ *                 starts its sum for q at a floor q0 (a power of two below
+ *                 a quarter of the smallest threshold), so every key lies in
+ *                 one window of cells, and reads cell (bits(q) >> shift)
+ *                 mod 2^w with one bitfield extract instead of a shift, a
+ *                 clamp and an add; the table's unused part holds the
+ *                 histograms (see tpcf_compile_wrap32).  Falls back to the
+ *                 clamped layout when nothing fits.  0 (default): the table
+ *                 starts at the first edge and the key is clamped;
  * prune           1: exact tile pruning.  Bounding caps of the column
  *                 catalog's aligned 64-point groups (built on first use,
  *                 4 doubles per group) and of each wavefront's rows bound the
@@ -394,16 +400,39 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
  * 32 bits of e = 1 - d as a signed integer.  A key maps to cell
  * clamp(key >> shift, lo, hi); entry cells[cell - lo] is a slot (< 0x8000),
  * 0x8000 | k when only edge k is undecided in the cell, or 0xFFFF when
- * several edges are.  direct = 1 (TPCF_FP32_CHORD only) asks for the direct
- * layout the kernels use for byte tables: lo = 0 and no key the kernel can
- * produce for norms within delta_max exceeds hi, so the clamp never acts;
- * it fails with TPCF_E_INVALID if that table would not fit.  out_cells must
- * hold max_cells entries (16..33792; the kernels use up to 33792 cells for
- * direct tables, 24576 for other byte tables, 12288 beyond 125 bins);
- * out_E (nbins+1 doubles, may be NULL) receives fl(1 - D_k). */
+ * several edges are.  direct = 1 (TPCF_FP32_CHORD only) asks for the cells
+ * of the wrapped layout (tpcf_compile_wrap32 with max_bytes = max_cells and
+ * the default launch's histogram and threshold bytes), in cell order lo..hi;
+ * its key is that of q summed from the floor, which always lies in
+ * [lo, hi].  It fails with TPCF_E_INVALID if that table would not fit.
+ * out_cells must hold max_cells entries (16..33792; the kernels use up to
+ * 32768 bytes for wrapped tables, 24576 for other byte tables, 12288 beyond
+ * 125 bins); out_E (nbins+1 doubles, may be NULL) receives fl(1 - D_k). */
 int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision, double delta_max,
                        int32_t max_cells, int32_t direct, int32_t *out_shift, int32_t *out_lo,
                        int32_t *out_hi, uint16_t *out_cells, double *out_E);
+
+/* Wrapped FP32 byte table (host only, for CPU tests; the layout of
+ * lut_direct = 1).  For unit vectors whose squared norms deviate from 1 by at
+ * most delta_max, the kernel forms q = fl(dz^2 + fl(dy^2 + fl(dx^2 + q0)))
+ * from the FP32 differences, with the floor q0 = *out_q0, a power of two at
+ * most a quarter of the smallest positive threshold and at least 2^-100.  Then
+ * q < out_qlo[k] implies d > D_k and q >= out_qhi[k] implies d <= D_k (nbins+1
+ * floats each, may be NULL), the floor included in the bounds.  Every key
+ * bits(q) >> *out_shift lies in [*out_lo, *out_hi]; cell c sits at entry
+ * c mod 2^(*out_wrap_bits) of out_image (2^(*out_wrap_bits) bytes, may be
+ * NULL), with the entry codes of tpcf_compile_cells in one byte (slot,
+ * 0x80 | k, or 0xFF); entries no key reaches are 0, and aux_bytes of them
+ * from the 16-aligned byte offset *out_aux_off on are free for the
+ * histograms and thresholds; when placing them after the table takes fewer
+ * bytes in all, *out_aux_off is the table's size instead.  The table is the
+ * smallest shift, then the smallest layout whose bytes in all stay within
+ * max_bytes (256..65536), that fits; at most 125 bins.  TPCF_E_INVALID if
+ * nothing fits. */
+int tpcf_compile_wrap32(const double *bin_edges_deg, int32_t nbins, double delta_max, int32_t max_bytes,
+                        int32_t aux_bytes, int32_t *out_shift, int32_t *out_wrap_bits, int32_t *out_lo,
+                        int32_t *out_hi, int32_t *out_aux_off, float *out_q0, float *out_qlo, float *out_qhi,
+                        uint8_t *out_image);
 
 /* Matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
  * doubles each) such that e >= out_hi[k] implies d <= D_k and e < out_lo[k]

@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
-    "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "version", "EXPORTED_SYMBOLS", "JobDesc",
+    "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "compile_wrap32", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
@@ -39,7 +39,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
-    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_band64",
+    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32", "tpcf_compile_band64",
     "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
     "tpcf_compile_band64_3d",
     "tpcf_last_error", "tpcf_version",
@@ -149,6 +149,7 @@ def lib():
         "tpcf_stats": ([P, P, cint], cint),
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
+        "tpcf_compile_wrap32": ([P, i32, ctypes.c_double, i32, i32, P, P, P, P, P, P, P, P, P], cint),
         "tpcf_compile_band64": ([P, i32, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_last_error": ([], ctypes.c_char_p),
@@ -486,6 +487,26 @@ def compile_band64(edges_deg):
     return lo, hi
 
 
+def compile_wrap32(edges_deg, delta_max: float = 0.0, max_bytes: int = 32768, aux_bytes: int = 0):
+    """Wrapped FP32 byte table of tpcf_compile_wrap32: a dict with shift,
+    wrap_bits, lo, hi, aux_off, q0 (the floor), qlo, qhi (the band with the
+    floor) and image (2^wrap_bits bytes)."""
+    e = _f64(edges_deg)
+    sh, wb, lo, hi, ao = (ctypes.c_int32() for _ in range(5))
+    q0 = ctypes.c_float()
+    qlo = np.empty(e.size, np.float32)
+    qhi = np.empty(e.size, np.float32)
+    _check(lib().tpcf_compile_wrap32(_p(e), e.size - 1, delta_max, max_bytes, aux_bytes, ctypes.byref(sh),
+                                     ctypes.byref(wb), ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(ao),
+                                     ctypes.byref(q0), _p(qlo), _p(qhi), None))
+    image = np.zeros(1 << wb.value, np.uint8)
+    _check(lib().tpcf_compile_wrap32(_p(e), e.size - 1, delta_max, max_bytes, aux_bytes, ctypes.byref(sh),
+                                     ctypes.byref(wb), ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(ao),
+                                     ctypes.byref(q0), None, None, _p(image)))
+    return {"shift": sh.value, "wrap_bits": wb.value, "lo": lo.value, "hi": hi.value, "aux_off": ao.value,
+            "q0": np.float32(q0.value), "qlo": qlo, "qhi": qhi, "image": image}
+
+
 def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: int | None = None,
                   direct: bool = False):
     """(shift, lo, hi, cells, E) of tpcf_compile_cells; by default the table
@@ -493,7 +514,7 @@ def compile_cells(edges_deg, precision: int, delta_max: float = 0.0, max_cells: 
     e = _f64(edges_deg)
     byte_table = e.size + 1 <= 127
     if max_cells is None:
-        max_cells = 33792 if direct else 24576 if byte_table else 12288
+        max_cells = 32768 if direct else 24576 if byte_table else 12288
     cells = np.zeros(max_cells, np.uint16)
     E = np.empty(e.size, np.float64)
     sh, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -453,6 +453,7 @@ std::string edges_key(const double *edges, int nbins, int precision, double delt
         k.append((const char *)&delta, sizeof delta);
     k.append((const char *)&t.lut_bytes, sizeof t.lut_bytes);
     k.append((const char *)&t.lut_direct, sizeof t.lut_direct);
+    k.append((const char *)&t.hist_copies, sizeof t.hist_copies);   // sizes a wrapped table's free piece
     return k;
 }
 
@@ -474,6 +475,8 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
     c.dThi.release(ctx->mem);
     c.dErad.release(ctx->mem);
 }
+
+int hist_copies_of(const Tuning &t, int nslots);
 
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta, int metric,
                  Compiled **out) {
@@ -520,9 +523,14 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
     } else if (precision == TPCF_FP32_CHORD) {
         c->band = make_band32(c->edges, delta);
-        if (c->entry_bytes == 1 && ctx->tune.lut_direct)
-            c->cells = make_cells32_direct(c->edges, c->band, delta,
-                                           ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxDirectLutBytes);
+        if (c->entry_bytes == 1 && ctx->tune.lut_direct) {
+            Band32 fb = make_band32(c->edges, delta, floor_for(c->band));
+            const int aux = aux_lds_bytes(nslots, hist_copies_of(ctx->tune, nslots), nbins + 1);
+            c->cells = make_cells32_wrap(c->edges, fb, delta,
+                                         ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kWrapLutBytes, aux);
+            if (!c->cells.cells.empty())
+                c->band = fb;
+        }
         if (c->cells.cells.empty())
             c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         qlo = c->band.qlo;
@@ -538,9 +546,10 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     }
     std::vector<uint8_t> packed;
     if (c->entry_bytes == 1) {
-        packed.resize(c->cells.cells.size());
+        const std::vector<uint16_t> &src = c->cells.direct ? c->cells.image : c->cells.cells;
+        packed.resize(src.size());
         for (size_t i = 0; i < packed.size(); ++i) {
-            uint16_t v = c->cells.cells[i];
+            uint16_t v = src[i];
             packed[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
         }
     } else {
@@ -784,6 +793,13 @@ int hist_copies_for(int nslots) {
     return 4;
 }
 
+// The copies a launch uses: at most what the slot count allows, 16 unless
+// the tuning asks for another count.
+int hist_copies_of(const Tuning &t, int nslots) {
+    const int want = t.hist_copies > 0 ? t.hist_copies : 16;
+    return std::min(hist_copies_for(nslots), want);
+}
+
 std::string cache_key(int32_t cat, const double *edges, int nbins, int precision, int64_t rb, int64_t re) {
     std::string k((const char *)&cat, sizeof cat);
     k.append((const char *)edges, sizeof(double) * (size_t)(nbins + 1));
@@ -941,7 +957,10 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     PairArgs a;
     memset(&a, 0, sizeof a);
     a.lut = cp.dlut.p;
-    a.lut_cells = (int32_t)cp.cells.cells.size();
+    a.lut_cells = (int32_t)(cp.cells.direct ? cp.cells.image.size() : cp.cells.cells.size());
+    a.lut_wrap_bits = cp.cells.wrap_bits;
+    a.aux_off = cp.cells.aux_off;
+    a.q_floor = cp.cells.q0;
     a.lut_entry_bytes = cp.entry_bytes;
     a.lut_shift = cp.cells.shift;
     a.lut_lo = cp.cells.lo;
@@ -972,10 +991,7 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.D = (const double *)cp.dD.p;
     a.nedges = nbins + 1;
     a.nslots = nbins + 2;
-    a.hist_copies = hist_copies_for(nbins + 2);
-    const int want_copies = ctx->tune.hist_copies > 0 ? ctx->tune.hist_copies : 16;
-    if (want_copies < a.hist_copies)
-        a.hist_copies = want_copies;
+    a.hist_copies = hist_copies_of(ctx->tune, nbins + 2);
     a.rows_per_lane = rows_per_lane_of(ctx->tune, cp.precision == TPCF_FP64_MATRIX);
     a.blocks_per_cu = ctx->tune.blocks_per_cu;
     a.stats = stats;
@@ -1882,9 +1898,11 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
         return fail(TPCF_E_INVALID, err);
     CellTable c;
     if (direct) {
-        c = make_cells32_direct(t, make_band32(t, delta_max), delta_max, max_cells);
+        const Band32 fb = make_band32(t, delta_max, floor_for(make_band32(t, delta_max)));
+        c = make_cells32_wrap(t, fb, delta_max, max_cells,
+                              aux_lds_bytes(nbins + 2, hist_copies_of(Tuning{}, nbins + 2), nbins + 1));
         if (c.cells.empty())
-            return fail(TPCF_E_INVALID, "no direct table fits in max_cells");
+            return fail(TPCF_E_INVALID, "no wrapped table fits in max_cells bytes");
     } else {
         const int m = std::min<int>(max_cells, kMaxLutCells);
         c = precision == TPCF_FP32_CHORD ? make_cells32(t, make_band32(t, delta_max), delta_max, m)
@@ -1898,6 +1916,46 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
     if (out_E)
         for (int k = 0; k <= nbins; ++k)
             out_E[k] = t.E[k];
+    return TPCF_OK;
+}
+
+int tpcf_compile_wrap32(const double *bin_edges_deg, int32_t nbins, double delta_max, int32_t max_bytes,
+                        int32_t aux_bytes, int32_t *out_shift, int32_t *out_wrap_bits, int32_t *out_lo,
+                        int32_t *out_hi, int32_t *out_aux_off, float *out_q0, float *out_qlo, float *out_qhi,
+                        uint8_t *out_image) {
+    if (!out_shift || !out_wrap_bits || !out_lo || !out_hi || !out_aux_off || !out_q0)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
+        return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
+    if (max_bytes < 256 || max_bytes > 65536 || aux_bytes < 0 || aux_bytes > max_bytes)
+        return fail(TPCF_E_INVALID, "max_bytes must be in [256, 65536] and aux_bytes in [0, max_bytes]");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges(bin_edges_deg, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    if (nbins + 2 > kMaxSlots8)
+        return fail(TPCF_E_INVALID, "wrapped tables hold one-byte entries (at most 125 bins)");
+    const Band32 fb = make_band32(t, delta_max, floor_for(make_band32(t, delta_max)));
+    const CellTable c = make_cells32_wrap(t, fb, delta_max, max_bytes, aux_bytes);
+    if (c.cells.empty())
+        return fail(TPCF_E_INVALID, "no wrapped table fits in max_bytes");
+    *out_shift = c.shift;
+    *out_wrap_bits = c.wrap_bits;
+    *out_lo = c.lo;
+    *out_hi = c.hi;
+    *out_aux_off = c.aux_off;
+    *out_q0 = c.q0;
+    for (int k = 0; k <= nbins; ++k) {
+        if (out_qlo)
+            out_qlo[k] = fb.qlo[k];
+        if (out_qhi)
+            out_qhi[k] = fb.qhi[k];
+    }
+    if (out_image)
+        for (size_t i = 0; i < c.image.size(); ++i) {
+            const uint16_t v = c.image[i];
+            out_image[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
+        }
     return TPCF_OK;
 }
 

@@ -220,16 +220,20 @@ bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::str
 //      qlo_k = RD32((((C- - a)_+)^2 (1-u)^5 - tau) / s),
 //  C+- = sqrt(2(1 - D_k) +- 2(delta + eps_d)), and s = 1 + 2^-20 absorbing
 //  the rounding of this host arithmetic (a few ulps of FP64).
-Band32 make_band32(const EdgeTables &t, double delta) {
+Band32 make_band32(const EdgeTables &t, double delta, float q0) {
     const double U = ldexp(1.0, -53), u = ldexp(1.0, -24);
     const double eps_d = 3.0 * U / (1.0 - 3.0 * U) * (1.0 + delta);
     const double a = 2.0 * u * (1.0 + delta);
-    const double grow = pow(1.0 + u, 5.0), shrink = pow(1.0 - u, 5.0);
+    // with a floor the chord term may see six roundings (a separate multiply
+    // and add in place of the first fused step), the floor three
+    const double grow = pow(1.0 + u, q0 > 0.0f ? 6.0 : 5.0), shrink = pow(1.0 - u, q0 > 0.0f ? 6.0 : 5.0);
+    const double fgrow = (double)q0 * pow(1.0 + u, 3.0), fshrink = (double)q0 * pow(1.0 - u, 3.0);
     const double tau = ldexp(1.0, -120);
     const double s = 1.0 + ldexp(1.0, -20);
     const double slack = 2.0 * (delta + eps_d);
     Band32 b;
     b.delta = delta;
+    b.q0 = q0;
     const int ne = (int)t.D.size();
     b.qlo.resize(ne);
     b.qhi.resize(ne);
@@ -245,7 +249,7 @@ Band32 make_band32(const EdgeTables &t, double delta) {
         }
         double base = 2.0 * (1.0 - D);
         double cp = sqrt(base + slack);
-        b.qhi[k] = round_up32(((cp + a) * (cp + a) * grow + tau) * s);
+        b.qhi[k] = round_up32(((cp + a) * (cp + a) * grow + fgrow + tau) * s);
         double tm = base - slack;
         if (tm <= 0.0) {
             b.qlo[k] = 0.0f;
@@ -254,7 +258,7 @@ Band32 make_band32(const EdgeTables &t, double delta) {
             if (cm <= 0.0) {
                 b.qlo[k] = 0.0f;
             } else {
-                double v = (cm * cm * shrink - tau) / s;
+                double v = (cm * cm * shrink + fshrink - tau) / s;
                 b.qlo[k] = v > 0.0 ? round_down32(v) : 0.0f;
             }
         }
@@ -433,19 +437,92 @@ void fill_cells32(const Band32 &b, int ne, CellTable *ct) {
 
 }  // namespace
 
-CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta, int max_cells) {
+float floor_for(const Band32 &b) {
+    // smallest positive finite threshold of the band without a floor
+    float tmin = HUGE_VALF;
+    for (size_t k = 0; k < b.qlo.size(); ++k) {
+        if (isfinite(b.qlo[k]) && b.qlo[k] > 0.0f)
+            tmin = std::min(tmin, b.qlo[k]);
+        if (isfinite(b.qhi[k]) && b.qhi[k] > 0.0f)
+            tmin = std::min(tmin, b.qhi[k]);
+    }
+    if (!isfinite(tmin))
+        return 1.0f;                // no positive threshold: any floor below the edges' range
+    int ex = 0;
+    frexpf(tmin, &ex);              // tmin in [2^(ex-1), 2^ex)
+    return ldexpf(1.0f, std::max(ex - 3, -100));    // at most tmin / 4, never below 2^-100
+}
+
+CellTable make_cells32_wrap(const EdgeTables &t, const Band32 &b, double delta, int max_bytes,
+                            int aux_bytes) {
     CellTable ct;
-    if (!(delta <= ldexp(1.0, -10)))
+    if (!(delta <= ldexp(1.0, -10)) || !(b.q0 > 0.0f))
         return ct;
-    const uint32_t ktop = qtop_key(delta);
+    // every q the kernel forms lies in [q0, qtop]: the floor is a lower bound
+    // of each partial sum, and qtop (for the largest chord) grows by the floor
+    const uint32_t klo_bits = fbits(b.q0);
+    const double qtop_d = (pow(2.0 * sqrt(1.0 + delta) + 4.0 * ldexp(1.0, -24), 2.0) + b.q0) * 1.0001;
+    const uint32_t ktop = fbits(round_up32(qtop_d));
+    const int aux = (aux_bytes + 15) & ~15;
     for (int shift = 12; shift <= 23; ++shift) {
-        if ((int64_t)(ktop >> shift) + 1 <= max_cells) {
+        const int64_t lo = klo_bits >> shift, hi = ktop >> shift, n = hi - lo + 1;
+        // the smallest table that holds the cells, with the histograms and
+        // thresholds after it, if that is smaller than holding them inside
+        int64_t after = 0;
+        for (int w = 8; w <= 16 && after == 0; ++w)
+            if (((int64_t)1 << w) >= n)
+                after = (int64_t)1 << w;
+        for (int w = 8; w <= 16; ++w) {
+            const int64_t size = (int64_t)1 << w, mask = size - 1;
+            if (after && after + aux <= max_bytes && after + aux < size) {
+                ct.shift = shift;
+                ct.lo = (int32_t)lo;
+                ct.hi = (int32_t)hi;
+                ct.direct = true;
+                ct.wrap_bits = 0;
+                while (((int64_t)1 << ct.wrap_bits) < after)
+                    ++ct.wrap_bits;
+                ct.aux_off = (int32_t)after;
+                ct.q0 = b.q0;
+                fill_cells32(b, (int)t.D.size(), &ct);
+                ct.image.assign((size_t)after, 0);
+                for (int64_t c = lo; c <= hi; ++c)
+                    ct.image[(size_t)(c & (after - 1))] = ct.cells[(size_t)(c - lo)];
+                return ct;
+            }
+            if (size > max_bytes)
+                break;
+            if (n + aux + 32 > size)
+                continue;
+            // the cells' arc is [lo & mask, hi & mask] (mod size); the rest of
+            // the table is never read, and the histograms and thresholds go into
+            // its longest contiguous piece
+            const int64_t f0 = (hi + 1) & mask, fn = size - n;
+            int64_t start, len;
+            if (f0 + fn <= size) {
+                start = f0;
+                len = fn;
+            } else if (size - f0 >= fn - (size - f0)) {
+                start = f0;
+                len = size - f0;
+            } else {
+                start = 0;
+                len = fn - (size - f0);
+            }
+            const int64_t a0 = (start + 15) & ~(int64_t)15;
+            if (a0 + aux > start + len)
+                continue;
             ct.shift = shift;
-            ct.lo = 0;
-            ct.hi = (int32_t)(ktop >> shift);
+            ct.lo = (int32_t)lo;
+            ct.hi = (int32_t)hi;
             ct.direct = true;
-            // keys never exceed ktop, so the open top cell changes no decision
+            ct.wrap_bits = w;
+            ct.aux_off = (int32_t)a0;
+            ct.q0 = b.q0;
             fill_cells32(b, (int)t.D.size(), &ct);
+            ct.image.assign((size_t)size, 0);
+            for (int64_t c = lo; c <= hi; ++c)
+                ct.image[(size_t)(c & mask)] = ct.cells[(size_t)(c - lo)];
             return ct;
         }
     }

@@ -23,6 +23,7 @@ struct EdgeTables {
 
 struct Band32 {
     double delta = 0;               // bound on | |v|^2 - 1 | used for the band
+    float q0 = 0;                   // floor added to q by the kernel (0: none)
     std::vector<float> qlo, qhi;
 };
 
@@ -37,8 +38,13 @@ struct Band64 {
 struct CellTable {
     int shift = 0;                  // cell = key >> shift
     int32_t lo = 0, hi = 0;         // clamp range of cells (inclusive)
-    bool direct = false;            // lo = 0 and no reachable key exceeds hi: no clamp needed
+    bool direct = false;            // wrapped layout: no clamp, cell c at c mod 2^wrap_bits
+    int wrap_bits = 0;              // wrapped layout: log2 of the table's entry count
+    int32_t aux_off = 0;            // wrapped layout: 16-aligned byte offset of the free piece
+                                    // that holds the histograms and thresholds
+    float q0 = 0;                   // wrapped layout: the floor of q (every key >= bits(q0) >> shift)
     std::vector<uint16_t> cells;    // hi - lo + 1 entries
+    std::vector<uint16_t> image;    // wrapped layout: 2^wrap_bits entries, cells in place, rest 0
     int n_certain = 0, n_medium = 0, n_multi = 0;
 };
 
@@ -48,8 +54,14 @@ struct CellTable {
 bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::string *err);
 
 // FP32 squared-chord band of every edge for catalogs whose squared norms
-// deviate from 1 by at most delta.
-Band32 make_band32(const EdgeTables &t, double delta);
+// deviate from 1 by at most delta.  With q0 > 0 the band is for
+// q = fl(dz^2 + fl(dy^2 + fl(dx^2 + q0))), the kernel's sum started at the
+// floor q0 instead of 0.
+Band32 make_band32(const EdgeTables &t, double delta, float q0 = 0.0f);
+// Floor for the wrapped layout: a power of two at most a quarter of the
+// smallest positive threshold of a band built without a floor (and at least
+// 2^-100, so no partial sum is subnormal).
+float floor_for(const Band32 &b);
 
 // 3-D edges: finite, strictly increasing, within [0, 1e150] (same length
 // unit as the coordinates), 1 <= nbins <= 256.  False with a message on
@@ -69,11 +81,17 @@ uint32_t qtop_key_3d(double rmax);
 CellTable make_cells32(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
 // The same with the top key given (every q above it goes to the top cell).
 CellTable make_cells32_top(const EdgeTables &t, const Band32 &b, uint32_t ktop, int max_cells);
-// Direct FP32 table: cells 0 .. bits(qtop) >> shift, where qtop bounds every
-// q the kernel can compute for norms within delta; the smallest shift whose
-// table has at most max_cells entries.  Returns a table with no cells if
-// delta is too large for the bound (above 2^-10) or none fits.
-CellTable make_cells32_direct(const EdgeTables &t, const Band32 &b, double delta, int max_cells);
+// Wrapped FP32 byte table for a band with a floor (b.q0 > 0): the kernel's
+// q lies in [q0, qtop] (qtop bounds the largest chord for norms within
+// delta), so its cells bits(q0) >> shift .. bits(qtop) >> shift are all the
+// keys there are; cell c is stored at c mod 2^w and read with one bitfield
+// extract, (bits >> shift) & (2^w - 1), no clamp and no offset.  The table
+// takes the smallest shift, then the smallest w, for which the unused part
+// of the table holds aux_bytes (the histograms and thresholds) in one
+// 16-aligned piece, or for which they fit after the table, whichever takes
+// fewer bytes in all, within max_bytes.  Returns a table with no cells if
+// delta is above 2^-10, the band has no floor, or nothing fits.
+CellTable make_cells32_wrap(const EdgeTables &t, const Band32 &b, double delta, int max_bytes, int aux_bytes);
 // etop bounds the keyed value from above (cells above it are not built; a
 // larger value falls into the top cell): 2 for e = 1 - d, the largest
 // squared distance for 3-D.

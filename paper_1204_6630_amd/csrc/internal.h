@@ -15,9 +15,10 @@ constexpr int kBlock = kWaves * kWaveSize;
 // edge index fits in 7 bits, else two bytes.
 constexpr int kMaxLutBytes = 24576;
 constexpr int kMaxLutCells = kMaxLutBytes;        // with one-byte entries
-// Direct-indexed FP32 tables (cell = bits(q) >> shift from cell 0, no clamp):
-// the largest table, and the smallest table the default shape asks for.
+// Largest cell-table budget a tuning may ask for, and the wrapped FP32
+// tables' default budget (table, histograms and thresholds together).
 constexpr int kMaxDirectLutBytes = 33792;
+constexpr int kWrapLutBytes = 32768;
 // Histogram copies in global memory (u64), indexed by work unit.
 constexpr int kGlobalCopies = 64;
 // Largest number of output slots (nbins <= 256 -> nbins + 2 slots).
@@ -90,8 +91,14 @@ struct PairArgs {
     int32_t lut_entry_bytes;     // 1 or 2
     int32_t lut_shift;           // cell = key >> shift
     int32_t lut_lo, lut_hi;      // clamp range of cells
-    int32_t lut_direct;          // 1: FP32 table indexed from cell 0 without a clamp
-                                 // (every reachable key lies inside it)
+    int32_t lut_direct;          // 1: wrapped FP32 byte table (lut_cells = 2^lut_wrap_bits;
+                                 // cell = (bits(q) >> shift) & (lut_cells - 1), q summed
+                                 // from the floor q_floor); the histograms and thresholds
+                                 // then start at LDS byte aux_off, inside the table's
+                                 // unused part
+    int32_t lut_wrap_bits;
+    int32_t aux_off;
+    float q_floor;
     // Pairs certainly beyond the last edge: FP32 path, bits(q) >= beyond_key
     // (the bits of the last edge's qhi); FP64 paths, high word of e = 1 - d
     // above beyond_key as signed integers (e > E_last on the vector path,
@@ -130,12 +137,22 @@ struct PairArgs {
                                  //  pairs binned by pruned blocks]
 };
 
-// LDS bytes used by one block for the given table sizes.
-inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_bytes, int nedges) {
-    int hist = kWaves * (nslots + 1) * hist_copies * 4;      // +1: discard row
-    int lut = ((lut_cells * lut_entry_bytes) + 15) & ~15;
+// LDS bytes of the histograms (with the discard row) and edge thresholds.
+inline int aux_lds_bytes(int nslots, int hist_copies, int nedges) {
+    int hist = kWaves * (nslots + 1) * hist_copies * 4;
     int thr = nedges * (4 + 4 + 8 + 8 + 8 + 8 + 8);
-    return hist + lut + thr;
+    return hist + thr;
+}
+
+// LDS bytes used by one block for the given table sizes; aux_off >= 0 places
+// the histograms and thresholds at that offset (inside a wrapped table).
+inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_bytes, int nedges,
+                     int aux_off = -1) {
+    int lut = ((lut_cells * lut_entry_bytes) + 15) & ~15;
+    int aux = aux_lds_bytes(nslots, hist_copies, nedges);
+    if (aux_off >= 0)
+        return aux_off + aux > lut ? aux_off + aux : lut;
+    return lut + aux;
 }
 
 // Margin (radians) of the pruning test: covers the FP32 copies of the rows

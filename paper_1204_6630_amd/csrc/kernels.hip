@@ -173,9 +173,8 @@ struct Smem {
     uint32_t *hist;      // kWaves x (nslots + 1) x copies
     double *D;
     double *E;
-    double *Tlo, *Thi;
-    float *qlo;
-    float *qhi;
+    double2 *Tband;      // matrix-core band (lo_k, hi_k), one 16-byte read per edge
+    float2 *qband;       // FP32 band (qlo_k, qhi_k), one 8-byte read per edge
     double *erad;        // edges in radians (pruning)
     unsigned char *lut;
     uint32_t hist_addr;  // LDS byte address of hist
@@ -183,21 +182,20 @@ struct Smem {
 };
 
 // LDS layout: the cell table first (at the start of the block's LDS, so a
-// direct table is indexed by the cell itself), then the histograms and the
-// edge thresholds.
+// wrapped table is indexed by the masked key itself), then the histograms
+// and the edge thresholds: after the table, or for a wrapped table at
+// aux_off, inside the part of the table that no key reaches.
 __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     Smem s;
-    const int lut_bytes = (a.lut_cells * a.lut_entry_bytes + 15) & ~15;
+    const int aux = a.lut_direct ? a.aux_off : (a.lut_cells * a.lut_entry_bytes + 15) & ~15;
     int hist_words = kWaves * (a.nslots + 1) * a.hist_copies;
     s.lut = base;
-    s.hist = reinterpret_cast<uint32_t *>(base + lut_bytes);
-    s.D = reinterpret_cast<double *>(base + lut_bytes + hist_words * 4);
+    s.hist = reinterpret_cast<uint32_t *>(base + aux);
+    s.D = reinterpret_cast<double *>(base + aux + hist_words * 4);
     s.E = s.D + a.nedges;
-    s.Tlo = s.E + a.nedges;
-    s.Thi = s.Tlo + a.nedges;
-    s.erad = s.Thi + a.nedges;
-    s.qlo = reinterpret_cast<float *>(s.erad + a.nedges);
-    s.qhi = s.qlo + a.nedges;
+    s.Tband = reinterpret_cast<double2 *>(s.E + a.nedges);
+    s.erad = reinterpret_cast<double *>(s.Tband + a.nedges);
+    s.qband = reinterpret_cast<float2 *>(s.erad + a.nedges);
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
     s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
     return s;
@@ -246,22 +244,26 @@ __device__ void flush_wave(const PairArgs &a, const Smem &s, unsigned long long 
     }
 }
 
+// A flagged entry: edge k alone is undecided in the cell (its FP32 band,
+// one 8-byte LDS read, settles q outside [qlo_k, qhi_k); inside it the exact
+// FP64 rule compares d with D_k), or several are (the rule counts them).
 template <bool LUT8, bool M3>
 __device__ __forceinline__ uint32_t resolve_fp32(uint32_t ent, uint32_t flag, float q, const Smem &s,
                                                  const PairArgs &a, const JobDev &jb, int i, int j,
                                                  uint32_t &n_exact) {
     if (ent != (flag | Code<LUT8>::kmask)) {
-        int k = (int)(ent ^ flag);
-        if (q < s.qlo[k])
+        const int k = (int)(ent ^ flag);
+        const float2 b = s.qband[k];
+        if (q < b.x)
             return (uint32_t)k;
-        if (q >= s.qhi[k])
+        if (q >= b.y)
             return (uint32_t)(k + 1);
         ++n_exact;
-        double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+        const double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
         return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
     }
     ++n_exact;
-    double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
+    const double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
     return count_le(d, s.D, a.nedges);
 }
 
@@ -296,6 +298,8 @@ struct Counters {
 // Loop constants of one wavefront.
 struct Consts {
     uint32_t shift;
+    uint32_t wbits;         // wrapped table: log2 of its entry count
+    float qfloor;           // wrapped table: the floor q is summed from
     uint32_t clo, chi;      // clamp range (VGPR copies)
     uint32_t lutbias;       // LDS address of cell c is c * entry_bytes + lutbias
     uint32_t rowstep;       // bytes between slots of the histogram
@@ -310,10 +314,11 @@ struct Consts {
 template <bool LUT8, bool DIRECT>
 __device__ __forceinline__ uint32_t addr32(uint32_t bits, const Consts &k) {
     if (DIRECT) {
-        // byte table from cell 0 at LDS address 0 (the kernel has no static
-        // LDS, so its dynamic LDS starts there); every key the kernel can
-        // produce lies inside it (checked on the host)
-        return bits >> k.shift;
+        // wrapped byte table at LDS address 0 (the kernel has no static LDS,
+        // so its dynamic LDS starts there): the floor keeps every key within
+        // 2^wbits cells of bits(q_floor) >> shift (checked on the host), so
+        // the key's low wbits bits address it without a clamp
+        return __builtin_amdgcn_ubfe(bits, k.shift, k.wbits);
     }
     return med3_u32(bits >> k.shift, k.clo, k.chi) * (LUT8 ? 1u : 2u) + k.lutbias;
 }
@@ -518,7 +523,8 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             float dx = xi[p] - xj[t];
             float dy = yi[p] - yj[t];
             float dz = zi[p] - zj[t];
-            float v = dx * dx;
+            // the wrapped table's sum starts at its floor (same instruction count)
+            float v = DIRECT ? __fmaf_rn(dx, dx, k.qfloor) : dx * dx;
             v = __fmaf_rn(dy, dy, v);
             v = __fmaf_rn(dz, dz, v);
             q[t][p] = v;
@@ -820,9 +826,10 @@ __device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, dou
                                                 uint32_t &n_exact) {
     if (ent != (flag | Code<LUT8>::kmask)) {
         int k = (int)(ent ^ flag);
-        if (e < s.Tlo[k])
+        const double2 b = s.Tband[k];
+        if (e < b.x)
             return (uint32_t)k;
-        if (e >= s.Thi[k])
+        if (e >= b.y)
             return (uint32_t)(k + 1);
         ++n_exact;
         double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
@@ -1011,21 +1018,26 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
         s.hist[w] = 0;
     const int lut_bytes = a.lut_cells * (LUT8 ? 1 : 2);
     const unsigned char *glut = reinterpret_cast<const unsigned char *>(a.lut);
+    // a wrapped table's unused piece holds the histograms and thresholds,
+    // which the copy must not overwrite
+    const uint32_t aux_lo = a.lut_direct ? (uint32_t)a.aux_off : (uint32_t)lut_bytes;
+    const uint32_t aux_n = (uint32_t)(hist_words * 4 + a.nedges * 48);
     for (int b = tid; b < lut_bytes; b += kBlock)
-        s.lut[b] = glut[b];
+        if ((uint32_t)b - aux_lo >= aux_n)
+            s.lut[b] = glut[b];
     for (int e = tid; e < a.nedges; e += kBlock) {
         s.D[e] = a.D[e];
         s.E[e] = a.E[e];
-        s.Tlo[e] = a.Tlo[e];
-        s.Thi[e] = a.Thi[e];
-        s.qlo[e] = a.qlo[e];
-        s.qhi[e] = a.qhi[e];
+        s.Tband[e] = make_double2(a.Tlo[e], a.Thi[e]);
+        s.qband[e] = make_float2(a.qlo[e], a.qhi[e]);
         s.erad[e] = a.erad ? a.erad[e] : 0.0;
     }
     __syncthreads();
 
     Consts k;
     k.shift = (uint32_t)a.lut_shift;
+    k.wbits = (uint32_t)a.lut_wrap_bits;
+    k.qfloor = a.q_floor;
     k.clo = to_vgpr((uint32_t)a.lut_lo);
     k.chi = to_vgpr((uint32_t)a.lut_hi);
     k.lutbias = s.lut_addr - (uint32_t)a.lut_lo * (LUT8 ? 1u : 2u);
@@ -1275,7 +1287,7 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
     if (args->n_units <= 0)
         return 0;
     const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->lut_entry_bytes,
-                              args->nedges);
+                              args->nedges, args->lut_direct ? args->aux_off : -1);
     const int grid = grid_for(args->n_units, lds, args->blocks_per_cu);
     hipStream_t st = (hipStream_t)stream;
     const bool b8 = args->lut_entry_bytes == 1;

@@ -107,28 +107,49 @@ def _pairs_at(g, theta):
     return a, b
 
 
-def _q32(a, b):
+def _q32(a, b, q0=None):
     """Kernel arithmetic in FP32 (separate multiply and add; the band covers
-    both this and the fused form)."""
+    both this and the fused form).  With a floor q0 (the wrapped layout) the
+    sum starts at q0."""
     fa = a.astype(np.float32)
     fb = b.astype(np.float32)
     d = fa - fb
     q = d[:, 0] * d[:, 0]
+    if q0 is not None:
+        q = q + np.float32(q0)
     q = q + d[:, 1] * d[:, 1]
     q = q + d[:, 2] * d[:, 2]
     return q.astype(np.float32)
+
+
+def _q32_fused(a, b, q0):
+    """The same with each step fused (one rounding): the product of two FP32
+    values and the FP32 sum are exact in FP64 up to a final rounding that can
+    only differ from the fused one by a double rounding, so this is checked
+    with a band margin of two FP32 ulps elsewhere, not bit for bit."""
+    d = (a.astype(np.float32) - b.astype(np.float32)).astype(np.float64)
+    q = np.float32(d[:, 0] * d[:, 0] + np.float64(q0))
+    q = np.float32(d[:, 1] * d[:, 1] + q.astype(np.float64))
+    q = np.float32(d[:, 2] * d[:, 2] + q.astype(np.float64))
+    return q
 
 
 def _dot64(a, b):
     return (a[:, 0] * b[:, 0] + a[:, 1] * b[:, 1]) + a[:, 2] * b[:, 2]
 
 
+@pytest.mark.parametrize("floored", [False, True])
 @pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
                                    synthcat.log_edges(0.001, 20.0, 30)])
-def test_fp32_band_adversary(edges):
-    """P10: pairs at theta = e_k (1 +- 10^-s), s = 3..9, every edge."""
+def test_fp32_band_adversary(edges, floored):
+    """P10: pairs at theta = e_k (1 +- 10^-s), s = 3..9, every edge; also for
+    the wrapped layout's band, whose q is summed from the floor q0."""
     g = np.random.default_rng(7)
     D, qlo, qhi = tp.compile_edges(edges, delta_max=4.5e-16)
+    q0 = None
+    if floored:
+        w = tp.compile_wrap32(edges, delta_max=4.5e-16)
+        qlo, qhi, q0 = w["qlo"], w["qhi"], w["q0"]
     er = edges * DEG
     thetas, rel, edge_of = [], [], []
     for k, e in enumerate(er):
@@ -141,9 +162,15 @@ def test_fp32_band_adversary(edges):
     rel = np.concatenate(rel)
     edge_of = np.concatenate(edge_of)
     a, b = _pairs_at(g, theta)
-    q = _q32(a, b)
+    q = _q32(a, b, q0)
     d = _dot64(a, b)
     truth = oracle.pair_slots(a.T, b.T, edges)
+    if floored:
+        # the fused form (each step one rounding) against the same band
+        qf = _q32_fused(a, b, q0)
+        for k in range(edges.size):
+            past = truth >= k + 1
+            assert np.all(past[qf >= qhi[k]]) and not np.any(past[qf < qlo[k]]), k
     in_band = np.zeros(theta.size, bool)
     for k in range(edges.size):
         above = q >= qhi[k]
@@ -166,11 +193,24 @@ def _emulate(a, b, edges, precision, delta, direct=None):
     D, qlo, qhi = tp.compile_edges(edges, delta_max=delta)
     shift, lo, hi, cells, E = tp.compile_cells(edges, precision, delta_max=delta, direct=direct)
     d = _dot64(a, b)
-    if precision == tp.FP32_CHORD:
+    if precision == tp.FP32_CHORD and direct:
+        # wrapped layout: q summed from the floor, cell = key mod 2^w of the
+        # table image, no clamp; the band is the floored one
+        nb = edges.size - 1
+        w = tp.compile_wrap32(edges, delta_max=delta, aux_bytes=_aux_bytes(nb))
+        assert (w["shift"], w["lo"], w["hi"]) == (shift, lo, hi)
+        qlo, qhi = w["qlo"], w["qhi"]
+        q = _q32(a, b, w["q0"])
+        key = (q.view(np.uint32) >> np.uint32(shift)).astype(np.int64)
+        assert key.min() >= lo and key.max() <= hi
+        img = w["image"][key & ((1 << w["wrap_bits"]) - 1)].astype(np.int64)
+        # one-byte codes back to the 16-bit ones of compile_cells
+        c = key - lo
+        assert np.array_equal(np.where(img == 0xFF, 0xFFFF, np.where(img & 0x80, 0x8000 | (img & 0x7F), img)),
+                              cells[c].astype(np.int64))
+    elif precision == tp.FP32_CHORD:
         q = _q32(a, b)
         key = q.view(np.uint32) >> np.uint32(shift)
-        # the direct layout (lo = 0) must hold every key without the clamp
-        assert lo > 0 or key.max() <= hi
         c = np.clip(key.astype(np.int64), lo, hi) - lo
     else:
         e = 1.0 - d
@@ -205,6 +245,61 @@ def _emulate(a, b, edges, precision, delta, direct=None):
             exact[idx] = True
             slot[idx] = int(np.sum(d[idx] <= D))
     return slot, flag, exact
+
+
+def _aux_bytes(nbins, copies=16):
+    """LDS bytes of the histograms and thresholds of a default launch (four
+    wavefronts, `copies` histogram copies of nbins + 3 words, 48 bytes of
+    thresholds per edge)."""
+    nslots = nbins + 2
+    allowed = 32 if nslots + 1 <= 48 else 16 if nslots + 1 <= 96 else 8 if nslots + 1 <= 192 else 4
+    return 4 * (nslots + 1) * min(copies, allowed) * 4 + (nbins + 1) * 48
+
+
+@pytest.mark.parametrize("nbins,budget", [(1, 32768), (20, 32768), (40, 32768), (125, 32768), (40, 31744),
+                                          (60, 32768)])
+def test_wrapped_table_layout(nbins, budget):
+    """The wrapped table: keys of every reachable q (coincident points give
+    q = q0, antipodal ones the largest q) lie in [lo, hi]; the image holds
+    cell c at c mod 2^w and zeros elsewhere; the free piece for the
+    histograms and thresholds misses every cell; the floor is a power of two
+    at most a quarter of the smallest positive threshold."""
+    edges = synthcat.log_edges(0.0005, 30.0, nbins)
+    aux = _aux_bytes(nbins)
+    w = tp.compile_wrap32(edges, delta_max=4.5e-16, max_bytes=budget, aux_bytes=aux)
+    size = 1 << w["wrap_bits"]
+    assert max(size, w["aux_off"] + aux) <= budget and w["image"].size == size
+    q0 = float(w["q0"])
+    assert np.frexp(q0)[0] == 0.5
+    _, qlo0, qhi0 = tp.compile_edges(edges, delta_max=4.5e-16)
+    pos = np.concatenate([qlo0[qlo0 > 0], qhi0[qhi0 > 0]])
+    assert 2.0 ** -100 <= q0 <= pos.min() / 4
+    lo, hi = w["lo"], w["hi"]
+    if w["aux_off"] >= size:
+        assert w["aux_off"] == size and hi - lo + 1 <= size     # the free bytes follow the table
+    else:
+        assert hi - lo + 1 + aux <= size
+    arc = np.arange(lo, hi + 1) & (size - 1)
+    assert np.unique(arc).size == arc.size
+    free = np.ones(size, bool)
+    free[arc] = False
+    assert w["aux_off"] % 16 == 0 and np.all(free[w["aux_off"]:w["aux_off"] + aux])
+    assert np.all(w["image"][free] == 0)
+    _, clo, chi, cells, _ = tp.compile_cells(edges, tp.FP32_CHORD, delta_max=4.5e-16, direct=True,
+                                             max_cells=budget)
+    assert (clo, chi) == (lo, hi)
+    img = w["image"][arc].astype(np.int64)
+    assert np.array_equal(np.where(img == 0xFF, 0xFFFF, np.where(img & 0x80, 0x8000 | (img & 0x7F), img)),
+                          cells.astype(np.int64))
+    g = np.random.default_rng(nbins)
+    a = g.normal(size=(4000, 3))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    b = np.concatenate([a[:1000], -a[1000:2000], g.normal(size=(2000, 3))])
+    b[2000:] /= np.linalg.norm(b[2000:], axis=1, keepdims=True)
+    for q in (_q32(a, b, w["q0"]), _q32_fused(a, b, w["q0"])):
+        key = q.view(np.uint32) >> np.uint32(w["shift"])
+        assert key.min() >= lo and key.max() <= hi
+    assert np.all(_q32(a[:1000], b[:1000], w["q0"]) == np.float32(q0))
 
 
 @pytest.mark.parametrize("precision,direct", [(tp.FP32_CHORD, True), (tp.FP32_CHORD, False),
