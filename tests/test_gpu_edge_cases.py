@@ -8,8 +8,8 @@
 * edges that include 0 and 180 degrees exactly, on the full sphere;
 * 16 seeded random cases: catalog sizes, bin counts, edge placements, point
   distributions (full sphere, clustered patch, duplicated points), kinds,
-  precisions and launch shapes drawn at random, each bit-exact against the
-  oracle.
+  precisions, launch shapes and FP32 table layouts (clamped or wrapped) drawn
+  at random, each bit-exact against the oracle.
 """
 
 import numpy as np
@@ -45,6 +45,21 @@ def sphere(ctx):
 
 
 _ref = {}
+
+
+@pytest.mark.parametrize("nbins", [1, 20, 125])
+def test_wrapped_table_on_the_full_sphere(ctx, sphere, nbins):
+    """The wrapped FP32 table (q summed from a floor, key masked, no clamp)
+    on the full sphere, where q reaches its largest values, with edges from
+    0 to 180 degrees and log edges from 1e-4 degrees."""
+    ca, cb, xa, xb = sphere
+    ctx.set_tuning(lut_direct=1)
+    try:
+        for edges in (np.linspace(0.0, 180.0, nbins + 1), synthcat.log_edges(1e-4, 180.0, nbins)):
+            got = ctx.count(tp.DR, ca, edges, cat_b=cb, precision=tp.FP32_CHORD)
+            assert np.array_equal(got, oracle.count(oracle.DR, xa, edges, b_xyz=xb))
+    finally:
+        ctx.set_tuning()
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -98,7 +113,7 @@ def _random_case(seed):
     kind = int(g.choice([tp.DD, tp.DR]))
     prec = int(g.choice(PRECS))
     tuning = {"rows_per_lane": int(g.choice([0, 2, 4])), "hist_copies": int(g.choice([0, 4, 8, 32])),
-              "max_cols": int(g.choice([0, 256, 1024]))}
+              "max_cols": int(g.choice([0, 256, 1024])), "lut_direct": int(g.choice([0, 1]))}
     return (ra[:na], dec[:na]), (ra[na:], dec[na:]), edges, kind, prec, tuning, style
 
 
