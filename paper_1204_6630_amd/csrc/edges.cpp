@@ -596,7 +596,9 @@ CellTable make_cells64(const EdgeTables &t, int max_cells, double etop) {
                                        0xffffffffULL);
         int s_min = 0, s_max = 0;
         for (int k = 0; k < ne; ++k) {
-            if (lo > t.E[k])
+            // E_k = -inf (an edge at 0, D_k = +inf): every pair is past it,
+            // the bottom cell's open end included
+            if (lo > t.E[k] || t.E[k] == -HUGE_VAL)
                 ++s_min;
             if (hi >= t.E[k])
                 ++s_max;

@@ -334,9 +334,10 @@ __device__ __forceinline__ uint32_t addr64(int32_t hi, const Consts &k) {
 // smallest and largest key hold the same certain slot, every key between
 // them maps to it.  When that holds on every lane the step adds its pairs
 // with one LDS atomic per lane instead of a lookup and an atomic per pair.
-// Used on the matrix-core path, whose tiles are compact (16 rows x 16
-// columns); on the vector paths a lane's rows lie 64 apart, the test succeeds
-// less often and its two dependent lookups cost more than they save.
+// Used on the matrix-core path (compact 16 x 16 tiles) and on the FP32 path
+// (a wavefront's 256 rows are consecutive in the Morton order: on the octant
+// workload 45 % of the steps that are not beyond the last edge pass); on
+// the FP64 vector path, whose steps are cheaper to look up than to test, not.
 __device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint32_t n, const Consts &k,
                                               Counters &cnt) {
     if (!wave_all(e_lo == e_hi && !(e_lo & k.flag)))
@@ -508,7 +509,7 @@ __device__ __forceinline__ void bin_block(int slot, uint32_t n, const PairArgs &
 // One step: JN columns against the P rows of every lane.  All JN * P table
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
-template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT, bool M3>
+template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT, bool M3, bool ONE>
 __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
@@ -543,6 +544,24 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             cnt.beyond += JN * P;
             ++cnt.beyond_steps;
             return;
+        }
+        if constexpr (ONE) {
+            // every pair of the step in one slot: the cells of each lane's
+            // smallest and largest key hold the same certain slot on every lane
+            // (a wavefront's 4 x 64 rows are consecutive in the Morton order, so
+            // at angles large against their extent this is common; with pruning
+            // such blocks are mostly pruned, and the kernel skips the test to
+            // save its registers)
+            uint32_t mx = __float_as_uint(q[0][0]);
+#pragma unroll
+            for (int t = 0; t < JN; ++t)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    mx = max(mx, __float_as_uint(q[t][p]));
+            const uint32_t e_lo = lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(m, k));
+            const uint32_t e_hi = lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(mx, k));
+            if (one_slot_step(e_lo, e_hi, JN * P, k, cnt))
+                return;
         }
     }
 #pragma unroll
@@ -669,7 +688,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP32 path).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
                                           const int (&ii)[P], const int (&il)[P], int ie, int j0, int j1,
@@ -701,7 +720,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
-            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
@@ -712,7 +731,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     }
     for (; j < j1; ++j) {
         const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
-        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
     }
 }
 
@@ -752,12 +771,12 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp32<LUT8, MASKED, P, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
+            cols_fp32<LUT8, MASKED, P, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp32<LUT8, MASKED, P, DIRECT, M3>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
+    cols_fp32<LUT8, MASKED, P, DIRECT, M3, !PRUNE>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
