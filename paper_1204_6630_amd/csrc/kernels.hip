@@ -605,7 +605,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
         }
 }
 
-template <bool LUT8, bool MASKED, int P, int JN, bool M3>
+template <bool LUT8, bool MASKED, int P, int JN, bool M3, bool ONE>
 __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie,
@@ -648,6 +648,19 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
             cnt.beyond += JN * P;
             ++cnt.beyond_steps;
             return;
+        }
+        if constexpr (ONE) {
+            // every pair of the step in one slot (as on the FP32 path)
+            int32_t mx = __double2hiint(e[0][0]);
+#pragma unroll
+            for (int t = 0; t < JN; ++t)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    mx = max(mx, __double2hiint(e[t][p]));
+            const uint32_t e_lo = lds_read_entry<LUT8>(addr64<LUT8>(m, k));
+            const uint32_t e_hi = lds_read_entry<LUT8>(addr64<LUT8>(mx, k));
+            if (one_slot_step(e_lo, e_hi, JN * P, k, cnt))
+                return;
         }
     }
 #pragma unroll
@@ -780,7 +793,7 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
-template <bool LUT8, bool MASKED, int P, bool M3>
+template <bool LUT8, bool MASKED, int P, bool M3, bool ONE>
 __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie, int j0, int j1,
@@ -790,9 +803,9 @@ __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, c
     cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
     for (; j + kColsPerStepF64 <= j1; j += kColsPerStepF64)
-        step_fp64<LUT8, MASKED, P, kColsPerStepF64, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        step_fp64<LUT8, MASKED, P, kColsPerStepF64, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
     for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        step_fp64<LUT8, MASKED, P, 1, M3, false>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
 }
 
 template <bool LUT8, bool MASKED, int P, bool PRUNE, bool M3>
@@ -822,12 +835,12 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp64<LUT8, MASKED, P, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
+            cols_fp64<LUT8, MASKED, P, M3, false>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp64<LUT8, MASKED, P, M3>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
+    cols_fp64<LUT8, MASKED, P, M3, !PRUNE>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
