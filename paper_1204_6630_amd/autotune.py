@@ -2,7 +2,7 @@
 
 Knobs: rows held per lane (or row groups of 16 on the matrix-core path), LDS
 histogram copies per wavefront, the largest column range of a work unit, the
-grid size, the cell-table budget and, for FP32 byte tables, the direct or the
+grid size, the cell-table budget and, for FP32 byte tables, the wrapped or the
 clamped table layout.  The search is a coordinate descent from the library's
 defaults: each knob in turn is swept over its candidates with the others held
 at the best values so far, on a sample of the caller's workload (a block of
@@ -43,7 +43,8 @@ def _device_key(precision: int, nbins: int) -> str:
         hip = getattr(torch.version, "hip", "") or ""
     except Exception:  # pragma: no cover
         name, hip = "unknown", ""
-    return f"v3|{name}|hip{hip}|prec{precision}|nbins{nbins}"
+    # the version part changes whenever the kernels' trade-offs do
+    return f"v4|{name}|hip{hip}|prec{precision}|nbins{nbins}"
 
 
 def _load_cache() -> dict:
