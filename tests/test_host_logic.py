@@ -585,3 +585,17 @@ def test_3d_matrix_band_is_safe_for_any_rounding(rmax):
             assert np.all(past[e2 >= hi[k]]), k
             assert not np.any(past[e2 < lo[k]]), k
     assert np.all(hi - lo <= 2.0 ** -46 * rmax * rmax * 1.01 + 4 * np.spacing(hi))
+
+
+@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX])
+def test_edge_at_zero_never_flags(precision):
+    """An edge at 0 degrees (D_0 = +inf, E_0 = -inf) is passed by every pair,
+    so no cell may leave it undecided (0x8000 | 0) and every cell's slot is
+    at least 1; the bottom cell, open towards -inf, included."""
+    for edges in (np.array([0.0, 1.0, 120.0]), np.linspace(0.0, 180.0, 31)):
+        _, _, _, cells, _ = tp.compile_cells(edges, precision)
+        cells = cells.astype(np.int64)
+        assert not np.any(cells == 0x8000)
+        certain = cells < 0x8000
+        assert np.all(cells[certain] >= 1)
+        assert np.all((cells[~certain] & 0x7FFF) >= 1) or np.all(cells[~certain] == 0xFFFF)
