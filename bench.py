@@ -111,6 +111,9 @@ def parse():
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3-D xi(r) step (1e6 x 2e6 points in a box of side 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=120,
+                    help="octant workload: jobs of the bounded serving leg (p50/p99 latency "
+                         "in the same line); 0 skips it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
@@ -606,6 +609,19 @@ def main():
         cb["extrapolated_full_step_s"] = round(pairs_step / (cb["value"] * 1e9), 1)
         res["cpu_baseline"] = cb
     ctx.close()
+    if args.serving_jobs > 0:
+        # the metric's latency half: a bounded Poisson job stream on a context
+        # of its own (the serving workload's recipe with fewer jobs)
+        sv = bench_serving(argparse.Namespace(**{**vars(args), "jobs": args.serving_jobs}), tp)
+        res["serving_stream"] = {
+            "jobs": sv["config"]["jobs"], "n_random": sv["config"]["n_random"],
+            "arrival_rate_per_s": sv["config"]["arrival_rate_per_s"],
+            "latency_ms": sv["latency_ms"], "gpairs_s_launched": sv["value"],
+            "served_gpairs_s_with_rr_cache": sv["served_gpairs_s_with_rr_cache"],
+            "makespan_s": round(sv["ms_per_step"] / 1e3, 3), "max_inflight": sv["max_inflight"],
+            "note": "DD/DR/RR jobs 40/40/20, sizes log-uniform [1e3, 1e6], 3 resident 2e6 "
+                    "randoms with cached RR, 1 GiB HBM budget; latency = arrival to result "
+                    "on the host; not in value"}
     print(json.dumps(res), flush=True)
 
 
