@@ -31,7 +31,7 @@ HIP_FLAGS = [
 HOST_FLAGS = [
     "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin",
     "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"),
-    "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
+    "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 
@@ -54,7 +54,7 @@ def build(out_dir: str | None = None, verbose: bool = True) -> str:
         objs.append(o)
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
-          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lm", "-pthread",
           "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, LIB)
     return LIB

@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -333,20 +334,69 @@ uint64_t quant21(double c, double lo = -1.0, double hi = 1.0) {
     return (uint64_t)t;
 }
 
+// Host threads for catalog preparation: large catalogs are split into
+// contiguous chunks, at most 16, none smaller than 32768 points.  Every
+// per-point result is computed exactly as in a serial loop, so the stored
+// catalog does not depend on the thread count.
+int host_threads(int64_t n) {
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    return (int)std::max<int64_t>(1, std::min<int64_t>({hw, 16, n / 32768}));
+}
+
+template <typename F>
+void parallel_chunks(int64_t n, int nt, F fn) {
+    if (nt <= 1) {
+        fn(0, 0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back(fn, t, n * t / nt, n * (t + 1) / nt);
+    for (auto &t : th)
+        t.join();
+}
+
 // Stored order: Morton order of the unit vectors, grouped by region first
-// when labels are given (so each region is a contiguous range of rows).
+// when labels are given (so each region is a contiguous range of rows).  The
+// key ends in the point index, so it is a strict total order: chunks sorted
+// on their own and merged pairwise give the one sorted sequence.
 std::vector<int64_t> morton_order(const double *x, const double *y, const double *z, int64_t n,
                                   const int32_t *region = nullptr, double lo = -1.0, double hi = 1.0) {
-    std::vector<std::tuple<int32_t, uint64_t, int64_t>> k((size_t)n);
-    for (int64_t i = 0; i < n; ++i)
-        k[i] = std::make_tuple(region ? region[i] : 0,
-                               spread3(quant21(x[i], lo, hi)) | spread3(quant21(y[i], lo, hi)) << 1 |
-                                   spread3(quant21(z[i], lo, hi)) << 2,
-                               i);
-    std::sort(k.begin(), k.end());
+    using Key = std::tuple<int32_t, uint64_t, int64_t>;
+    std::vector<Key> k((size_t)n), tmp;
+    const int nt = host_threads(n);
+    std::vector<int64_t> bound((size_t)nt + 1);
+    for (int t = 0; t <= nt; ++t)
+        bound[t] = n * t / nt;
+    parallel_chunks(n, nt, [&](int, int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i)
+            k[i] = std::make_tuple(region ? region[i] : 0,
+                                   spread3(quant21(x[i], lo, hi)) | spread3(quant21(y[i], lo, hi)) << 1 |
+                                       spread3(quant21(z[i], lo, hi)) << 2,
+                                   i);
+        std::sort(k.begin() + b, k.begin() + e);
+    });
+    if (nt > 1)
+        tmp.resize((size_t)n);
+    // merge rounds: runs of w chunks become runs of 2w chunks
+    for (int w = 1; w < nt; w *= 2) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; t += 2 * w) {
+            const int64_t b = bound[t], m = bound[std::min(t + w, nt)], e = bound[std::min(t + 2 * w, nt)];
+            th.emplace_back([&, b, m, e] {
+                std::merge(k.begin() + b, k.begin() + m, k.begin() + m, k.begin() + e, tmp.begin() + b);
+            });
+        }
+        for (auto &t : th)
+            t.join();
+        k.swap(tmp);
+    }
     std::vector<int64_t> order((size_t)n);
-    for (int64_t i = 0; i < n; ++i)
-        order[i] = std::get<2>(k[i]);
+    parallel_chunks(n, nt, [&](int, int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i)
+            order[i] = std::get<2>(k[i]);
+    });
     return order;
 }
 
@@ -412,15 +462,17 @@ int add_catalog(tpcf_ctx *ctx, const double *x, const double *y, const double *z
     size_t alloc_n = (size_t)(n > 0 ? n : 1);
     std::vector<double> h64(3 * alloc_n, 0.0);
     std::vector<float> h32(3 * alloc_n, 0.0f);
-    for (int64_t r = 0; r < n; ++r) {
-        const int64_t i = c.order[r];
-        h64[r] = x[i];
-        h64[alloc_n + r] = y[i];
-        h64[2 * alloc_n + r] = z[i];
-        h32[r] = (float)x[i];
-        h32[alloc_n + r] = (float)y[i];
-        h32[2 * alloc_n + r] = (float)z[i];
-    }
+    parallel_chunks(n, host_threads(n), [&](int, int64_t b, int64_t e) {
+        for (int64_t r = b; r < e; ++r) {
+            const int64_t i = c.order[r];
+            h64[r] = x[i];
+            h64[alloc_n + r] = y[i];
+            h64[2 * alloc_n + r] = z[i];
+            h32[r] = (float)x[i];
+            h32[alloc_n + r] = (float)y[i];
+            h32[2 * alloc_n + r] = (float)z[i];
+        }
+    });
     c.bytes64 = sizeof(double) * 3 * alloc_n;
     c.bytes32 = sizeof(float) * 3 * alloc_n;
     TRY(dev_alloc(ctx->mem, (void **)&c.d64, c.bytes64));
@@ -1188,16 +1240,19 @@ int tpcf_upload_catalog_regions(tpcf_ctx *ctx, const double *ra_deg, const doubl
     if (n > 0 && (!ra_deg || !dec_deg))
         return fail(TPCF_E_INVALID, "ra_deg/dec_deg is NULL");
     const double deg = M_PI / 180.0;
-    std::vector<double> x((size_t)n), y((size_t)n), z((size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i)
         if (!isfinite(ra_deg[i]) || !isfinite(dec_deg[i]))
             return fail(TPCF_E_INVALID, "ra/dec must be finite");
-        double a = ra_deg[i] * deg;
-        double b = dec_deg[i] * deg;
-        x[i] = cos(b) * cos(a);
-        y[i] = cos(b) * sin(a);
-        z[i] = sin(b);
-    }
+    std::vector<double> x((size_t)n), y((size_t)n), z((size_t)n);
+    parallel_chunks(n, host_threads(n), [&](int, int64_t b0, int64_t e0) {
+        for (int64_t i = b0; i < e0; ++i) {
+            double a = ra_deg[i] * deg;
+            double b = dec_deg[i] * deg;
+            x[i] = cos(b) * cos(a);
+            y[i] = cos(b) * sin(a);
+            z[i] = sin(b);
+        }
+    });
     return add_catalog(ctx, x.data(), y.data(), z.data(), n, out_cat, region, region ? nreg : 0);
 }
 
