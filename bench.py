@@ -95,6 +95,9 @@ def parse():
                     help="octant: 1e6 x 2e6 DD+DR+RR (default); batched: 64 uneven catalogs "
                          "against one 1e6 random in one launch; serving: Poisson job stream")
     ap.add_argument("--jobs", type=int, default=300, help="serving: number of jobs")
+    ap.add_argument("--defer-release-mb", type=int, default=1024,
+                    help="serving: finished jobs' catalogs are released in batches of up to "
+                         "this many MiB (0 releases each at its job's completion)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune each path's launch shape on a sample first (default: the "
                          "library's defaults, which are the tuned shapes for this workload)")
@@ -240,7 +243,8 @@ def bench_serving(args, tp):
         j.arrival = float(a)
     used0, _ = ctx.hbm_usage()
     ctx.set_hbm_budget(used0 + (1 << 30))
-    srv = Server(LibraryBackend(ctx, e), randoms=rnd, n_random=n_random, max_inflight=8)
+    srv = Server(LibraryBackend(ctx, e), randoms=rnd, n_random=n_random, max_inflight=8,
+                 max_deferred_bytes=args.defer_release_mb << 20)
     print(f"# serving: rate {rate/1e9:.0f} Gpairs/s, lambda {lam:.2f}/s, {len(jobs)} jobs",
           file=sys.stderr, flush=True)
     ctx.stats(reset=True)
@@ -263,7 +267,8 @@ def bench_serving(args, tp):
         "data": "synthetic",
         "config": {"workload": "serving_stream", "jobs": len(jobs), "n_random": n_random,
                    "randoms": 3, "nbins": int(e.size - 1), "arrival_rate_per_s": round(lam, 3),
-                   "hbm_budget_bytes": 1 << 30, "parallelism": "single-gpu"},
+                   "hbm_budget_bytes": 1 << 30, "defer_release_mb": args.defer_release_mb,
+                   "parallelism": "single-gpu"},
         "latency_ms": {"p50": round(rep.percentile(50) * 1e3, 2),
                        "p99": round(rep.percentile(99) * 1e3, 2)},
         "computed_pairs": computed, "served_pairs": rep.pairs,

@@ -227,6 +227,9 @@ struct tpcf_ctx {
     std::map<int64_t, AsyncJob> jobs;
     std::map<std::string, std::unique_ptr<BatchGraph>> graphs;
     std::map<std::string, std::vector<uint64_t>> result_cache;
+    // pinned result buffers of retired jobs, reused by later submits:
+    // hipHostFree would wait for the whole device at every completion
+    std::vector<uint64_t *> pinned_free;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     uint64_t pairs_since_reset = 0;
@@ -1143,8 +1146,8 @@ void retire_job(tpcf_ctx *ctx, std::map<int64_t, AsyncJob>::iterator it) {
     AsyncJob &j = it->second;
     if (j.ev)
         (void)hipEventDestroy(j.ev);
-    if (j.hres)
-        (void)hipHostFree(j.hres);
+    if (j.hres)      // the job's event has completed: no GPU work reads it
+        ctx->pinned_free.push_back(j.hres);
     if (j.ws >= 0)
         ctx->pool[j.ws].inflight--;
     ctx->jobs.erase(it);
@@ -1208,6 +1211,9 @@ int tpcf_close(tpcf_ctx *ctx) {
     (void)sync_all(ctx);
     while (!ctx->jobs.empty())
         retire_job(ctx, ctx->jobs.begin());
+    for (uint64_t *p : ctx->pinned_free)
+        (void)hipHostFree(p);
+    ctx->pinned_free.clear();
     drop_graphs(ctx);
     for (auto &kv : ctx->cats) {
         if (kv.second.owns64)
@@ -1653,7 +1659,12 @@ int tpcf_submit(tpcf_ctx *ctx, const tpcf_job_desc *job, int64_t *out_job) {
         Workspace &w = ctx->pool[best];
         TRY(w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots));
         void *pinned = nullptr;
-        HIP_TRY(hipHostMalloc(&pinned, sizeof(uint64_t) * (kMaxSlots + 8), hipHostMallocCoherent));
+        if (!ctx->pinned_free.empty()) {
+            pinned = ctx->pinned_free.back();
+            ctx->pinned_free.pop_back();
+        } else {
+            HIP_TRY(hipHostMalloc(&pinned, sizeof(uint64_t) * (kMaxSlots + 8), hipHostMallocCoherent));
+        }
         j.hres = (uint64_t *)pinned;
         j.hcancel = (volatile int *)(j.hres + kMaxSlots);
         *j.hcancel = 0;
@@ -1669,7 +1680,7 @@ int tpcf_submit(tpcf_ctx *ctx, const tpcf_job_desc *job, int64_t *out_job) {
             (void)hipStreamSynchronize(w.stream);
             if (j.ev)
                 (void)hipEventDestroy(j.ev);
-            (void)hipHostFree(pinned);
+            ctx->pinned_free.push_back((uint64_t *)pinned);
             return rc ? rc : fail(TPCF_E_HIP, std::string("submit: ") + hipGetErrorString(e));
         }
         j.ws = best;

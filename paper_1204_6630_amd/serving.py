@@ -7,9 +7,14 @@ random catalog, RR of a resident random catalog) arrive over time.  The loop
     device memory fits the HBM budget (catalog upload, then ``tpcf_submit``);
     a job that does not fit waits until completed jobs release memory;
   * polls in-flight jobs, which run concurrently on the library's streams,
-    records each result and its latency (arrival to result on the host), and
-    releases the job's catalog;
-  * serves repeated RR requests from the library's result cache.
+    records each result and its latency (arrival to result on the host);
+  * releases finished jobs' catalogs in batches: when nothing is in flight,
+    when admission needs the memory, or past ``max_deferred_bytes``.  Freeing
+    device memory waits for the whole device, so a release at every
+    completion would stall the loop behind the longest running job;
+  * serves repeated RR requests from the library's result cache, and an RR
+    request for a random catalog whose RR count is still running waits for
+    that count and takes its result instead of launching a second one.
 
 The device side is the C library; this module only sequences calls.  The
 backend is injectable so the admission logic can be exercised without a GPU.
@@ -90,13 +95,15 @@ class LibraryBackend:
 
 class Server:
     def __init__(self, backend, randoms: list, n_random: int, max_inflight: int = 8,
-                 clock=time.perf_counter, idle=lambda: time.sleep(0.0002)):
+                 clock=time.perf_counter, idle=lambda: time.sleep(0.0002),
+                 max_deferred_bytes: int = 1 << 30):
         self.b = backend
         self.randoms = randoms          # resident random catalog ids
         self.n_random = n_random
         self.max_inflight = max_inflight
         self.clock = clock
         self.idle = idle
+        self.max_deferred_bytes = max_deferred_bytes
 
     def bytes_needed(self, job: Job) -> int:
         own = job.n * BYTES_PER_POINT if job.kind != "RR" else 0
@@ -107,6 +114,18 @@ class Server:
         pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
         waiting = collections.deque()
         inflight = {}                  # job handle -> (job, own catalog or None)
+        deferred = []                  # catalogs of finished jobs, not yet released
+        rr_leader = {}                 # random index -> handle of its running RR count
+        followers = collections.defaultdict(list)   # handle -> RR jobs waiting on it
+        deferred_bytes = 0
+
+        def release_deferred():
+            nonlocal deferred_bytes
+            for c in deferred:
+                self.b.release(c)
+            deferred.clear()
+            deferred_bytes = 0
+
         t0 = self.clock()
         while pending or waiting or inflight:
             now = self.clock() - t0
@@ -114,10 +133,22 @@ class Server:
                 waiting.append(pending.popleft())
             progressed = False
             # admission, in arrival order
-            while waiting and len(inflight) < self.max_inflight:
+            while waiting:
                 job = waiting[0]
+                if job.kind == "RR" and job.random in rr_leader:
+                    # needs no slot: it waits on the running count
+                    waiting.popleft()
+                    followers[rr_leader[job.random]].append(job)
+                    rep.admitted_at[job.id] = self.clock() - t0
+                    progressed = True
+                    continue
+                if len(inflight) >= self.max_inflight:
+                    break
                 used, budget = self.b.usage()
                 if budget and used + self.bytes_needed(job) > budget and inflight:
+                    if deferred:
+                        release_deferred()
+                        continue    # check again with that memory back
                     break           # wait for memory to be released
                 cat = None
                 try:
@@ -134,10 +165,15 @@ class Server:
                     if cat is not None:
                         self.b.release(cat)
                     if e.code == -5 and inflight:
+                        if deferred:
+                            release_deferred()
+                            continue
                         break       # over budget: retry once something completes
                     raise
                 waiting.popleft()
                 inflight[h] = (job, cat)
+                if job.kind == "RR":
+                    rr_leader[job.random] = h
                 rep.admitted_at[job.id] = self.clock() - t0
                 rep.max_inflight = max(rep.max_inflight, len(inflight))
                 rep.max_bytes = max(rep.max_bytes, self.b.usage()[0])
@@ -152,12 +188,22 @@ class Server:
                 rep.results[job.id] = res
                 rep.latency[job.id] = t - job.arrival
                 rep.pairs += job.pairs(self.n_random)
+                if job.kind == "RR" and rr_leader.get(job.random) == h:
+                    del rr_leader[job.random]
+                for f in followers.pop(h, []):
+                    rep.results[f.id] = res.copy()
+                    rep.latency[f.id] = t - f.arrival
+                    rep.pairs += f.pairs(self.n_random)
                 if cat is not None:
-                    self.b.release(cat)
+                    deferred.append(cat)
+                    deferred_bytes += self.bytes_needed(job)
                 progressed = True
+            if deferred and (not inflight or deferred_bytes > self.max_deferred_bytes):
+                release_deferred()
             if not progressed:
                 self.idle()
         rep.makespan = self.clock() - t0
+        release_deferred()
         return rep
 
 

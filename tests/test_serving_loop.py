@@ -137,3 +137,102 @@ def test_poisson_arrivals_rate():
     a = poisson_arrivals(20000, 40.0, g)
     assert np.all(np.diff(a) > 0)
     assert abs(a[-1] / 20000 - 1 / 40.0) < 0.05 / 40.0 * 5
+
+
+class ReleaseWatch(FakeBackend):
+    """Records, at each release, how many jobs are still running and whether
+    the loop was blocked on memory (an upload would not have fit)."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.release_log = []
+
+    def release(self, cat):
+        self.release_log.append(len(self.jobs))
+        super().release(cat)
+
+
+def test_catalogs_are_released_in_batches_when_the_device_is_idle():
+    # no budget: a release (a device-wide wait on the GPU) only happens
+    # once nothing is in flight, or past the deferred-bytes cap
+    jobs = _jobs(150, seed=3, rate=400.0)
+    clock = FakeClock()
+    be = ReleaseWatch(clock, budget=0)
+    srv = Server(be, randoms=[101, 102, 103], n_random=1000, max_inflight=4,
+                 clock=clock, idle=clock.advance)
+    rep = srv.run(jobs)
+    assert set(rep.results) == {j.id for j in jobs}
+    assert be.used == 10_000 and not be.cats
+    assert len(be.release_log) == sum(1 for j in jobs if j.kind != "RR")
+    assert all(n == 0 for n in be.release_log)
+    # a small cap forces releases while jobs run; everything still completes
+    clock = FakeClock()
+    be = ReleaseWatch(clock, budget=0)
+    srv = Server(be, randoms=[101, 102, 103], n_random=1000, max_inflight=4,
+                 clock=clock, idle=clock.advance, max_deferred_bytes=1)
+    rep = srv.run(jobs)
+    assert set(rep.results) == {j.id for j in jobs}
+    assert be.used == 10_000
+    assert any(n > 0 for n in be.release_log)
+
+
+def test_deferred_catalogs_are_released_when_admission_needs_memory():
+    # a tight budget: admission frees the deferred catalogs rather than wait
+    jobs = _jobs(150, seed=4, rate=400.0)
+    budget = 10_000 + 3 * 100_000 * BYTES_PER_POINT
+    clock = FakeClock()
+    be = ReleaseWatch(clock, budget=budget)
+    srv = Server(be, randoms=[101, 102, 103], n_random=1000, max_inflight=4,
+                 clock=clock, idle=clock.advance)
+    rep = srv.run(jobs)
+    assert set(rep.results) == {j.id for j in jobs}
+    assert be.peak <= budget and be.used == 10_000
+    assert any(n > 0 for n in be.release_log)
+
+
+class RRWatch(FakeBackend):
+    """Flags a second RR count of one random catalog while the first runs."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.rr_running = {}        # job id -> random catalog id
+        self.rr_submits = 0
+        self.overlap = False
+
+    def submit(self, kind, a, b):
+        jid = super().submit(kind, a, b)
+        if kind == tp.RR:
+            self.rr_submits += 1
+            self.overlap |= a in self.rr_running.values()
+            self.rr_running[jid] = a
+        return jid
+
+    def poll(self, jid):
+        res = super().poll(jid)
+        if res is not None:
+            self.rr_running.pop(jid, None)
+        return res
+
+
+def test_rr_requests_share_a_running_rr_count():
+    # RR requests 1 ms apart over three random catalogs (an RR count takes
+    # 25 ms here), with small DR jobs between them: later requests arrive
+    # while their random catalog's RR count runs and take its result
+    jobs = []
+    for k in range(90):
+        if k % 3 == 2:
+            jobs.append(Job(id=k, kind="DR", arrival=k * 1e-3, n=20, random=k % 3))
+        else:
+            jobs.append(Job(id=k, kind="RR", arrival=k * 1e-3, random=(k // 3) % 3))
+    clock = FakeClock()
+    be = RRWatch(clock, budget=0, rate=2e7)
+    srv = Server(be, randoms=[101, 102, 103], n_random=1000, max_inflight=4,
+                 clock=clock, idle=clock.advance)
+    rep = srv.run(jobs)
+    assert set(rep.results) == {j.id for j in jobs}
+    assert not be.overlap
+    n_rr = sum(1 for j in jobs if j.kind == "RR")
+    assert be.rr_submits < n_rr // 4
+    for j in jobs:
+        assert int(rep.results[j.id][0]) == tp.__dict__[j.kind]
+        assert rep.latency[j.id] >= 0
