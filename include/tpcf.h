@@ -158,7 +158,10 @@ int tpcf_catalog_order(tpcf_ctx *ctx, int32_t cat, int64_t *out_order);
 /* Number of objects of a catalog. */
 int tpcf_catalog_size(tpcf_ctx *ctx, int32_t cat, int64_t *out_n);
 
-/* Release a catalog id and the device memory the library owns for it. */
+/* Release a catalog id and the device memory the library owns for it.
+ * Freeing device memory waits until all work on the device has finished
+ * (jobs in flight on any stream included), so callers that keep jobs running
+ * release catalogs in batches rather than at every completion. */
 int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat);
 
 /* Jackknife regions.  The paper judges its residuals against the statistical
