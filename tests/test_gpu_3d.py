@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import paper_1204_6630_amd as tp
+import rounding_probes as rp
 import synthcat
 
 pytestmark = pytest.mark.gpu
@@ -56,6 +57,31 @@ def test_lattice_ties_on_edges(ctx, prec, offset):
         assert np.array_equal(got, ref)
     finally:
         ctx.release_catalog(cid)
+
+
+@pytest.mark.parametrize("prec", PRECS3)
+def test_rounding_order_probes_3d(ctx, prec):
+    """The exact FP64 rule of every 3-D path is (dx^2 + dy^2) + dz^2 of the
+    rounded differences, unfused and left to right: probe pairs where fused or
+    reordered evaluations give another distance bin, expected histograms from
+    exact rational arithmetic (DR over all cross pairs, DD over the union)."""
+    def build():
+        a, b, edges = rp.box_probes()
+        cross = [(i, j) for i in range(a.shape[0]) for j in range(b.shape[0])]
+        u = np.concatenate([a, b])
+        upper = [(i, j) for i in range(u.shape[0]) for j in range(i + 1, u.shape[0])]
+        return (a, b, edges, u, rp.expected_box_hist(a, b, edges, cross),
+                rp.expected_box_hist(u, u, edges, upper))
+    a, b, edges, u, exp_dr, exp_dd = _cached("probes3d", build)
+    ca = ctx.upload_catalog_3d(*a.T.copy())
+    cb = ctx.upload_catalog_3d(*b.T.copy())
+    cu = ctx.upload_catalog_3d(*u.T.copy())
+    try:
+        assert np.array_equal(ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec), exp_dr)
+        assert np.array_equal(ctx.count(tp.DD, cu, edges, precision=prec), exp_dd)
+    finally:
+        for c in (ca, cb, cu):
+            ctx.release_catalog(c)
 
 
 @pytest.fixture(scope="module")

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import paper_1204_6630_amd as tp
+import rounding_probes as rp
 import synthcat
 
 pytestmark = pytest.mark.gpu
@@ -154,6 +155,36 @@ def test_exact_dot_probes_on_every_threshold(ctx, prec):
         assert np.array_equal(got, ref)
         got = ctx.count(tp.DD, cu, edges, precision=prec)
         assert np.array_equal(got, oracle.count(oracle.DD, u, edges))
+        for c in (ca, cb, cu):
+            ctx.release_catalog(c)
+
+
+def _probe_sets():
+    if "probes" not in _cache:
+        a, b, edges = rp.sky_probes()
+        cross = [(i, j) for i in range(a.shape[0]) for j in range(b.shape[0])]
+        u = np.concatenate([a, b])
+        upper = [(i, j) for i in range(u.shape[0]) for j in range(i + 1, u.shape[0])]
+        _cache["probes"] = (a, b, edges, u, rp.expected_sky_hist(a, b, edges, cross),
+                            rp.expected_sky_hist(u, u, edges, upper))
+    return _cache["probes"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_rounding_order_probes(ctx, prec):
+    """The exact FP64 rule of every path is the unfused, left-to-right dot
+    product: probe pairs where fused or reordered evaluations land in another
+    bin (edges placed between them), with expected histograms from exact
+    rational arithmetic rounded after each operation, for DR (all cross pairs)
+    and DD (the union, auto-pairs with the masked diagonal)."""
+    a, b, edges, u, exp_dr, exp_dd = _probe_sets()
+    ca = ctx.upload_catalog_xyz(*a.T.copy())
+    cb = ctx.upload_catalog_xyz(*b.T.copy())
+    cu = ctx.upload_catalog_xyz(*u.T.copy())
+    try:
+        assert np.array_equal(ctx.count(tp.DR, ca, edges, cat_b=cb, precision=prec), exp_dr)
+        assert np.array_equal(ctx.count(tp.DD, cu, edges, precision=prec), exp_dd)
+    finally:
         for c in (ca, cb, cu):
             ctx.release_catalog(c)
 

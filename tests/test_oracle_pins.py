@@ -18,6 +18,7 @@ import pytest
 from scipy.spatial.distance import cdist
 
 import oracle
+import rounding_probes as rp
 import synthcat
 from oracle import tiny
 
@@ -590,3 +591,120 @@ def test_3d_region_counts_deletion_identity_and_pure_python():
             if ra_[j] != ra_[i]:
                 touch[ra_[j], s] += 1
     assert np.array_equal(tot, dd_t) and np.array_equal(touch, dd_touch)
+
+
+# --------------------------------------------------------------------------
+# FP64 operation order of the rule.  The angle is the arc-cosine of the dot
+# product (Section 3, first bullet), read as (x_i x_j + y_i y_j) + z_i z_j
+# with each operation rounded and no FMA (the paper's CPU in Table 1 has
+# none); the 3-D squared distance likewise.  The probes are pairs where a
+# fused, reordered or correctly rounded evaluation gives another angle, with
+# edges placed between the two, and the expected values come from exact
+# rational arithmetic rounded after each operation (tests/rounding_probes.py).
+# --------------------------------------------------------------------------
+
+ORDERS = ("fma_xy_then_add_z", "fma_yx_then_add_z", "add_xy_then_fma_z", "fma_chain_x_y_z",
+          "fma_chain_y_x_z", "x_plus_yz", "xz_plus_y", "correctly_rounded")
+
+
+def _sky_expected(a, b):
+    return np.array([rp.angle_of(rp.dot_orders(a[i], b[i])["rule"]) for i in range(a.shape[0])])
+
+
+def _box_expected(a, b):
+    return np.array([math.sqrt(rp.d2_orders(a[i], b[i])["rule"]) for i in range(a.shape[0])])
+
+
+def test_dot_product_order_is_pinned_by_probes():
+    a, b, edges = rp.sky_probes()
+    er = edges * DEG
+    assert a.shape[0] == 40 and np.all(np.abs(a) >= 0.05) and np.all(np.abs(b) >= 0.05)
+    # the oracle's angles are the rule's, bit for bit
+    assert np.array_equal(oracle.pair_angles(a.T, b.T), _sky_expected(a, b))
+    slots = oracle.pair_slots(a.T, b.T, edges)
+    rule = np.array([rp.slot(t, er) for t in _sky_expected(a, b)])
+    assert np.array_equal(slots, rule)
+    # every other order moves at least one probe to another bin
+    for name in ORDERS:
+        alt = np.array([rp.slot(rp.angle_of(rp.dot_orders(a[i], b[i])[name]), er)
+                        for i in range(a.shape[0])])
+        assert np.any(alt != rule), name
+    # whole DR histogram of every cross pair
+    pairs = [(i, j) for i in range(a.shape[0]) for j in range(b.shape[0])]
+    exp = rp.expected_sky_hist(a, b, edges, pairs)
+    assert np.array_equal(oracle.count(oracle.DR, a.T, edges, b_xyz=b.T), exp)
+    assert not np.array_equal(rp.expected_sky_hist(a, b, edges, pairs, "fma_chain_x_y_z"), exp)
+
+
+def test_squared_distance_order_is_pinned_by_probes():
+    a, b, edges = rp.box_probes()
+    assert np.array_equal(oracle.pair_distances(a.T, b.T), _box_expected(a, b))
+    rule = np.array([rp.slot(r, edges) for r in _box_expected(a, b)])
+    for name in ORDERS:
+        alt = np.array([rp.slot(math.sqrt(rp.d2_orders(a[i], b[i])[name]), edges)
+                        for i in range(a.shape[0])])
+        assert np.any(alt != rule), name
+    pairs = [(i, j) for i in range(a.shape[0]) for j in range(b.shape[0])]
+    exp = rp.expected_box_hist(a, b, edges, pairs)
+    assert np.array_equal(oracle.count3d(oracle.DR, a.T, edges, b_xyz=b.T), exp)
+
+
+def _has_fma_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return " fma " in f.read().replace("\n", " ")
+    except OSError:
+        return False
+
+
+def _planted_oracle(tmp_path, how):
+    """A copy of the C oracle with the rounding order broken: `fma_call`
+    rewrites the dot product and the squared distance with fma(); `contracted`
+    builds the unchanged source with contraction on and FMA instructions."""
+    import ctypes
+    import subprocess
+    with open(os.path.join(os.path.dirname(oracle.__file__), "tpcf_oracle.c")) as f:
+        src = f.read()
+    flags = ["-ffp-contract=off"]
+    if how == "fma_call":
+        for old, new in (("double d = (xi * xj + yi * yj) + zi * zj;",
+                          "double d = fma(zi, zj, fma(yi, yj, xi * xj));"),
+                         ("double d2 = (dx * dx + dy * dy) + dz * dz;",
+                          "double d2 = fma(dz, dz, fma(dy, dy, dx * dx));")):
+            assert old in src
+            src = src.replace(old, new)
+    else:
+        flags = ["-ffp-contract=fast", "-mfma"]
+    c = tmp_path / "planted.c"
+    c.write_text(src)
+    so = tmp_path / "planted.so"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", *flags, "-fno-fast-math", "-fno-builtin", "-fPIC",
+                           "-shared", "-pthread", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    P, i64 = ctypes.c_void_p, ctypes.c_int64
+    for fn in (lib.oracle_pair_angles, lib.oracle_pair_distances):
+        fn.argtypes = [i64, P, P, P, P, P, P, P]
+        fn.restype = ctypes.c_int
+    return lib
+
+
+def _call_pairs(fn, a, b):
+    cols = [np.ascontiguousarray(a[:, c]) for c in range(3)] + \
+           [np.ascontiguousarray(b[:, c]) for c in range(3)]
+    out = np.empty(a.shape[0])
+    fn(a.shape[0], *[v.ctypes.data for v in cols], out.ctypes.data)
+    return out
+
+
+@pytest.mark.parametrize("how", ["fma_call", "contracted"])
+def test_rounding_order_pins_catch_a_fused_oracle(tmp_path, how):
+    """Planted mistake: an oracle whose dot product and squared distance use
+    fused multiply-adds (by an fma() call, or by building the same source with
+    contraction on) fails the probes above."""
+    if how == "contracted" and not _has_fma_cpu():
+        pytest.skip("host CPU has no FMA instructions")
+    lib = _planted_oracle(tmp_path, how)
+    a, b, edges = rp.sky_probes()
+    assert not np.array_equal(_call_pairs(lib.oracle_pair_angles, a, b), _sky_expected(a, b))
+    a, b, edges = rp.box_probes()
+    assert not np.array_equal(_call_pairs(lib.oracle_pair_distances, a, b), _box_expected(a, b))
