@@ -5,9 +5,8 @@ One step = the whole hot path over the large single-GPU workload (1e6
 clustered data points, 2e6 uniform randoms over the octant, 40 log bins over
 [0.0005, 30] deg): DD, DR and RR histograms on the GPU, copied to the host,
 then Landy-Szalay w(theta).  Catalogs are resident in HBM before the timed
-region starts.  The three exact paths (FP32 chord, FP64 vector, FP64 matrix
-cores) are each tuned on a sample, timed and checked against each other; the
-fastest is the headline value.  Prints one JSON line.
+region starts.  The two exact paths (FP32 chord, FP64 vector) are each timed
+and checked against each other; the fastest is the headline value.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -34,13 +33,8 @@ PEAK_GPAIRS = FP32_LANE_OPS / OPS_PER_PAIR_FP32 / 1e9
 # (three products, two sums, 1 - d) plus the key.
 FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_PAIR_FP64 = 7
-# FP64 matrix-core path: MI355X dense FP64 MFMA peak, and the algorithmic
-# flops of one pair (three products, two sums for the dot, one for 1 - d).
-PEAK_FP64_TFLOPS = 78.6
-FLOPS_PER_PAIR = 6
-PATH_NAMES = {0: "fp32_chord", 1: "fp64", 2: "fp64_matrix"}
-KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)",
-                2: "pairs_kernel<2> (FP64 matrix cores)"}
+PATH_NAMES = {0: "fp32_chord", 1: "fp64"}
+KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_octant_1e6x2e6.txt")
 
@@ -70,19 +64,12 @@ def measured_traffic(path: str):
 
 def roofline(prec: int, kernel_gpairs: float, ms_per_launch: float, traffic=None, kernel=None,
              ops_per_pair=None) -> dict:
-    if prec == 2:
-        fpp = ops_per_pair or FLOPS_PER_PAIR
-        achieved = kernel_gpairs * 1e9 * fpp / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "flops_per_pair": fpp}
+    if prec == 0:
+        peak = FP32_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP32) / 1e9
     else:
-        if prec == 0:
-            peak = FP32_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP32) / 1e9
-        else:
-            peak = FP64_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP64) / 1e9
-        roof = {"bound": "alu", "achieved": round(kernel_gpairs, 1), "peak": round(peak, 1),
-                "unit": "Gpairs/s", "frac": round(kernel_gpairs / peak, 4)}
+        peak = FP64_LANE_OPS / (ops_per_pair or OPS_PER_PAIR_FP64) / 1e9
+    roof = {"bound": "alu", "achieved": round(kernel_gpairs, 1), "peak": round(peak, 1),
+            "unit": "Gpairs/s", "frac": round(kernel_gpairs / peak, 4)}
     roof.update({"traffic": traffic, "kernel": kernel or KERNEL_NAMES[prec],
                  "kernel_ms_per_launch": round(ms_per_launch, 3)})
     return roof
@@ -106,7 +93,6 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0,
                     help="catalog size factor (1.0 = the full workload)")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-matrix", action="store_true", help="skip the FP64 matrix-core path")
     ap.add_argument("--no-prune", action="store_true",
                     help="skip the extra run with exact tile pruning (never the headline)")
     ap.add_argument("--no-jackknife", action="store_true",
@@ -374,10 +360,10 @@ def main():
         tot = [int(x.sum()) for x in h]
         ok = tot == [nd * (nd - 1) // 2, nd * nr, nr * (nr - 1) // 2]
         t = ctx.get_tuning()     # 0 = the library's default
-        rpl = t["rows_per_lane"] or (2 if prec == tp.FP64_MATRIX else 4)
+        rpl = t["rows_per_lane"] or 4
         tuning = dict(t, rows_per_lane=rpl, autotuned=tuning is not None)
-        rows_per_step = rpl * (16 if prec == tp.FP64_MATRIX else 64)
-        cols_per_step = {tp.FP32_CHORD: 4, tp.FP64: 2, tp.FP64_MATRIX: 16}[prec]
+        rows_per_step = rpl * 64
+        cols_per_step = {tp.FP32_CHORD: 4, tp.FP64: 2}[prec]
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
                 "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,
                 "beyond": beyond, "one_slot": one_slot, "per_kind": per_kind,
@@ -388,8 +374,6 @@ def main():
     paths = [tp.FP32_CHORD]
     if not args.no_fp64:
         paths.append(tp.FP64)
-    if not args.no_matrix:
-        paths.append(tp.FP64_MATRIX)
     runs = {}
     for prec in paths:
         runs[prec] = run(prec, args.steps, args.warmup)
@@ -504,7 +488,7 @@ def main():
         xi3d = {"workload": w3.name, "n_d": n3d, "n_r": n3r, "nbins": int(w3.edges.size - 1),
                 "r_range": [float(w3.edges[0]), float(w3.edges[-1])], "pairs_per_step": pairs3}
         hist3 = {}
-        for prec in (tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX):
+        for prec in (tp.FP32_CHORD, tp.FP64):
             def step3():
                 ctx.count_async(tp.DD, b_d, w3.edges, out3[0].data_ptr(), precision=prec)
                 ctx.count_async(tp.DR, b_d, w3.edges, out3[1].data_ptr(), cat_b=b_r, precision=prec)
@@ -534,14 +518,13 @@ def main():
                 "kernel_ms_per_launch": round(kms / max(1, nl), 3),
                 "exact_rate": st.exact / max(1, st.pairs),
                 # FP32: 3 differences, a square, 2 FMAs and the key (as for
-                # angles); FP64 (vector and matrix cores): 3 differences,
-                # 3 squares, 2 sums (the key is the high word of r^2)
+                # angles); FP64: 3 differences, 3 squares, 2 sums (the key
+                # is the high word of r^2)
                 "roofline": roofline(prec, pairs3 * args.steps / (kms / 1e3) / 1e9, kms / max(1, nl),
                                      kernel={tp.FP32_CHORD: "pairs_kernel<5> (3-D FP32)",
-                                             tp.FP64: "pairs_kernel<4> (3-D FP64)",
-                                             tp.FP64_MATRIX: "pairs_kernel<8> (3-D FP64 matrix cores)"}[prec],
+                                             tp.FP64: "pairs_kernel<4> (3-D FP64)"}[prec],
                                      ops_per_pair=7 if prec == tp.FP32_CHORD else 8)}
-        for other in (tp.FP64, tp.FP64_MATRIX):
+        for other in (tp.FP64,):
             if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[other])):
                 sys.exit("3-D histograms differ between precisions")
         if not args.no_prune:

@@ -14,7 +14,7 @@
  * Conventions for every entry point:
  *   - plain C types only; no exception crosses the boundary;
  *   - every call returns an int status (TPCF_OK or a negative TPCF_E_* code);
- *     tpcf_last_error() returns a message for the calling thread;
+ *     tpcf_last_error(ctx) returns a message for the calling thread;
  *   - sizes and row indices are int64_t; catalogs hold at most 2^31 - 1024
  *     objects;
  *   - host input arrays are read during the call only (copied if needed);
@@ -54,20 +54,14 @@ typedef struct tpcf_ctx tpcf_ctx;   /* opaque; owns device state */
 /* Pair kinds (Section 1). */
 enum { TPCF_DD = 0, TPCF_DR = 1, TPCF_RR = 2 };
 
-/* Precision modes.
+/* Precision modes (identical counts).
  * TPCF_FP32_CHORD: bulk pairs are classified from the FP32 squared chord
  *   |f_i - f_j|^2 of FP32 copies of the unit vectors, against FP32 chord^2
  *   bands proven to contain every edge; a pair inside a band is re-decided in
  *   FP64 with the exact counting rule.
  * TPCF_FP64: every pair's FP64 dot product d is computed as in the counting
- *   rule and compared with D_k (the plain path).
- * TPCF_FP64_MATRIX: the FP64 matrix cores evaluate e = 1 - d for tiles of
- *   16 x 16 pairs (A rows (-x_i, -y_i, -z_i, 1) times B columns
- *   (x_j, y_j, z_j, 1), one v_mfma_f64_16x16x4 per tile); pairs whose e lies
- *   within 2^-48 of 1 - D_k are re-decided with the exact rule.  The vector
- *   units then only bin.  The library keeps a 32-byte-per-point operand pack
- *   of each catalog used this way. */
-enum { TPCF_FP32_CHORD = 0, TPCF_FP64 = 1, TPCF_FP64_MATRIX = 2 };
+ *   rule and compared with D_k (the plain path). */
+enum { TPCF_FP32_CHORD = 0, TPCF_FP64 = 1 };
 
 enum {
     TPCF_OK = 0,
@@ -124,10 +118,8 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y,
  * batch.  Precisions: TPCF_FP32_CHORD (FP32 squared distances of FP32 copies
  * against a proven band, band pairs re-decided with the exact rule) and
  * TPCF_FP64 (the rule's r2 against S_k = the smallest double whose square
- * root reaches e_k) and TPCF_FP64_MATRIX (r2 = |a|^2 + |b|^2 - 2 a.b from the
- * FP64 matrix cores, the squared norms in the operand pack and the
- * accumulator, against a band of 2^-47 R^2; band pairs re-decided with the
- * exact rule).  Pruning (tuning field prune) uses bounding balls.  The FP32 band widens with the largest
+ * root reaches e_k).  Pruning (tuning field prune) uses bounding balls.  The
+ * FP32 band widens with the largest
  * norm R of the catalogs (about 2^-23 R in r), so coordinates centred on the
  * survey keep fewer pairs on the exact path.  Rows are stored in Morton order
  * of the bounding box; tpcf_catalog_order returns it. */
@@ -144,11 +136,16 @@ int tpcf_upload_catalog_3d_regions(tpcf_ctx *ctx, const double *x, const double 
 
 /* Zero-copy attach of caller-owned device memory: d_xyz64 points to 3*n
  * doubles on the context's device laid out as x[0..n), y[0..n), z[0..n)
- * (unit vectors, same norm limit as above).  The caller keeps the memory
- * alive and unchanged until the catalog is released.  The library adds its
- * own FP32 copy.  Checked on the device; TPCF_E_INVALID if a vector fails
- * the norm limit or is not finite. */
-int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t *out_cat);
+ * (unit vectors, same norm limit as above).  d_xyz32 is NULL, or 3*n floats
+ * on the same device in the same layout holding the FP32 copies rounded to
+ * nearest, (float)x[i] etc.; with NULL the library makes its own copy.  The
+ * caller keeps both arrays alive and unchanged until the catalog is
+ * released.  Checked on the device; TPCF_E_INVALID if a vector fails the
+ * norm limit or is not finite, or if a given FP32 copy is not the rounded
+ * FP64 value (the FP32 band is proven for round-to-nearest copies).  Rows
+ * keep the caller's order. */
+int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, const float *d_xyz32, int64_t n,
+                        int32_t *out_cat);
 
 /* Storage order of a catalog: out_order (host, n int64) receives, for each
  * stored row r, the index of that object in the uploaded arrays.  Attached
@@ -197,12 +194,14 @@ int tpcf_count_regions(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
                        const double *bin_edges_deg, int32_t nbins, int precision,
                        uint64_t *out_total, uint64_t *out_touch);
 
-/* Count pairs (synchronous).
+/* Count pairs (synchronous): the DD, DR or RR histogram of the paper's
+ * estimator (Section 1, the pair counts defined below Eq. 1), binned in theta
+ * (Section 2) by the counting rule above (Section 3, first bullet).
  * kind       TPCF_DD or TPCF_RR: unordered pairs i < j of cat_a, cat_b must be
  *            -1; TPCF_DR: every pair (i in cat_a, j in cat_b).
  * bin_edges_deg  nbins+1 finite, strictly increasing values in [0, 180]
  *            (host array); 1 <= nbins <= 256.
- * precision  TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX (identical results).
+ * precision  TPCF_FP32_CHORD or TPCF_FP64 (identical results).
  * row_begin, row_end  restrict i to rows [row_begin, row_end) of cat_a, in
  *            the catalog's stored order (tpcf_catalog_order); -1, -1 selects
  *            all rows.  For DD/RR the pairs are (i, j) with i in the range and
@@ -239,7 +238,10 @@ typedef struct tpcf_job_desc {
 enum { TPCF_BATCH_GRAPH = 1 };
 
 /* Count many requests in one launch (e.g. many data catalogs of uneven size
- * against one resident random catalog, or jackknife subsamples).  All jobs
+ * against one resident random catalog, or jackknife subsamples): each job is
+ * a DD, DR or RR count as tpcf_count (Section 1, the pair counts below
+ * Eq. 1); the paper gives each histogram a GPU of its own (Section 3, third
+ * bullet), here the work units of all jobs share one launch.  All jobs
  * must share the same edges, nbins and precision.  The work units of every
  * job form one list, largest first, processed by one kernel launch; each job
  * gets its own histogram.  out_u64: host array of njobs * (nbins+2) slots,
@@ -251,9 +253,10 @@ enum { TPCF_BATCH_GRAPH = 1 };
 int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, int flags,
                      uint64_t *out_u64);
 
-/* Asynchronous jobs for serving.  tpcf_submit validates and enqueues one
- * request on one of four library streams (jobs on different streams overlap
- * on the device) and returns a job id.  An RR request whose result is
+/* Asynchronous jobs for serving.  Each job is one DD, DR or RR count as
+ * tpcf_count (Section 1, the pair counts below Eq. 1).  tpcf_submit
+ * validates and enqueues one request on one of four library streams (jobs on
+ * different streams overlap on the device) and returns a job id.  An RR request whose result is
  * cached (same catalog, edges, precision and rows; the cache is cleared for a
  * catalog when it is released) completes at submit without device work.
  * tpcf_poll sets *done = 1 and writes nbins+2 slots to out_u64 (may be NULL)
@@ -269,9 +272,7 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
 
 /* Launch shape of later launches (set by the autotuner; defaults are fine).
  * Every field 0 takes the default.
- * rows_per_lane   vector paths: 2 or 4 rows held in registers per lane;
- *                 matrix-core path: 2 or 4 groups of 16 rows per wavefront
- *                 (default 4 on the vector paths, 2 on the matrix-core path);
+ * rows_per_lane   2 or 4 rows held in registers per lane (default 4);
  * hist_copies     LDS histogram copies per wavefront, 4, 8, 16 or 32
  *                 (default 16); a value above what the slot count allows
  *                 (32 up to 46 slots, 16 up to 94, 8 up to 190, else 4) is
@@ -295,10 +296,12 @@ int tpcf_cancel(tpcf_ctx *ctx, int64_t job);
  * prune           1: exact tile pruning.  Bounding caps of the column
  *                 catalog's aligned 64-point groups (built on first use,
  *                 4 doubles per group) and of each wavefront's rows bound the
- *                 angles of a row block x 64-column block; when that interval,
- *                 widened by 1e-6 rad and at least 1e-5 rad from 0 and pi,
- *                 contains no edge, all of the block's pairs go to that slot
- *                 without being evaluated.  3-D catalogs: bounding balls
+ *                 angles of a row block x 64-column block (widened by
+ *                 1e-6 rad); the counting rule's dot products of the block's
+ *                 pairs then lie in an interval that also covers the
+ *                 catalogs' norm deviation | |v|^2 - 1 |, and when no
+ *                 threshold D_k falls inside it all of the block's pairs go
+ *                 to one slot without being evaluated.  3-D catalogs: bounding balls
  *                 (mean and largest distance from it) bound the distances,
  *                 widened by 2^-22 R (R the largest norm) and 1e-12
  *                 relative.  Counts are unchanged; 0 (default) evaluates
@@ -340,7 +343,7 @@ typedef struct tpcf_counters {
     uint64_t pairs;           /* pairs evaluated */
     uint64_t flagged;         /* pairs that left the table-driven path for a threshold comparison */
     uint64_t exact;           /* pairs re-decided with the exact FP64 rule (FP32_CHORD band
-                                 pairs, FP64 ties, matrix-core band pairs) */
+                                 pairs, FP64 ties) */
     uint64_t rare_steps;      /* wavefront steps (64 lanes x a few pairs each) that took the
                                  rare path */
     uint64_t beyond_steps;    /* steps whose pairs all lay certainly beyond the last edge,
@@ -399,8 +402,8 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
 
 /* Cell table of the pair kernels for the given edges (host only, for CPU
  * tests of the host logic).  precision selects the key: TPCF_FP32_CHORD uses
- * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 and TPCF_FP64_MATRIX the high
- * 32 bits of e = 1 - d as a signed integer.  A key maps to cell
+ * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 the high 32 bits of e = 1 - d
+ * as a signed integer.  A key maps to cell
  * clamp(key >> shift, lo, hi); entry cells[cell - lo] is a slot (< 0x8000),
  * 0x8000 | k when only edge k is undecided in the cell, or 0xFFFF when
  * several edges are.  direct = 1 (TPCF_FP32_CHORD only) asks for the cells
@@ -437,11 +440,6 @@ int tpcf_compile_wrap32(const double *bin_edges_deg, int32_t nbins, double delta
                         int32_t *out_hi, int32_t *out_aux_off, float *out_q0, float *out_qlo, float *out_qhi,
                         uint8_t *out_image);
 
-/* Matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
- * doubles each) such that e >= out_hi[k] implies d <= D_k and e < out_lo[k]
- * implies d > D_k whenever e is within 2^-48 of 1 - d. */
-int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_lo, double *out_hi);
-
 /* 3-D edge compilation (host only, for CPU tests): for nbins+1 distance
  * edges (as tpcf_upload_catalog_3d) and points of FP64 norm at most rmax
  * (0 <= rmax <= 2^51):
@@ -454,17 +452,11 @@ int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_
 int tpcf_compile_edges_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_S,
                           float *out_qlo, float *out_qhi);
 
-/* 3-D matrix-core band (host only, for CPU tests): out_lo, out_hi (nbins+1
- * doubles each) such that, for points of norm at most rmax, a matrix-core
- * r2 >= out_hi[k] implies that the rule's r2 is >= S_k and r2 < out_lo[k]
- * that it is < S_k, whenever the matrix-core value is within 2^-47 rmax^2 of
- * the rule's. */
-int tpcf_compile_band64_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_lo,
-                           double *out_hi);
-
 /* Message describing the last failed call on the calling thread ("" if none).
- * Valid until the next call on the same thread. */
-const char *tpcf_last_error(void);
+ * Messages are kept per host thread, not per context: ctx may be NULL (for
+ * the calls that take no context, or a failed tpcf_open) and is not
+ * dereferenced.  Valid until the next call on the same thread. */
+const char *tpcf_last_error(const tpcf_ctx *ctx);
 
 /* Library version string. */
 const char *tpcf_version(void);

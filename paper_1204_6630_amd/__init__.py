@@ -18,13 +18,13 @@ import os
 import numpy as np
 
 __all__ = [
-    "DD", "DR", "RR", "FP32_CHORD", "FP64", "FP64_MATRIX", "compile_band64", "TpcfError", "Context", "lib", "lib_path",
+    "DD", "DR", "RR", "FP32_CHORD", "FP64", "TpcfError", "Context", "lib", "lib_path",
     "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "compile_wrap32", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
 DD, DR, RR = 0, 1, 2
-FP32_CHORD, FP64, FP64_MATRIX = 0, 1, 2
+FP32_CHORD, FP64 = 0, 1
 MAX_REGIONS = 1024
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,9 +39,8 @@ EXPORTED_SYMBOLS = (
     "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
-    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32", "tpcf_compile_band64",
+    "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32",
     "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
-    "tpcf_compile_band64_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -123,8 +122,7 @@ def lib():
         "tpcf_upload_catalog_3d": ([P, P, P, P, i64, P], cint),
         "tpcf_upload_catalog_3d_regions": ([P, P, P, P, i64, P, i32, P], cint),
         "tpcf_compile_edges_3d": ([P, i32, ctypes.c_double, P, P, P], cint),
-        "tpcf_compile_band64_3d": ([P, i32, ctypes.c_double, P, P], cint),
-        "tpcf_attach_catalog": ([P, P, i64, P], cint),
+        "tpcf_attach_catalog": ([P, P, P, i64, P], cint),
         "tpcf_catalog_order": ([P, i32, P], cint),
         "tpcf_catalog_size": ([P, i32, P], cint),
         "tpcf_release_catalog": ([P, i32], cint),
@@ -150,9 +148,8 @@ def lib():
         "tpcf_landy_szalay": ([P, P, P, i32, i64, i64, cint, P], cint),
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
         "tpcf_compile_wrap32": ([P, i32, ctypes.c_double, i32, i32, P, P, P, P, P, P, P, P, P], cint),
-        "tpcf_compile_band64": ([P, i32, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
-        "tpcf_last_error": ([], ctypes.c_char_p),
+        "tpcf_last_error": ([P], ctypes.c_char_p),
         "tpcf_version": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -165,7 +162,7 @@ def lib():
 
 def _check(rc: int):
     if rc != 0:
-        msg = lib().tpcf_last_error().decode(errors="replace")
+        msg = lib().tpcf_last_error(None).decode(errors="replace")
         raise TpcfError(rc, msg)
 
 
@@ -272,19 +269,27 @@ class Context:
                                              ctypes.byref(cid)))
         return cid.value
 
-    def attach_catalog(self, xyz64_device) -> int:
+    def attach_catalog(self, xyz64_device, xyz32_device=None) -> int:
         """Attach a contiguous float64 device tensor of shape (3, n) (rows x, y,
-        z); the tensor must stay alive and unchanged while the id is in use."""
+        z) and, optionally, a float32 tensor of the same shape holding its
+        round-to-nearest copies (else the library makes its own); both must
+        stay alive and unchanged while the id is in use."""
+        def ok(t, dtype):
+            return getattr(t, "dtype", None) is not None and str(t.dtype) == dtype and t.dim() == 2 \
+                and t.shape[0] == 3 and t.is_contiguous() and t.is_cuda
         t = xyz64_device
-        if getattr(t, "dtype", None) is None or str(t.dtype) != "torch.float64" or t.dim() != 2 \
-                or t.shape[0] != 3 or not t.is_contiguous() or not t.is_cuda:
+        if not ok(t, "torch.float64"):
             raise ValueError("need a contiguous float64 CUDA tensor of shape (3, n)")
-        # the tensor may still be being written on torch's stream; the
-        # library reads it on its own
+        f = xyz32_device
+        if f is not None and (not ok(f, "torch.float32") or f.shape != t.shape or f.device != t.device):
+            raise ValueError("the FP32 copies must be a contiguous float32 CUDA tensor shaped like the FP64 one")
+        # the tensors may still be being written on torch's stream; the
+        # library reads them on its own
         import torch
         torch.cuda.current_stream(t.device).synchronize()
         cid = ctypes.c_int32()
-        _check(lib().tpcf_attach_catalog(self._h, ctypes.c_void_p(t.data_ptr()), t.shape[1],
+        _check(lib().tpcf_attach_catalog(self._h, ctypes.c_void_p(t.data_ptr()),
+                                         ctypes.c_void_p(f.data_ptr()) if f is not None else None, t.shape[1],
                                          ctypes.byref(cid)))
         return cid.value
 
@@ -467,24 +472,6 @@ def compile_edges_3d(edges, rmax: float):
     qhi = np.empty(e.size, dtype=np.float32)
     _check(lib().tpcf_compile_edges_3d(_p(e), e.size - 1, rmax, _p(S), _p(qlo), _p(qhi)))
     return S, qlo, qhi
-
-
-def compile_band64_3d(edges, rmax: float):
-    """(lo, hi) of tpcf_compile_band64_3d."""
-    e = _f64(edges)
-    lo = np.empty(e.size, dtype=np.float64)
-    hi = np.empty(e.size, dtype=np.float64)
-    _check(lib().tpcf_compile_band64_3d(_p(e), e.size - 1, rmax, _p(lo), _p(hi)))
-    return lo, hi
-
-
-def compile_band64(edges_deg):
-    """(lo, hi) of tpcf_compile_band64."""
-    e = _f64(edges_deg)
-    lo = np.empty(e.size, np.float64)
-    hi = np.empty(e.size, np.float64)
-    _check(lib().tpcf_compile_band64(_p(e), e.size - 1, _p(lo), _p(hi)))
-    return lo, hi
 
 
 def compile_wrap32(edges_deg, delta_max: float = 0.0, max_bytes: int = 32768, aux_bytes: int = 0):

@@ -1,6 +1,6 @@
 """Autotuner for the pair kernels' launch shape.
 
-Knobs: rows held per lane (or row groups of 16 on the matrix-core path), LDS
+Knobs: rows held per lane, LDS
 histogram copies per wavefront, the largest column range of a work unit, the
 grid size, the cell-table budget and, for FP32 byte tables, the wrapped or the
 clamped table layout.  The search is a coordinate descent from the library's

@@ -24,8 +24,6 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # matrix-core results straight into VGPRs (no accumulator-register copies)
-    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"),
 ]
 HOST_FLAGS = [

@@ -50,14 +50,12 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 constexpr double kMaxDelta = 9.5367431640625e-07;   // 2^-20
-constexpr double kMatrixTau = 3.552713678800501e-15; // 2^-48, see make_band64
 constexpr double kMaxCoord3d = 1125899906842624.0;    // 2^50: largest |coordinate| of a 3-D catalog
 constexpr int kPoolStreams = 4;
 
 // Launch shape, set by tpcf_set_tuning (the autotuner) or left at defaults.
-// Launch shape.  Zero fields take the defaults, which are the shapes the
-// autotuner picked on the large octant workload: 4 rows per lane on the vector
-// paths and 4 row groups of 16 on the matrix-core path, 16 histogram copies,
+// Zero fields take the defaults, which are the shapes the autotuner picked on
+// the large octant workload: 4 rows per lane, 16 histogram copies,
 // 4096-column units, and clamped cell tables of up to 24 KB.
 struct Tuning {
     int rows_per_lane = 0;   // 2 or 4
@@ -69,12 +67,7 @@ struct Tuning {
     int prune = 0;           // 1: exact tile pruning
 };
 
-// Default: 4 rows per lane on the vector paths, 2 row groups of 16 on the
-// matrix-core path (fewer registers, more wavefronts to overlap the matrix
-// cores with the binning).
-int rows_per_lane_of(const Tuning &t, bool matrix) {
-    return t.rows_per_lane ? t.rows_per_lane : matrix ? 2 : 4;
-}
+int rows_per_lane_of(const Tuning &t) { return t.rows_per_lane ? t.rows_per_lane : 4; }
 
 int max_cols_of(const Tuning &t) { return t.max_cols ? t.max_cols : 4096; }
 
@@ -133,10 +126,9 @@ struct Catalog {
     float *d32 = nullptr;       // x[n], y[n], z[n]
     size_t bytes64 = 0, bytes32 = 0;
     bool owns64 = true;
+    bool owns32 = true;
     double delta = 0;           // bound on | |v|^2 - 1 |
     std::vector<int64_t> order; // stored row r holds upload row order[r] (empty: identity)
-    double *dpack = nullptr;    // matrix-core operand pack, built on first use
-    size_t bytes_pack = 0;
     double *dcaps = nullptr;    // bounding caps of aligned 64-point groups, built on first use
     size_t bytes_caps = 0;
     // jackknife regions: stored rows of region r are [reg_start[r], reg_start[r+1])
@@ -151,14 +143,13 @@ struct Catalog {
 
 struct Compiled {
     EdgeTables edges;
-    DevBuf dD, dE, dqlo, dqhi, dlut, dTlo, dThi, dErad;
+    DevBuf dD, dE, dqlo, dqhi, dlut, dErad;
     CellTable cells;
     Band32 band;
     int precision = 0;
     int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
     double delta = 0;      // norm bound of the band (3-D: rmax)
     int metric = 0;
-    std::vector<double> thi;   // matrix-core band upper ends (host copy)
 };
 
 struct Plan {
@@ -526,8 +517,6 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
     c.dqlo.release(ctx->mem);
     c.dqhi.release(ctx->mem);
     c.dlut.release(ctx->mem);
-    c.dTlo.release(ctx->mem);
-    c.dThi.release(ctx->mem);
     c.dErad.release(ctx->mem);
 }
 
@@ -560,19 +549,11 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     const int table_bytes = ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxLutBytes;
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     std::vector<float> qlo(c->edges.D.size(), 0.0f), qhi(c->edges.D.size(), 0.0f);
-    std::vector<double> tlo = c->edges.E, thi = c->edges.E;
     if (metric && precision == TPCF_FP32_CHORD) {
         c->band = make_band32_3d(c->edges, delta);
         c->cells = make_cells32_top(c->edges, c->band, qtop_key_3d(delta), max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
-    } else if (metric && precision == TPCF_FP64_MATRIX) {
-        const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
-        Band64 b = make_band64_3d(c->edges, delta);
-        c->cells = make_cells64_band(b, max_cells, top > 1e-300 ? top : 1e-300);
-        tlo = b.lo;
-        thi = b.hi;
-        c->thi = b.hi;
     } else if (metric) {
         const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
         c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
@@ -590,12 +571,6 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
             c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         qlo = c->band.qlo;
         qhi = c->band.qhi;
-    } else if (precision == TPCF_FP64_MATRIX) {
-        Band64 b = make_band64(c->edges, kMatrixTau);
-        c->cells = make_cells64_band(b, max_cells);
-        tlo = b.lo;
-        thi = b.hi;
-        c->thi = b.hi;
     } else {
         c->cells = make_cells64(c->edges, max_cells);
     }
@@ -614,8 +589,7 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
     int rc;
     if ((rc = upload_blocking(ctx->mem, c->dD, c->edges.D)) || (rc = upload_blocking(ctx->mem, c->dE, c->edges.E)) ||
         (rc = upload_blocking(ctx->mem, c->dqlo, qlo)) || (rc = upload_blocking(ctx->mem, c->dqhi, qhi)) ||
-        (rc = upload_blocking(ctx->mem, c->dlut, packed)) || (rc = upload_blocking(ctx->mem, c->dTlo, tlo)) ||
-        (rc = upload_blocking(ctx->mem, c->dThi, thi)) ||
+        (rc = upload_blocking(ctx->mem, c->dlut, packed)) ||
         (rc = upload_blocking(ctx->mem, c->dErad, c->edges.edge_rad))) {
         free_compiled(ctx, *c);
         return rc;
@@ -663,7 +637,7 @@ Unit mk_unit(int64_t i0, int64_t i1, int64_t j0, int64_t j1, int64_t row_lo, int
 }
 
 Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, int64_t T,
-               int64_t max_cols, int64_t align) {
+               int64_t max_cols) {
     Plan p;
     uint64_t pairs = 0;
     if (auto_pairs) {
@@ -675,13 +649,13 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
     }
     p.pairs = pairs;
     const int64_t bj = chunk_width(pairs, T, max_cols);
-    // Row tiles start on multiples of `align` (valid rows from row_lo = rb).
+    // Row tiles start at rb (valid rows from row_lo = rb).
     // Column chunks lie on a common grid of multiples of bj, so units of
     // different row tiles cover the same column ranges; the list is ordered
     // column chunk first, so the units in flight at any time (a grid-stride
     // window of consecutive units) share their columns and the column data
     // stays in each XCD's L2.
-    const int64_t i_first = rb - rb % align;
+    const int64_t i_first = rb;
     if (auto_pairs) {
         for (int64_t i0 = i_first; i0 < re; i0 += T) {
             const int64_t i1 = i0 + T < re ? i0 + T : re;
@@ -719,12 +693,11 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
 
 // Work units of a whole-catalog request with jackknife regions: no unit
 // crosses a region boundary on either side, and each carries its two region
-// ids.  Row tiles are cut at region ends (and start on multiples of `align`,
-// valid rows from the region start); columns are cut on the bj grid and at
-// region starts (matrix-core units start on multiples of 16, valid columns
-// from col_lo).  Auto-pairs: per row tile a diagonal unit over the tile's
-// own columns, then the columns after it.  Ordered column chunk first.
-Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64_t max_cols, int64_t align,
+// ids.  Row tiles are cut at region ends (starting at the region start);
+// columns are cut on the bj grid and at region starts.  Auto-pairs: per row
+// tile a diagonal unit over the tile's own columns, then the columns after
+// it.  Ordered column chunk first.
+Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64_t max_cols,
                        const std::vector<int64_t> &sa, const std::vector<int64_t> &sb) {
     Plan p;
     p.pairs = auto_pairs ? (uint64_t)na * (uint64_t)(na > 0 ? na - 1 : 0) / 2 : (uint64_t)na * (uint64_t)nb;
@@ -747,7 +720,7 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
         const int64_t s0 = sa[(size_t)r], s1 = sa[(size_t)r + 1];
         if (s0 == s1)
             continue;   // empty region
-        for (int64_t i0 = s0 - s0 % align; i0 < s1; i0 += T)
+        for (int64_t i0 = s0; i0 < s1; i0 += T)
             tiles.push_back(Tile{i0, i0 + T < s1 ? i0 + T : s1, i0 > s0 ? i0 : s0, (int32_t)r});
     }
     if (auto_pairs) {
@@ -756,7 +729,7 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
                 p.units.push_back(mk_unit(t.i0, t.i1, t.i0, t.i1, t.lo, t.i0, t.reg, t.reg));
             for (int64_t j = t.i1; j < na;) {
                 const int64_t c1 = next_cut(sa, j, na);
-                p.units.push_back(mk_unit(t.i0, t.i1, j - j % align, c1, t.lo, j, t.reg, region_of(sa, j)));
+                p.units.push_back(mk_unit(t.i0, t.i1, j, c1, t.lo, j, t.reg, region_of(sa, j)));
                 j = c1;
             }
         }
@@ -768,23 +741,20 @@ Plan make_plan_regions(bool auto_pairs, int64_t na, int64_t nb, int64_t T, int64
             const int64_t c1 = next_cut(sb, j, nb);
             const int32_t rj = region_of(sb, j);
             for (const Tile &t : tiles)
-                p.units.push_back(mk_unit(t.i0, t.i1, j - j % align, c1, t.lo, j, t.reg, rj));
+                p.units.push_back(mk_unit(t.i0, t.i1, j, c1, t.lo, j, t.reg, rj));
             j = c1;
         }
     }
     return p;
 }
 
-int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re,
-             bool matrix, Plan **out) {
-    // vector paths: 64 lanes x rows_per_lane rows per wavefront; matrix-core
-    // path: rows_per_lane groups of 16 rows per wavefront, 16-aligned tiles
-    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * rows_per_lane_of(ctx->tune, matrix);
-    const int64_t align = matrix ? 16 : 1;
+int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, Plan **out) {
+    // 64 lanes x rows_per_lane rows per wavefront, four wavefronts per tile
+    const int64_t T = (int64_t)kWaves * kWaveSize * rows_per_lane_of(ctx->tune);
     const int64_t max_cols = max_cols_of(ctx->tune);
     char buf[160];
-    snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld:%lld:%lld:%lld:%lld", (int)auto_pairs, (long long)na,
-             (long long)nb, (long long)rb, (long long)re, (long long)T, (long long)max_cols, (long long)align);
+    snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld:%lld:%lld:%lld", (int)auto_pairs, (long long)na,
+             (long long)nb, (long long)rb, (long long)re, (long long)T, (long long)max_cols);
     auto it = ctx->plans.find(buf);
     if (it != ctx->plans.end()) {
         *out = it->second.get();
@@ -797,7 +767,7 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
             kv.second->dunits.release(ctx->mem);
         ctx->plans.clear();
     }
-    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re, T, max_cols, align));
+    auto p = std::make_unique<Plan>(make_plan(auto_pairs, na, nb, rb, re, T, max_cols));
     TRY(upload_blocking(ctx->mem, p->dunits, p->units));
     *out = p.get();
     ctx->plans[buf] = std::move(p);
@@ -807,13 +777,12 @@ int get_plan(tpcf_ctx *ctx, bool auto_pairs, int64_t na, int64_t nb, int64_t rb,
 // Plan of a whole-catalog request with jackknife regions (cached like get_plan,
 // keyed by the catalog ids, which are never reused).
 int get_plan_regions(tpcf_ctx *ctx, bool auto_pairs, int32_t cat_a, int32_t cat_b, const Catalog &A,
-                     const Catalog &B, bool matrix, Plan **out) {
-    const int64_t T = (int64_t)kWaves * (matrix ? 16 : kWaveSize) * rows_per_lane_of(ctx->tune, matrix);
-    const int64_t align = matrix ? 16 : 1;
+                     const Catalog &B, Plan **out) {
+    const int64_t T = (int64_t)kWaves * kWaveSize * rows_per_lane_of(ctx->tune);
     const int64_t max_cols = max_cols_of(ctx->tune);
     char buf[160];
-    snprintf(buf, sizeof buf, "R%d:%d:%d:%lld:%lld:%lld", (int)auto_pairs, (int)cat_a, (int)cat_b, (long long)T,
-             (long long)max_cols, (long long)align);
+    snprintf(buf, sizeof buf, "R%d:%d:%d:%lld:%lld", (int)auto_pairs, (int)cat_a, (int)cat_b, (long long)T,
+             (long long)max_cols);
     auto it = ctx->plans.find(buf);
     if (it != ctx->plans.end()) {
         *out = it->second.get();
@@ -827,7 +796,7 @@ int get_plan_regions(tpcf_ctx *ctx, bool auto_pairs, int32_t cat_a, int32_t cat_
         ctx->plans.clear();
     }
     auto p = std::make_unique<Plan>(
-        make_plan_regions(auto_pairs, A.n, B.n, T, max_cols, align, A.reg_start, B.reg_start));
+        make_plan_regions(auto_pairs, A.n, B.n, T, max_cols, A.reg_start, B.reg_start));
     if (p->units.size() > (size_t)0x7fffffff / kWaves)
         return fail(TPCF_E_INVALID, "too many work units (region boundaries split the work too finely)");
     TRY(upload_blocking(ctx->mem, p->dunits, p->units));
@@ -864,28 +833,6 @@ std::string cache_key(int32_t cat, const double *edges, int nbins, int precision
     return k;
 }
 
-// Matrix-core operand pack of a catalog, built on the device on first use.
-int ensure_pack(tpcf_ctx *ctx, Catalog &c) {
-    if (c.dpack)
-        return TPCF_OK;
-    const int64_t groups = (c.n + 15) / 16 > 0 ? (c.n + 15) / 16 : 1;
-    c.bytes_pack = sizeof(double) * 64 * (size_t)groups;
-    TRY(dev_alloc(ctx->mem, (void **)&c.dpack, c.bytes_pack));
-    hipError_t e = hipSuccess;
-    if (c.n > 0)
-        e = (hipError_t)tpcf_launch_pack16(c.d64, c.n, c.dpack, c.metric, ctx->main.stream);
-    else
-        e = (hipError_t)tpcf_launch_zero_u64((unsigned long long *)c.dpack, (int64_t)(c.bytes_pack / 8), ctx->main.stream);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(ctx->main.stream);
-    if (e != hipSuccess) {
-        dev_free(ctx->mem, c.dpack, c.bytes_pack);
-        c.dpack = nullptr;
-        return fail(TPCF_E_HIP, std::string("operand pack: ") + hipGetErrorString(e));
-    }
-    return TPCF_OK;
-}
-
 // Bounding caps of a catalog's aligned 64-point groups, built on the device on
 // first use (pruning).
 int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
@@ -912,8 +859,8 @@ int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
 int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r, bool regions = false) {
     if (d.kind != TPCF_DD && d.kind != TPCF_DR && d.kind != TPCF_RR)
         return fail(TPCF_E_INVALID, "kind must be TPCF_DD, TPCF_DR or TPCF_RR");
-    if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64 && d.precision != TPCF_FP64_MATRIX)
-        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX");
+    if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64)
+        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD or TPCF_FP64");
     if (d.nbins < 1 || d.nbins > 256)
         return fail(TPCF_E_INVALID, "nbins must be in [1, 256]");
     if (!d.bin_edges_deg)
@@ -954,11 +901,6 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
     TRY(set_device(ctx));
     const double delta = delta_override >= 0 ? delta_override : std::max(r->A->band_param(), r->B->band_param());
     TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, r->metric, &r->cp));
-    const bool matrix = d.precision == TPCF_FP64_MATRIX;
-    if (matrix) {
-        TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->A)));
-        TRY(ensure_pack(ctx, const_cast<Catalog &>(*r->B)));
-    }
     if (ctx->tune.prune)
         TRY(ensure_caps(ctx, const_cast<Catalog &>(*r->B)));
     r->cache_key.clear();
@@ -968,11 +910,11 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
         if (r->A->nreg < 1 || r->B->nreg != r->A->nreg)
             return fail(TPCF_E_INVALID, "both catalogs need region labels with the same number of regions");
         TRY(get_plan_regions(ctx, r->auto_pairs, r->cat_a, r->auto_pairs ? r->cat_a : r->cat_b, *r->A, *r->B,
-                             matrix, &r->plan));
+                             &r->plan));
         r->pairs = r->plan->pairs;
         return TPCF_OK;
     }
-    TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, matrix, &r->plan));
+    TRY(get_plan(ctx, r->auto_pairs, r->A->n, r->B->n, rb, re, &r->plan));
     r->pairs = r->plan->pairs;
     if (d.kind == TPCF_RR)
         r->cache_key = cache_key(d.cat_a, d.bin_edges_deg, d.nbins, d.precision, rb, re);
@@ -995,10 +937,6 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
     j.bx64 = r.B->d64;
     j.by64 = r.B->d64 + nb;
     j.bz64 = r.B->d64 + 2 * nb;
-    j.apack = r.A->dpack;
-    j.bpack = r.B->dpack;
-    j.a_groups = (int32_t)((r.A->n + 15) / 16);
-    j.b_groups = (int32_t)((r.B->n + 15) / 16);
     j.bcaps = r.B->dcaps;
     j.hist = hist;
     j.cancel = cancel;
@@ -1008,7 +946,9 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
     return j;
 }
 
-PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned long long *stats) {
+// Kernel arguments of a launch with compiled edges cp.  delta: bound on
+// | |v|^2 - 1 | over the launch's sky catalogs (angular pruning).
+PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned long long *stats, double delta) {
     PairArgs a;
     memset(&a, 0, sizeof a);
     a.lut = cp.dlut.p;
@@ -1026,6 +966,7 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     // 3-D: the FP32 row copies move each point by at most 2^-24 R per
     // component (sqrt(3) 2^-24 R in all); cp.delta holds R for 3-D edges
     a.prune_margin = cp.metric ? ldexp(cp.delta, -22) + 1e-300 : 0.0;
+    a.prune_delta = cp.metric ? 0.0 : delta;
     a.erad = (const double *)cp.dErad.p;
     // key of the last edge's certain side (see PairArgs::beyond_key)
     const size_t last = cp.edges.D.size() - 1;
@@ -1033,7 +974,7 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
         float qh = cp.band.qhi[last];
         memcpy(&a.beyond_key, &qh, sizeof qh);
     } else {
-        const double t = cp.precision == TPCF_FP64_MATRIX ? cp.thi[last] : cp.edges.E[last];
+        const double t = cp.edges.E[last];
         uint64_t b;
         memcpy(&b, &t, sizeof b);
         a.beyond_key = (uint32_t)(b >> 32);
@@ -1041,13 +982,11 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     a.qlo = (const float *)cp.dqlo.p;
     a.qhi = (const float *)cp.dqhi.p;
     a.E = (const double *)cp.dE.p;
-    a.Tlo = (const double *)cp.dTlo.p;
-    a.Thi = (const double *)cp.dThi.p;
     a.D = (const double *)cp.dD.p;
     a.nedges = nbins + 1;
     a.nslots = nbins + 2;
     a.hist_copies = hist_copies_of(ctx->tune, nbins + 2);
-    a.rows_per_lane = rows_per_lane_of(ctx->tune, cp.precision == TPCF_FP64_MATRIX);
+    a.rows_per_lane = rows_per_lane_of(ctx->tune);
     a.blocks_per_cu = ctx->tune.blocks_per_cu;
     a.stats = stats;
     return a;
@@ -1090,7 +1029,7 @@ int launch_one(tpcf_ctx *ctx, Workspace &w, const Request &r, unsigned long long
     TRY(w.copies.ensure(ctx->mem, sizeof(unsigned long long) * ((size_t)kGlobalCopies * kMaxSlots + 1)));
     unsigned long long *copies = (unsigned long long *)w.copies.p;
     HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots + 1, w.stream));
-    PairArgs a = args_of(ctx, *r.cp, r.nbins, (unsigned long long *)w.stats.p);
+    PairArgs a = args_of(ctx, *r.cp, r.nbins, (unsigned long long *)w.stats.p, std::max(r.A->delta, r.B->delta));
     a.jobs = nullptr;
     a.job0 = job_of(r, copies, cancel);
     a.job0.touch = touch;
@@ -1180,11 +1119,23 @@ int finish_job(tpcf_ctx *ctx, std::map<int64_t, AsyncJob>::iterator it, uint64_t
     return TPCF_OK;
 }
 
+// Device memory of the context's device?
+bool on_device(const tpcf_ctx *ctx, const void *p) {
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != ctx->device) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *tpcf_last_error(void) { return g_err.c_str(); }
+const char *tpcf_last_error(const tpcf_ctx *) { return g_err.c_str(); }
 
 const char *tpcf_version(void) { return "tpcf 0.2 (gfx950)"; }
 
@@ -1218,8 +1169,8 @@ int tpcf_close(tpcf_ctx *ctx) {
     for (auto &kv : ctx->cats) {
         if (kv.second.owns64)
             dev_free(ctx->mem, kv.second.d64, kv.second.bytes64);
-        dev_free(ctx->mem, kv.second.d32, kv.second.bytes32);
-        dev_free(ctx->mem, kv.second.dpack, kv.second.bytes_pack);
+        if (kv.second.owns32)
+            dev_free(ctx->mem, kv.second.d32, kv.second.bytes32);
         dev_free(ctx->mem, kv.second.dcaps, kv.second.bytes_caps);
     }
     for (auto &kv : ctx->compiled)
@@ -1300,7 +1251,8 @@ int tpcf_upload_catalog_xyz(tpcf_ctx *ctx, const double *x, const double *y, con
     return add_catalog(ctx, x, y, z, n, out_cat);
 }
 
-int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t *out_cat) {
+int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, const float *d_xyz32, int64_t n,
+                        int32_t *out_cat) {
     if (!ctx)
         return fail(TPCF_E_INVALID, "context is NULL");
     if (!out_cat)
@@ -1310,42 +1262,54 @@ int tpcf_attach_catalog(tpcf_ctx *ctx, const double *d_xyz64, int64_t n, int32_t
     if (!d_xyz64)
         return fail(TPCF_E_INVALID, "d_xyz64 is NULL");
     TRY(set_device(ctx));
-    hipPointerAttribute_t attr;
-    memset(&attr, 0, sizeof attr);
-    if (hipPointerGetAttributes(&attr, d_xyz64) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-        attr.device != ctx->device) {
-        (void)hipGetLastError();
+    if (!on_device(ctx, d_xyz64))
         return fail(TPCF_E_INVALID, "d_xyz64 is not device memory of the context's device");
-    }
+    if (d_xyz32 && !on_device(ctx, d_xyz32))
+        return fail(TPCF_E_INVALID, "d_xyz32 is not device memory of the context's device");
     Catalog c;
     c.n = n;
     c.owns64 = false;
     c.d64 = const_cast<double *>(d_xyz64);
     c.bytes32 = sizeof(float) * 3 * (size_t)n;
-    TRY(dev_alloc(ctx->mem, (void **)&c.d32, c.bytes32));
+    if (d_xyz32) {
+        c.owns32 = false;
+        c.d32 = const_cast<float *>(d_xyz32);
+    } else {
+        TRY(dev_alloc(ctx->mem, (void **)&c.d32, c.bytes32));
+    }
+    auto drop32 = [&] {
+        if (c.owns32)
+            dev_free(ctx->mem, c.d32, c.bytes32);
+    };
     Workspace &w = ctx->main;
     int rc = w.out.ensure(ctx->mem, sizeof(unsigned long long) * kMaxSlots);
     if (rc) {
-        dev_free(ctx->mem, c.d32, c.bytes32);
+        drop32();
         return rc;
     }
-    double *dmax = (double *)w.out.p;
-    hipError_t e = (hipError_t)tpcf_launch_zero_u64((unsigned long long *)dmax, 1, w.stream);
+    unsigned long long *chk = (unsigned long long *)w.out.p;
+    hipError_t e = (hipError_t)tpcf_launch_zero_u64(chk, 2, w.stream);
     if (e == hipSuccess)
-        e = (hipError_t)tpcf_launch_to_float(c.d64, n, c.d32, dmax, w.stream);
-    double dev = 0.0;
+        e = (hipError_t)tpcf_launch_to_float(c.d64, n, c.owns32 ? c.d32 : nullptr, d_xyz32, chk, w.stream);
+    unsigned long long h[2] = {0, 0};
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&dev, dmax, sizeof(double), hipMemcpyDeviceToHost, w.stream);
+        e = hipMemcpyAsync(h, chk, sizeof h, hipMemcpyDeviceToHost, w.stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(w.stream);
     if (e != hipSuccess) {
-        dev_free(ctx->mem, c.d32, c.bytes32);
+        drop32();
         return fail(TPCF_E_HIP, std::string("attach: ") + hipGetErrorString(e));
     }
-    double delta = dev + 4.0 * ldexp(1.0, -53);
+    double dev;
+    memcpy(&dev, &h[0], sizeof dev);
+    const double delta = dev + 4.0 * ldexp(1.0, -53);
     if (!(delta <= kMaxDelta)) {
-        dev_free(ctx->mem, c.d32, c.bytes32);
+        drop32();
         return fail(TPCF_E_INVALID, "attached vectors must be finite with | |v|^2 - 1 | <= 2^-20");
+    }
+    if (h[1]) {
+        drop32();
+        return fail(TPCF_E_INVALID, "d_xyz32 must hold the FP64 vectors rounded to nearest FP32");
     }
     c.delta = delta;
     int32_t id = ctx->next_id++;
@@ -1398,8 +1362,8 @@ int tpcf_release_catalog(tpcf_ctx *ctx, int32_t cat) {
     }
     if (it->second.owns64)
         dev_free(ctx->mem, it->second.d64, it->second.bytes64);
-    dev_free(ctx->mem, it->second.d32, it->second.bytes32);
-    dev_free(ctx->mem, it->second.dpack, it->second.bytes_pack);
+    if (it->second.owns32)
+        dev_free(ctx->mem, it->second.d32, it->second.bytes32);
     dev_free(ctx->mem, it->second.dcaps, it->second.bytes_caps);
     ctx->cats.erase(it);
     return TPCF_OK;
@@ -1563,7 +1527,7 @@ int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, in
             free_graph(ctx, *g);
             return rc;
         }
-        PairArgs a = args_of(ctx, *reqs[0].cp, nbins, (unsigned long long *)ctx->main.stats.p);
+        PairArgs a = args_of(ctx, *reqs[0].cp, nbins, (unsigned long long *)ctx->main.stats.p, delta);
         a.jobs = (const JobDev *)g->jobs.p;
         a.units = (const Unit *)g->units.p;
         a.n_units = (int32_t)hu.size();
@@ -1950,8 +1914,8 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
                        int32_t *out_hi, uint16_t *out_cells, double *out_E) {
     if (!out_shift || !out_lo || !out_hi || !out_cells)
         return fail(TPCF_E_INVALID, "NULL argument");
-    if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64 && precision != TPCF_FP64_MATRIX)
-        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD, TPCF_FP64 or TPCF_FP64_MATRIX");
+    if (precision != TPCF_FP32_CHORD && precision != TPCF_FP64)
+        return fail(TPCF_E_INVALID, "precision must be TPCF_FP32_CHORD or TPCF_FP64");
     if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
         return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
     if (max_cells < 16 || max_cells > kMaxDirectLutBytes)
@@ -1972,8 +1936,7 @@ int tpcf_compile_cells(const double *bin_edges_deg, int32_t nbins, int precision
     } else {
         const int m = std::min<int>(max_cells, kMaxLutCells);
         c = precision == TPCF_FP32_CHORD ? make_cells32(t, make_band32(t, delta_max), delta_max, m)
-            : precision == TPCF_FP64_MATRIX ? make_cells64_band(make_band64(t, kMatrixTau), m)
-                                             : make_cells64(t, m);
+                                         : make_cells64(t, m);
     }
     *out_shift = c.shift;
     *out_lo = c.lo;
@@ -2025,21 +1988,6 @@ int tpcf_compile_wrap32(const double *bin_edges_deg, int32_t nbins, double delta
     return TPCF_OK;
 }
 
-int tpcf_compile_band64(const double *bin_edges_deg, int32_t nbins, double *out_lo, double *out_hi) {
-    if (!out_lo || !out_hi)
-        return fail(TPCF_E_INVALID, "NULL argument");
-    EdgeTables t;
-    std::string err;
-    if (!compile_edges(bin_edges_deg, nbins, &t, &err))
-        return fail(TPCF_E_INVALID, err);
-    Band64 b = make_band64(t, kMatrixTau);
-    for (int k = 0; k <= nbins; ++k) {
-        out_lo[k] = b.lo[k];
-        out_hi[k] = b.hi[k];
-    }
-    return TPCF_OK;
-}
-
 int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_max, double *out_D,
                        float *out_qlo, float *out_qhi) {
     if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
@@ -2056,24 +2004,6 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
             out_qlo[k] = b.qlo[k];
         if (out_qhi)
             out_qhi[k] = b.qhi[k];
-    }
-    return TPCF_OK;
-}
-
-int tpcf_compile_band64_3d(const double *bin_edges, int32_t nbins, double rmax, double *out_lo,
-                           double *out_hi) {
-    if (!out_lo || !out_hi)
-        return fail(TPCF_E_INVALID, "NULL argument");
-    if (!(rmax >= 0.0) || rmax > 2.0 * kMaxCoord3d)
-        return fail(TPCF_E_INVALID, "rmax must be in [0, 2^51]");
-    EdgeTables t;
-    std::string err;
-    if (!compile_edges_3d(bin_edges, nbins, &t, &err))
-        return fail(TPCF_E_INVALID, err);
-    Band64 b = make_band64_3d(t, rmax);
-    for (int k = 0; k <= nbins; ++k) {
-        out_lo[k] = b.lo[k];
-        out_hi[k] = b.hi[k];
     }
     return TPCF_OK;
 }

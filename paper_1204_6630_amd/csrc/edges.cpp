@@ -609,111 +609,4 @@ CellTable make_cells64(const EdgeTables &t, int max_cells, double etop) {
     return ct;
 }
 
-// Band for e computed by the matrix cores as A.B with A = (-x_i, -y_i, -z_i, 1)
-// and B = (x_j, y_j, z_j, 1).  Every partial sum is bounded by 2(1 + delta),
-// so four fused (or separately rounded) operations in any order leave e
-// within 8 * 2^-53 * 2 of 1 - v_i.v_j, and the counting rule's unfused d is
-// within gamma_3 of v_i.v_j: together below 2e-15.  With tau = 2^-48
-// (3.6e-15):
-//     e >= hi_k = RU(RU(1 - D_k) + tau)  =>  d <= D_k,
-//     e <  lo_k = RD(RD(1 - D_k) - tau)  =>  d >  D_k,
-// where RU/RD step one double outward (the subtraction 1 - D_k is exact for
-// D_k >= 1/2 and within half an ulp otherwise).
-Band64 make_band64(const EdgeTables &t, double tau) {
-    Band64 b;
-    b.tau = tau;
-    const int ne = (int)t.D.size();
-    b.lo.resize(ne);
-    b.hi.resize(ne);
-    for (int k = 0; k < ne; ++k) {
-        const double D = t.D[k];
-        if (D == HUGE_VAL) {
-            b.lo[k] = b.hi[k] = -HUGE_VAL;
-            continue;
-        }
-        if (D == -HUGE_VAL) {
-            b.lo[k] = b.hi[k] = HUGE_VAL;
-            continue;
-        }
-        const double e = 1.0 - D;
-        b.hi[k] = nextafter(nextafter(e, HUGE_VAL) + tau, HUGE_VAL);
-        b.lo[k] = nextafter(nextafter(e, -HUGE_VAL) - tau, -HUGE_VAL);
-    }
-    return b;
-}
-
-// 3-D matrix-core band.  The matrix cores evaluate C + sum_k A_k B_k with
-// A = (-2x_i, -2y_i, -2z_i, 1), B = (x_j, y_j, z_j, q_j) and C = q_i, where q
-// is the squared norm rounded as (x^2 + y^2) + z^2; every term and partial
-// sum is bounded by 4 R^2 (R >= every norm), so at most five roundings, in
-// any order and fused or not, leave the result within 20 U R^2 of
-// q_i + q_j - 2 a.b (U = 2^-53); each q is within 3.0001 U R^2 of the exact
-// squared norm; and the rule's r2 is within 5.0001 U (2R)^2 of the exact
-// squared distance.  Together: within 50 U R^2 < tau = 2^-47 R^2 of the rule's
-// r2, so r2_mma >= hi_k = RU(S_k + tau) gives r2 >= S_k and
-// r2_mma < lo_k = RD(S_k - tau) gives r2 < S_k (RU/RD: one double outward
-// after the rounded sum).
-Band64 make_band64_3d(const EdgeTables &t, double rmax) {
-    Band64 b;
-    b.tau = ldexp(rmax * rmax, -47) + 1e-300;
-    const int ne = (int)t.E.size();
-    b.lo.resize(ne);
-    b.hi.resize(ne);
-    for (int k = 0; k < ne; ++k) {
-        const double S = t.E[k];
-        if (S == -HUGE_VAL) {           // a zero edge: every pair is at or past it
-            b.lo[k] = b.hi[k] = -HUGE_VAL;
-            continue;
-        }
-        b.hi[k] = nextafter(S + b.tau, HUGE_VAL);
-        b.lo[k] = nextafter(S - b.tau, -HUGE_VAL);
-    }
-    return b;
-}
-
-CellTable make_cells64_band(const Band64 &b, int max_cells, double etop) {
-    const int ne = (int)b.lo.size();
-    const int32_t ktop = dhi(etop);
-    double tmin = HUGE_VAL;
-    for (int k = 0; k < ne; ++k) {
-        if (isfinite(b.lo[k]) && b.lo[k] > 0.0)
-            tmin = std::min(tmin, b.lo[k]);
-        if (isfinite(b.hi[k]) && b.hi[k] > 0.0)
-            tmin = std::min(tmin, b.hi[k]);
-    }
-    CellTable ct;
-    for (int shift = 9; shift <= 20; ++shift) {
-        int64_t hi = ktop >> shift;
-        int64_t lo = isfinite(tmin) ? (int64_t)(dhi(tmin) >> shift) - 1 : hi - 1;
-        if (lo < 0)
-            lo = 0;
-        if (hi - lo + 1 <= max_cells || shift == 20) {
-            if (hi - lo + 1 > max_cells)
-                lo = hi - max_cells + 1;
-            ct.shift = shift;
-            ct.lo = (int32_t)lo;
-            ct.hi = (int32_t)hi;
-            break;
-        }
-    }
-    const int n = ct.hi - ct.lo + 1;
-    ct.cells.resize(n);
-    for (int c = ct.lo; c <= ct.hi; ++c) {
-        double lo = c == ct.lo ? -HUGE_VAL : dfrom((uint64_t)((uint32_t)c << ct.shift) << 32);
-        double hi = c == ct.hi ? HUGE_VAL
-                               : dfrom(((uint64_t)((((uint32_t)c + 1u) << ct.shift) - 1u) << 32) |
-                                       0xffffffffULL);
-        int s_min = 0, s_max = 0;
-        for (int k = 0; k < ne; ++k) {
-            if (lo >= b.hi[k])
-                ++s_min;
-            if (hi >= b.lo[k])
-                ++s_max;
-        }
-        ct.cells[c - ct.lo] = encode(s_min, s_max);
-    }
-    tally(&ct);
-    return ct;
-}
-
 }  // namespace tpcf

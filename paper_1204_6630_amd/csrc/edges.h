@@ -27,14 +27,6 @@ struct Band32 {
     std::vector<float> qlo, qhi;
 };
 
-// FP64 band of every edge for e = 1 - d evaluated by the matrix cores (fused
-// products, unspecified summation order): e >= hi_k implies d <= D_k and
-// e < lo_k implies d > D_k for the counting rule's d.
-struct Band64 {
-    double tau = 0;
-    std::vector<double> lo, hi;
-};
-
 struct CellTable {
     int shift = 0;                  // cell = key >> shift
     int32_t lo = 0, hi = 0;         // clamp range of cells (inclusive)
@@ -96,14 +88,5 @@ CellTable make_cells32_wrap(const EdgeTables &t, const Band32 &b, double delta, 
 // larger value falls into the top cell): 2 for e = 1 - d, the largest
 // squared distance for 3-D.
 CellTable make_cells64(const EdgeTables &t, int max_cells, double etop = 2.0 + 1.0 / 262144.0);
-
-Band64 make_band64(const EdgeTables &t, double tau);
-// 3-D: band of every edge for r2 computed by the matrix cores as
-// |a|^2 + |b|^2 - 2 a.b for points of norm at most rmax: r2 >= hi_k implies
-// that the rule's r2 reaches S_k, r2 < lo_k that it does not.
-Band64 make_band64_3d(const EdgeTables &t, double rmax);
-// Cells over the high word of e (as make_cells64) against a Band64; etop as
-// for make_cells64.
-CellTable make_cells64_band(const Band64 &b, int max_cells, double etop = 2.0 + 1.0 / 262144.0);
 
 }  // namespace tpcf

@@ -35,11 +35,10 @@ constexpr uint16_t kMulti = 0xFFFF;
 constexpr int kMaxSlots8 = 127;
 
 // One work unit: the row tile starting at i0 with valid rows [row_lo, i1),
-// against columns j in [j0, j1) with valid columns from col_lo, of job `job`.
-// A unit needs per-pair masking when its valid rows do not fill the tile,
-// when j1 cuts a column group short or col_lo > j0 (matrix-core path: units
-// start i0 and j0 on multiples of 16; on the vector paths col_lo == j0), or,
-// for auto-pairs, when its columns overlap its rows (the j <= i diagonal).
+// against columns j in [j0, j1) of job `job` (col_lo == j0, kept for the
+// plan's bookkeeping).  A unit needs per-pair masking when its valid rows do
+// not fill the tile or, for auto-pairs, when its columns overlap its rows
+// (the j <= i diagonal).
 // reg_a / reg_b: jackknife regions of the unit's rows and columns (-1: none).
 struct Unit {
     int32_t i0, i1, j0, j1;
@@ -54,11 +53,6 @@ struct JobDev {
     const float *bx32, *by32, *bz32;
     const double *ax64, *ay64, *az64;
     const double *bx64, *by64, *bz64;
-    // Matrix-core operands: groups of 16 points, 64 doubles per group in lane
-    // order (lane l holds component l / 16 of point 16 g + l % 16; component 3
-    // is 1), zero-padded to whole groups.
-    const double *apack, *bpack;
-    int32_t a_groups, b_groups;
     // Bounding caps of the column catalog's aligned 64-point groups (stored
     // order): centre x, y, z and an upper bound of the angular radius (3-D:
     // the points' mean and the largest distance from it); null unless
@@ -100,9 +94,8 @@ struct PairArgs {
     int32_t aux_off;
     float q_floor;
     // Pairs certainly beyond the last edge: FP32 path, bits(q) >= beyond_key
-    // (the bits of the last edge's qhi); FP64 paths, high word of e = 1 - d
-    // above beyond_key as signed integers (e > E_last on the vector path,
-    // e >= the band's upper end on the matrix-core path).
+    // (the bits of the last edge's qhi); FP64 path, high word of e = 1 - d
+    // above beyond_key as signed integers (e > E_last).
     uint32_t beyond_key;
 
     // Exact tile pruning: 1 = a wavefront bins a whole aligned 64-column
@@ -112,17 +105,18 @@ struct PairArgs {
     const double *erad;
 
     // 0: angles on the sky (dot products against D_k); 1: 3-D distances
-    // (squared distances of Cartesian points, D_k = -S_k, E_k = S_k); no
-    // pruning and no matrix-core path for 3-D.
+    // (squared distances of Cartesian points, D_k = -S_k, E_k = S_k).
     int32_t metric;
     // 3-D pruning: absolute widening of the distance interval of a block
     // (covers the FP32 copies of the rows, 2^-22 times the largest norm).
     double prune_margin;
+    // Angular pruning: bound on | |v|^2 - 1 | of the catalogs' stored
+    // vectors (the rule's dot product is |v_i| |v_j| cos(phi), not cos(phi)).
+    double prune_delta;
 
     // Edge thresholds (device).
     const float *qlo, *qhi;      // FP32 chord^2 bands, nedges each
     const double *E;             // fl(1 - D_k), nedges
-    const double *Tlo, *Thi;     // matrix-core band of e = 1 - d, nedges each
     const double *D;             // D_k, nedges
     int32_t nedges;              // nbins + 1
     int32_t nslots;              // nbins + 2
@@ -137,10 +131,14 @@ struct PairArgs {
                                  //  pairs binned by pruned blocks]
 };
 
+// LDS bytes per edge: D_k, fl(1 - D_k), the edge in radians (pruning) and
+// the FP32 band (qlo_k, qhi_k).
+constexpr int kEdgeLdsBytes = 8 + 8 + 8 + 8;
+
 // LDS bytes of the histograms (with the discard row) and edge thresholds.
 inline int aux_lds_bytes(int nslots, int hist_copies, int nedges) {
     int hist = kWaves * (nslots + 1) * hist_copies * 4;
-    int thr = nedges * (4 + 4 + 8 + 8 + 8 + 8 + 8);
+    int thr = nedges * kEdgeLdsBytes;
     return hist + thr;
 }
 
@@ -155,13 +153,14 @@ inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_b
     return lut + aux;
 }
 
-// Margin (radians) of the pruning test: covers the FP32 copies of the rows
-// (<= 1.2e-7 rad), the arithmetic of the caps and the counting rule's own
-// rounding of the angle away from 0 and pi.
+// Margin (radians) of the geometric angle interval of the pruning test:
+// covers the FP32 copies of the rows (directions move by <= 1.2e-7 rad) and
+// the rounding of the caps' arithmetic (<= ~3e-8 rad, acos near 1 included).
 constexpr double kPruneMargin = 1e-6;
-// Pruning is never applied when a block's angles may come within this of 0
-// or pi, where the rule's acos is ill-conditioned.
-constexpr double kPruneGuard = 1e-5;
+// Absolute slack of the pruning test's dot-product interval: the rule's own
+// rounding (gamma_3 (1 + delta) < 3.4e-16) and that of the two cosines and
+// the interval arithmetic (a few units of 2^-53).
+constexpr double kPruneDotSlack = 2e-15;
 
 }  // namespace tpcf
 
@@ -173,11 +172,12 @@ int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
 // njobs x kGlobalCopies x nslots) into out (njobs x nslots).
 int tpcf_launch_reduce_copies(const unsigned long long *copies, int32_t nslots, int32_t njobs,
                               unsigned long long *out, void *stream);
-int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
-                         double *maxdev_out, void *stream);
-// Matrix-core operand pack of an FP64 SoA catalog (see JobDev::apack);
-// metric 1 (3-D): component 3 holds the squared norm instead of 1.
-int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, int metric, void *stream);
+// FP32 copies of an FP64 SoA catalog, or (given32 non-null) a check that
+// given32 holds them; check_out[0] receives the largest | |v|^2 - 1 | (bits
+// of a double, +inf for a non-finite value), check_out[1] a non-zero value
+// if a given copy differs.  check_out is zeroed by the caller.
+int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32, const float *given32,
+                         unsigned long long *check_out, void *stream);
 // Bounding caps of the aligned 64-point groups of an FP64 SoA catalog
 // (see JobDev::bcaps): 4 doubles per group; metric 1 (3-D): bounding balls.
 int tpcf_launch_caps64(const double *xyz64, int64_t n, double *caps, int metric, void *stream);

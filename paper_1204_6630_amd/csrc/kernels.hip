@@ -173,7 +173,6 @@ struct Smem {
     uint32_t *hist;      // kWaves x (nslots + 1) x copies
     double *D;
     double *E;
-    double2 *Tband;      // matrix-core band (lo_k, hi_k), one 16-byte read per edge
     float2 *qband;       // FP32 band (qlo_k, qhi_k), one 8-byte read per edge
     double *erad;        // edges in radians (pruning)
     unsigned char *lut;
@@ -193,8 +192,7 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     s.hist = reinterpret_cast<uint32_t *>(base + aux);
     s.D = reinterpret_cast<double *>(base + aux + hist_words * 4);
     s.E = s.D + a.nedges;
-    s.Tband = reinterpret_cast<double2 *>(s.E + a.nedges);
-    s.erad = reinterpret_cast<double *>(s.Tband + a.nedges);
+    s.erad = s.E + a.nedges;
     s.qband = reinterpret_cast<float2 *>(s.erad + a.nedges);
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
     s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
@@ -334,10 +332,9 @@ __device__ __forceinline__ uint32_t addr64(int32_t hi, const Consts &k) {
 // smallest and largest key hold the same certain slot, every key between
 // them maps to it.  When that holds on every lane the step adds its pairs
 // with one LDS atomic per lane instead of a lookup and an atomic per pair.
-// Used on the matrix-core path (compact 16 x 16 tiles) and on the FP32 path
-// (a wavefront's 256 rows are consecutive in the Morton order: on the octant
-// workload 45 % of the steps that are not beyond the last edge pass); on
-// the FP64 vector path, whose steps are cheaper to look up than to test, not.
+// A wavefront's 256 rows are consecutive in the Morton order, so at angles
+// large against their extent this is common (on the octant workload 45 % of
+// the FP32 steps that are not beyond the last edge pass).
 __device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint32_t n, const Consts &k,
                                               Counters &cnt) {
     if (!wave_all(e_lo == e_hi && !(e_lo & k.flag)))
@@ -349,13 +346,18 @@ __device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint
 
 // ---------------------------------------------------------------------------
 // Exact tile pruning.  A bounding cap (unit centre c, angular radius rho) of
-// the wavefront's rows and one of an aligned 64-column block bound the angle
-// of every pair of the block to [acos(c_r . c_b) - rho_r - rho_b,
-// acos(c_r . c_b) + rho_r + rho_b].  Widened by kPruneMargin (which covers
-// the FP32 row copies, the cap arithmetic and the counting rule's rounding of
-// the angle) and kept away from 0 and pi, an interval that contains no edge
-// puts every pair of the block in one slot: the wavefront adds the block's
-// pairs to that slot without evaluating them.
+// the wavefront's rows and one of an aligned 64-column block bound the
+// geometric angle phi (between the normalised directions) of every pair of
+// the block to [acos(c_r . c_b) - rho_r - rho_b, acos(c_r . c_b) + rho_r +
+// rho_b], widened by kPruneMargin (the FP32 row copies and the cap
+// arithmetic).  The counting rule does not see phi but the FP64 dot product
+// of the stored vectors, whose squared norms deviate from 1 by up to delta:
+// d = |v_i| |v_j| cos(phi) + err with |v_i| |v_j| in [1 - delta, 1 + delta]
+// and |err| <= kPruneDotSlack (the rule's rounding and that of the cosines
+// below).  So every pair's d lies in [cos(hi) - delta |cos(hi)| - slack,
+// cos(lo) + delta |cos(lo)| + slack]; when no threshold D_k falls inside
+// that interval every pair passes the same edges, and the wavefront adds the
+// block's pairs to that slot without evaluating them.
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -425,20 +427,21 @@ __device__ __forceinline__ int edges_le(const double *erad, int n, double t) {
 }
 
 // The slot of every pair between the row cap and the column block's cap, or
-// -1 when the test cannot prove one.  Wavefront-uniform.
-__device__ __forceinline__ int prune_slot(const Cap &r, const double *bcap, const Smem &s, int nedges) {
+// -1 when the test cannot prove one (see above; delta bounds the catalogs'
+// | |v|^2 - 1 |).  Wavefront-uniform.
+__device__ __forceinline__ int prune_slot(const Cap &r, const double *bcap, const Smem &s, int nedges,
+                                          double delta) {
     const cdouble_p bc = (cdouble_p)bcap;
-    const double d = fmin(fmax(r.x * bc[0] + r.y * bc[1] + r.z * bc[2], -1.0), 1.0);
-    const double th = acos(d);
+    const double c = fmin(fmax(r.x * bc[0] + r.y * bc[1] + r.z * bc[2], -1.0), 1.0);
+    const double th = acos(c);
     const double spread = r.rho + bc[3] + kPruneMargin;
-    const double lo = th - spread, hi = th + spread;
-    int slot = -1;
-    if (lo >= kPruneGuard && hi <= M_PI - kPruneGuard) {
-        const int a = edges_le(s.erad, nedges, lo);
-        if (a == edges_le(s.erad, nedges, hi))
-            slot = a;
-    }
-    return __builtin_amdgcn_readfirstlane(slot);
+    const double lo = fmax(th - spread, 0.0), hi = fmin(th + spread, M_PI);
+    const double clo = cos(lo), chi = cos(hi);
+    const double dhi = clo + delta * fabs(clo) + kPruneDotSlack;
+    const double dlo = chi - delta * fabs(chi) - kPruneDotSlack;
+    // pairs with the largest d pass the fewest edges
+    const uint32_t a = count_le(dhi, s.D, nedges), b = count_le(dlo, s.D, nedges);
+    return __builtin_amdgcn_readfirstlane(a == b ? (int)a : -1);
 }
 
 // 3-D: bounding ball of the points held by the lanes (centre = their mean,
@@ -493,7 +496,7 @@ __device__ __forceinline__ Cap block_cap(const double (&x)[N], const double (&y)
 
 template <bool M3>
 __device__ __forceinline__ int block_slot(const Cap &r, const double *bcap, const Smem &s, const PairArgs &a) {
-    return M3 ? prune_slot3(r, bcap, s, a.nedges, a.prune_margin) : prune_slot(r, bcap, s, a.nedges);
+    return M3 ? prune_slot3(r, bcap, s, a.nedges, a.prune_margin) : prune_slot(r, bcap, s, a.nedges, a.prune_delta);
 }
 
 // Add n pairs of this lane to `slot` (the overflow slot through the register
@@ -843,202 +846,13 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
     cols_fp64<LUT8, MASKED, P, M3, !PRUNE>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// Layout of v_mfma_f64_16x16x4f64 on gfx950 (measured with one-hot operands):
-// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; output register r of
-// lane l is D[l / 16 + 4 r][l % 16].  The diagonal masking and the exact
-// re-decision depend on it, so the parity tests check it.
-__device__ __forceinline__ int mma_row(int lane, int r) { return (lane >> 4) + 4 * r; }
-__device__ __forceinline__ int mma_col(int lane) { return lane & 15; }
-
-template <bool LUT8, bool M3>
-__device__ __forceinline__ uint32_t resolve_mma(uint32_t ent, uint32_t flag, double e, const Smem &s,
-                                                const PairArgs &a, const JobDev &jb, int i, int j,
-                                                uint32_t &n_exact) {
-    if (ent != (flag | Code<LUT8>::kmask)) {
-        int k = (int)(ent ^ flag);
-        const double2 b = s.Tband[k];
-        if (e < b.x)
-            return (uint32_t)k;
-        if (e >= b.y)
-            return (uint32_t)(k + 1);
-        ++n_exact;
-        double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
-        return (uint32_t)k + (d <= s.D[k] ? 1u : 0u);
-    }
-    ++n_exact;
-    double d = rule_value<M3>(jb.ax64[i], jb.ay64[i], jb.az64[i], jb.bx64[j], jb.by64[j], jb.bz64[j]);
-    return count_le(d, s.D, a.nedges);
-}
-
-// Bin the 16 x (RG x 16) pairs of one column group whose e = 1 - d the matrix
-// cores left in d (row group g, output register r of this lane: row
-// ib + 16 g + mma_row(lane, r), column 16 jg + mma_col(lane)).
-template <bool LUT8, bool MASKED, int RG, bool M3>
-__device__ __forceinline__ void bin_tile(const PairArgs &a, const JobDev &jb, const Smem &s,
-                                         const Consts &k, const v4d (&d)[RG], int ib, int rlo, int ie,
-                                         int jg, int clo, int j1, int lane, Counters &cnt) {
-    if (!MASKED) {
-        // every pair of the tile certainly beyond the last edge: high word of
-        // e above that of the band's upper end
-        int32_t m = __double2hiint(d[0][0]);
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                m = min(m, __double2hiint(d[g][r]));
-        if (wave_all(m > (int32_t)k.beyond)) {
-            cnt.beyond += RG * 4;
-            ++cnt.beyond_steps;
-            return;
-        }
-        int32_t mx = __double2hiint(d[0][0]);
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                mx = max(mx, __double2hiint(d[g][r]));
-        if (one_slot_step(lds_read_entry<LUT8>(addr64<LUT8>(m, k)), lds_read_entry<LUT8>(addr64<LUT8>(mx, k)),
-                          RG * 4, k, cnt))
-            return;
-    }
-    uint32_t ent[RG][4];
-    uint32_t any = 0;
-#pragma unroll
-    for (int g = 0; g < RG; ++g)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            ent[g][r] = lds_read_entry<LUT8>(addr64<LUT8>(__double2hiint(d[g][r]), k));
-#pragma unroll
-    for (int g = 0; g < RG; ++g)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            any |= ent[g][r];
-    if (any & k.flag) {
-        ++cnt.rare;
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (ent[g][r] & k.flag) {
-                    ++cnt.flag;
-                    int i = min(ib + 16 * g + mma_row(lane, r), jb.na - 1);
-                    // opaque here, so the row addresses of this rare path are
-                    // formed on demand and do not occupy registers in the loop
-                    asm volatile("" : "+v"(i));
-                    const int j = min(16 * jg + mma_col(lane), jb.nb - 1);
-                    ent[g][r] = resolve_mma<LUT8, M3>(ent[g][r], k.flag, d[g][r], s, a, jb, i, j, cnt.exact);
-                }
-    }
-#pragma unroll
-    for (int g = 0; g < RG; ++g)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            uint32_t v = ent[g][r];
-            if (MASKED) {
-                const int i = ib + 16 * g + mma_row(lane, r);
-                const int j = 16 * jg + mma_col(lane);
-                bool ok = i >= rlo && i < ie && j >= clo && j < j1 && (!jb.auto_pairs || j > i);
-                v = ok ? v : (uint32_t)a.nslots;
-            }
-            lds_inc(__umul24(v, k.rowstep) + k.lanebase);
-        }
-}
-
-// Column groups of [j0, j1) against the RG row groups of this wavefront: RG
-// matrix-core products per 16-column group, then the binning of their pairs.
-// The products of one group are binned before the next group's are issued
-// (no double buffer): that keeps the wavefront near 100 registers, and the
-// other wavefronts of the SIMD keep the matrix cores busy meanwhile.  The
-// column operands are fetched two groups ahead (clamped to the last group of
-// the catalog, so the reads never leave it).
-template <bool LUT8, bool MASKED, int RG, bool M3>
-__device__ __forceinline__ void cols_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                                         const double (&A)[RG], const v4d (&C)[RG], int ib, int rlo, int ie,
-                                         int j0, int clo, int j1, int lane, Counters &cnt) {
-    const gdouble_p bp = (gdouble_p)jb.bpack + lane;
-    const v4d zero = {0.0, 0.0, 0.0, 0.0};
-    const int jg0 = j0 >> 4;
-    const int jg_end = (j1 + 15) >> 4;
-    const int jg_last = jb.b_groups - 1;
-    double bq0 = bp[(size_t)min(jg0, jg_last) * 64];
-    double bq1 = bp[(size_t)min(jg0 + 1, jg_last) * 64];
-    for (int jg = jg0; jg < jg_end; ++jg) {
-        const double b = bq0;
-        bq0 = bq1;
-        bq1 = bp[(size_t)min(jg + 2, jg_last) * 64];
-        v4d d[RG];
-#pragma unroll
-        for (int g = 0; g < RG; ++g)
-            d[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[g], b, M3 ? C[g] : zero, 0, 0, 0);
-        bin_tile<LUT8, MASKED, RG, M3>(a, jb, s, k, d, ib, rlo, ie, jg, clo, j1, lane, cnt);
-    }
-}
-
-// Matrix-core path, one wavefront: RG groups of 16 rows starting at ib
-// (valid rows [rlo, ie)) against the column groups of [j0, j1).  For every
-// 16-column group one FP64 MFMA per row group yields e = 1 - d for 256 pairs
-// (A rows (-x_i, -y_i, -z_i, 1), B columns (x_j, y_j, z_j, 1)); the pairs are
-// then binned exactly as on the vector path, against the matrix-core band.
-template <bool LUT8, bool MASKED, int RG, bool PRUNE, bool M3>
-__device__ void rows_mma(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
-                         int ib, int rlo, int ie, int j0, int clo, int j1, int lane, Counters &cnt) {
-    const gdouble_p ap = (gdouble_p)jb.apack + lane;
-    double A[RG];
-    v4d C[RG];
-    const int g0 = ib >> 4;
-#pragma unroll
-    for (int g = 0; g < RG; ++g) {
-        const int gg = min(g0 + g, jb.a_groups - 1);   // groups past the catalog are masked
-        const double v = ap[(size_t)gg * 64];
-        if (M3) {
-            // 3-D: A row (-2x, -2y, -2z, 1) against B column (x, y, z, |b|^2),
-            // and the accumulator starts at |a|^2 of the output's row: the
-            // product is |a|^2 + |b|^2 - 2 a.b
-            A[g] = lane < 48 ? -2.0 * v : 1.0;
-            const gdouble_p q = (gdouble_p)jb.apack + (size_t)gg * 64 + 48 + mma_row(lane, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                C[g][r] = q[4 * r];
-        } else {
-            A[g] = lane < 48 ? -v : v;
-            C[g] = v4d{0.0, 0.0, 0.0, 0.0};
-        }
-    }
-    if (PRUNE && !MASKED && jb.bcaps) {
-        // unmasked: rows [ib, ib + 16 RG) are all valid; lane l takes one
-        const int i = ib + lane % (16 * RG);
-        const double xr[1] = {jb.ax64[i]}, yr[1] = {jb.ay64[i]}, zr[1] = {jb.az64[i]};
-        const Cap rc = block_cap<M3, 1>(xr, yr, zr);
-        for (int j = j0; j < j1;) {
-            const int jn = min(j1, (j & ~63) + 64);
-            if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
-                if (slot >= 0) {
-                    bin_block(slot, 16 * RG, a, k, cnt);
-                    cnt.pruned += (unsigned long long)16 * RG * 64;
-                    j = jn;
-                    continue;
-                }
-            }
-            cols_mma<LUT8, MASKED, RG, M3>(a, jb, s, k, A, C, ib, rlo, ie, j, j, jn, lane, cnt);
-            j = jn;
-        }
-        return;
-    }
-    cols_mma<LUT8, MASKED, RG, M3>(a, jb, s, k, A, C, ib, rlo, ie, j0, clo, j1, lane, cnt);
-}
-
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
-// table, 1 FP64 vector, 2 FP64 matrix cores; 3-D distances: 5 FP32 squared
-// distance with a clamped table, 4 FP64 vector, 8 FP64 matrix cores.  P: rows per lane of the vector
-// paths (a wavefront covers P * 64 rows of a unit) or row groups of 16 of the
-// matrix-core path (P * 16 rows).
+// table, 1 FP64 vector; 3-D distances: 5 FP32 squared distance with a
+// clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
+// rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
 __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
-    constexpr bool MMA = PREC == 2 || PREC == 8;
-    constexpr int kRowsPerWave = MMA ? P * 16 : P * kWaveSize;
+    constexpr int kRowsPerWave = P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
     const int tid = threadIdx.x;
@@ -1053,14 +867,13 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
     // a wrapped table's unused piece holds the histograms and thresholds,
     // which the copy must not overwrite
     const uint32_t aux_lo = a.lut_direct ? (uint32_t)a.aux_off : (uint32_t)lut_bytes;
-    const uint32_t aux_n = (uint32_t)(hist_words * 4 + a.nedges * 48);
+    const uint32_t aux_n = (uint32_t)(hist_words * 4 + a.nedges * kEdgeLdsBytes);
     for (int b = tid; b < lut_bytes; b += kBlock)
         if ((uint32_t)b - aux_lo >= aux_n)
             s.lut[b] = glut[b];
     for (int e = tid; e < a.nedges; e += kBlock) {
         s.D[e] = a.D[e];
         s.E[e] = a.E[e];
-        s.Tband[e] = make_double2(a.Tlo[e], a.Thi[e]);
         s.qband[e] = make_float2(a.qlo[e], a.qhi[e]);
         s.erad[e] = a.erad ? a.erad[e] : 0.0;
     }
@@ -1106,19 +919,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             }
             const int ie = min(un.i1, ib + kRowsPerWave);
             const int rlo = max(un.row_lo, ib);
-            // col_lo > j0 occurs on the matrix-core path only (vector plans start
-            // every unit at its first valid column)
-            bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib ||
-                          un.col_lo > un.j0;
-            if (MMA) {
-                masked = masked || (un.j1 & 15) != 0;
-                if (masked)
-                    rows_mma<LUT8, true, P, PRUNE, PREC == 8>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
-                                                              cnt);
-                else
-                    rows_mma<LUT8, false, P, PRUNE, PREC == 8>(a, jb, s, k, ib, rlo, ie, un.j0, un.col_lo, un.j1, lane,
-                                                    cnt);
-            } else if (PREC == 0 || PREC == 3 || PREC == 5) {
+            const bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib;
+            if (PREC == 0 || PREC == 3 || PREC == 5) {
                 constexpr bool M3 = PREC == 5;
                 if (masked)
                     rows_fp32<LUT8, true, P, PREC == 3, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
@@ -1190,15 +992,24 @@ __global__ void reduce_copies_kernel(const unsigned long long *copies, int32_t n
 
 // FP32 copies (round to nearest) of an FP64 SoA block of 3n values, and the
 // largest |x^2 + y^2 + z^2 - 1| (FP64, unfused), +inf if a value is not finite.
-__global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsigned long long *maxdev) {
+// With `given` (caller-owned FP32 copies) nothing is written: every given
+// value is compared with the rounded FP64 one and *mismatch is set if one
+// differs.
+__global__ void to_float_kernel(const double *xyz, int64_t n, float *out, const float *given,
+                                unsigned long long *maxdev, unsigned long long *mismatch) {
     __shared__ double red[256];
     double m = 0.0;
+    bool differs = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-        out[i] = (float)x;
-        out[n + i] = (float)y;
-        out[2 * n + i] = (float)z;
+        if (given) {
+            differs = differs || given[i] != (float)x || given[n + i] != (float)y || given[2 * n + i] != (float)z;
+        } else {
+            out[i] = (float)x;
+            out[n + i] = (float)y;
+            out[2 * n + i] = (float)z;
+        }
         double t = x * x;
         double u = y * y;
         double v = z * z;
@@ -1208,6 +1019,8 @@ __global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsign
             dev = __builtin_huge_val();
         m = dev > m ? dev : m;
     }
+    if (differs)
+        atomicOr(mismatch, 1ull);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
@@ -1217,34 +1030,6 @@ __global__ void to_float_kernel(const double *xyz, int64_t n, float *out, unsign
     }
     if (threadIdx.x == 0)
         atomicMax(maxdev, (unsigned long long)__double_as_longlong(red[0]));
-}
-
-// Matrix-core operand pack: pack[64 g + l] = component l / 16 of point
-// 16 g + l % 16 (component 3 is 1), zero past the end of the catalog.
-__global__ void pack16_kernel(const double *xyz, int64_t n, double *pack, int64_t total, int metric) {
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = idx >> 6;
-        const int l = (int)(idx & 63);
-        const int64_t p = 16 * g + (l & 15);
-        const int c = l >> 4;
-        double v = 0.0;
-        if (p < n) {
-            if (c < 3) {
-                v = xyz[(int64_t)c * n + p];
-            } else if (metric) {
-                // 3-D: the squared norm, (x^2 + y^2) + z^2 rounded per operation
-                const double x = xyz[p], y = xyz[n + p], z = xyz[2 * n + p];
-                const double t = x * x;
-                const double u = y * y;
-                const double w = z * z;
-                v = (t + u) + w;
-            } else {
-                v = 1.0;
-            }
-        }
-        pack[idx] = v;
-    }
 }
 
 // Bounding cap of every aligned group of 64 stored points: one wavefront per
@@ -1336,10 +1121,6 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
             launch_pairs<4, true>(P, prune, grid, lds, st, *args);
         else if (precision == 1)
             launch_pairs<4, false>(P, prune, grid, lds, st, *args);
-        else if (precision == 2 && b8)
-            launch_pairs<8, true>(P, prune, grid, lds, st, *args);
-        else if (precision == 2)
-            launch_pairs<8, false>(P, prune, grid, lds, st, *args);
         else
             return (int)hipErrorInvalidValue;
         return (int)hipGetLastError();
@@ -1356,26 +1137,9 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
             launch_pairs<1, true>(P, prune, grid, lds, st, *args);
         else
             launch_pairs<1, false>(P, prune, grid, lds, st, *args);
-    } else if (precision == 2) {
-        if (b8)
-            launch_pairs<2, true>(P, prune, grid, lds, st, *args);
-        else
-            launch_pairs<2, false>(P, prune, grid, lds, st, *args);
     } else {
         return (int)hipErrorInvalidValue;
     }
-    return (int)hipGetLastError();
-}
-
-extern "C" int tpcf_launch_pack16(const double *xyz64, int64_t n, double *pack, int metric, void *stream) {
-    const int64_t total = ((n + 15) / 16) * 64;
-    if (total <= 0)
-        return 0;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 4096)
-        blocks = 4096;
-    hipLaunchKernelGGL(pack16_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, xyz64, n,
-                       pack, total, metric);
     return (int)hipGetLastError();
 }
 
@@ -1410,15 +1174,16 @@ extern "C" int tpcf_launch_reduce_copies(const unsigned long long *copies, int32
     return (int)hipGetLastError();
 }
 
-extern "C" int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32,
-                                    double *maxdev_out, void *stream) {
-    // maxdev_out is a device double, zeroed by the caller
+extern "C" int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32, const float *given32,
+                                    unsigned long long *check_out, void *stream) {
+    // check_out: two device words zeroed by the caller, [0] the largest norm
+    // deviation (a double's bits), [1] non-zero if a given FP32 copy differs
     if (n <= 0)
         return 0;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 2048)
         blocks = 2048;
     hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
-                       xyz64, n, xyz32, reinterpret_cast<unsigned long long *>(maxdev_out));
+                       xyz64, n, xyz32, given32, check_out, check_out + 1);
     return (int)hipGetLastError();
 }

@@ -294,5 +294,55 @@ def box_1e6x2e6(scale: float = 1.0, side: float = 1000.0) -> Workload3d:
     return Workload3d(f"box{int(side)}_{nd:.0e}x{nr:.0e}".replace("+0", ""), d, r, log_edges(0.5, 150.0, 30))
 
 
+def near_limit_clusters(n_per: int = 1024, stream: int = 0):
+    """Caller-given FP64 vectors (for the xyz entry point) whose squared norms
+    deviate from 1 by 0.90 .. 0.95 x 2^-20, the largest deviation that entry
+    accepts, in pairs of tight clusters (radius ~1e-6 rad) whose centres lie
+    a few 1e-6 rad on either side of a bin edge.  A pair's dot product is then
+    |a| |b| cos(phi), which moves its angle by up to ~1e-6 cot(phi): tens of
+    1e-6 rad, far more than the clusters' distance from the edge, so binning
+    the true directions instead of the given vectors puts these pairs in the
+    wrong bin.  Squared norms are above 1 where the centres lie past the edge
+    and below 1 where they lie short of it (both cross the edge); clusters
+    short of an edge hold n_per / 2 points, the others n_per, so the two
+    crossings do not cancel in a histogram.  Cluster pairs sit 30 deg apart,
+    beyond the last edge of each other.
+    Returns (a_xyz (3, 4.5 n_per), b_xyz (3, 4.5 n_per), edges_deg)."""
+    g = rng_for(97, stream)
+    limit = 2.0 ** -20
+    edges = np.array([0.1, 0.5, 2.0, 5.0])
+    specs = [(0.5, 5e-6, 1.0), (0.5, -5e-6, -1.0), (2.0, 4e-6, 1.0), (2.0, -4e-6, -1.0),
+             (0.1, 3e-6, 1.0), (0.1, -3e-6, -1.0)]
+
+    def tangent_basis(c):
+        t = np.cross(c, [0.0, 0.0, 1.0] if abs(c[2]) < 0.9 else [1.0, 0.0, 0.0])
+        t /= np.linalg.norm(t)
+        return t, np.cross(c, t)
+
+    def cluster(c, sign):
+        n = n_per if sign > 0 else n_per // 2
+        e1, e2 = tangent_basis(c)
+        x = g.normal(0.0, 2e-7, size=(n, 1))
+        y = g.normal(0.0, 2e-7, size=(n, 1))
+        p = c[None, :] + x * e1[None, :] + y * e2[None, :]
+        p /= np.linalg.norm(p, axis=1)[:, None]
+        return p * np.sqrt(1.0 + sign * limit * g.uniform(0.90, 0.95, size=(n, 1)))
+
+    A, B = [], []
+    for k, (edge_deg, offset, sign) in enumerate(specs):
+        ra, dec = math.radians(30.0 * k), math.radians(20.0)
+        c = np.array([math.cos(dec) * math.cos(ra), math.cos(dec) * math.sin(ra), math.sin(dec)])
+        e1, e2 = tangent_basis(c)
+        phi = g.uniform(0.0, 2.0 * math.pi)
+        t = math.cos(phi) * e1 + math.sin(phi) * e2
+        theta = math.radians(edge_deg) + offset
+        c2 = math.cos(theta) * c + math.sin(theta) * t
+        A.append(cluster(c, sign))
+        B.append(cluster(c2 / np.linalg.norm(c2), sign))
+    a = np.concatenate(A).T.copy()
+    b = np.concatenate(B).T.copy()
+    return a, b, edges
+
+
 WORKLOADS = {"patch30_1e4": patch30_1e4, "octant_1e5": octant_1e5,
              "octant_1e6x2e6": octant_1e6x2e6, "batched_64": batched_64}

@@ -9,7 +9,7 @@
 
 static int check(int rc, const char *what) {
     if (rc != TPCF_OK) {
-        fprintf(stderr, "%s failed (%d): %s\n", what, rc, tpcf_last_error());
+        fprintf(stderr, "%s failed (%d): %s\n", what, rc, tpcf_last_error(NULL));
         exit(1);
     }
     return rc;
@@ -37,8 +37,8 @@ int main(void) {
     check(tpcf_open(0, NULL, &ctx), "tpcf_open");
     int32_t cat = -1;
     check(tpcf_upload_catalog(ctx, ra, dec, (int64_t)n, &cat), "tpcf_upload_catalog");
-    const int precisions[3] = {TPCF_FP32_CHORD, TPCF_FP64, TPCF_FP64_MATRIX};
-    for (int p = 0; p < 3; ++p) {
+    const int precisions[2] = {TPCF_FP32_CHORD, TPCF_FP64};
+    for (int p = 0; p < 2; ++p) {
         check(tpcf_count(ctx, TPCF_DD, cat, -1, edges, nbins, precisions[p], -1, -1, out), "tpcf_count");
         for (int s = 0; s < nbins + 2; ++s)
             printf("%s%llu", s ? " " : "", (unsigned long long)out[s]);

@@ -51,6 +51,6 @@ def test_c_client_counts_equal_the_oracle(tmp_path):
     assert r.returncode == 0, r.stderr
     got = [np.array([int(v) for v in line.split()], dtype=np.uint64) for line in r.stdout.strip().splitlines()]
     ref = oracle.count(oracle.DD, oracle.radec_to_xyz(d.ra, d.dec), e)
-    assert len(got) == 3
+    assert len(got) == 2
     for g in got:
         assert np.array_equal(g, ref)

@@ -39,7 +39,7 @@ def small_batch(ctx):
     return wl, cats, cr
 
 
-@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX])
+@pytest.mark.parametrize("prec", [tp.FP32_CHORD, tp.FP64])
 def test_batch_equals_single_counts_and_oracle(ctx, small_batch, prec):
     wl, cats, cr = small_batch
     e = wl.edges_deg

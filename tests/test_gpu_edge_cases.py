@@ -21,7 +21,7 @@ import synthcat
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
+PRECS = [tp.FP32_CHORD, tp.FP64]
 
 
 @pytest.fixture(scope="module")

@@ -19,7 +19,7 @@ import synthcat
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
+PRECS = [tp.FP32_CHORD, tp.FP64]
 _cache = {}
 
 
@@ -288,7 +288,18 @@ def test_attach_torch_tensor_and_async(ctx, patch):
     ctx.synchronize()
     assert np.array_equal(out.cpu().numpy().astype(np.uint64), ref["DR"])
     ctx.release_catalog(ca)
-    del t
+    # the caller's own FP32 copies (round to nearest) are taken as they are
+    t32 = t.to(torch.float32).contiguous()
+    cb = ctx.attach_catalog(t, t32)
+    for prec in PRECS:
+        assert np.array_equal(ctx.count(tp.DD, cb, wl.edges_deg, precision=prec), ref["DD"])
+    ctx.release_catalog(cb)
+    # copies that are not the rounded FP64 values are refused
+    bad = t32.clone()
+    bad[0, 5] = torch.nextafter(bad[0, 5], torch.tensor(2.0, dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(tp.TpcfError):
+        ctx.attach_catalog(t, bad)
+    del t, t32, bad
 
 
 def test_timing_and_stats(ctx, patch):
@@ -332,6 +343,38 @@ def test_pruning_keeps_counts_exact(ctx, patch, prec):
                                         row_end=7777), part)
     finally:
         ctx.set_tuning()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_pruning_exact_for_norms_at_the_accepted_limit(ctx, prec):
+    """Vectors whose squared norms deviate from 1 by up to 0.95 x 2^-20 (the
+    xyz entry's limit), in tight clusters a few 1e-6 rad from bin edges: the
+    rule's dot product |a| |b| cos(phi) puts these pairs in other bins than
+    their directions would, so a pruning test blind to the norm deviation
+    would bin whole blocks wrongly.  DR and DD of the union, pruning off and
+    on, against the oracle; the oracle's histograms differ from those of the
+    normalised vectors (the test is sensitive), and pruning does bin blocks."""
+    a, b, e = _cache.setdefault("near_limit", synthcat.near_limit_clusters())
+    u = np.concatenate([a, b], axis=1)
+    ref_dr = _oracle("near_limit_dr", lambda: oracle.count(oracle.DR, a, e, b_xyz=b))
+    ref_dd = _oracle("near_limit_dd", lambda: oracle.count(oracle.DD, u, e))
+    unit = lambda v: v / np.sqrt((v * v).sum(axis=0))
+    assert not np.array_equal(ref_dr, oracle.count(oracle.DR, unit(a), e, b_xyz=unit(b)))
+    ca = ctx.upload_catalog_xyz(*a)
+    cb = ctx.upload_catalog_xyz(*b)
+    cu = ctx.upload_catalog_xyz(*u)
+    try:
+        for prune in (0, 1):
+            ctx.set_tuning(prune=prune)
+            ctx.stats(reset=True)
+            assert np.array_equal(ctx.count(tp.DR, ca, e, cat_b=cb, precision=prec), ref_dr), prune
+            assert np.array_equal(ctx.count(tp.DD, cu, e, precision=prec), ref_dd), prune
+            st = ctx.stats(reset=True)
+            assert (st.pruned_pairs > 0) == (prune == 1)
+    finally:
+        ctx.set_tuning()
+        for c in (ca, cb, cu):
+            ctx.release_catalog(c)
 
 
 @pytest.mark.parametrize("prec", PRECS)

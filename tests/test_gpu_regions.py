@@ -18,7 +18,7 @@ import synthcat
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX]
+PRECS = [tp.FP32_CHORD, tp.FP64]
 _cache = {}
 
 
@@ -194,9 +194,9 @@ def test_full_octant_deleted_region_equals_reduced_catalog_counts(ctx):
             finally:
                 ctx.release_catalog(sd)
                 ctx.release_catalog(sr)
-        # matrix path agrees with the FP32 path at full size
-        mdd = ctx.count_regions(tp.DD, cd, wl.edges_deg, precision=tp.FP64_MATRIX)
-        assert np.array_equal(mdd[0], dd_t) and np.array_equal(mdd[1], dd_touch)
+        # the FP64 path agrees with the FP32 path at full size
+        fdd = ctx.count_regions(tp.DD, cd, wl.edges_deg, precision=tp.FP64)
+        assert np.array_equal(fdd[0], dd_t) and np.array_equal(fdd[1], dd_touch)
     finally:
         ctx.release_catalog(cd)
         ctx.release_catalog(cr)

@@ -375,61 +375,6 @@ def test_open_without_gpu_fails_cleanly():
         tp.Context(0)
 
 
-@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
-                                   np.array([0.0, 1e-5, 0.5, 60.0, 90.0, 120.0, 179.0, 180.0])])
-def test_matrix_band_is_safe_for_any_rounding(edges):
-    """The matrix-core band: whatever order or fusion the matrix cores use,
-    their e is within ~2e-15 of 1 - d.  Pairs at theta = e_k (1 +- 10^-s) get
-    e = 1 - d (rounded up, down, or moved by up to 2e-15 either way); every
-    decision the band calls certain must equal the oracle's."""
-    g = np.random.default_rng(11)
-    lo, hi = tp.compile_band64(edges)
-    er = edges * DEG
-    thetas = []
-    for e in er:
-        if 0.0 < e < math.pi:
-            for s in range(6, 16):
-                for sign in (-1.0, 1.0):
-                    thetas.append(np.full(20, e * (1.0 + sign * 10.0 ** -s)))
-    theta = np.clip(np.concatenate(thetas), 0.0, math.pi)
-    a, b = _pairs_at(g, theta)
-    d = _dot64(a, b)
-    truth = oracle.pair_slots(a.T, b.T, edges)
-    base = 1.0 - d
-    for shift in (-2e-15, -1e-15, 0.0, 1e-15, 2e-15):
-        e = base + shift
-        for k in range(edges.size):
-            past = truth >= k + 1
-            assert np.all(past[e >= hi[k]]), (k, shift)
-            assert not np.any(past[e < lo[k]]), (k, shift)
-    # the band is narrow: a few times 2^-48 around 1 - D_k
-    D, _, _ = tp.compile_edges(edges)
-    fin = np.isfinite(D)
-    assert np.all(hi[fin] - lo[fin] < 2 ** -45)
-
-
-def test_matrix_cells_are_consistent_with_the_band():
-    edges = synthcat.log_edges(0.0005, 30.0, 40)
-    lo, hi = tp.compile_band64(edges)
-    shift, clo, chi, cells, _ = tp.compile_cells(edges, tp.FP64_MATRIX)
-    g = np.random.default_rng(12)
-    # e values spread over the whole range in log space, plus the band edges
-    e = np.concatenate([10.0 ** g.uniform(-12, 0.3, 200000), lo[np.isfinite(lo)], hi[np.isfinite(hi)],
-                        np.nextafter(lo[np.isfinite(lo)], -1), np.nextafter(hi[np.isfinite(hi)], 3)])
-    key = (e.view(np.uint64) >> np.uint64(32)).astype(np.uint32).view(np.int32).astype(np.int64) >> shift
-    ent = cells[np.clip(key, clo, chi) - clo].astype(np.int64)
-    certain = ent < 0x8000
-    smin = np.array([np.sum(x >= hi) for x in e])
-    smax = np.array([np.sum(x >= lo) for x in e])
-    assert np.all(ent[certain] == smin[certain])
-    assert np.all(smin[certain] == smax[certain])
-    med = (ent >= 0x8000) & (ent != 0xFFFF)
-    k = ent[med] & 0x7FFF
-    assert np.all(smin[med] >= k) and np.all(smax[med] <= k + 1)
-
-
-# --- host jackknife (tpcf_jackknife) -----------------------------------------
-
 def test_host_jackknife_equals_oracle_recount():
     """tpcf_jackknife on oracle region counts against the oracle's delete-one
     jackknife by recount of the reduced catalogs (an independent route:
@@ -553,41 +498,7 @@ def test_3d_fp32_band_adversary(rmax):
     assert np.all(in_band[rel < 0.1 * half])
 
 
-@pytest.mark.parametrize("rmax", [1.0, 1000.0, 3.0e5])
-def test_3d_matrix_band_is_safe_for_any_rounding(rmax):
-    """The matrix cores' r2 = |a|^2 + |b|^2 - 2 a.b lies within 50 U R^2 of the
-    rule's r2 (the derivation beside make_band64_3d): values perturbed by up
-    to that much, and the products summed in other orders, never cross a band
-    the wrong way; the band is no wider than 2^-46 R^2 plus an ulp."""
-    g = np.random.default_rng(17)
-    edges = synthcat.log_edges(1e-3 * rmax, 0.3 * rmax, 24)
-    S, _, _ = tp.compile_edges_3d(edges, rmax=rmax)
-    lo, hi = tp.compile_band64_3d(edges, rmax=rmax)
-    rs, ks = [], []
-    for k, e in enumerate(edges):
-        for s_ in range(3, 16):
-            for sign in (-1.0, 1.0):
-                rs.append(np.full(40, e * (1.0 + sign * 10.0 ** -s_)))
-    r = np.concatenate(rs)
-    a, b = _pairs_at_distance(g, r, rmax)
-    d = a - b
-    r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
-    qa = (a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1]) + a[:, 2] * a[:, 2]
-    qb = (b[:, 0] * b[:, 0] + b[:, 1] * b[:, 1]) + b[:, 2] * b[:, 2]
-    dot = (a * b).sum(axis=1)
-    forms = [qa + qb - 2.0 * dot,
-             (qb - 2.0 * (a[:, 2] * b[:, 2])) + (qa - 2.0 * (a[:, 0] * b[:, 0] + a[:, 1] * b[:, 1]))]
-    U = 2.0 ** -53
-    for e2 in forms + [r2 + g.uniform(-48.0, 48.0, size=r2.size) * U * rmax * rmax]:
-        assert np.all(np.abs(e2 - r2) <= 50.0 * U * rmax * rmax)
-        for k in range(edges.size):
-            past = r2 >= S[k]
-            assert np.all(past[e2 >= hi[k]]), k
-            assert not np.any(past[e2 < lo[k]]), k
-    assert np.all(hi - lo <= 2.0 ** -46 * rmax * rmax * 1.01 + 4 * np.spacing(hi))
-
-
-@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64, tp.FP64_MATRIX])
+@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64])
 def test_edge_at_zero_never_flags(precision):
     """An edge at 0 degrees (D_0 = +inf, E_0 = -inf) is passed by every pair,
     so no cell may leave it undecided (0x8000 | 0) and every cell's slot is
