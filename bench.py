@@ -344,7 +344,7 @@ def main():
         t1 = time.perf_counter()
         ctx.set_timing(False)
         kms, launches = ctx.kernel_time(reset=True)
-        pairs, flagged, exact, rare, beyond, one_slot, pruned = ctx.stats(reset=True)
+        st = ctx.stats(reset=True)
         # per kind: one more launch of each, timed alone with HIP events
         per_kind = {}
         for name, kind, a, b, npairs in (("DD", tp.DD, cd, -1, nd * (nd - 1) // 2),
@@ -365,8 +365,9 @@ def main():
         rows_per_step = rpl * 64
         cols_per_step = {tp.FP32_CHORD: 4, tp.FP64: 2}[prec]
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
-                "totals_ok": ok, "flagged": flagged, "exact": exact, "pairs": pairs, "rare": rare,
-                "beyond": beyond, "one_slot": one_slot, "per_kind": per_kind,
+                "totals_ok": ok, "flagged": st.flagged, "exact": st.exact, "pairs": st.pairs,
+                "rare": st.rare_steps, "beyond": st.beyond_steps, "one_slot": st.one_slot_steps,
+                "two_slot": st.two_slot_steps, "per_kind": per_kind,
                 "tuning": tuning, "pairs_per_wave_step": rows_per_step * cols_per_step}
 
     print(f"# workload {wl.name}: N_D={nd} N_R={nr} nbins={edges.size - 1} "
@@ -397,7 +398,8 @@ def main():
                 "exact_rate": r["exact"] / max(1, r["pairs"]),
                 "rare_step_rate": r["rare"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
                 "beyond_last_edge_rate": r["beyond"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
-                "one_slot_rate": r["one_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
+                "one_slot_rate": r["one_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
+                "two_slot_rate": r["two_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
 
     sums = {prec: summary(prec) for prec in paths}
     pruned = None

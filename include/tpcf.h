@@ -352,6 +352,9 @@ typedef struct tpcf_counters {
                                  added with one LDS atomic per lane */
     uint64_t pruned_pairs;    /* pairs binned by pruned blocks without being evaluated
                                  (tuning field prune) */
+    uint64_t two_slot_steps;  /* steps where each lane's pairs fell in two adjacent slots,
+                                 decided by one threshold comparison per pair and added with
+                                 two LDS atomics per lane */
 } tpcf_counters;
 
 /* Copy the statistics to *out (may be NULL) and, with reset = 1, clear

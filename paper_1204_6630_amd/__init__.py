@@ -64,7 +64,8 @@ BATCH_GRAPH = 1
 class Counters(ctypes.Structure):
     """struct tpcf_counters"""
     _fields_ = [(n, ctypes.c_uint64) for n in ("pairs", "flagged", "exact", "rare_steps",
-                                               "beyond_steps", "one_slot_steps", "pruned_pairs")]
+                                               "beyond_steps", "one_slot_steps", "pruned_pairs",
+                                               "two_slot_steps")]
 
 
 Stats = collections.namedtuple("Stats", [n for n, _ in Counters._fields_])

@@ -1823,6 +1823,7 @@ int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset) {
         out->beyond_steps = tot[5];
         out->one_slot_steps = tot[6];
         out->pruned_pairs = tot[7];
+        out->two_slot_steps = tot[0];
     }
     if (reset)
         ctx->pairs_since_reset = 0;

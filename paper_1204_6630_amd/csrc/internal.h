@@ -126,9 +126,9 @@ struct PairArgs {
     int32_t rows_per_lane;       // 2 or 4: a unit spans kWaves * 64 * rows_per_lane rows
     int32_t blocks_per_cu;       // grid = CUs x this (0: the blocks that fit at once)
 
-    unsigned long long *stats;   // [-, flagged, exact, skipped units, rare-path steps,
-                                 //  steps counted beyond the last edge, one-slot steps,
-                                 //  pairs binned by pruned blocks]
+    unsigned long long *stats;   // [two-slot steps, flagged, exact, skipped units, rare-path
+                                 //  steps, steps counted beyond the last edge, one-slot
+                                 //  steps, pairs binned by pruned blocks]
 };
 
 // LDS bytes per edge: D_k, fl(1 - D_k), the edge in radians (pruning) and

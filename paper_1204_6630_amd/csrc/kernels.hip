@@ -290,6 +290,7 @@ struct Counters {
     uint32_t beyond = 0;        // this lane's pairs counted beyond the last edge (per unit)
     uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
     uint32_t one_slot_steps = 0;  // steps binned with one atomic per lane (uniform)
+    uint32_t two_slot_steps = 0;  // steps binned with two atomics per lane (uniform)
     unsigned long long pruned = 0;  // pairs binned by pruned blocks (uniform)
 };
 
@@ -327,21 +328,51 @@ __device__ __forceinline__ uint32_t addr64(int32_t hi, const Consts &k) {
     return (uint32_t)c * (LUT8 ? 1u : 2u) + k.lutbias;
 }
 
-// One slot for all of a lane's pairs: slots never decrease as the key grows
-// (keys below the table share its bottom cell), so if the cells of the
-// smallest and largest key hold the same certain slot, every key between
-// them maps to it.  When that holds on every lane the step adds its pairs
-// with one LDS atomic per lane instead of a lookup and an atomic per pair.
-// A wavefront's 256 rows are consecutive in the Morton order, so at angles
-// large against their extent this is common (on the octant workload 45 % of
-// the FP32 steps that are not beyond the last edge pass).
-__device__ __forceinline__ bool one_slot_step(uint32_t e_lo, uint32_t e_hi, uint32_t n, const Consts &k,
+// Slot range of a lane's pairs.  A cell entry bounds the slots of its keys: a
+// certain slot s gives [s, s], edge k undecided gives [k, k+1] (a cell with
+// several undecided edges gives [kmask, kmask+1], which no test below
+// accepts).  Slots never decrease as the key grows (keys below the table
+// share its bottom cell), so the entries of a lane's smallest and largest key
+// bound the slots of all its pairs: lo = the lower end of the first, and
+// span = the upper end of the second minus lo.
+template <bool LUT8>
+__device__ __forceinline__ void slot_range(uint32_t e_lo, uint32_t e_hi, uint32_t &lo, uint32_t &span) {
+    constexpr uint32_t m = Code<LUT8>::kmask, sh = LUT8 ? 7 : 15;
+    lo = e_lo & m;
+    span = (e_hi & m) + (e_hi >> sh) - lo;
+}
+
+// One slot for all of a lane's pairs (span 0).  When that holds on every lane
+// the step adds its pairs with one LDS atomic per lane instead of a lookup and
+// an atomic per pair.  A wavefront's 256 rows are consecutive in the Morton
+// order, so at angles large against their extent this is common (on the
+// octant workload 45 % of the FP32 steps that are not beyond the last edge
+// pass).
+__device__ __forceinline__ bool one_slot_step(uint32_t lo, uint32_t span, uint32_t n, const Consts &k,
                                               Counters &cnt) {
-    if (!wave_all(e_lo == e_hi && !(e_lo & k.flag)))
+    if (!wave_all(span == 0))
         return false;
-    lds_add(__umul24(e_lo, k.rowstep) + k.lanebase, n);
+    lds_add(__umul24(lo, k.rowstep) + k.lanebase, n);
     ++cnt.one_slot_steps;
     return true;
+}
+
+// Two adjacent slots [lo, lo+1] (or one) for all of a lane's pairs, on every
+// lane: then each pair needs one comparison with edge lo's threshold instead
+// of a table lookup, and the step adds its pairs with two LDS atomics per
+// lane.
+template <bool LUT8>
+__device__ __forceinline__ bool two_slot_range(uint32_t lo, uint32_t span) {
+    return (__builtin_amdgcn_ballot_w64(span <= 1u) & __builtin_amdgcn_ballot_w64(lo != Code<LUT8>::kmask)) == ~0ull;
+}
+
+__device__ __forceinline__ void two_slot_add(uint32_t base, uint32_t n, uint32_t n_up, const Consts &k,
+                                             Counters &cnt) {
+    const uint32_t addr = __umul24(base, k.rowstep) + k.lanebase;
+    lds_add(addr, n - n_up);
+    if (n_up)
+        lds_add(addr + k.rowstep, n_up);
+    ++cnt.two_slot_steps;
 }
 
 // ---------------------------------------------------------------------------
@@ -561,10 +592,40 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     mx = max(mx, __float_as_uint(q[t][p]));
-            const uint32_t e_lo = lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(m, k));
-            const uint32_t e_hi = lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(mx, k));
-            if (one_slot_step(e_lo, e_hi, JN * P, k, cnt))
+            uint32_t base, span;
+            slot_range<LUT8>(lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(m, k)),
+                             lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(mx, k)), base, span);
+            if (one_slot_step(base, span, JN * P, k, cnt))
                 return;
+            if (two_slot_range<LUT8>(base, span)) {
+                // a pair is past edge `base` when q >= qhi and not past it when
+                // q < qlo; x = fl(q - qhi) has the sign of q - qhi unless it is
+                // zero, and |x| > fl(qhi - qlo) puts q outside [qlo, qhi)
+                // (fl is monotone), so the sign of x decides every such pair;
+                // lanes with one slot compare with +inf (x = -inf)
+                // (a decided pair's x is nonzero, so its sign bit counts the
+                // pairs below the threshold: no compare-and-carry, whose
+                // mask hazard costs wait states on gfx950)
+                const float2 b = s.qband[min(base, (uint32_t)(a.nedges - 1))];
+                const float thr = span ? b.y : __builtin_huge_valf();
+                const float width = b.y - b.x;
+                uint32_t n_below = 0;
+                float near = __builtin_huge_valf();
+#pragma unroll
+                for (int t = 0; t < JN; ++t)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const float x = q[t][p] - thr;
+                        n_below += __float_as_uint(x) >> 31;
+                        near = fminf(near, fabsf(x));
+                    }
+                // count before the test, so the differences die here
+                asm volatile("" : "+v"(n_below));
+                if (wave_all(near > width)) {
+                    two_slot_add(base, JN * P, JN * P - n_below, k, cnt);
+                    return;
+                }
+            }
         }
     }
 #pragma unroll
@@ -621,22 +682,18 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
         yj[t] = by[j + t];
         zj[t] = bz[j + t];
     }
-    double d[JN][P], e[JN][P];
+    // e: the table key's value (1 - d, or r^2 in 3-D); the rule's value d
+    // itself is formed again, with the same operations, in the rare path
+    double e[JN][P];
     uint32_t ent[JN][P];
 #pragma unroll
     for (int t = 0; t < JN; ++t) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (M3) {
-                // key on the squared distance itself; d = -r^2 for the thresholds
-                const double r2 = exact_d2(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
-                d[t][p] = -r2;
-                e[t][p] = r2;
-            } else {
-                double dd = exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
-                d[t][p] = dd;
-                e[t][p] = 1.0 - dd;
-            }
+            if (M3)
+                e[t][p] = exact_d2(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
+            else
+                e[t][p] = 1.0 - exact_dot(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
         }
     }
     if (!MASKED) {
@@ -660,10 +717,31 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
                 for (int p = 0; p < P; ++p)
                     mx = max(mx, __double2hiint(e[t][p]));
-            const uint32_t e_lo = lds_read_entry<LUT8>(addr64<LUT8>(m, k));
-            const uint32_t e_hi = lds_read_entry<LUT8>(addr64<LUT8>(mx, k));
-            if (one_slot_step(e_lo, e_hi, JN * P, k, cnt))
+            uint32_t base, span;
+            slot_range<LUT8>(lds_read_entry<LUT8>(addr64<LUT8>(m, k)), lds_read_entry<LUT8>(addr64<LUT8>(mx, k)),
+                             base, span);
+            if (one_slot_step(base, span, JN * P, k, cnt))
                 return;
+            if (two_slot_range<LUT8>(base, span)) {
+                // past edge `base` when e > E_base, not past it when e < E_base,
+                // and the exact rule decides e == E_base (as in resolve_fp64);
+                // lanes with one slot compare with +inf
+                const double thr = span ? s.E[min(base, (uint32_t)(a.nedges - 1))] : __builtin_huge_val();
+                uint32_t n_up = 0, tie = 0;
+#pragma unroll
+                for (int t = 0; t < JN; ++t)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        n_up += e[t][p] > thr ? 1u : 0u;
+                        tie |= e[t][p] == thr ? 1u : 0u;
+                    }
+                // count before the test, so nothing of it stays live past it
+                asm volatile("" : "+v"(n_up), "+v"(tie));
+                if (!__builtin_amdgcn_ballot_w64(tie != 0)) {
+                    two_slot_add(base, JN * P, n_up, k, cnt);
+                    return;
+                }
+            }
         }
     }
 #pragma unroll
@@ -687,7 +765,8 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & k.flag) {
                     ++cnt.flag;
-                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], k.flag, e[t][p], d[t][p], s, a, cnt.exact);
+                    const double d = rule_value<M3>(xi[p], yi[p], zi[p], xj[t], yj[t], zj[t]);
+                    ent[t][p] = resolve_fp64<LUT8>(ent[t][p], k.flag, e[t][p], d, s, a, cnt.exact);
                 }
     }
 #pragma unroll
@@ -851,7 +930,7 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
 // clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
 // rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
-__global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PRUNE ? 1 : 5))) void pairs_kernel(PairArgs a) {
     constexpr int kRowsPerWave = P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
@@ -966,6 +1045,8 @@ __global__ __launch_bounds__(kBlock) void pairs_kernel(PairArgs a) {
             atomicAdd(&a.stats[5], (unsigned long long)cnt.beyond_steps);
         if (cnt.one_slot_steps)
             atomicAdd(&a.stats[6], (unsigned long long)cnt.one_slot_steps);
+        if (cnt.two_slot_steps)
+            atomicAdd(&a.stats[0], (unsigned long long)cnt.two_slot_steps);
         if (cnt.pruned)
             atomicAdd(&a.stats[7], cnt.pruned);
     }

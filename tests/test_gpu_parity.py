@@ -310,7 +310,9 @@ def test_timing_and_stats(ctx, patch):
     ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD)
     ms, n = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    pairs, flagged, exact, rare, beyond, one_slot, pruned = ctx.stats(reset=True)
+    st = ctx.stats(reset=True)
+    pairs, flagged, exact, rare = st.pairs, st.flagged, st.exact, st.rare_steps
+    beyond, one_slot, two_slot = st.beyond_steps, st.one_slot_steps, st.two_slot_steps
     assert n == 1 and ms > 0
     assert pairs == wl.data[0].n * wl.randoms[0].n
     assert exact <= flagged <= pairs
@@ -319,7 +321,7 @@ def test_timing_and_stats(ctx, patch):
     # a 30 x 30 deg patch against edges up to 10 deg: many wavefront steps
     # (4 rows x 2 columns per lane) lie wholly beyond the last edge
     assert 0 < beyond * 512 < pairs
-    assert (beyond + one_slot + rare) * 512 <= pairs
+    assert (beyond + one_slot + two_slot + rare) * 512 <= pairs
 
 
 @pytest.mark.parametrize("prec", PRECS)
