@@ -89,10 +89,20 @@ def _ptr(a):
 
 
 def default_threads() -> int:
+    """Host threads for the row loop: the cores this process may run on,
+    at most OMP_NUM_THREADS when that is set (a shared machine's share of
+    cores), and at most 64."""
     try:
-        return max(1, min(len(os.sched_getaffinity(0)), 64))
+        n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover
-        return max(1, min(os.cpu_count() or 1, 64))
+        n = os.cpu_count() or 1
+    try:
+        cap = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        cap = 0
+    if cap > 0:
+        n = min(n, cap)
+    return max(1, min(n, 64))
 
 
 def radec_to_xyz(ra_deg, dec_deg):

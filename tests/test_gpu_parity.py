@@ -383,8 +383,9 @@ def test_pruning_exact_for_norms_at_the_accepted_limit(ctx, prec):
 def test_dense_patch_wide_bins_takes_every_branch(ctx, prec):
     """A dense 3 x 3 deg patch with four wide bins: many wavefront steps lie
     wholly beyond the last edge, many have all their pairs in one slot (one
-    atomic per lane), the rest go through the per-pair lookups; the counts
-    equal the oracle's."""
+    atomic per lane) or two adjacent slots (one threshold comparison per
+    pair), the rest go through the per-pair lookups; the counts equal the
+    oracle's."""
     g = synthcat.rng_for(97, 0)
     patch = (10.0, 13.0, 20.0, 23.0)
     d = synthcat.uniform_patch(20_000, patch, g)
@@ -401,6 +402,7 @@ def test_dense_patch_wide_bins_takes_every_branch(ctx, prec):
     st = ctx.stats(reset=True)
     assert st.beyond_steps > 0
     assert st.one_slot_steps > 0
+    assert st.two_slot_steps > 0
     # pruning bins whole blocks inside the wide bins and beyond the last edge
     try:
         ctx.set_tuning(prune=1)

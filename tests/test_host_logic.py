@@ -188,6 +188,62 @@ def test_fp32_band_adversary(edges, floored):
     assert np.all(in_band[rel < 0.1 * half])
 
 
+@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
+                                   synthcat.log_edges(0.001, 20.0, 30),
+                                   np.array([0.0, 1.0, 90.0, 180.0])])
+def test_two_slot_decision_matches_the_band(edges):
+    """The kernels' two-slot steps: for a pair whose slot is k or k+1, the
+    FP32 difference x = fl(q - qhi_k) decides it when |x| > fl(qhi_k - qlo_k),
+    and then the sign of x gives the slot the FP64 rule gives.  Pairs at
+    theta = e_k (1 +- 10^-s), s = 2..9, and spread between the neighbouring
+    edges; band pairs are never decided, and most pairs are."""
+    g = np.random.default_rng(11)
+    D, qlo, qhi = tp.compile_edges(edges, delta_max=4.5e-16)
+    er = edges * DEG
+    thetas, ks = [], []
+    for k, e in enumerate(er):
+        for s in range(2, 10):
+            for sign in (-1.0, 1.0):
+                thetas.append(np.full(40, e * (1.0 + sign * 10.0 ** -s)))
+                ks.append(np.full(40, k))
+        lo = er[k - 1] if k else 0.5 * e
+        hi = er[k + 1] if k + 1 < er.size else min(1.5 * e + 1e-3, math.pi)
+        thetas.append(g.uniform(lo, hi, 400))
+        ks.append(np.full(400, k))
+    theta = np.clip(np.concatenate(thetas), 0.0, math.pi)
+    k = np.concatenate(ks)
+    a, b = _pairs_at(g, theta)
+    q = _q32(a, b)
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    ours = (truth == k) | (truth == k + 1)
+    thr = qhi.astype(np.float32)[k]
+    width = qhi.astype(np.float32)[k] - qlo.astype(np.float32)[k]
+    x = q - thr                                     # FP32, round to nearest
+    decided = np.abs(x) > width
+    slot = k + (x >= 0).astype(np.int64)
+    assert np.array_equal(slot[ours & decided], truth[ours & decided])
+    in_band = (q >= qlo[k]) & (q < qhi[k])
+    assert not np.any(in_band & decided)
+    assert decided[ours].mean() > 0.25
+
+
+@pytest.mark.parametrize("precision", [tp.FP32_CHORD, tp.FP64])
+def test_cell_slot_ranges_never_decrease(precision):
+    """Each cell entry bounds the slots of its keys ([s, s] for a certain
+    slot, [k, k+1] for one undecided edge); the kernels' one- and two-slot
+    steps rely on both ends being non-decreasing along the table."""
+    edges = synthcat.log_edges(0.0005, 30.0, 40)
+    _, _, _, cells, _ = tp.compile_cells(edges, precision, delta_max=4.5e-16)
+    c = cells.astype(np.int64)
+    multi = c == 0xFFFF
+    flag = (c & 0x8000) != 0
+    lo = np.where(flag, c & 0x7FFF, c)
+    hi = np.where(flag, (c & 0x7FFF) + 1, c)
+    keep = ~multi
+    assert np.all(np.diff(lo[keep]) >= 0) and np.all(np.diff(hi[keep]) >= 0)
+    assert np.all(hi - lo <= 1)
+
+
 def _emulate(a, b, edges, precision, delta, direct=None):
     """Numpy transcription of the kernels' per-pair classification."""
     D, qlo, qhi = tp.compile_edges(edges, delta_max=delta)
