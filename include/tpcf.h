@@ -223,6 +223,27 @@ int tpcf_count_async(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
                      const double *bin_edges_deg, int32_t nbins, int precision,
                      int64_t row_begin, int64_t row_end, uint64_t *d_out_u64);
 
+/* tpcf_count for callers that cannot allocate device memory (code that
+ * must not call hipMalloc or hipFree, such as tight serving loops or hosts
+ * that forbid allocation during a run).  Same arguments, result, totals check
+ * and errors as tpcf_count, and the same kernels, but every work buffer (the
+ * histogram copies, the work-queue counter, the output slots, the edge and
+ * cell tables and the work-unit list) lives in a fixed 16 MiB array in device
+ * memory, one per device, set up by tpcf_open and held until the process
+ * ends.  The call allocates no device memory, creates no event and does not
+ * use the RR result cache; catalogs must already be uploaded or attached.
+ * Exact tile pruning is not applied (its bounding caps are built on first
+ * use, which allocates); the counts are the same.  Requests whose work-unit
+ * list does not fit the array (beyond roughly 3e5 units, which the plan keeps
+ * below by widening column chunks, e.g. a 1e6 x 2e6 DR fits) fail with
+ * TPCF_E_INVALID.  Synchronous: the array is free again when the call
+ * returns.  All calls on one device share its array, so calls that overlap
+ * on the same device (from several threads or contexts) race; the caller
+ * serialises them. */
+int tpcf_count_noalloc(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b,
+                       const double *bin_edges_deg, int32_t nbins, int precision,
+                       int64_t row_begin, int64_t row_end, uint64_t *out_u64);
+
 /* One counting request, as used by batches and submitted jobs.  Fields have
  * the meaning of the tpcf_count arguments of the same names; the edges array
  * is read during the call only. */

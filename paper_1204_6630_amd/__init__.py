@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_open", "tpcf_close", "tpcf_upload_catalog", "tpcf_upload_catalog_xyz",
     "tpcf_attach_catalog", "tpcf_catalog_order", "tpcf_catalog_size", "tpcf_release_catalog",
     "tpcf_upload_catalog_regions", "tpcf_catalog_regions", "tpcf_count_regions", "tpcf_jackknife", "tpcf_count",
-    "tpcf_count_async", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
+    "tpcf_count_async", "tpcf_count_noalloc", "tpcf_count_batch", "tpcf_submit", "tpcf_poll", "tpcf_wait",
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32",
@@ -133,6 +133,7 @@ def lib():
         "tpcf_jackknife": ([P, P, P, P, P, P, i32, i32, i64, P, i64, P, cint, P, P, P], cint),
         "tpcf_count": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
         "tpcf_count_async": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
+        "tpcf_count_noalloc": ([P, cint, i32, i32, P, i32, cint, i64, i64, P], cint),
         "tpcf_count_batch": ([P, P, i32, cint, P], cint),
         "tpcf_submit": ([P, P, P], cint),
         "tpcf_poll": ([P, i64, P, P], cint),

@@ -522,6 +522,62 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
 
 int hist_copies_of(const Tuning &t, int nslots);
 
+// Host part of the edge compiler: thresholds, FP32 band and cell table of
+// one edges array for the given tuning, and the table packed as the kernels
+// read it.  Allocates no device memory.
+int compile_host(const Tuning &tune, const double *edges, int nbins, int precision, double delta, int metric,
+                 Compiled *c, std::vector<uint8_t> *packed, std::vector<float> *qlo, std::vector<float> *qhi) {
+    std::string err;
+    if (!(metric ? compile_edges_3d(edges, nbins, &c->edges, &err) : compile_edges(edges, nbins, &c->edges, &err)))
+        return fail(TPCF_E_INVALID, err);
+    c->precision = precision;
+    c->delta = delta;
+    c->metric = metric;
+    const int nslots = nbins + 2;
+    c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
+    const int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
+    const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
+    qlo->assign(c->edges.D.size(), 0.0f);
+    qhi->assign(c->edges.D.size(), 0.0f);
+    if (metric && precision == TPCF_FP32_CHORD) {
+        c->band = make_band32_3d(c->edges, delta);
+        c->cells = make_cells32_top(c->edges, c->band, qtop_key_3d(delta), max_cells);
+        *qlo = c->band.qlo;
+        *qhi = c->band.qhi;
+    } else if (metric) {
+        const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
+        c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
+    } else if (precision == TPCF_FP32_CHORD) {
+        c->band = make_band32(c->edges, delta);
+        if (c->entry_bytes == 1 && tune.lut_direct) {
+            Band32 fb = make_band32(c->edges, delta, floor_for(c->band));
+            const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
+            c->cells = make_cells32_wrap(c->edges, fb, delta, tune.lut_bytes ? tune.lut_bytes : kWrapLutBytes, aux);
+            if (!c->cells.cells.empty())
+                c->band = fb;
+        }
+        if (c->cells.cells.empty())
+            c->cells = make_cells32(c->edges, c->band, delta, max_cells);
+        *qlo = c->band.qlo;
+        *qhi = c->band.qhi;
+    } else {
+        c->cells = make_cells64(c->edges, max_cells);
+    }
+    packed->clear();
+    if (c->entry_bytes == 1) {
+        const std::vector<uint16_t> &src = c->cells.direct ? c->cells.image : c->cells.cells;
+        packed->resize(src.size());
+        for (size_t i = 0; i < packed->size(); ++i) {
+            uint16_t v = src[i];
+            (*packed)[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
+        }
+    } else {
+        packed->resize(c->cells.cells.size() * 2);
+        memcpy(packed->data(), c->cells.cells.data(), packed->size());
+    }
+    return TPCF_OK;
+}
+
 int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, double delta, int metric,
                  Compiled **out) {
     std::string key = edges_key(edges, nbins, precision, delta, metric, ctx->tune);
@@ -538,54 +594,9 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
         ctx->compiled.clear();
     }
     auto c = std::make_unique<Compiled>();
-    std::string err;
-    if (!(metric ? compile_edges_3d(edges, nbins, &c->edges, &err) : compile_edges(edges, nbins, &c->edges, &err)))
-        return fail(TPCF_E_INVALID, err);
-    c->precision = precision;
-    c->delta = delta;
-    c->metric = metric;
-    const int nslots = nbins + 2;
-    c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    const int table_bytes = ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kMaxLutBytes;
-    const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
-    std::vector<float> qlo(c->edges.D.size(), 0.0f), qhi(c->edges.D.size(), 0.0f);
-    if (metric && precision == TPCF_FP32_CHORD) {
-        c->band = make_band32_3d(c->edges, delta);
-        c->cells = make_cells32_top(c->edges, c->band, qtop_key_3d(delta), max_cells);
-        qlo = c->band.qlo;
-        qhi = c->band.qhi;
-    } else if (metric) {
-        const double top = 4.0 * delta * delta * (1.0 + ldexp(1.0, -10));
-        c->cells = make_cells64(c->edges, max_cells, top > 1e-300 ? top : 1e-300);
-    } else if (precision == TPCF_FP32_CHORD) {
-        c->band = make_band32(c->edges, delta);
-        if (c->entry_bytes == 1 && ctx->tune.lut_direct) {
-            Band32 fb = make_band32(c->edges, delta, floor_for(c->band));
-            const int aux = aux_lds_bytes(nslots, hist_copies_of(ctx->tune, nslots), nbins + 1);
-            c->cells = make_cells32_wrap(c->edges, fb, delta,
-                                         ctx->tune.lut_bytes ? ctx->tune.lut_bytes : kWrapLutBytes, aux);
-            if (!c->cells.cells.empty())
-                c->band = fb;
-        }
-        if (c->cells.cells.empty())
-            c->cells = make_cells32(c->edges, c->band, delta, max_cells);
-        qlo = c->band.qlo;
-        qhi = c->band.qhi;
-    } else {
-        c->cells = make_cells64(c->edges, max_cells);
-    }
     std::vector<uint8_t> packed;
-    if (c->entry_bytes == 1) {
-        const std::vector<uint16_t> &src = c->cells.direct ? c->cells.image : c->cells.cells;
-        packed.resize(src.size());
-        for (size_t i = 0; i < packed.size(); ++i) {
-            uint16_t v = src[i];
-            packed[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
-        }
-    } else {
-        packed.resize(c->cells.cells.size() * 2);
-        memcpy(packed.data(), c->cells.cells.data(), packed.size());
-    }
+    std::vector<float> qlo, qhi;
+    TRY(compile_host(ctx->tune, edges, nbins, precision, delta, metric, c.get(), &packed, &qlo, &qhi));
     int rc;
     if ((rc = upload_blocking(ctx->mem, c->dD, c->edges.D)) || (rc = upload_blocking(ctx->mem, c->dE, c->edges.E)) ||
         (rc = upload_blocking(ctx->mem, c->dqlo, qlo)) || (rc = upload_blocking(ctx->mem, c->dqhi, qhi)) ||
@@ -605,14 +616,14 @@ int get_compiled(tpcf_ctx *ctx, const double *edges, int nbins, int precision, d
 // need tens of GB of them).
 constexpr double kMaxUnits = 16777216.0;
 
-int64_t chunk_width(uint64_t pairs, int64_t T, int64_t max_cols) {
+int64_t chunk_width(uint64_t pairs, int64_t T, int64_t max_cols, double max_units = kMaxUnits) {
     int64_t bj = (int64_t)((double)pairs / 4096.0 / (double)T);
     bj = (bj + 255) / 256 * 256;
     if (bj > max_cols)
         bj = max_cols;
     if (bj < 256)
         bj = 256;
-    const double need = (double)pairs / (double)T / kMaxUnits;   // columns per unit for kMaxUnits units
+    const double need = (double)pairs / (double)T / max_units;   // columns per unit for max_units units
     if ((double)bj < need)
         bj = ((int64_t)need + 256) / 256 * 256;
     return bj;
@@ -637,7 +648,7 @@ Unit mk_unit(int64_t i0, int64_t i1, int64_t j0, int64_t j1, int64_t row_lo, int
 }
 
 Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, int64_t T,
-               int64_t max_cols) {
+               int64_t max_cols, double max_units = kMaxUnits) {
     Plan p;
     uint64_t pairs = 0;
     if (auto_pairs) {
@@ -648,7 +659,7 @@ Plan make_plan(bool auto_pairs, int64_t na, int64_t nb, int64_t rb, int64_t re, 
         pairs = (uint64_t)(re - rb) * (uint64_t)nb;
     }
     p.pairs = pairs;
-    const int64_t bj = chunk_width(pairs, T, max_cols);
+    const int64_t bj = chunk_width(pairs, T, max_cols, max_units);
     // Row tiles start at rb (valid rows from row_lo = rb).
     // Column chunks lie on a common grid of multiples of bj, so units of
     // different row tiles cover the same column ranges; the list is ordered
@@ -854,9 +865,8 @@ int ensure_caps(tpcf_ctx *ctx, Catalog &c) {
     return TPCF_OK;
 }
 
-// Validate one request.  delta_override >= 0 compiles the FP32 band for that
-// norm bound (shared by every job of a batch) instead of the request's own.
-int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r, bool regions = false) {
+// Check one request and resolve its catalogs and row range (no allocation).
+int validate(tpcf_ctx *ctx, const tpcf_job_desc &d, Request *r) {
     if (d.kind != TPCF_DD && d.kind != TPCF_DR && d.kind != TPCF_RR)
         return fail(TPCF_E_INVALID, "kind must be TPCF_DD, TPCF_DR or TPCF_RR");
     if (d.precision != TPCF_FP32_CHORD && d.precision != TPCF_FP64)
@@ -898,6 +908,15 @@ int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Reques
     r->metric = r->A->metric;
     if (r->B->metric != r->metric)
         return fail(TPCF_E_INVALID, "a sky catalog and a 3-D catalog cannot be paired");
+    return TPCF_OK;
+}
+
+// Validate one request and get its tables and plan.  delta_override >= 0
+// compiles the FP32 band for that norm bound (shared by every job of a batch)
+// instead of the request's own.
+int prepare(tpcf_ctx *ctx, const tpcf_job_desc &d, double delta_override, Request *r, bool regions = false) {
+    TRY(validate(ctx, d, r));
+    const int64_t rb = r->rb, re = r->re;
     TRY(set_device(ctx));
     const double delta = delta_override >= 0 ? delta_override : std::max(r->A->band_param(), r->B->band_param());
     TRY(get_compiled(ctx, d.bin_edges_deg, d.nbins, d.precision, delta, r->metric, &r->cp));
@@ -1149,6 +1168,8 @@ int tpcf_open(int device, void *hip_stream, tpcf_ctx **out) {
     auto ctx = std::make_unique<tpcf_ctx>();
     ctx->device = device;
     HIP_TRY(hipSetDevice(device));
+    // the device address of this device's fixed work area (tpcf_count_noalloc)
+    HIP_TRY((hipError_t)tpcf_scratch_init(device));
     TRY(init_workspace(ctx.get(), ctx->main, (hipStream_t)hip_stream));
     HIP_TRY(hipStreamSynchronize(ctx->main.stream));
     *out = ctx.release();
@@ -1445,6 +1466,95 @@ int tpcf_count_async(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, cons
     Request r;
     TRY(prepare(ctx, desc_of(kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end), -1, &r));
     return launch_one(ctx, ctx->main, r, (unsigned long long *)d_out_u64, nullptr);
+}
+
+int tpcf_count_noalloc(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, const double *bin_edges_deg,
+                       int32_t nbins, int precision, int64_t row_begin, int64_t row_end, uint64_t *out_u64) {
+    if (!ctx)
+        return fail(TPCF_E_INVALID, "context is NULL");
+    if (!out_u64)
+        return fail(TPCF_E_INVALID, "out_u64 is NULL");
+    Request r;
+    TRY(validate(ctx, desc_of(kind, cat_a, cat_b, bin_edges_deg, nbins, precision, row_begin, row_end), &r));
+    TRY(set_device(ctx));
+    unsigned char *base = (unsigned char *)tpcf_scratch_ptr(ctx->device);
+    if (!base)
+        return fail(TPCF_E_HIP, "the fixed work area of this device has no address (tpcf_open sets it up)");
+    // tables on the host; their device copies go into the work area
+    const double delta = std::max(r.A->band_param(), r.B->band_param());
+    Compiled c;
+    std::vector<uint8_t> packed;
+    std::vector<float> qlo, qhi;
+    TRY(compile_host(ctx->tune, bin_edges_deg, nbins, precision, delta, r.metric, &c, &packed, &qlo, &qhi));
+    const int nslots = nbins + 2, nedges = nbins + 1;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_copies = take(sizeof(unsigned long long) * ((size_t)kGlobalCopies * nslots + 1));
+    const size_t o_out = take(sizeof(unsigned long long) * (size_t)nslots);
+    const size_t o_D = take(sizeof(double) * nedges), o_E = take(sizeof(double) * nedges);
+    const size_t o_qlo = take(sizeof(float) * nedges), o_qhi = take(sizeof(float) * nedges);
+    const size_t o_rad = take(sizeof(double) * nedges);
+    const size_t o_lut = take(packed.size());
+    const size_t o_units = off;
+    if (o_units >= kScratchBytes)
+        return fail(TPCF_E_INVALID, "the tables do not fit the fixed work area");
+    const size_t max_units = (kScratchBytes - o_units) / sizeof(Unit);
+    // the unit list is sized for half the room (the triangular lists of
+    // auto-pairs hold a few more units than the estimate), then checked
+    const int64_t T = (int64_t)kWaves * kWaveSize * rows_per_lane_of(ctx->tune);
+    Plan plan = make_plan(r.auto_pairs, r.A->n, r.B->n, r.rb, r.re, T, max_cols_of(ctx->tune), 0.5 * (double)max_units);
+    if (plan.units.size() > max_units) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "the request needs %zu work units; the fixed work area (%zu MiB) holds %zu",
+                 plan.units.size(), kScratchBytes >> 20, max_units);
+        return fail(TPCF_E_INVALID, buf);
+    }
+    for (const Unit &u : plan.units)   // each unit's LDS counts must stay below 2^32
+        if ((uint64_t)(u.i1 - u.i0) * (uint64_t)(u.j1 - u.j0) >= ((uint64_t)1 << 32))
+            return fail(TPCF_E_INVALID, "the request is too large for the fixed work area");
+    hipStream_t st = ctx->main.stream;
+    auto h2d = [&](size_t at, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(base + at, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    HIP_TRY(h2d(o_D, c.edges.D.data(), sizeof(double) * c.edges.D.size()));
+    HIP_TRY(h2d(o_E, c.edges.E.data(), sizeof(double) * c.edges.E.size()));
+    HIP_TRY(h2d(o_qlo, qlo.data(), sizeof(float) * qlo.size()));
+    HIP_TRY(h2d(o_qhi, qhi.data(), sizeof(float) * qhi.size()));
+    HIP_TRY(h2d(o_rad, c.edges.edge_rad.data(), sizeof(double) * c.edges.edge_rad.size()));
+    HIP_TRY(h2d(o_lut, packed.data(), packed.size()));
+    HIP_TRY(h2d(o_units, plan.units.data(), sizeof(Unit) * plan.units.size()));
+    // the histogram copies and the queue counter start at zero (a kernel, not a memset)
+    unsigned long long *copies = (unsigned long long *)(base + o_copies);
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64(copies, (int64_t)kGlobalCopies * nslots + 1, st));
+    c.dD.p = base + o_D;
+    c.dE.p = base + o_E;
+    c.dqlo.p = base + o_qlo;
+    c.dqhi.p = base + o_qhi;
+    c.dErad.p = base + o_rad;
+    c.dlut.p = base + o_lut;
+    PairArgs a = args_of(ctx, c, nbins, (unsigned long long *)ctx->main.stats.p, delta);
+    a.prune = 0;     // bounding caps are built on first use, which allocates: count every pair
+    a.jobs = nullptr;
+    a.job0 = job_of(r, copies, nullptr);
+    a.units = (const Unit *)(base + o_units);
+    a.n_units = (int32_t)plan.units.size();
+    a.queue = (unsigned int *)(copies + (size_t)kGlobalCopies * nslots);
+    int lrc = tpcf_launch_pairs(&a, r.precision, st);
+    if (lrc == 0)
+        lrc = tpcf_launch_reduce_copies(copies, nslots, 1, (unsigned long long *)(base + o_out), st);
+    if (lrc)
+        return fail(TPCF_E_HIP, std::string("kernel launch: ") + hipGetErrorString((hipError_t)lrc));
+    std::vector<uint64_t> h((size_t)nslots);
+    HIP_TRY(hipMemcpyAsync(h.data(), base + o_out, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    TRY(check_total(h.data(), nslots, plan.pairs));
+    ctx->pairs_since_reset += plan.pairs;
+    memcpy(out_u64, h.data(), sizeof(uint64_t) * h.size());
+    return TPCF_OK;
 }
 
 int tpcf_count_batch(tpcf_ctx *ctx, const tpcf_job_desc *jobs, int32_t njobs, int flags, uint64_t *out_u64) {

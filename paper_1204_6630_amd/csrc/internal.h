@@ -2,6 +2,7 @@
 // Not part of the public ABI (see include/tpcf.h).
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace tpcf {
@@ -164,8 +165,18 @@ constexpr double kPruneDotSlack = 2e-15;
 
 }  // namespace tpcf
 
+// Size of the fixed per-device work area of tpcf_count_noalloc (histogram
+// copies, work-queue counter, output slots, edge and cell tables, and the
+// work-unit list).
+constexpr size_t kScratchBytes = size_t(16) << 20;
+
 // Launchers implemented in kernels.hip.
 extern "C" {
+// Look up (once per device, with that device current) the device address of
+// the fixed work area; 0 or a hipError_t.
+int tpcf_scratch_init(int device);
+// The address found by tpcf_scratch_init for this device, or null.
+void *tpcf_scratch_ptr(int device);
 int tpcf_launch_pairs(const tpcf::PairArgs *args, int precision, void *stream);
 int tpcf_launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
 // Sum the kGlobalCopies copies of each of njobs histograms (contiguous,

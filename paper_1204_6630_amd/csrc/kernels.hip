@@ -29,6 +29,8 @@
 // FP32 chord^2 uses explicit fmaf, which the error band accounts for.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 using namespace tpcf;
@@ -1267,4 +1269,48 @@ extern "C" int tpcf_launch_to_float(const double *xyz64, int64_t n, float *xyz32
     hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        xyz64, n, xyz32, given32, check_out, check_out + 1);
     return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Work area of the entry point that allocates nothing (tpcf_count_noalloc):
+// a fixed array in device memory, one per device the library runs on, held
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, looked up once per device with
+// that device current, and kernels receive that pointer as an argument.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+extern "C" int tpcf_scratch_init(int device) {
+    if (device < 0 || device >= kMaxScratchDevices)
+        return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device])
+        return 0;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess)
+        return (int)e;
+    if (cur != device)
+        return (int)hipErrorInvalidDevice;      // the caller makes the device current first
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return (int)e;
+    if (!ptr)
+        return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return 0;
+}
+
+extern "C" void *tpcf_scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxScratchDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
