@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3-D xi(r) step (1e6 x 2e6 points in a box of side 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2,
+                    help="default line: timed steps of the batched 64-catalog leg (0 skips it)")
     ap.add_argument("--serving-jobs", type=int, default=120,
                     help="octant workload: jobs of the bounded serving leg (p50/p99 latency "
                          "in the same line); 0 skips it")
@@ -149,6 +151,17 @@ def bench_batched(args, tp, torch):
     sizes = [c.n for c in wl.data]
     pairs = sum(n * (n - 1) // 2 for n in sizes) + sum(n * r.n for n in sizes) + r.n * (r.n - 1) // 2
     print(f"# batched: {len(jobs)} jobs, {pairs:.4e} pairs", file=sys.stderr, flush=True)
+    tuning = {"autotuned": False}
+    if args.autotune:
+        # the launch shape for this workload: a sample of DR row blocks of the
+        # two largest catalogs against the randoms and a DD block
+        from paper_1204_6630_amd.autotune import autotune
+        big = sorted(range(len(cats)), key=lambda k: -sizes[k])[:2]
+        sample = [(tp.DR, cats[k], cr, 0, min(sizes[k], 8192)) for k in big]
+        sample.append((tp.DD, cats[big[0]], -1, 0, min(sizes[big[0]], 8192)))
+        t = autotune(ctx, sample, e, tp.FP32_CHORD)
+        tuning = dict(t["tuning"], autotuned=True, cached=t["cached"])
+        print(f"# batched tuning: {tuning}", file=sys.stderr, flush=True)
     ref = ctx.count_batch(jobs, e, graph=True)          # capture + warm-up
     for _ in range(args.warmup):
         ctx.count_batch(jobs, e, graph=True)
@@ -162,7 +175,8 @@ def bench_batched(args, tp, torch):
     kms, launches = ctx.kernel_time(reset=True)
     if not np.array_equal(got, ref):
         sys.exit("graph replay differs from the first batch")
-    # the same jobs as separate launches
+    # the same jobs as separate plain launches (the library's default shape)
+    ctx.set_tuning()
     out = torch.zeros((len(jobs), e.size + 1), dtype=torch.int64, device="cuda:0")
     for k, (kind, a, b) in enumerate(jobs):
         ctx.count_async(kind, a, e, out[k].data_ptr(), cat_b=b)
@@ -188,9 +202,11 @@ def bench_batched(args, tp, torch):
         "config": {"workload": wl.name, "catalogs": len(cats), "n_random": r.n,
                    "nbins": int(e.size - 1), "pairs_per_step": pairs, "jobs": len(jobs),
                    "parallelism": "single-gpu"},
-        "roofline": roofline(tp.FP32_CHORD, kg, kms / max(1, launches)),
+        "roofline": roofline(tp.FP32_CHORD, kg, kms / max(1, launches),
+                             kernel="pairs_kernel<0> (FP32 chord), one launch for all jobs"),
         "separate_launches_gpairs_s": round(sep_value, 2),
         "batched_over_separate": round(value / sep_value, 3),
+        "tuning": tuning,
     }
 
 
@@ -612,6 +628,20 @@ def main():
             "note": "DD/DR/RR jobs 40/40/20, sizes log-uniform [1e3, 1e6], 3 resident 2e6 "
                     "randoms with cached RR, 1 GiB HBM budget; latency = arrival to result "
                     "on the host; not in value"}
+    if args.batched_steps > 0:
+        # the batched workload's leg: 129 jobs in one graph-replayed launch
+        # (autotuned launch shape) against the same jobs as separate launches
+        bt = bench_batched(argparse.Namespace(**{**vars(args), "steps": args.batched_steps, "warmup": 1,
+                                                 "autotune": True}), tp, torch)
+        res["batched_64"] = {
+            "workload": bt["config"]["workload"], "jobs": bt["config"]["jobs"],
+            "pairs_per_step": bt["config"]["pairs_per_step"], "steps": bt["steps"],
+            "gpairs_s_one_launch": bt["value"], "ms_per_step": bt["ms_per_step"],
+            "separate_launches_gpairs_s": bt["separate_launches_gpairs_s"],
+            "batched_over_separate": bt["batched_over_separate"], "roofline": bt["roofline"],
+            "tuning": bt["tuning"],
+            "note": "64 data catalogs (5e3..5e5 points, 20x20 deg sub-patches) + one 1e6 random "
+                    "catalog: 64 DD + 64 DR + 1 RR jobs in one hipGraph-replayed launch; not in value"}
     print(json.dumps(res), flush=True)
 
 

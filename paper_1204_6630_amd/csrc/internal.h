@@ -159,8 +159,8 @@ inline int lds_bytes(int nslots, int hist_copies, int lut_cells, int lut_entry_b
 // the rounding of the caps' arithmetic (<= ~3e-8 rad, acos near 1 included).
 constexpr double kPruneMargin = 1e-6;
 // Absolute slack of the pruning test's dot-product interval: the rule's own
-// rounding (gamma_3 (1 + delta) < 3.4e-16) and that of the two cosines and
-// the interval arithmetic (a few units of 2^-53).
+// rounding (gamma_3 (1 + delta) < 3.4e-16) and that of the interval
+// arithmetic (a few units of 2^-53).
 constexpr double kPruneDotSlack = 2e-15;
 
 }  // namespace tpcf

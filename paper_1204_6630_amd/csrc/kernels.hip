@@ -293,7 +293,7 @@ struct Counters {
     uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
     uint32_t one_slot_steps = 0;  // steps binned with one atomic per lane (uniform)
     uint32_t two_slot_steps = 0;  // steps binned with two atomics per lane (uniform)
-    unsigned long long pruned = 0;  // pairs binned by pruned blocks (uniform)
+    uint32_t pruned_blocks = 0;     // wavefront blocks (P x 64 rows x 64 columns) binned whole (uniform)
 };
 
 // Loop constants of one wavefront.
@@ -386,11 +386,12 @@ __device__ __forceinline__ void two_slot_add(uint32_t base, uint32_t n, uint32_t
 // arithmetic).  The counting rule does not see phi but the FP64 dot product
 // of the stored vectors, whose squared norms deviate from 1 by up to delta:
 // d = |v_i| |v_j| cos(phi) + err with |v_i| |v_j| in [1 - delta, 1 + delta]
-// and |err| <= kPruneDotSlack (the rule's rounding and that of the cosines
-// below).  So every pair's d lies in [cos(hi) - delta |cos(hi)| - slack,
-// cos(lo) + delta |cos(lo)| + slack]; when no threshold D_k falls inside
-// that interval every pair passes the same edges, and the wavefront adds the
-// block's pairs to that slot without evaluating them.
+// and |err| <= kPruneDotSlack (the rule's rounding).  So every pair's d lies
+// in [lo - delta |lo| - slack, hi + delta |hi| + slack] for any bounds
+// lo <= cos(phi) <= hi over the block (prune_slot forms them without
+// trigonometric functions); when no threshold D_k falls inside that interval
+// every pair passes the same edges, and the wavefront adds the block's pairs
+// to that slot without evaluating them.
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -409,6 +410,19 @@ __device__ __forceinline__ double wave_min_d(double v) {
 struct Cap {
     double x, y, z, rho;
 };
+
+// A wavefront-uniform double moved to scalar registers (lane 0's value).
+__device__ __forceinline__ double uniform_d(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    // readfirstlane returns a signed int: take its 32 bits without sign extension
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
+__device__ __forceinline__ Cap uniform_cap(const Cap &c) {
+    return Cap{uniform_d(c.x), uniform_d(c.y), uniform_d(c.z), uniform_d(c.rho)};
+}
 
 // Cap of the points (x, y, z) held by the lanes (every lane contributes n
 // points; duplicates are harmless).  Identical on every lane.
@@ -446,35 +460,47 @@ __device__ __forceinline__ Cap cap_of(const double (&x)[N], const double (&y)[N]
     return c;
 }
 
-// Number of edges <= t (edges increasing, in LDS).
-__device__ __forceinline__ int edges_le(const double *erad, int n, double t) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (erad[mid] <= t)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Number of thresholds (non-increasing, in LDS) that v passes (v <= T[k]),
+// and whether w passes the same ones: lane L compares both with T[L + 64 m],
+// one LDS read and two ballots per 64 thresholds.  -1 when they differ.
+// Wavefront-uniform.
+__device__ __forceinline__ int same_count_le(double v, double w, const double *T, int n, int lane) {
+    int count = 0;
+    for (int b = 0; b < n; b += kWaveSize) {
+        const double t = b + lane < n ? T[b + lane] : -__builtin_huge_val();
+        const uint64_t mv = __builtin_amdgcn_ballot_w64(v <= t);
+        if (mv != __builtin_amdgcn_ballot_w64(w <= t))
+            return -1;
+        count += __builtin_popcountll(mv);
     }
-    return lo;
+    return count;
 }
 
 // The slot of every pair between the row cap and the column block's cap, or
 // -1 when the test cannot prove one (see above; delta bounds the catalogs'
-// | |v|^2 - 1 |).  Wavefront-uniform.
+// | |v|^2 - 1 |).  With c = cos(theta_c) the dot product of the two centres,
+// sn an upper bound of sin(theta_c) and rho the summed radii, every pair's
+// geometric angle is theta_c + t with |t| <= rho, and
+// cos(theta_c + t) = c cos t - sin(theta_c) sin t lies within
+// [c - sn rho - max(c, 0) rho^2 / 2, c + sn rho + max(-c, 0) rho^2 / 2]
+// (1 - t^2 / 2 <= cos t <= 1, |sin t| <= |t|).  No trigonometric function is
+// evaluated; the margin in rho (1e-6 rad) widens the interval by at least
+// sn 1e-6 > 6e-14, far above the rounding of this arithmetic.
 __device__ __forceinline__ int prune_slot(const Cap &r, const double *bcap, const Smem &s, int nedges,
-                                          double delta) {
+                                          double delta, int lane) {
     const cdouble_p bc = (cdouble_p)bcap;
     const double c = fmin(fmax(r.x * bc[0] + r.y * bc[1] + r.z * bc[2], -1.0), 1.0);
-    const double th = acos(c);
-    const double spread = r.rho + bc[3] + kPruneMargin;
-    const double lo = fmax(th - spread, 0.0), hi = fmin(th + spread, M_PI);
-    const double clo = cos(lo), chi = cos(hi);
-    const double dhi = clo + delta * fabs(clo) + kPruneDotSlack;
-    const double dlo = chi - delta * fabs(chi) - kPruneDotSlack;
+    const double rho = r.rho + bc[3] + kPruneMargin;
+    const double h = 0.5 * rho * rho;
+    // an upper bound of the sine: 1 - c^2 formed as (1 - c)(1 + c), plus the
+    // rounding of c and of that product
+    const double sn = sqrt((1.0 - c) * (1.0 + c) + 4e-15);
+    double hi = c + sn * rho + fmax(-c, 0.0) * h;
+    double lo = c - sn * rho - fmax(c, 0.0) * h;
+    hi = hi + delta * fabs(hi) + kPruneDotSlack;
+    lo = lo - delta * fabs(lo) - kPruneDotSlack;
     // pairs with the largest d pass the fewest edges
-    const uint32_t a = count_le(dhi, s.D, nedges), b = count_le(dlo, s.D, nedges);
-    return __builtin_amdgcn_readfirstlane(a == b ? (int)a : -1);
+    return same_count_le(hi, lo, s.D, nedges, lane);
 }
 
 // 3-D: bounding ball of the points held by the lanes (centre = their mean,
@@ -509,27 +535,37 @@ __device__ __forceinline__ Cap ball_of(const double (&x)[N], const double (&y)[N
 // widened by margin (the FP32 copies of the rows, at most 2^-22 R) and by
 // 1e-12 relative (the rule's and this arithmetic's rounding).
 __device__ __forceinline__ int prune_slot3(const Cap &r, const double *bcap, const Smem &s, int nedges,
-                                           double margin) {
+                                           double margin, int lane) {
     const cdouble_p bc = (cdouble_p)bcap;
     const double dx = r.x - bc[0], dy = r.y - bc[1], dz = r.z - bc[2];
     const double dc = sqrt(dx * dx + dy * dy + dz * dz);
     const double spread = r.rho + bc[3];
     const double w = margin + 1e-12 * (dc + spread);
     const double lo = dc - spread - w, hi = dc + spread + w;
-    const int a = edges_le(s.erad, nedges, lo);
-    const int slot = a == edges_le(s.erad, nedges, hi) ? a : -1;
-    return __builtin_amdgcn_readfirstlane(slot);
+    // a pair at distance r passes edge k when e_k <= r: lane L compares
+    // both ends with edge L + 64 m
+    int count = 0;
+    for (int b = 0; b < nedges; b += kWaveSize) {
+        const double t = b + lane < nedges ? s.erad[b + lane] : __builtin_huge_val();
+        const uint64_t ml = __builtin_amdgcn_ballot_w64(t <= lo);
+        if (ml != __builtin_amdgcn_ballot_w64(t <= hi))
+            return -1;
+        count += __builtin_popcountll(ml);
+    }
+    return count;
 }
 
 // Block cap and block slot for either metric.
 template <bool M3, int N>
 __device__ __forceinline__ Cap block_cap(const double (&x)[N], const double (&y)[N], const double (&z)[N]) {
-    return M3 ? ball_of<N>(x, y, z) : cap_of<N>(x, y, z);
+    return uniform_cap(M3 ? ball_of<N>(x, y, z) : cap_of<N>(x, y, z));
 }
 
 template <bool M3>
-__device__ __forceinline__ int block_slot(const Cap &r, const double *bcap, const Smem &s, const PairArgs &a) {
-    return M3 ? prune_slot3(r, bcap, s, a.nedges, a.prune_margin) : prune_slot(r, bcap, s, a.nedges, a.prune_delta);
+__device__ __forceinline__ int block_slot(const Cap &r, const double *bcap, const Smem &s, const PairArgs &a,
+                                          int lane) {
+    return M3 ? prune_slot3(r, bcap, s, a.nedges, a.prune_margin, lane)
+              : prune_slot(r, bcap, s, a.nedges, a.prune_delta, lane);
 }
 
 // Add n pairs of this lane to `slot` (the overflow slot through the register
@@ -549,7 +585,7 @@ template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT, bool M3, bool ONE>
 __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
-                                          const int (&il)[P], int ie, int j, const float (&xj)[JN],
+                                          int ib, int lane, int ie, int j, const float (&xj)[JN],
                                           const float (&yj)[JN], const float (&zj)[JN], Counters &cnt) {
     float q[JN][P];
     uint32_t ent[JN][P];
@@ -651,10 +687,14 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             for (int p = 0; p < P; ++p)
                 if (ent[t][p] & k.flag) {
                     ++cnt.flag;
-                    int i = il[p];
-                    // opaque here, so the row addresses of this rare path are
-                    // formed on demand and do not occupy registers in the loop
-                    asm volatile("" : "+v"(i));
+                    // the row is formed here, on demand, from an opaque copy
+                    // of the lane index, so no row index or address of this
+                    // rare path is hoisted into registers of the loop (tail
+                    // lanes read row ib)
+                    int l = lane;
+                    asm volatile("" : "+v"(l));
+                    int i = ib + p * kWaveSize + l;
+                    i = i < ie ? i : ib;
                     ent[t][p] = resolve_fp32<LUT8, M3>(ent[t][p], k.flag, q[t][p], s, a, jb, i, j + t, cnt.exact);
                 }
     }
@@ -788,7 +828,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
 template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
-                                          const int (&ii)[P], const int (&il)[P], int ie, int j0, int j1,
+                                          const int (&ii)[P], int ib, int lane, int ie, int j0, int j1,
                                           Counters &cnt) {
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
@@ -817,7 +857,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
-            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
@@ -828,7 +868,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     }
     for (; j < j1; ++j) {
         const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
-        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, xj, yj, zj, cnt);
+        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, cnt);
     }
 }
 
@@ -838,15 +878,15 @@ template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
-    int ii[P], il[P];
+    int ii[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         int i = ib + p * kWaveSize + lane;
         ii[p] = i;
-        il[p] = i < ie ? i : ib;    // tail lanes read a valid row; masked below
-        xi[p] = jb.ax32[il[p]];
-        yi[p] = jb.ay32[il[p]];
-        zi[p] = jb.az32[il[p]];
+        const int il = i < ie ? i : ib;    // tail lanes read a valid row; masked below
+        xi[p] = jb.ax32[il];
+        yi[p] = jb.ay32[il];
+        zi[p] = jb.az32[il];
     }
     if (PRUNE && !MASKED && jb.bcaps) {
         double xd[P], yd[P], zd[P];
@@ -860,20 +900,20 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
         for (int j = j0; j < j1;) {
             const int jn = min(j1, (j & ~63) + 64);
             if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
+                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a, lane);
                 if (slot >= 0) {
                     bin_block(slot, P * 64, a, k, cnt);
-                    cnt.pruned += (unsigned long long)P * kWaveSize * 64;
+                    ++cnt.pruned_blocks;
                     j = jn;
                     continue;
                 }
             }
-            cols_fp32<LUT8, MASKED, P, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, il, ie, j, jn, cnt);
+            cols_fp32<LUT8, MASKED, P, DIRECT, M3, true>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp32<LUT8, MASKED, P, DIRECT, M3, !PRUNE>(a, jb, s, k, xi, yi, zi, ii, il, ie, j0, j1, cnt);
+    cols_fp32<LUT8, MASKED, P, DIRECT, M3, true>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j0, j1, cnt);
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
@@ -911,20 +951,20 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
         for (int j = j0; j < j1;) {
             const int jn = min(j1, (j & ~63) + 64);
             if ((j & 63) == 0 && jn - j == 64) {
-                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a);
+                const int slot = block_slot<M3>(rc, jb.bcaps + (size_t)(j >> 6) * 4, s, a, lane);
                 if (slot >= 0) {
                     bin_block(slot, P * 64, a, k, cnt);
-                    cnt.pruned += (unsigned long long)P * kWaveSize * 64;
+                    ++cnt.pruned_blocks;
                     j = jn;
                     continue;
                 }
             }
-            cols_fp64<LUT8, MASKED, P, M3, false>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
+            cols_fp64<LUT8, MASKED, P, M3, true>(a, jb, s, k, xi, yi, zi, ii, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp64<LUT8, MASKED, P, M3, !PRUNE>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
+    cols_fp64<LUT8, MASKED, P, M3, true>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
@@ -932,7 +972,7 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
 // clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
 // rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PRUNE ? 1 : 5))) void pairs_kernel(PairArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void pairs_kernel(PairArgs a) {
     constexpr int kRowsPerWave = P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
@@ -1049,8 +1089,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PRUNE ? 
             atomicAdd(&a.stats[6], (unsigned long long)cnt.one_slot_steps);
         if (cnt.two_slot_steps)
             atomicAdd(&a.stats[0], (unsigned long long)cnt.two_slot_steps);
-        if (cnt.pruned)
-            atomicAdd(&a.stats[7], cnt.pruned);
+        if (cnt.pruned_blocks)
+            atomicAdd(&a.stats[7], (unsigned long long)cnt.pruned_blocks * (unsigned long long)(kRowsPerWave * 64));
     }
 }
 
