@@ -7,8 +7,8 @@ an MI355X).
   close, three jobs equal their separate launches, and sampled stored row
   blocks of two catalogs (DD and DR) equal the oracle.
 * Serving: the first jobs of the job stream at their full sizes (up to 1e6
-  points against 2e6 randoms) through submit/wait, each with a sampled row
-  block against the oracle.
+  points against 2e6 randoms) through submit/wait, each also submitted for a
+  sampled row block whose returned histogram equals the oracle.
 """
 
 import numpy as np
@@ -89,7 +89,8 @@ def test_serving_jobs_at_full_size(ctx):
             assert int(got.sum()) == (n * nb if kind == tp.DR else n * (n - 1) // 2), job
             xs = _stored(ctx, cid, oracle.radec_to_xyz(cat.ra, cat.dec))
             r0, r1 = _rows(n, 96, job["id"])
-            part = ctx.count(kind, cid, e, cat_b=other, row_begin=r0, row_end=r1)
+            # the job's own result for a row range, through submit and wait
+            part = ctx.wait(ctx.submit(kind, cid, e, cat_b=other, row_begin=r0, row_end=r1), e.size + 1)
             if kind == tp.DR:
                 xr = oracle.radec_to_xyz(randoms[job["random"]].ra, randoms[job["random"]].dec)
                 ref = oracle.count(oracle.DR, xs, e, b_xyz=xr, row_begin=r0, row_end=r1)
