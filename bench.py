@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3-D xi(r) step (1e6 x 2e6 points in a box of side 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--theta-max", type=float, default=0.0,
+                    help="octant workload: last edge in degrees (0: the workload's 30 deg)")
     ap.add_argument("--batched-steps", type=int, default=2,
                     help="default line: timed steps of the batched 64-catalog leg (0 skips it)")
     ap.add_argument("--serving-jobs", type=int, default=120,
@@ -224,12 +226,14 @@ def bench_serving(args, tp):
     spec = synthcat.serving_jobs(n_jobs=args.jobs, size_hi=int(1_000_000 * args.scale))
     print(f"# serving: generating {len(spec)} job catalogs", file=sys.stderr, flush=True)
     jobs = []
-    for s in spec:
+    for k, s in enumerate(spec):
         j = Job(id=s["id"], kind=s["kind"], arrival=0.0, random=s["random"])
         if s["kind"] != "RR":
             c = synthcat.serving_catalog(s)
             j.ra, j.dec, j.n = c.ra, c.dec, c.n
         jobs.append(j)
+        if (k + 1) % 250 == 0:
+            print(f"# serving: {k + 1} job catalogs generated", file=sys.stderr, flush=True)
     # sustained rate: one DR of a 1e5 catalog against a resident random
     g = synthcat.rng_for(5, 999)
     probe = ctx.upload_catalog(*synthcat.uniform_patch(100_000, synthcat.OCTANT, g))
@@ -308,6 +312,10 @@ def main():
     d, r = wl.data[0], wl.randoms[0]
     nd, nr = d.n, r.n
     edges = wl.edges_deg
+    if args.theta_max:
+        # the same catalogs with the 40 log bins reaching theta_max (edges to
+        # 120 deg leave no wavefront step wholly beyond the last edge)
+        edges = synthcat.log_edges(float(edges[0]), args.theta_max, edges.size - 1)
     nslots = edges.size + 1
     pairs_step = nd * (nd - 1) // 2 + nd * nr + nr * (nr - 1) // 2
 
@@ -572,7 +580,7 @@ def main():
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
-                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 else None)
+                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 and not args.theta_max else None)
     res = {
         "metric": METRIC,
         "value": hs["gpairs_s"],

@@ -424,6 +424,14 @@ int tpcf_jackknife(const uint64_t *dd, const uint64_t *dd_touch, const uint64_t 
 int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_max,
                        double *out_D, float *out_qlo, float *out_qhi);
 
+/* The FP32 dot-product screen of the angular kernels (host only, for CPU
+ * tests): for catalogs whose squared norms deviate from 1 by at most
+ * delta_max, a pair whose FP32 copies have p = fl32(f_i . f_j) <= *out_p
+ * (with any order of fused or separate roundings) has the rule's d <= D of
+ * the last edge, i.e. lies at or beyond it (Section 3, first bullet: the
+ * angle from the dot product).  -inf when no pair can pass the last edge. */
+int tpcf_compile_screen(const double *bin_edges_deg, int32_t nbins, double delta_max, float *out_p);
+
 /* Cell table of the pair kernels for the given edges (host only, for CPU
  * tests of the host logic).  precision selects the key: TPCF_FP32_CHORD uses
  * the bits of q = fl32 |f_i - f_j|^2, TPCF_FP64 the high 32 bits of e = 1 - d

@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32",
-    "tpcf_compile_edges", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
+    "tpcf_compile_edges", "tpcf_compile_screen", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -151,6 +151,7 @@ def lib():
         "tpcf_compile_cells": ([P, i32, cint, ctypes.c_double, i32, i32, P, P, P, P, P], cint),
         "tpcf_compile_wrap32": ([P, i32, ctypes.c_double, i32, i32, P, P, P, P, P, P, P, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
+        "tpcf_compile_screen": ([P, i32, ctypes.c_double, P], cint),
         "tpcf_last_error": ([P], ctypes.c_char_p),
         "tpcf_version": ([], ctypes.c_char_p),
     }
@@ -464,6 +465,14 @@ def compile_edges(edges_deg, delta_max: float = 0.0):
     qhi = np.empty(e.size, np.float32)
     _check(lib().tpcf_compile_edges(_p(e), e.size - 1, delta_max, _p(D), _p(qlo), _p(qhi)))
     return D, qlo, qhi
+
+
+def compile_screen(edges_deg, delta_max: float = 0.0) -> float:
+    """The FP32 dot-product screen of the last edge (tpcf_compile_screen)."""
+    e = _f64(edges_deg)
+    out = np.zeros(1, dtype=np.float32)
+    _check(lib().tpcf_compile_screen(_p(e), e.size - 1, float(delta_max), _p(out)))
+    return float(out[0])
 
 
 def compile_edges_3d(edges, rmax: float):

@@ -965,6 +965,33 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
     return j;
 }
 
+// Threshold of the FP32 dot-product screen for the edge with threshold D
+// (angular catalogs, squared norms within 1 +- delta).  The kernel forms
+// p = fl32(f_i . f_j) of the FP32 copies f = fl32(v) with three roundings
+// (fused or not).  With u = 2^-24:
+//   |p - f_i . f_j| <= gamma_3(u) |f_i| |f_j| <= gamma_3(u) (1 + u)^2 (1 + delta)
+//   |f_i . f_j - v_i . v_j| <= (2u + u^2) |v_i| |v_j| <= (2u + u^2)(1 + delta)
+//   |d - v_i . v_j| <= gamma_3(2^-53)(1 + delta)   (the rule's dot product)
+// plus 3 * 2^-126 for FP32 underflow in the products.  So p <= D - E with E
+// the sum proves d <= D.  The result is rounded down to a float; a 2^-20
+// relative widening of E covers this function's own FP64 rounding.
+float dot_screen32(double D, double delta) {
+    if (!(D > -HUGE_VAL))
+        return -HUGE_VALF;          // no pair passes this edge
+    if (D == HUGE_VAL)
+        return HUGE_VALF;           // every pair passes it
+    const double u = ldexp(1.0, -24), U = ldexp(1.0, -53);
+    const double g3 = 3.0 * u / (1.0 - 3.0 * u), G3 = 3.0 * U / (1.0 - 3.0 * U);
+    const double E = (g3 * (1.0 + u) * (1.0 + u) * (1.0 + delta) + (2.0 * u + u * u) * (1.0 + delta) +
+                      G3 * (1.0 + delta) + 3.0 * ldexp(1.0, -126)) *
+                     (1.0 + ldexp(1.0, -20));
+    const double P = D - E;
+    float f = (float)P;
+    if ((double)f > P)
+        f = nextafterf(f, -HUGE_VALF);
+    return f;
+}
+
 // Kernel arguments of a launch with compiled edges cp.  delta: bound on
 // | |v|^2 - 1 | over the launch's sky catalogs (angular pruning).
 PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned long long *stats, double delta) {
@@ -992,11 +1019,16 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
     if (cp.precision == TPCF_FP32_CHORD) {
         float qh = cp.band.qhi[last];
         memcpy(&a.beyond_key, &qh, sizeof qh);
+        a.p_beyond = cp.metric ? -HUGE_VALF : dot_screen32(cp.edges.D[last], cp.delta);
+        // the screen pays where steps beyond the last edge come in runs: a
+        // last edge below 90 degrees (positive threshold)
+        a.screen = !cp.metric && cp.edges.D[last] > 0.0 && a.p_beyond > 0.0f ? 1 : 0;
     } else {
         const double t = cp.edges.E[last];
         uint64_t b;
         memcpy(&b, &t, sizeof b);
         a.beyond_key = (uint32_t)(b >> 32);
+        a.p_beyond = -HUGE_VALF;
     }
     a.qlo = (const float *)cp.dqlo.p;
     a.qhi = (const float *)cp.dqhi.p;
@@ -2116,6 +2148,19 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
         if (out_qhi)
             out_qhi[k] = b.qhi[k];
     }
+    return TPCF_OK;
+}
+
+int tpcf_compile_screen(const double *bin_edges_deg, int32_t nbins, double delta_max, float *out_p) {
+    if (!out_p)
+        return fail(TPCF_E_INVALID, "out_p is NULL");
+    if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
+        return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges(bin_edges_deg, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    *out_p = dot_screen32(t.D[(size_t)nbins], delta_max);
     return TPCF_OK;
 }
 

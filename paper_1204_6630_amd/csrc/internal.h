@@ -98,6 +98,14 @@ struct PairArgs {
     // (the bits of the last edge's qhi); FP64 path, high word of e = 1 - d
     // above beyond_key as signed integers (e > E_last).
     uint32_t beyond_key;
+    // Angular FP32 path: the dot product p = fl32(f_i . f_j) of the FP32
+    // copies, p <= p_beyond, proves the rule's d <= D_last (the pair is past
+    // the last edge); -inf when no such screen applies (3-D catalogs).
+    float p_beyond;
+    // 1: FP32 angular launches screen the steps after a step beyond the last
+    // edge with p (chosen when the last edge is below 90 degrees, where such
+    // steps come in runs; without them the screen's code only costs)
+    int32_t screen;
 
     // Exact tile pruning: 1 = a wavefront bins a whole aligned 64-column
     // block at once when the bounding caps put every pair of the block

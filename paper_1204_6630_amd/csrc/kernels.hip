@@ -307,6 +307,7 @@ struct Consts {
     uint32_t lanebase;      // LDS address of this lane's copy of slot 0
     uint32_t flag;          // flag bit of the cell entries (VGPR copy)
     uint32_t beyond;        // PairArgs::beyond_key (VGPR copy)
+    float pbeyond;          // PairArgs::p_beyond
 };
 
 // LDS address of the cell-table entry of an FP32 key (the bit pattern of q)
@@ -586,7 +587,8 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
                                           int ib, int lane, int ie, int j, const float (&xj)[JN],
-                                          const float (&yj)[JN], const float (&zj)[JN], Counters &cnt) {
+                                          const float (&yj)[JN], const float (&zj)[JN], bool &screen,
+                                          Counters &cnt) {
     float q[JN][P];
     uint32_t ent[JN][P];
 #pragma unroll
@@ -615,8 +617,10 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
         if (wave_all(m >= k.beyond)) {
             cnt.beyond += JN * P;
             ++cnt.beyond_steps;
+            screen = true;
             return;
         }
+        screen = false;
         if constexpr (ONE) {
             // every pair of the step in one slot: the cells of each lane's
             // smallest and largest key hold the same certain slot on every lane
@@ -824,8 +828,39 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
         }
 }
 
+// Steps beyond the last edge, screened with the FP32 dot product of the
+// copies (angular catalogs): p = fl32(f_i . f_j), one multiply and two FMAs
+// per pair, and p <= p_beyond on every pair proves the rule's d <= D_last
+// (dot_screen32 on the host derives the margin).  Whole blocks of 4 columns
+// from j on are counted beyond the last edge while every pair of the block
+// passes; returns the first column not counted.
+template <int P>
+__device__ __forceinline__ int screen_run(const JobDev &jb, const Consts &k, const float (&xi)[P],
+                                          const float (&yi)[P], const float (&zi)[P], int j, int j1,
+                                          Counters &cnt) {
+    constexpr int W = kColsPerStepF32;
+    cfloat_p bx = (cfloat_p)jb.bx32;
+    cfloat_p by = (cfloat_p)jb.by32;
+    cfloat_p bz = (cfloat_p)jb.bz32;
+    for (; j + W <= j1; j += W) {
+        float mp = -__builtin_huge_valf();
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            const float xj = bx[j + t], yj = by[j + t], zj = bz[j + t];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                mp = fmaxf(mp, __fmaf_rn(zi[p], zj, __fmaf_rn(yi[p], yj, xi[p] * xj)));
+        }
+        if (!wave_all(mp <= k.pbeyond))
+            break;
+        cnt.beyond += W * P;
+        cnt.beyond_steps += W / kColsPerStepF32;
+    }
+    return j;
+}
+
 // Columns [j0, j1) against the P rows of every lane (FP32 path).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE, bool SCREEN>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
                                           const int (&ii)[P], int ib, int lane, int ie, int j0, int j1,
@@ -835,6 +870,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     cfloat_p bz = (cfloat_p)jb.bz32;
     constexpr int JN = kColsPerStepF32;
     int j = j0;
+    bool screen = false;    // the previous step lay beyond the last edge
     if (j + JN <= j1) {
         // the columns of the next step are read (through the scalar unit)
         // while the current step computes; the last prefetch re-reads the
@@ -857,24 +893,46 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
-            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, cnt);
+            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, screen,
+                                                            cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
                 yj[t] = yn[t];
                 zj[t] = zn[t];
             }
+            if constexpr (SCREEN && !MASKED && !M3) {
+                if (screen) {
+                    // the step lay beyond the last edge: screen the blocks
+                    // after it with the cheaper dot-product proof; the
+                    // regular steps resume where a block fails it
+                    const int js = screen_run<P>(jb, k, xi, yi, zi, j + JN, j1, cnt);
+                    if (js != j + JN) {
+                        j = js - JN;
+                        if (js + JN <= j1) {
+#pragma unroll
+                            for (int t = 0; t < JN; ++t) {
+                                xj[t] = bx[js + t];
+                                yj[t] = by[js + t];
+                                zj[t] = bz[js + t];
+                            }
+                        }
+                    }
+                    screen = false;
+                }
+            }
         }
     }
     for (; j < j1; ++j) {
         const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
-        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, cnt);
+        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, screen,
+                                                          cnt);
     }
 }
 
 
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3, bool SCREEN>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
@@ -908,12 +966,12 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp32<LUT8, MASKED, P, DIRECT, M3, true>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, jn, cnt);
+            cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, SCREEN>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp32<LUT8, MASKED, P, DIRECT, M3, true>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j0, j1, cnt);
+    cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, SCREEN>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j0, j1, cnt);
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
@@ -968,7 +1026,8 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
-// table, 1 FP64 vector; 3-D distances: 5 FP32 squared distance with a
+// table, 6 and 7 the same with the dot-product screen of steps beyond the
+// last edge, 1 FP64 vector; 3-D distances: 5 FP32 squared distance with a
 // clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
 // rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
@@ -1010,6 +1069,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     k.rowstep = (uint32_t)a.hist_copies * 4u;
     k.flag = to_vgpr(Code<LUT8>::flag);
     k.beyond = to_vgpr(a.beyond_key);
+    k.pbeyond = a.p_beyond;
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     Counters cnt;
@@ -1041,12 +1101,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             const int ie = min(un.i1, ib + kRowsPerWave);
             const int rlo = max(un.row_lo, ib);
             const bool masked = (ie - ib < kRowsPerWave) || (jb.auto_pairs && un.j0 < ie) || rlo > ib;
-            if (PREC == 0 || PREC == 3 || PREC == 5) {
+            if (PREC == 0 || PREC == 3 || PREC == 5 || PREC == 6 || PREC == 7) {
                 constexpr bool M3 = PREC == 5;
+                constexpr bool DIRECT = PREC == 3 || PREC == 7;
+                constexpr bool SCREEN = PREC >= 6;
                 if (masked)
-                    rows_fp32<LUT8, true, P, PREC == 3, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, true, P, DIRECT, PRUNE, M3, SCREEN>(a, jb, s, k, ib, ie, un.j0, un.j1, lane,
+                                                                          cnt);
                 else
-                    rows_fp32<LUT8, false, P, PREC == 3, PRUNE, M3>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
+                    rows_fp32<LUT8, false, P, DIRECT, PRUNE, M3, SCREEN>(a, jb, s, k, ib, ie, un.j0, un.j1, lane,
+                                                                           cnt);
             } else {
                 constexpr bool M3 = PREC == 4;
                 if (masked)
@@ -1248,7 +1312,14 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
             return (int)hipErrorInvalidValue;
         return (int)hipGetLastError();
     }
-    if (precision == 0) {
+    if (precision == 0 && args->screen) {
+        if (b8 && args->lut_direct)
+            launch_pairs<7, true>(P, prune, grid, lds, st, *args);
+        else if (b8)
+            launch_pairs<6, true>(P, prune, grid, lds, st, *args);
+        else
+            launch_pairs<6, false>(P, prune, grid, lds, st, *args);
+    } else if (precision == 0) {
         if (b8 && args->lut_direct)
             launch_pairs<3, true>(P, prune, grid, lds, st, *args);
         else if (b8)

@@ -217,9 +217,12 @@ def test_two_slot_decision_matches_the_band(edges):
     truth = oracle.pair_slots(a.T, b.T, edges)
     ours = (truth == k) | (truth == k + 1)
     thr = qhi.astype(np.float32)[k]
-    width = qhi.astype(np.float32)[k] - qlo.astype(np.float32)[k]
-    x = q - thr                                     # FP32, round to nearest
-    decided = np.abs(x) > width
+    with np.errstate(invalid="ignore"):
+        # an edge at 0 has qlo = qhi = -inf: the width is NaN and, as in the
+        # kernel, no pair is decided by the comparison (the lookup settles it)
+        width = qhi.astype(np.float32)[k] - qlo.astype(np.float32)[k]
+        x = q - thr                                 # FP32, round to nearest
+        decided = np.abs(x) > width
     slot = k + (x >= 0).astype(np.int64)
     assert np.array_equal(slot[ours & decided], truth[ours & decided])
     in_band = (q >= qlo[k]) & (q < qhi[k])
@@ -242,6 +245,53 @@ def test_cell_slot_ranges_never_decrease(precision):
     keep = ~multi
     assert np.all(np.diff(lo[keep]) >= 0) and np.all(np.diff(hi[keep]) >= 0)
     assert np.all(hi - lo <= 1)
+
+
+def _p32(a, b, fused):
+    """The FP32 dot product of the FP32 copies, with a separate multiply and
+    add at each step, or (fused) each step rounded once: the products of
+    two floats are exact in FP64, so the FP64 sum rounded to FP32 is one
+    rounding up to a double rounding, which the screen's bound covers."""
+    fa, fb = a.astype(np.float32), b.astype(np.float32)
+    if not fused:
+        p = fa[:, 0] * fb[:, 0]
+        p = p + fa[:, 1] * fb[:, 1]
+        return p + fa[:, 2] * fb[:, 2]
+    da, db = fa.astype(np.float64), fb.astype(np.float64)
+    p = np.float32(da[:, 0] * db[:, 0])
+    p = np.float32(da[:, 1] * db[:, 1] + p.astype(np.float64))
+    return np.float32(da[:, 2] * db[:, 2] + p.astype(np.float64))
+
+
+@pytest.mark.parametrize("delta", [4.5e-16, 2.0 ** -21])
+@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
+                                   synthcat.log_edges(0.001, 20.0, 30),
+                                   synthcat.log_edges(0.01, 120.0, 12),
+                                   np.array([0.0, 1.0, 179.0])])
+def test_dot_screen_never_screens_a_pair_before_the_last_edge(edges, delta):
+    """The FP32 kernels' screen of steps beyond the last edge: p = fl32(f_i .
+    f_j) <= p_beyond must imply that the FP64 rule puts the pair at or past
+    the last edge.  Pairs at theta = e_last (1 +- 10^-s), s = 2..9, random
+    orientations, norms perturbed by up to delta; separate and fused sums.
+    Pairs a relative 1e-4 past the edge are screened (the screen is not
+    vacuous)."""
+    g = np.random.default_rng(21)
+    p_beyond = tp.compile_screen(edges, delta_max=delta)
+    e = edges[-1] * DEG
+    thetas = [np.full(2000, e * (1.0 + sgn * 10.0 ** -s)) for s in range(2, 10) for sgn in (-1.0, 1.0)]
+    theta = np.clip(np.concatenate(thetas), 0.0, math.pi)
+    a, b = _pairs_at(g, theta)
+    # squared norms within 1 +- delta (as the library's bound allows)
+    a *= np.sqrt(1.0 + g.uniform(-delta, delta, size=theta.size))[:, None]
+    b *= np.sqrt(1.0 + g.uniform(-delta, delta, size=theta.size))[:, None]
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    last = edges.size          # the overflow slot
+    for fused in (False, True):
+        screened = _p32(a, b, fused) <= np.float32(p_beyond)
+        assert np.all(truth[screened] == last), fused
+    if 0.0 < edges[-1] < 179.0:
+        far = theta > e * (1.0 + 1e-4)
+        assert np.all((_p32(a, b, True) <= np.float32(p_beyond))[far])
 
 
 def _emulate(a, b, edges, precision, delta, direct=None):
