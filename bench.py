@@ -35,6 +35,9 @@ FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_PAIR_FP64 = 7
 PATH_NAMES = {0: "fp32_chord", 1: "fp64"}
 KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)"}
+# the FP32 angular kernel with the dot-product screen of steps beyond the last
+# edge, launched when the last edge is below 90 degrees
+KERNEL_SCREENED = "pairs_kernel<6> (FP32 chord with the dot-product screen)"
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_octant_1e6x2e6.txt")
 
@@ -205,7 +208,8 @@ def bench_batched(args, tp, torch):
                    "nbins": int(e.size - 1), "pairs_per_step": pairs, "jobs": len(jobs),
                    "parallelism": "single-gpu"},
         "roofline": roofline(tp.FP32_CHORD, kg, kms / max(1, launches),
-                             kernel="pairs_kernel<0> (FP32 chord), one launch for all jobs"),
+                             kernel="pairs_kernel<6> (FP32 chord with the dot-product screen), one "
+                                    "launch for all jobs"),
         "separate_launches_gpairs_s": round(sep_value, 2),
         "batched_over_separate": round(value / sep_value, 3),
         "tuning": tuning,
@@ -455,7 +459,8 @@ def main():
                   # the roofline of the pairs the kernel still evaluated
                   "roofline_evaluated_pairs": roofline(
                       tp.FP32_CHORD, evaluated / (kms / 1e3) / 1e9, kms / (3 * args.steps),
-                      kernel="pairs_kernel<0> with pruning (FP32 chord)"),
+                      kernel="pairs_kernel<6> with pruning (FP32 chord)"
+                      if float(edges[-1]) < 90.0 else "pairs_kernel<0> with pruning (FP32 chord)"),
                   "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
                           "blocks are not evaluated, so not comparable to value"}
     jack = None
@@ -494,7 +499,9 @@ def main():
                 "ms_per_step": round(ms, 3), "kernel_ms_per_step": round(kms / args.steps, 3),
                 "roofline": roofline(tp.FP32_CHORD, pairs_step * args.steps / (kms / 1e3) / 1e9,
                                      kms / (3 * args.steps),
-                                     kernel="pairs_kernel<0> with region copies (FP32 chord)"),
+                                     kernel="pairs_kernel<6> with region copies (FP32 chord)"
+                                     if float(edges[-1]) < 90.0 else
+                                     "pairs_kernel<0> with region copies (FP32 chord)"),
                 "over_plain_step": round(ms / sums[tp.FP32_CHORD]["ms_per_step"], 3),
                 "note": "DD+DR+RR with per-region counts (FP32 chord) + host jackknife of w; "
                         "same totals as the plain step"}
@@ -579,8 +586,10 @@ def main():
         del out3
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
+    screened = float(edges[-1]) < 90.0
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
-                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 and not args.theta_max else None)
+                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 and not args.theta_max else None,
+                    kernel=KERNEL_SCREENED if head == tp.FP32_CHORD and screened else None)
     res = {
         "metric": METRIC,
         "value": hs["gpairs_s"],
