@@ -34,10 +34,10 @@ PEAK_GPAIRS = FP32_LANE_OPS / OPS_PER_PAIR_FP32 / 1e9
 FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_PAIR_FP64 = 7
 PATH_NAMES = {0: "fp32_chord", 1: "fp64"}
-KERNEL_NAMES = {0: "pairs_kernel<0> (FP32 chord)", 1: "pairs_kernel<1> (FP64 vector)"}
-# the FP32 angular kernel with the dot-product screen of steps beyond the last
-# edge, launched when the last edge is below 90 degrees
-KERNEL_SCREENED = "pairs_kernel<6> (FP32 chord with the dot-product screen)"
+# the FP32 angular kernel decides steps from the dot product first and forms
+# the chord where that does not settle them
+KERNEL_NAMES = {0: "pairs_kernel<6> (FP32, dot product first, chord where needed)",
+                1: "pairs_kernel<1> (FP64 vector)"}
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_octant_1e6x2e6.txt")
 
@@ -208,8 +208,7 @@ def bench_batched(args, tp, torch):
                    "nbins": int(e.size - 1), "pairs_per_step": pairs, "jobs": len(jobs),
                    "parallelism": "single-gpu"},
         "roofline": roofline(tp.FP32_CHORD, kg, kms / max(1, launches),
-                             kernel="pairs_kernel<6> (FP32 chord with the dot-product screen), one "
-                                    "launch for all jobs"),
+                             kernel=KERNEL_NAMES[0] + ", one launch for all jobs"),
         "separate_launches_gpairs_s": round(sep_value, 2),
         "batched_over_separate": round(value / sep_value, 3),
         "tuning": tuning,
@@ -395,7 +394,7 @@ def main():
         return {"s": t1 - t0, "kernel_ms": kms, "launches": launches, "hist": h, "w": ws,
                 "totals_ok": ok, "flagged": st.flagged, "exact": st.exact, "pairs": st.pairs,
                 "rare": st.rare_steps, "beyond": st.beyond_steps, "one_slot": st.one_slot_steps,
-                "two_slot": st.two_slot_steps, "per_kind": per_kind,
+                "two_slot": st.two_slot_steps, "chord": st.chord_steps, "per_kind": per_kind,
                 "tuning": tuning, "pairs_per_wave_step": rows_per_step * cols_per_step}
 
     print(f"# workload {wl.name}: N_D={nd} N_R={nr} nbins={edges.size - 1} "
@@ -427,7 +426,8 @@ def main():
                 "rare_step_rate": r["rare"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
                 "beyond_last_edge_rate": r["beyond"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
                 "one_slot_rate": r["one_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
-                "two_slot_rate": r["two_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
+                "two_slot_rate": r["two_slot"] * r["pairs_per_wave_step"] / max(1, r["pairs"]),
+                "chord_step_rate": r["chord"] * r["pairs_per_wave_step"] / max(1, r["pairs"])}
 
     sums = {prec: summary(prec) for prec in paths}
     pruned = None
@@ -459,7 +459,7 @@ def main():
                   # the roofline of the pairs the kernel still evaluated
                   "roofline_evaluated_pairs": roofline(
                       tp.FP32_CHORD, evaluated / (kms / 1e3) / 1e9, kms / (3 * args.steps),
-                      kernel="pairs_kernel<6> with pruning (FP32 chord)"
+                      kernel="pairs_kernel<6> with pruning (FP32)"
                       if float(edges[-1]) < 90.0 else "pairs_kernel<0> with pruning (FP32 chord)"),
                   "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
                           "blocks are not evaluated, so not comparable to value"}
@@ -499,7 +499,7 @@ def main():
                 "ms_per_step": round(ms, 3), "kernel_ms_per_step": round(kms / args.steps, 3),
                 "roofline": roofline(tp.FP32_CHORD, pairs_step * args.steps / (kms / 1e3) / 1e9,
                                      kms / (3 * args.steps),
-                                     kernel="pairs_kernel<6> with region copies (FP32 chord)"
+                                     kernel="pairs_kernel<6> with region copies (FP32)"
                                      if float(edges[-1]) < 90.0 else
                                      "pairs_kernel<0> with region copies (FP32 chord)"),
                 "over_plain_step": round(ms / sums[tp.FP32_CHORD]["ms_per_step"], 3),
@@ -586,10 +586,8 @@ def main():
         del out3
     head = max(paths, key=lambda p: sums[p]["gpairs_s"])
     hs = sums[head]
-    screened = float(edges[-1]) < 90.0
     roof = roofline(head, hs["kernel_gpairs_s"], hs["kernel_ms_per_launch"],
-                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 and not args.theta_max else None,
-                    kernel=KERNEL_SCREENED if head == tp.FP32_CHORD and screened else None)
+                    measured_traffic(PATH_NAMES[head]) if args.scale == 1.0 and not args.theta_max else None)
     res = {
         "metric": METRIC,
         "value": hs["gpairs_s"],

@@ -376,6 +376,9 @@ typedef struct tpcf_counters {
     uint64_t two_slot_steps;  /* steps where each lane's pairs fell in two adjacent slots,
                                  decided by one threshold comparison per pair and added with
                                  two LDS atomics per lane */
+    uint64_t chord_steps;     /* FP32 angular steps that formed the squared chord: the
+                                 dot product did not decide them, or the step lay at
+                                 small angles where the chord comes first */
 } tpcf_counters;
 
 /* Copy the statistics to *out (may be NULL) and, with reset = 1, clear
@@ -431,6 +434,22 @@ int tpcf_compile_edges(const double *bin_edges_deg, int32_t nbins, double delta_
  * the last edge, i.e. lies at or beyond it (Section 3, first bullet: the
  * angle from the dot product).  -inf when no pair can pass the last edge. */
 int tpcf_compile_screen(const double *bin_edges_deg, int32_t nbins, double delta_max, float *out_p);
+
+/* Tables of the FP32 angular kernels' dot-product path (host only, for CPU
+ * tests of the host logic).  A step first forms p = fl32(f_i . f_j) of the
+ * FP32 copies (Section 3: the angle comes from the dot product); each lane
+ * keys its largest and smallest p as q' = fl32(2 - 2p), a negative q' read
+ * as +0, into the cell clamp(bits(q') >> shift, lo, hi), whose entry
+ * cells[cell - lo] has the codes of tpcf_compile_cells.  Per edge k (nbins+1
+ * floats each, any may be NULL): q' >= out_khi[k] proves that the FP64 rule
+ * puts the pair at or past edge k and q' < out_klo[k] that it does not;
+ * p <= out_plo[k] and p >= out_phi[k] prove the same directly on p.
+ * out_cells holds max_cells entries (16..33792; the kernels use 1024 bytes).
+ * Returns TPCF_E_INVALID for invalid edges, delta_max outside [0, 2^-20] or
+ * NULL shift/lo/hi/cells. */
+int tpcf_compile_dot(const double *bin_edges_deg, int32_t nbins, double delta_max, int32_t max_cells,
+                     float *out_klo, float *out_khi, float *out_plo, float *out_phi, int32_t *out_shift,
+                     int32_t *out_lo, int32_t *out_hi, uint16_t *out_cells);
 
 /* Cell table of the pair kernels for the given edges (host only, for CPU
  * tests of the host logic).  precision selects the key: TPCF_FP32_CHORD uses

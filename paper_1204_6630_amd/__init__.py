@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "DD", "DR", "RR", "FP32_CHORD", "FP64", "TpcfError", "Context", "lib", "lib_path",
-    "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "compile_wrap32", "version", "EXPORTED_SYMBOLS", "JobDesc",
+    "landy_szalay", "jackknife", "compile_edges_3d", "MAX_REGIONS", "compile_edges", "compile_cells", "compile_wrap32", "compile_dot", "version", "EXPORTED_SYMBOLS", "JobDesc",
     "BATCH_GRAPH", "Tuning", "Counters", "Stats",
 ]
 
@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "tpcf_cancel", "tpcf_set_tuning", "tpcf_get_tuning", "tpcf_set_hbm_budget",
     "tpcf_hbm_usage", "tpcf_synchronize", "tpcf_set_timing", "tpcf_kernel_time",
     "tpcf_stats", "tpcf_landy_szalay", "tpcf_compile_cells", "tpcf_compile_wrap32",
-    "tpcf_compile_edges", "tpcf_compile_screen", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
+    "tpcf_compile_edges", "tpcf_compile_screen", "tpcf_compile_dot", "tpcf_upload_catalog_3d", "tpcf_upload_catalog_3d_regions", "tpcf_compile_edges_3d",
     "tpcf_last_error", "tpcf_version",
 )
 
@@ -65,7 +65,7 @@ class Counters(ctypes.Structure):
     """struct tpcf_counters"""
     _fields_ = [(n, ctypes.c_uint64) for n in ("pairs", "flagged", "exact", "rare_steps",
                                                "beyond_steps", "one_slot_steps", "pruned_pairs",
-                                               "two_slot_steps")]
+                                               "two_slot_steps", "chord_steps")]
 
 
 Stats = collections.namedtuple("Stats", [n for n, _ in Counters._fields_])
@@ -152,6 +152,7 @@ def lib():
         "tpcf_compile_wrap32": ([P, i32, ctypes.c_double, i32, i32, P, P, P, P, P, P, P, P, P], cint),
         "tpcf_compile_edges": ([P, i32, ctypes.c_double, P, P, P], cint),
         "tpcf_compile_screen": ([P, i32, ctypes.c_double, P], cint),
+        "tpcf_compile_dot": ([P, i32, ctypes.c_double, i32, P, P, P, P, P, P, P, P], cint),
         "tpcf_last_error": ([P], ctypes.c_char_p),
         "tpcf_version": ([], ctypes.c_char_p),
     }
@@ -473,6 +474,21 @@ def compile_screen(edges_deg, delta_max: float = 0.0) -> float:
     out = np.zeros(1, dtype=np.float32)
     _check(lib().tpcf_compile_screen(_p(e), e.size - 1, float(delta_max), _p(out)))
     return float(out[0])
+
+
+def compile_dot(edges_deg, delta_max: float = 0.0, max_cells: int = 1024):
+    """Tables of the dot-product path (tpcf_compile_dot): a dict with the key
+    band klo, khi, the band in p plo, phi, and the cell table shift, lo, hi,
+    cells of the key q' = fl32(2 - 2p)."""
+    e = _f64(edges_deg)
+    out = {n: np.empty(e.size, np.float32) for n in ("klo", "khi", "plo", "phi")}
+    cells = np.zeros(max_cells, np.uint16)
+    sh, lo, hi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().tpcf_compile_dot(_p(e), e.size - 1, float(delta_max), int(max_cells), _p(out["klo"]),
+                                  _p(out["khi"]), _p(out["plo"]), _p(out["phi"]), ctypes.byref(sh),
+                                  ctypes.byref(lo), ctypes.byref(hi), _p(cells)))
+    out.update(shift=sh.value, lo=lo.value, hi=hi.value, cells=cells[:hi.value - lo.value + 1].copy())
+    return out
 
 
 def compile_edges_3d(edges, rmax: float):

@@ -146,6 +146,10 @@ struct Compiled {
     DevBuf dD, dE, dqlo, dqhi, dlut, dErad;
     CellTable cells;
     Band32 band;
+    // Angular FP32: cell table of the dot-product key q' = fl(2 - 2p), packed
+    // after the chord table (at byte plut_src of dlut); no cells otherwise.
+    CellTable pcells;
+    int plut_src = 0;
     int precision = 0;
     int entry_bytes = 2;   // 1: byte entries (0x80 | k, 0xFF), 2: 16-bit codes
     double delta = 0;      // norm bound of the band (3-D: rmax)
@@ -165,7 +169,7 @@ struct Workspace {
     bool own = false;
     DevBuf copies;   // kGlobalCopies x nslots u64
     DevBuf out;      // kMaxSlots u64
-    DevBuf stats;    // 8 u64
+    DevBuf stats;    // kStats u64
     DevBuf touch;    // nreg x kGlobalCopies x nslots u64 (jackknife regions)
     DevBuf tout;     // nreg x nslots u64
     int inflight = 0;
@@ -249,8 +253,8 @@ int init_workspace(tpcf_ctx *ctx, Workspace &w, hipStream_t borrowed) {
         HIP_TRY(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
         w.own = true;
     }
-    TRY(w.stats.ensure(ctx->mem, sizeof(unsigned long long) * 8));
-    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w.stats.p, 8, w.stream));
+    TRY(w.stats.ensure(ctx->mem, sizeof(unsigned long long) * kStats));
+    HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w.stats.p, kStats, w.stream));
     return TPCF_OK;
 }
 
@@ -522,6 +526,22 @@ void free_compiled(tpcf_ctx *ctx, Compiled &c) {
 
 int hist_copies_of(const Tuning &t, int nslots);
 
+// Cell entries as the kernels read them, appended to *out: one byte (slot,
+// 0x80 | k, 0xFF) or the 16-bit codes.
+void pack_cells(const std::vector<uint16_t> &src, int entry_bytes, std::vector<uint8_t> *out) {
+    const size_t at = out->size();
+    if (entry_bytes == 1) {
+        out->resize(at + src.size());
+        for (size_t i = 0; i < src.size(); ++i) {
+            const uint16_t v = src[i];
+            (*out)[at + i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
+        }
+    } else {
+        out->resize(at + src.size() * 2);
+        memcpy(out->data() + at, src.data(), src.size() * 2);
+    }
+}
+
 // Host part of the edge compiler: thresholds, FP32 band and cell table of
 // one edges array for the given tuning, and the table packed as the kernels
 // read it.  Allocates no device memory.
@@ -535,7 +555,14 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
     c->metric = metric;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    const int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
+    // angular FP32: the dot-product table takes kDotLutBytes of LDS, and by
+    // default the chord table leaves room for it within kLdsTarget
+    const bool dot = !metric && precision == TPCF_FP32_CHORD;
+    const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
+    const int pbytes = dot ? kDotLutBytes : 0;
+    int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
+    if (dot && !tune.lut_bytes)
+        table_bytes = std::min(table_bytes, std::max(4096, (kLdsTarget - aux - pbytes - 16) & ~15));
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     qlo->assign(c->edges.D.size(), 0.0f);
     qhi->assign(c->edges.D.size(), 0.0f);
@@ -551,8 +578,8 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
         c->band = make_band32(c->edges, delta);
         if (c->entry_bytes == 1 && tune.lut_direct) {
             Band32 fb = make_band32(c->edges, delta, floor_for(c->band));
-            const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
-            c->cells = make_cells32_wrap(c->edges, fb, delta, tune.lut_bytes ? tune.lut_bytes : kWrapLutBytes, aux);
+            const int wrap_bytes = tune.lut_bytes ? tune.lut_bytes : kWrapLutBytes - pbytes - 16;
+            c->cells = make_cells32_wrap(c->edges, fb, delta, wrap_bytes, aux);
             if (!c->cells.cells.empty())
                 c->band = fb;
         }
@@ -560,20 +587,23 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
             c->cells = make_cells32(c->edges, c->band, delta, max_cells);
         *qlo = c->band.qlo;
         *qhi = c->band.qhi;
+        // the dot-product key's table and the per-pair band in p, after the
+        // chord band's entries in qlo / qhi
+        c->pcells = make_cells32_top(c->edges, make_band_dot32(c->edges, delta), dot_top_key(delta),
+                                     pbytes / c->entry_bytes);
+        std::vector<float> plo, phi;
+        make_pband32(c->edges, delta, &plo, &phi);
+        qlo->insert(qlo->end(), plo.begin(), plo.end());
+        qhi->insert(qhi->end(), phi.begin(), phi.end());
     } else {
         c->cells = make_cells64(c->edges, max_cells);
     }
     packed->clear();
-    if (c->entry_bytes == 1) {
-        const std::vector<uint16_t> &src = c->cells.direct ? c->cells.image : c->cells.cells;
-        packed->resize(src.size());
-        for (size_t i = 0; i < packed->size(); ++i) {
-            uint16_t v = src[i];
-            (*packed)[i] = v == kMulti ? 0xFF : (v & kMedium) ? (uint8_t)(0x80 | (v & 0x7F)) : (uint8_t)v;
-        }
-    } else {
-        packed->resize(c->cells.cells.size() * 2);
-        memcpy(packed->data(), c->cells.cells.data(), packed->size());
+    pack_cells(c->cells.direct ? c->cells.image : c->cells.cells, c->entry_bytes, packed);
+    if (!c->pcells.cells.empty()) {
+        packed->resize((packed->size() + 15) & ~(size_t)15, 0);
+        c->plut_src = (int)packed->size();
+        pack_cells(c->pcells.cells, c->entry_bytes, packed);
     }
     return TPCF_OK;
 }
@@ -966,26 +996,15 @@ JobDev job_of(const Request &r, unsigned long long *hist, const int *cancel) {
 }
 
 // Threshold of the FP32 dot-product screen for the edge with threshold D
-// (angular catalogs, squared norms within 1 +- delta).  The kernel forms
-// p = fl32(f_i . f_j) of the FP32 copies f = fl32(v) with three roundings
-// (fused or not).  With u = 2^-24:
-//   |p - f_i . f_j| <= gamma_3(u) |f_i| |f_j| <= gamma_3(u) (1 + u)^2 (1 + delta)
-//   |f_i . f_j - v_i . v_j| <= (2u + u^2) |v_i| |v_j| <= (2u + u^2)(1 + delta)
-//   |d - v_i . v_j| <= gamma_3(2^-53)(1 + delta)   (the rule's dot product)
-// plus 3 * 2^-126 for FP32 underflow in the products.  So p <= D - E with E
-// the sum proves d <= D.  The result is rounded down to a float; a 2^-20
-// relative widening of E covers this function's own FP64 rounding.
+// (angular catalogs, squared norms within 1 +- delta): p = fl32(f_i . f_j) of
+// the FP32 copies satisfies |p - d| <= E = dot_error32(delta), so p <= D - E
+// proves d <= D.  The result is rounded down to a float.
 float dot_screen32(double D, double delta) {
     if (!(D > -HUGE_VAL))
         return -HUGE_VALF;          // no pair passes this edge
     if (D == HUGE_VAL)
         return HUGE_VALF;           // every pair passes it
-    const double u = ldexp(1.0, -24), U = ldexp(1.0, -53);
-    const double g3 = 3.0 * u / (1.0 - 3.0 * u), G3 = 3.0 * U / (1.0 - 3.0 * U);
-    const double E = (g3 * (1.0 + u) * (1.0 + u) * (1.0 + delta) + (2.0 * u + u * u) * (1.0 + delta) +
-                      G3 * (1.0 + delta) + 3.0 * ldexp(1.0, -126)) *
-                     (1.0 + ldexp(1.0, -20));
-    const double P = D - E;
+    const double P = D - dot_error32(delta);
     float f = (float)P;
     if ((double)f > P)
         f = nextafterf(f, -HUGE_VALF);
@@ -1020,9 +1039,19 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
         float qh = cp.band.qhi[last];
         memcpy(&a.beyond_key, &qh, sizeof qh);
         a.p_beyond = cp.metric ? -HUGE_VALF : dot_screen32(cp.edges.D[last], cp.delta);
-        // the screen pays where steps beyond the last edge come in runs: a
-        // last edge below 90 degrees (positive threshold)
-        a.screen = !cp.metric && cp.edges.D[last] > 0.0 && a.p_beyond > 0.0f ? 1 : 0;
+        if (!cp.pcells.cells.empty()) {
+            a.plut_cells = (int32_t)cp.pcells.cells.size();
+            a.plut_shift = cp.pcells.shift;
+            a.plut_lo = cp.pcells.lo;
+            a.plut_hi = cp.pcells.hi;
+            a.plut_src = cp.plut_src;
+            const int base = lds_bytes(nbins + 2, hist_copies_of(ctx->tune, nbins + 2), a.lut_cells, cp.entry_bytes,
+                                       nbins + 1, cp.cells.direct ? cp.cells.aux_off : -1);
+            a.plut_lds = (base + 15) & ~15;
+            // steps are tried with the dot product first where its error is
+            // below 1 % of the chord^2 (about 0.6 deg); a heuristic only
+            a.q_dot = (float)(400.0 * dot_error32(cp.delta));
+        }
     } else {
         const double t = cp.edges.E[last];
         uint64_t b;
@@ -1528,7 +1557,7 @@ int tpcf_count_noalloc(tpcf_ctx *ctx, int kind, int32_t cat_a, int32_t cat_b, co
     const size_t o_copies = take(sizeof(unsigned long long) * ((size_t)kGlobalCopies * nslots + 1));
     const size_t o_out = take(sizeof(unsigned long long) * (size_t)nslots);
     const size_t o_D = take(sizeof(double) * nedges), o_E = take(sizeof(double) * nedges);
-    const size_t o_qlo = take(sizeof(float) * nedges), o_qhi = take(sizeof(float) * nedges);
+    const size_t o_qlo = take(sizeof(float) * qlo.size()), o_qhi = take(sizeof(float) * qhi.size());
     const size_t o_rad = take(sizeof(double) * nedges);
     const size_t o_lut = take(packed.size());
     const size_t o_units = off;
@@ -1943,17 +1972,17 @@ int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset) {
         return fail(TPCF_E_INVALID, "context is NULL");
     TRY(set_device(ctx));
     TRY(sync_all(ctx));
-    unsigned long long tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long tot[kStats] = {};
     std::vector<Workspace *> ws{&ctx->main};
     for (auto &w : ctx->pool)
         ws.push_back(&w);
     for (Workspace *w : ws) {
-        unsigned long long h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long h[kStats] = {};
         HIP_TRY(hipMemcpy(h, w->stats.p, sizeof h, hipMemcpyDeviceToHost));
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < kStats; ++i)
             tot[i] += h[i];
         if (reset)
-            HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w->stats.p, 8, w->stream));
+            HIP_TRY((hipError_t)tpcf_launch_zero_u64((unsigned long long *)w->stats.p, kStats, w->stream));
     }
     if (reset)
         TRY(sync_all(ctx));
@@ -1966,6 +1995,7 @@ int tpcf_stats(tpcf_ctx *ctx, tpcf_counters *out, int reset) {
         out->one_slot_steps = tot[6];
         out->pruned_pairs = tot[7];
         out->two_slot_steps = tot[0];
+        out->chord_steps = tot[8];
     }
     if (reset)
         ctx->pairs_since_reset = 0;
@@ -2161,6 +2191,40 @@ int tpcf_compile_screen(const double *bin_edges_deg, int32_t nbins, double delta
     if (!compile_edges(bin_edges_deg, nbins, &t, &err))
         return fail(TPCF_E_INVALID, err);
     *out_p = dot_screen32(t.D[(size_t)nbins], delta_max);
+    return TPCF_OK;
+}
+
+int tpcf_compile_dot(const double *bin_edges_deg, int32_t nbins, double delta_max, int32_t max_cells,
+                     float *out_klo, float *out_khi, float *out_plo, float *out_phi, int32_t *out_shift,
+                     int32_t *out_lo, int32_t *out_hi, uint16_t *out_cells) {
+    if (!out_shift || !out_lo || !out_hi || !out_cells)
+        return fail(TPCF_E_INVALID, "NULL argument");
+    if (!(delta_max >= 0.0) || delta_max > kMaxDelta)
+        return fail(TPCF_E_INVALID, "delta_max must be in [0, 2^-20]");
+    if (max_cells < 16 || max_cells > kMaxDirectLutBytes)
+        return fail(TPCF_E_INVALID, "max_cells must be in [16, 33792]");
+    EdgeTables t;
+    std::string err;
+    if (!compile_edges(bin_edges_deg, nbins, &t, &err))
+        return fail(TPCF_E_INVALID, err);
+    const Band32 b = make_band_dot32(t, delta_max);
+    const CellTable c = make_cells32_top(t, b, dot_top_key(delta_max), max_cells);
+    std::vector<float> plo, phi;
+    make_pband32(t, delta_max, &plo, &phi);
+    for (int k = 0; k <= nbins; ++k) {
+        if (out_klo)
+            out_klo[k] = b.qlo[k];
+        if (out_khi)
+            out_khi[k] = b.qhi[k];
+        if (out_plo)
+            out_plo[k] = plo[k];
+        if (out_phi)
+            out_phi[k] = phi[k];
+    }
+    *out_shift = c.shift;
+    *out_lo = c.lo;
+    *out_hi = c.hi;
+    memcpy(out_cells, c.cells.data(), sizeof(uint16_t) * c.cells.size());
     return TPCF_OK;
 }
 

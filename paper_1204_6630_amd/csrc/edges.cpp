@@ -266,6 +266,81 @@ Band32 make_band32(const EdgeTables &t, double delta, float q0) {
     return b;
 }
 
+// Dot product of the FP32 copies.  With u = 2^-24 and U = 2^-53:
+//  * |p - f_i . f_j| <= gamma_3(u) |f_i| |f_j| <= gamma_3(u) (1 + u)^2 (1 + delta)
+//    (three roundings, fused or not; Cauchy-Schwarz for the sum of the
+//    absolute products);
+//  * |f_i . f_j - v_i . v_j| <= (2u + u^2)(1 + delta) (|f - v| <= u |v|);
+//  * |d - v_i . v_j| <= gamma_3(U)(1 + delta) (the rule's own sum);
+//  * 3 * 2^-126 for FP32 underflow in the products.
+// The sum, widened by 2^-20 for this function's own rounding, bounds |p - d|.
+double dot_error32(double delta) {
+    const double u = ldexp(1.0, -24), U = ldexp(1.0, -53);
+    const double g3 = 3.0 * u / (1.0 - 3.0 * u), G3 = 3.0 * U / (1.0 - 3.0 * U);
+    return (g3 * (1.0 + u) * (1.0 + u) * (1.0 + delta) + (2.0 * u + u * u) * (1.0 + delta) + G3 * (1.0 + delta) +
+            3.0 * ldexp(1.0, -126)) *
+           (1.0 + ldexp(1.0, -20));
+}
+
+// The key q' = fl(2 - 2p): 2p is exact and the FMA rounds 2 - 2p once, with a
+// relative error of at most u (no underflow: 2 - 2p is 0 or at least 2^-23
+// for p near 1, and near 2 for tiny p).  With x = 2 - 2p and E = dot_error32:
+//  * q' >= qhi_k with qhi_k >= 2 (1 - D_k + E)(1 + u) gives
+//    x >= q'/(1 + u) >= 2 (1 - D_k + E), so p <= D_k - E and d <= D_k;
+//  * q' < qlo_k with qlo_k <= 2 (1 - D_k - E)(1 - u) gives (q' >= 0)
+//    x <= q'/(1 - u) < 2 (1 - D_k - E), so p > D_k + E and d > D_k.
+// The kernel replaces a negative q' (x < 0, p > 1) by +0: a positive qlo_k
+// means D_k + E < 1 < p, so q' = 0 < qlo_k is still right, and qhi_k > 0 for
+// every finite D_k (D_k <= 1), so 0 never reaches it.  s = 1 + 2^-20 covers
+// the rounding of 1 - D_k here.
+Band32 make_band_dot32(const EdgeTables &t, double delta) {
+    const double u = ldexp(1.0, -24), E = dot_error32(delta), s = 1.0 + ldexp(1.0, -20);
+    Band32 b;
+    b.delta = delta;
+    const int ne = (int)t.D.size();
+    b.qlo.resize(ne);
+    b.qhi.resize(ne);
+    for (int k = 0; k < ne; ++k) {
+        const double D = t.D[k];
+        if (D == HUGE_VAL) {
+            b.qlo[k] = b.qhi[k] = -HUGE_VALF;
+            continue;
+        }
+        if (D == -HUGE_VAL) {
+            b.qlo[k] = b.qhi[k] = HUGE_VALF;
+            continue;
+        }
+        b.qhi[k] = round_up32(2.0 * (1.0 - D + E) * (1.0 + u) * s);
+        const double lo = 2.0 * (1.0 - D - E) * (1.0 - u) / s;
+        b.qlo[k] = lo > 0.0 ? round_down32(lo) : 0.0f;
+    }
+    return b;
+}
+
+uint32_t dot_top_key(double delta) {
+    // |p| <= (1 + delta)(1 + E'): q' <= 4 (1 + delta) + a few ulps
+    return fbits(round_up32(4.0 * (1.0 + delta) * (1.0 + ldexp(1.0, -18))));
+}
+
+// p <= D_k - E gives d <= D_k and p > D_k + E gives d > D_k; the bounds are
+// widened by s = 1 + 2^-20 (covering the FP64 rounding of D_k +- E s, which
+// is far below E (s - 1)) and rounded outward to floats.
+void make_pband32(const EdgeTables &t, double delta, std::vector<float> *plo, std::vector<float> *phi) {
+    const double E = dot_error32(delta) * (1.0 + ldexp(1.0, -20));
+    const int ne = (int)t.D.size();
+    plo->resize(ne);
+    phi->resize(ne);
+    for (int k = 0; k < ne; ++k) {
+        const double D = t.D[k];
+        if (D == HUGE_VAL || D == -HUGE_VAL) {
+            (*plo)[k] = (*phi)[k] = D == HUGE_VAL ? HUGE_VALF : -HUGE_VALF;
+            continue;
+        }
+        (*plo)[k] = round_down32(D - E);
+        (*phi)[k] = round_up32(D + E);
+    }
+}
+
 // 3-D edges.  The counting rule bins a pair by r = sqrt(r2), r2 the FP64
 // sum (dx^2 + dy^2) + dz^2 of the coordinate differences.  sqrt is
 // non-decreasing (and correctly rounded), so r >= e_k <=> r2 >= S_k with S_k

@@ -50,6 +50,23 @@ bool compile_edges(const double *edges_deg, int nbins, EdgeTables *out, std::str
 // q = fl(dz^2 + fl(dy^2 + fl(dx^2 + q0))), the kernel's sum started at the
 // floor q0 instead of 0.
 Band32 make_band32(const EdgeTables &t, double delta, float q0 = 0.0f);
+// Bound on |p - d| for p = fl32(f_i . f_j), the dot product of the FP32 copies
+// (one multiply and two FMAs, or separate multiplies and adds), and d the
+// counting rule's FP64 dot product of the vectors, whose squared norms lie
+// within 1 +- delta.
+double dot_error32(double delta);
+// Band of the dot-product key.  The kernel forms q' = max(fl(2 - 2p), +0)
+// (one FMA; as a bit pattern, negative results go to 0) for the largest and
+// smallest p of a lane; q' >= qhi_k proves d <= D_k and q' < qlo_k proves
+// d > D_k.  Cell tables of this band (make_cells32_top with dot_top_key) give
+// the slot range of a lane's pairs from their extreme p.
+Band32 make_band_dot32(const EdgeTables &t, double delta);
+// Upper bound of every q' the kernel forms (keys above go to the top cell).
+uint32_t dot_top_key(double delta);
+// The band in p itself, for per-pair decisions: p <= plo_k proves d <= D_k
+// and p >= phi_k proves d > D_k (+inf for an edge at 0, -inf for an edge no
+// pair reaches).
+void make_pband32(const EdgeTables &t, double delta, std::vector<float> *plo, std::vector<float> *phi);
 // Floor for the wrapped layout: a power of two at most a quarter of the
 // smallest positive threshold of a band built without a floor (and at least
 // 2^-100, so no partial sum is subnormal).

@@ -20,6 +20,13 @@ constexpr int kMaxLutCells = kMaxLutBytes;        // with one-byte entries
 // tables' default budget (table, histograms and thresholds together).
 constexpr int kMaxDirectLutBytes = 33792;
 constexpr int kWrapLutBytes = 32768;
+// Angular FP32 launches also hold the dot-product key's cell table (bytes),
+// and by default size the chord table so that a block's LDS stays within
+// kLdsTarget (five blocks of four wavefronts in a CU's 160 KiB).
+constexpr int kDotLutBytes = 1024;
+constexpr int kLdsTarget = 32768;
+// Work statistics words of a launch (see PairArgs::stats).
+constexpr int kStats = 9;
 // Histogram copies in global memory (u64), indexed by work unit.
 constexpr int kGlobalCopies = 64;
 // Largest number of output slots (nbins <= 256 -> nbins + 2 slots).
@@ -102,10 +109,16 @@ struct PairArgs {
     // copies, p <= p_beyond, proves the rule's d <= D_last (the pair is past
     // the last edge); -inf when no such screen applies (3-D catalogs).
     float p_beyond;
-    // 1: FP32 angular launches screen the steps after a step beyond the last
-    // edge with p (chosen when the last edge is below 90 degrees, where such
-    // steps come in runs; without them the screen's code only costs)
-    int32_t screen;
+    // Angular FP32 path, dot product first (plut_cells > 0): the cell table of
+    // the key q' = fl(2 - 2p) (cell = clamp(bits(q') >> plut_shift, plut_lo,
+    // plut_hi), plut_cells entries at byte plut_src of lut, copied to LDS byte
+    // plut_lds), and the band in p, nedges (plo, phi) pairs after the chord
+    // band in qlo / qhi.  Steps are tried with p first while the previous
+    // chord step's smallest q was at least q_dot.
+    int32_t plut_cells;
+    int32_t plut_shift, plut_lo, plut_hi;
+    int32_t plut_src, plut_lds;
+    float q_dot;
 
     // Exact tile pruning: 1 = a wavefront bins a whole aligned 64-column
     // block at once when the bounding caps put every pair of the block
@@ -135,14 +148,15 @@ struct PairArgs {
     int32_t rows_per_lane;       // 2 or 4: a unit spans kWaves * 64 * rows_per_lane rows
     int32_t blocks_per_cu;       // grid = CUs x this (0: the blocks that fit at once)
 
-    unsigned long long *stats;   // [two-slot steps, flagged, exact, skipped units, rare-path
-                                 //  steps, steps counted beyond the last edge, one-slot
-                                 //  steps, pairs binned by pruned blocks]
+    unsigned long long *stats;   // kStats words: [two-slot steps, flagged, exact, skipped
+                                 //  units, rare-path steps, steps counted beyond the last
+                                 //  edge, one-slot steps, pairs binned by pruned blocks,
+                                 //  angular FP32 steps that formed the chord]
 };
 
-// LDS bytes per edge: D_k, fl(1 - D_k), the edge in radians (pruning) and
-// the FP32 band (qlo_k, qhi_k).
-constexpr int kEdgeLdsBytes = 8 + 8 + 8 + 8;
+// LDS bytes per edge: D_k, fl(1 - D_k), the edge in radians (pruning), the
+// FP32 chord band (qlo_k, qhi_k) and the band in p (plo_k, phi_k).
+constexpr int kEdgeLdsBytes = 8 + 8 + 8 + 8 + 8;
 
 // LDS bytes of the histograms (with the discard row) and edge thresholds.
 inline int aux_lds_bytes(int nslots, int hist_copies, int nedges) {

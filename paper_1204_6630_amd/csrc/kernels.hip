@@ -176,10 +176,12 @@ struct Smem {
     double *D;
     double *E;
     float2 *qband;       // FP32 band (qlo_k, qhi_k), one 8-byte read per edge
+    float2 *pband;       // band in p (plo_k, phi_k), dot-product path
     double *erad;        // edges in radians (pruning)
     unsigned char *lut;
     uint32_t hist_addr;  // LDS byte address of hist
     uint32_t lut_addr;   // LDS byte address of lut
+    uint32_t plut_addr;  // LDS byte address of the dot-product key's table
 };
 
 // LDS layout: the cell table first (at the start of the block's LDS, so a
@@ -196,8 +198,10 @@ __device__ __forceinline__ Smem carve(unsigned char *base, const PairArgs &a) {
     s.E = s.D + a.nedges;
     s.erad = s.E + a.nedges;
     s.qband = reinterpret_cast<float2 *>(s.erad + a.nedges);
+    s.pband = s.qband + a.nedges;
     s.hist_addr = (uint32_t)(uintptr_t)(lds_u32 *)s.hist;
     s.lut_addr = (uint32_t)(uintptr_t)(lds_u8 *)s.lut;
+    s.plut_addr = s.lut_addr + (uint32_t)a.plut_lds;
     return s;
 }
 
@@ -290,11 +294,43 @@ __device__ __forceinline__ uint32_t resolve_fp64(uint32_t ent, uint32_t flag, do
 struct Counters {
     uint32_t flag = 0, exact = 0, rare = 0;
     uint32_t beyond = 0;        // this lane's pairs counted beyond the last edge (per unit)
-    uint32_t beyond_steps = 0;  // wavefront steps counted that way (wavefront-uniform)
-    uint32_t one_slot_steps = 0;  // steps binned with one atomic per lane (uniform)
-    uint32_t two_slot_steps = 0;  // steps binned with two atomics per lane (uniform)
+    // Step kinds of the current column range, 16 bits each (wavefront-
+    // uniform, kept in scalar registers): steps beyond the last edge, in one
+    // slot, in two slots, and (dot-product kernels) steps that formed the
+    // chord; folded into the totals below after every range of at most
+    // kFoldCols columns.
+    uint64_t steps = 0;
+    uint32_t beyond_steps = 0, one_slot_steps = 0, two_slot_steps = 0, chord_steps = 0;
     uint32_t pruned_blocks = 0;     // wavefront blocks (P x 64 rows x 64 columns) binned whole (uniform)
+
+    __device__ __forceinline__ void fold() {
+        beyond_steps += (uint32_t)(steps & 0xFFFF);
+        one_slot_steps += (uint32_t)((steps >> 16) & 0xFFFF);
+        two_slot_steps += (uint32_t)((steps >> 32) & 0xFFFF);
+        chord_steps += (uint32_t)(steps >> 48);
+        steps = 0;
+    }
 };
+
+// Longest column range one call of the column loops covers: at most
+// kFoldCols / 2 steps, below the 16-bit step fields of Counters.
+constexpr int kFoldCols = 65536;
+
+// How a wavefront step was binned (wavefront-uniform).  A step beyond the
+// last edge adds nothing to the histograms: the caller counts its pairs in
+// the lane's register.  kUndecided: the dot product did not settle the step.
+enum : uint32_t { kBeyond = 0, kOneSlot = 1, kTwoSlot = 2, kLookup = 3, kUndecided = 4 };
+
+// Per-step bookkeeping, done once after the step whichever way it went (so
+// the counters are not carried through the step's branches).  The step
+// functions' codes are wavefront-uniform, but the compiler cannot tell
+// (their paths hold per-lane branches), so the callers pass them through
+// readfirstlane to keep the code and the branches on it scalar.
+template <uint32_t N>
+__device__ __forceinline__ void account(uint32_t code, Counters &cnt) {
+    cnt.beyond += code == kBeyond ? N : 0u;
+    cnt.steps += code <= kTwoSlot ? (uint64_t)1 << (16 * code) : 0;
+}
 
 // Loop constants of one wavefront.
 struct Consts {
@@ -308,6 +344,11 @@ struct Consts {
     uint32_t flag;          // flag bit of the cell entries (VGPR copy)
     uint32_t beyond;        // PairArgs::beyond_key (VGPR copy)
     float pbeyond;          // PairArgs::p_beyond
+    // dot-product key's table: cell = bits(q') >> pshift clamped to
+    // [pclo, pchi], LDS address cell * entry_bytes + pbias (VGPR copies: the
+    // dot-product loop then needs no scalar registers for them)
+    uint32_t pshift, pclo, pchi, pbias;
+    uint32_t qdot;          // bits of PairArgs::q_dot
 };
 
 // LDS address of the cell-table entry of an FP32 key (the bit pattern of q)
@@ -356,7 +397,6 @@ __device__ __forceinline__ bool one_slot_step(uint32_t lo, uint32_t span, uint32
     if (!wave_all(span == 0))
         return false;
     lds_add(__umul24(lo, k.rowstep) + k.lanebase, n);
-    ++cnt.one_slot_steps;
     return true;
 }
 
@@ -371,11 +411,12 @@ __device__ __forceinline__ bool two_slot_range(uint32_t lo, uint32_t span) {
 
 __device__ __forceinline__ void two_slot_add(uint32_t base, uint32_t n, uint32_t n_up, const Consts &k,
                                              Counters &cnt) {
+    // both adds on every lane (a lane with one slot adds 0 to the next row,
+    // at most the discard row): no per-lane branch, so the step's outcome
+    // stays wavefront-uniform for the compiler
     const uint32_t addr = __umul24(base, k.rowstep) + k.lanebase;
     lds_add(addr, n - n_up);
-    if (n_up)
-        lds_add(addr + k.rowstep, n_up);
-    ++cnt.two_slot_steps;
+    lds_add(addr + k.rowstep, n_up);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,11 +624,11 @@ __device__ __forceinline__ void bin_block(int slot, uint32_t n, const PairArgs &
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
 template <bool LUT8, bool MASKED, int P, int JN, bool DIRECT, bool M3, bool ONE>
-__device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+__device__ __forceinline__ uint32_t step_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P],
                                           const float (&zi)[P], const int (&ii)[P],
                                           int ib, int lane, int ie, int j, const float (&xj)[JN],
-                                          const float (&yj)[JN], const float (&zj)[JN], bool &screen,
+                                          const float (&yj)[JN], const float (&zj)[JN], uint32_t &qmin,
                                           Counters &cnt) {
     float q[JN][P];
     uint32_t ent[JN][P];
@@ -614,13 +655,9 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 m = min(m, __float_as_uint(q[t][p]));
-        if (wave_all(m >= k.beyond)) {
-            cnt.beyond += JN * P;
-            ++cnt.beyond_steps;
-            screen = true;
-            return;
-        }
-        screen = false;
+        qmin = m;
+        if (wave_all(m >= k.beyond))
+            return kBeyond;
         if constexpr (ONE) {
             // every pair of the step in one slot: the cells of each lane's
             // smallest and largest key hold the same certain slot on every lane
@@ -638,7 +675,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             slot_range<LUT8>(lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(m, k)),
                              lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(mx, k)), base, span);
             if (one_slot_step(base, span, JN * P, k, cnt))
-                return;
+                return kOneSlot;
             if (two_slot_range<LUT8>(base, span)) {
                 // a pair is past edge `base` when q >= qhi and not past it when
                 // q < qlo; x = fl(q - qhi) has the sign of q - qhi unless it is
@@ -665,7 +702,7 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
                 asm volatile("" : "+v"(n_below));
                 if (wave_all(near > width)) {
                     two_slot_add(base, JN * P, JN * P - n_below, k, cnt);
-                    return;
+                    return kTwoSlot;
                 }
             }
         }
@@ -713,10 +750,85 @@ __device__ __forceinline__ void step_fp32(const PairArgs &a, const JobDev &jb, c
             }
             lds_inc(__umul24(e, k.rowstep) + k.lanebase);
         }
+    return kLookup;
+}
+
+// LDS address of the dot-product key's cell: q' = fl(2 - 2p) as a bit
+// pattern, a negative q' (p > 1) read as +0 through a signed maximum.
+template <bool LUT8>
+__device__ __forceinline__ uint32_t paddr(float qd, const Consts &k) {
+    const uint32_t bits = (uint32_t)max((int32_t)__float_as_uint(qd), 0);
+    return med3_u32(bits >> k.pshift, k.pclo, k.pchi) * (LUT8 ? 1u : 2u) + k.pbias;
+}
+
+// One step of an angular FP32 wavefront decided from the dot product of the
+// FP32 copies, p = fl32(f_i . f_j) (one multiply and two FMAs per pair;
+// |p - d| is bounded by the host's dot_error32).  Whole steps only: all
+// pairs beyond the last edge (p <= p_beyond), every lane's pairs in one slot,
+// or in two adjacent slots with every pair outside the band in p of the edge
+// between them.  The slot range of a lane comes from the cells of the key
+// q' = fl(2 - 2p) of its largest and smallest p (q' does not increase with
+// p).  Returns false, having counted nothing, when p does not decide the
+// step; the caller then forms the chord.
+template <bool LUT8, int P, int JN>
+__device__ __forceinline__ uint32_t step_dot(const PairArgs &a, const Smem &s, const Consts &k, const float (&xi)[P],
+                                         const float (&yi)[P], const float (&zi)[P], const float (&xj)[JN],
+                                         const float (&yj)[JN], const float (&zj)[JN], Counters &cnt) {
+    float p[JN][P];
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+            p[t][r] = __fmaf_rn(zi[r], zj[t], __fmaf_rn(yi[r], yj[t], xi[r] * xj[t]));
+    float pmax = p[0][0];
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+            pmax = fmaxf(pmax, p[t][r]);
+    if (wave_all(pmax <= k.pbeyond))
+        return kBeyond;
+    float pmin = p[0][0];
+#pragma unroll
+    for (int t = 0; t < JN; ++t)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+            pmin = fminf(pmin, p[t][r]);
+    uint32_t base, span;
+    slot_range<LUT8>(lds_read_entry<LUT8>(paddr<LUT8>(__fmaf_rn(-2.0f, pmax, 2.0f), k)),
+                     lds_read_entry<LUT8>(paddr<LUT8>(__fmaf_rn(-2.0f, pmin, 2.0f), k)), base, span);
+    if (one_slot_step(base, span, JN * P, k, cnt))
+        return kOneSlot;
+    if (two_slot_range<LUT8>(base, span)) {
+        // a pair is past edge `base` when p <= plo and not past it when
+        // p >= phi; x = fl(p - phi) has the sign of p - phi unless it is
+        // zero, and |x| > fl(phi - plo) puts p outside (plo, phi) (fl is
+        // monotone), so the sign bit of x counts the pairs in the upper
+        // slot; lanes with one slot compare with -inf (x = +inf, lower slot)
+        const float2 b = s.pband[min(base, (uint32_t)(a.nedges - 1))];
+        const float thr = span ? b.y : -__builtin_huge_valf();
+        const float width = b.y - b.x;
+        uint32_t n_up = 0;
+        float near = __builtin_huge_valf();
+#pragma unroll
+        for (int t = 0; t < JN; ++t)
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const float x = p[t][r] - thr;
+                n_up += __float_as_uint(x) >> 31;
+                near = fminf(near, fabsf(x));
+            }
+        asm volatile("" : "+v"(n_up));
+        if (wave_all(near > width)) {
+            two_slot_add(base, JN * P, n_up, k, cnt);
+            return kTwoSlot;
+        }
+    }
+    return kUndecided;
 }
 
 template <bool LUT8, bool MASKED, int P, int JN, bool M3, bool ONE>
-__device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+__device__ __forceinline__ uint32_t step_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const double (&xi)[P], const double (&yi)[P],
                                           const double (&zi)[P], const int (&ii)[P], int ie,
                                           int j, cdouble_p bx, cdouble_p by, cdouble_p bz,
@@ -751,9 +863,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
             for (int p = 0; p < P; ++p)
                 m = min(m, __double2hiint(e[t][p]));
         if (wave_all(m > (int32_t)k.beyond)) {
-            cnt.beyond += JN * P;
-            ++cnt.beyond_steps;
-            return;
+            return kBeyond;
         }
         if constexpr (ONE) {
             // every pair of the step in one slot (as on the FP32 path)
@@ -767,7 +877,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
             slot_range<LUT8>(lds_read_entry<LUT8>(addr64<LUT8>(m, k)), lds_read_entry<LUT8>(addr64<LUT8>(mx, k)),
                              base, span);
             if (one_slot_step(base, span, JN * P, k, cnt))
-                return;
+                return kOneSlot;
             if (two_slot_range<LUT8>(base, span)) {
                 // past edge `base` when e > E_base, not past it when e < E_base,
                 // and the exact rule decides e == E_base (as in resolve_fp64);
@@ -785,7 +895,7 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
                 asm volatile("" : "+v"(n_up), "+v"(tie));
                 if (!__builtin_amdgcn_ballot_w64(tie != 0)) {
                     two_slot_add(base, JN * P, n_up, k, cnt);
-                    return;
+                    return kTwoSlot;
                 }
             }
         }
@@ -826,41 +936,49 @@ __device__ __forceinline__ void step_fp64(const PairArgs &a, const JobDev &jb, c
             }
             lds_inc(__umul24(v, k.rowstep) + k.lanebase);
         }
+    return kLookup;
 }
 
-// Steps beyond the last edge, screened with the FP32 dot product of the
-// copies (angular catalogs): p = fl32(f_i . f_j), one multiply and two FMAs
-// per pair, and p <= p_beyond on every pair proves the rule's d <= D_last
-// (dot_screen32 on the host derives the margin).  Whole blocks of 4 columns
-// from j on are counted beyond the last edge while every pair of the block
-// passes; returns the first column not counted.
-template <int P>
-__device__ __forceinline__ int screen_run(const JobDev &jb, const Consts &k, const float (&xi)[P],
-                                          const float (&yi)[P], const float (&zi)[P], int j, int j1,
-                                          Counters &cnt) {
+// Steps decided by the dot product alone (dot-product kernels): from column
+// j on, while step_dot settles each step of kColsPerStepF32 columns (beyond
+// the last edge, one slot, two slots).  Returns the first column of the
+// step it could not settle (or of the columns left over), which the chord
+// loop takes next.
+template <bool LUT8, int P>
+__device__ __forceinline__ int dot_run(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
+                                       const float (&xi)[P], const float (&yi)[P], const float (&zi)[P], int j,
+                                       int j1, Counters &cnt) {
     constexpr int W = kColsPerStepF32;
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
     cfloat_p bz = (cfloat_p)jb.bz32;
+    // steps beyond, in one slot, in two slots: 16-bit fields as in
+    // Counters::steps (a column range holds at most kFoldCols / W steps)
+    uint64_t n = 0;
     for (; j + W <= j1; j += W) {
-        float mp = -__builtin_huge_valf();
+        float xj[W], yj[W], zj[W];
 #pragma unroll
         for (int t = 0; t < W; ++t) {
-            const float xj = bx[j + t], yj = by[j + t], zj = bz[j + t];
-#pragma unroll
-            for (int p = 0; p < P; ++p)
-                mp = fmaxf(mp, __fmaf_rn(zi[p], zj, __fmaf_rn(yi[p], yj, xi[p] * xj)));
+            xj[t] = bx[j + t];
+            yj[t] = by[j + t];
+            zj[t] = bz[j + t];
         }
-        if (!wave_all(mp <= k.pbeyond))
+        const uint32_t code = step_dot<LUT8, P, W>(a, s, k, xi, yi, zi, xj, yj, zj, cnt);
+        if (code == kUndecided)
             break;
-        cnt.beyond += W * P;
-        cnt.beyond_steps += W / kColsPerStepF32;
+        n += (uint64_t)1 << (16 * code);
     }
+    cnt.beyond += (uint32_t)(n & 0xFFFF) * (uint32_t)(W * P);
+    cnt.steps += n;
     return j;
 }
 
-// Columns [j0, j1) against the P rows of every lane (FP32 path).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE, bool SCREEN>
+// Columns [j0, j1) against the P rows of every lane (FP32 path).  With DOT
+// (angular kernels with the dot-product table), after an unmasked chord step
+// whose smallest q reached q_dot on every lane (the wavefront works at
+// angles where p decides most steps), the following steps go to dot_run;
+// the chord loop resumes at the first step p leaves undecided.
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE, bool DOT>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
                                           const int (&ii)[P], int ib, int lane, int ie, int j0, int j1,
@@ -870,7 +988,6 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
     cfloat_p bz = (cfloat_p)jb.bz32;
     constexpr int JN = kColsPerStepF32;
     int j = j0;
-    bool screen = false;    // the previous step lay beyond the last edge
     if (j + JN <= j1) {
         // the columns of the next step are read (through the scalar unit)
         // while the current step computes; the last prefetch re-reads the
@@ -893,20 +1010,20 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
-            step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, screen,
-                                                            cnt);
+            uint32_t qmin = 0;
+            account<JN * P>(__builtin_amdgcn_readfirstlane(step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(
+                                a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, qmin, cnt)),
+                            cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
                 yj[t] = yn[t];
                 zj[t] = zn[t];
             }
-            if constexpr (SCREEN && !MASKED && !M3) {
-                if (screen) {
-                    // the step lay beyond the last edge: screen the blocks
-                    // after it with the cheaper dot-product proof; the
-                    // regular steps resume where a block fails it
-                    const int js = screen_run<P>(jb, k, xi, yi, zi, j + JN, j1, cnt);
+            if constexpr (DOT && !MASKED && !M3) {
+                cnt.steps += (uint64_t)1 << 48;     // a step that formed the chord
+                if (wave_all(qmin >= k.qdot)) {
+                    const int js = dot_run<LUT8, P>(a, jb, s, k, xi, yi, zi, j + JN, j1, cnt);
                     if (js != j + JN) {
                         j = js - JN;
                         if (js + JN <= j1) {
@@ -918,21 +1035,23 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
                             }
                         }
                     }
-                    screen = false;
                 }
             }
         }
     }
     for (; j < j1; ++j) {
         const float xj[1] = {bx[j]}, yj[1] = {by[j]}, zj[1] = {bz[j]};
-        step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, screen,
-                                                          cnt);
+        uint32_t qmin = 0;
+        account<P>(__builtin_amdgcn_readfirstlane(step_fp32<LUT8, MASKED, P, 1, DIRECT, M3, false>(
+                       a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, qmin, cnt)),
+                   cnt);
     }
+    cnt.fold();
 }
 
 
 // One wavefront: rows [ib, ie) (at most P * 64) against columns [j0, j1).
-template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3, bool SCREEN>
+template <bool LUT8, bool MASKED, int P, bool DIRECT, bool PRUNE, bool M3, bool DOT>
 __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k, int ib, int ie,
                           int j0, int j1, int lane, Counters &cnt) {
     float xi[P], yi[P], zi[P];
@@ -966,12 +1085,14 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
                     continue;
                 }
             }
-            cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, SCREEN>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, jn, cnt);
+            cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, DOT>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, jn, cnt);
             j = jn;
         }
         return;
     }
-    cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, SCREEN>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j0, j1, cnt);
+    for (int jc = j0; jc < j1; jc += kFoldCols)
+        cols_fp32<LUT8, MASKED, P, DIRECT, M3, true, DOT>(a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, jc,
+                                                          j1 - jc > kFoldCols ? jc + kFoldCols : j1, cnt);
 }
 
 // Columns [j0, j1) against the P rows of every lane (FP64 vector path).
@@ -985,9 +1106,14 @@ __device__ __forceinline__ void cols_fp64(const PairArgs &a, const JobDev &jb, c
     cdouble_p bz = (cdouble_p)jb.bz64;
     int j = j0;
     for (; j + kColsPerStepF64 <= j1; j += kColsPerStepF64)
-        step_fp64<LUT8, MASKED, P, kColsPerStepF64, M3, ONE>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        account<kColsPerStepF64 * P>(__builtin_amdgcn_readfirstlane(step_fp64<LUT8, MASKED, P, kColsPerStepF64, M3, ONE>(
+                                         a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt)),
+                                     cnt);
     for (; j < j1; ++j)
-        step_fp64<LUT8, MASKED, P, 1, M3, false>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt);
+        account<P>(__builtin_amdgcn_readfirstlane(
+                       step_fp64<LUT8, MASKED, P, 1, M3, false>(a, jb, s, k, xi, yi, zi, ii, ie, j, bx, by, bz, cnt)),
+                   cnt);
+    cnt.fold();
 }
 
 template <bool LUT8, bool MASKED, int P, bool PRUNE, bool M3>
@@ -1022,12 +1148,14 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
         }
         return;
     }
-    cols_fp64<LUT8, MASKED, P, M3, true>(a, jb, s, k, xi, yi, zi, ii, ie, j0, j1, cnt);
+    for (int jc = j0; jc < j1; jc += kFoldCols)
+        cols_fp64<LUT8, MASKED, P, M3, true>(a, jb, s, k, xi, yi, zi, ii, ie, jc,
+                                             j1 - jc > kFoldCols ? jc + kFoldCols : j1, cnt);
 }
 
 // PREC: 0 FP32 chord with a clamped table, 3 FP32 chord with a direct byte
-// table, 6 and 7 the same with the dot-product screen of steps beyond the
-// last edge, 1 FP64 vector; 3-D distances: 5 FP32 squared distance with a
+// table, 6 and 7 the same with the dot product tried first (angular), 1 FP64
+// vector; 3-D distances: 5 FP32 squared distance with a
 // clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
 // rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
@@ -1051,10 +1179,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     for (int b = tid; b < lut_bytes; b += kBlock)
         if ((uint32_t)b - aux_lo >= aux_n)
             s.lut[b] = glut[b];
+    if (PREC >= 6) {
+        const int plut_bytes = a.plut_cells * (LUT8 ? 1 : 2);
+        for (int b = tid; b < plut_bytes; b += kBlock)
+            s.lut[a.plut_lds + b] = glut[a.plut_src + b];
+    }
     for (int e = tid; e < a.nedges; e += kBlock) {
         s.D[e] = a.D[e];
         s.E[e] = a.E[e];
         s.qband[e] = make_float2(a.qlo[e], a.qhi[e]);
+        s.pband[e] = PREC >= 6 ? make_float2(a.qlo[a.nedges + e], a.qhi[a.nedges + e]) : make_float2(0.0f, 0.0f);
         s.erad[e] = a.erad ? a.erad[e] : 0.0;
     }
     __syncthreads();
@@ -1070,6 +1204,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     k.flag = to_vgpr(Code<LUT8>::flag);
     k.beyond = to_vgpr(a.beyond_key);
     k.pbeyond = a.p_beyond;
+    k.pshift = to_vgpr((uint32_t)a.plut_shift);
+    k.pclo = to_vgpr((uint32_t)a.plut_lo);
+    k.pchi = to_vgpr((uint32_t)a.plut_hi);
+    k.pbias = to_vgpr(s.plut_addr - (uint32_t)a.plut_lo * (LUT8 ? 1u : 2u));
+    k.qdot = __float_as_uint(a.q_dot);
     k.lanebase = s.hist_addr +
                  (uint32_t)((wave * (a.nslots + 1) * a.hist_copies + (lane & (a.hist_copies - 1))) * 4);
     Counters cnt;
@@ -1094,7 +1233,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         const int ib = un.i0 + part * kRowsPerWave;
         if (ib < un.i1) {
             // a cancelled job skips its remaining units (the flag lives in host memory)
-            if (jb.cancel && __hip_atomic_load(jb.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+            if (jb.cancel && __builtin_amdgcn_readfirstlane(
+                                 __hip_atomic_load(jb.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
                 ++n_skip;
                 continue;
             }
@@ -1104,13 +1244,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             if (PREC == 0 || PREC == 3 || PREC == 5 || PREC == 6 || PREC == 7) {
                 constexpr bool M3 = PREC == 5;
                 constexpr bool DIRECT = PREC == 3 || PREC == 7;
-                constexpr bool SCREEN = PREC >= 6;
+                constexpr bool DOT = PREC >= 6;
                 if (masked)
-                    rows_fp32<LUT8, true, P, DIRECT, PRUNE, M3, SCREEN>(a, jb, s, k, ib, ie, un.j0, un.j1, lane,
-                                                                          cnt);
+                    rows_fp32<LUT8, true, P, DIRECT, PRUNE, M3, DOT>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
-                    rows_fp32<LUT8, false, P, DIRECT, PRUNE, M3, SCREEN>(a, jb, s, k, ib, ie, un.j0, un.j1, lane,
-                                                                           cnt);
+                    rows_fp32<LUT8, false, P, DIRECT, PRUNE, M3, DOT>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
             } else {
                 constexpr bool M3 = PREC == 4;
                 if (masked)
@@ -1155,6 +1293,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             atomicAdd(&a.stats[0], (unsigned long long)cnt.two_slot_steps);
         if (cnt.pruned_blocks)
             atomicAdd(&a.stats[7], (unsigned long long)cnt.pruned_blocks * (unsigned long long)(kRowsPerWave * 64));
+        if (cnt.chord_steps)
+            atomicAdd(&a.stats[8], (unsigned long long)cnt.chord_steps);
     }
 }
 
@@ -1290,8 +1430,10 @@ void launch_pairs(int P, bool prune, int grid, int lds, hipStream_t st, const Pa
 extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stream) {
     if (args->n_units <= 0)
         return 0;
-    const int lds = lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->lut_entry_bytes,
-                              args->nedges, args->lut_direct ? args->aux_off : -1);
+    const int lds = args->plut_cells > 0 && precision == 0 && args->metric == 0
+                        ? args->plut_lds + args->plut_cells * args->lut_entry_bytes
+                        : lds_bytes(args->nslots, args->hist_copies, args->lut_cells, args->lut_entry_bytes,
+                                    args->nedges, args->lut_direct ? args->aux_off : -1);
     const int grid = grid_for(args->n_units, lds, args->blocks_per_cu);
     hipStream_t st = (hipStream_t)stream;
     const bool b8 = args->lut_entry_bytes == 1;
@@ -1312,7 +1454,7 @@ extern "C" int tpcf_launch_pairs(const PairArgs *args, int precision, void *stre
             return (int)hipErrorInvalidValue;
         return (int)hipGetLastError();
     }
-    if (precision == 0 && args->screen) {
+    if (precision == 0 && args->plut_cells > 0) {
         if (b8 && args->lut_direct)
             launch_pairs<7, true>(P, prune, grid, lds, st, *args);
         else if (b8)

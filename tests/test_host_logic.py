@@ -294,6 +294,89 @@ def test_dot_screen_never_screens_a_pair_before_the_last_edge(edges, delta):
         assert np.all((_p32(a, b, True) <= np.float32(p_beyond))[far])
 
 
+def _slot_range(code):
+    """[lo, hi] of cell codes (0xFFFF: several undecided edges -> None)."""
+    c = code.astype(np.int64)
+    flag = (c & 0x8000) != 0
+    lo = np.where(flag, c & 0x7FFF, c)
+    return lo, np.where(flag, lo + 1, lo), c == 0xFFFF
+
+
+@pytest.mark.parametrize("delta", [4.5e-16, 2.0 ** -21])
+@pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
+                                   synthcat.log_edges(0.001, 20.0, 30),
+                                   synthcat.log_edges(0.01, 120.0, 12),
+                                   np.array([0.0, 1.0, 179.0])])
+def test_dot_path_decides_like_the_rule(edges, delta):
+    """The angular FP32 kernels' dot-product path.  For p = fl32(f_i . f_j)
+    (separate or fused roundings) and the key q' = fl32(2 - 2p) (negative read
+    as +0): the cell of q' bounds the rule's slot; q' >= khi_k and q' < klo_k
+    decide edge k as the rule does; p <= plo_k and p >= phi_k too; and the
+    two-slot decision (x = fl(p - phi_k) with |x| > fl(phi_k - plo_k), the
+    sign bit meaning past the edge) gives the rule's slot.  Pairs at
+    theta = e_k (1 +- 10^-s), s = 2..9, and spread between the edges, with
+    norms perturbed by up to delta; most pairs away from the edges are
+    decided (the path is not vacuous)."""
+    g = np.random.default_rng(31)
+    t = tp.compile_dot(edges, delta_max=delta)
+    er = edges * DEG
+    thetas, ks, near = [], [], []
+    for k, e in enumerate(er):
+        for s_ in range(2, 10):
+            for sgn in (-1.0, 1.0):
+                thetas.append(np.full(30, e * (1.0 + sgn * 10.0 ** -s_)))
+                ks.append(np.full(30, k))
+                near.append(np.full(30, s_ >= 4))
+        lo = er[k - 1] if k else 0.5 * e
+        hi = er[k + 1] if k + 1 < er.size else min(1.5 * e + 1e-3, math.pi)
+        thetas.append(g.uniform(lo, hi, 300))
+        ks.append(np.full(300, k))
+        near.append(np.zeros(300, bool))
+    theta = np.clip(np.concatenate(thetas), 0.0, math.pi)
+    k = np.concatenate(ks)
+    near = np.concatenate(near)
+    a, b = _pairs_at(g, theta)
+    a *= np.sqrt(1.0 + g.uniform(-delta, delta, size=theta.size))[:, None]
+    b *= np.sqrt(1.0 + g.uniform(-delta, delta, size=theta.size))[:, None]
+    truth = oracle.pair_slots(a.T, b.T, edges)
+    klo, khi = t["klo"][k], t["khi"][k]
+    plo, phi = t["plo"][k], t["phi"][k]
+    past = truth >= k + 1
+    for fused in (False, True):
+        p = _p32(a, b, fused)
+        qd = np.float32(2.0 - 2.0 * p.astype(np.float64))     # one rounding of the exact 2 - 2p
+        qd = np.where(qd.view(np.int32) < 0, np.float32(0.0), qd).astype(np.float32)
+        key = (qd.view(np.uint32) >> np.uint32(t["shift"])).astype(np.int64)
+        lo_s, hi_s, multi = _slot_range(t["cells"][np.clip(key, t["lo"], t["hi"]) - t["lo"]])
+        assert np.all(((truth >= lo_s) & (truth <= hi_s)) | multi), fused
+        assert np.all(past[qd >= khi]) and not np.any(past[qd < klo]), fused
+        assert np.all(past[p <= plo]) and not np.any(past[p >= phi]), fused
+        with np.errstate(invalid="ignore"):
+            x = (p - phi).astype(np.float32)
+            w = (phi - plo).astype(np.float32)
+            decided = np.abs(x) > w
+        two = (truth == k) | (truth == k + 1)
+        got = np.where(x < 0, k + 1, k)
+        assert np.array_equal(got[decided & two], truth[decided & two]), fused
+        if 0.0 < edges[-1] < 179.0 and delta < 1e-10:
+            far = ~near & (edges[k] >= 1.0)
+            assert np.mean(decided[far]) > 0.9, fused
+            assert np.mean(~multi[far]) > 0.9, fused
+
+
+def test_dot_cell_slot_ranges_never_decrease():
+    """The dot-product key's cells: both ends of the slot range are
+    non-decreasing along the table (q' grows with the angle), as the
+    one- and two-slot steps need."""
+    t = tp.compile_dot(synthcat.log_edges(0.0005, 30.0, 40), delta_max=4.5e-16)
+    lo, hi, multi = _slot_range(t["cells"])
+    keep = ~multi
+    assert np.all(np.diff(lo[keep]) >= 0) and np.all(np.diff(hi[keep]) >= 0)
+    assert np.all(hi - lo <= 1)
+    # the table reaches from the small angles (multi) to beyond the last edge
+    assert multi[0] and lo[-1] == 41
+
+
 def _emulate(a, b, edges, precision, delta, direct=None):
     """Numpy transcription of the kernels' per-pair classification."""
     D, qlo, qhi = tp.compile_edges(edges, delta_max=delta)
