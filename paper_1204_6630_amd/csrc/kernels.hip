@@ -109,6 +109,30 @@ __device__ __forceinline__ bool wave_all(bool pred) {
     return __builtin_amdgcn_ballot_w64(pred) == ~0ull;
 }
 
+// Balanced reductions of the JN x P values of a step (depth ~log3 instead
+// of a chain of JN * P dependent instructions).
+template <typename T, typename F, int N>
+__device__ __forceinline__ T tree_reduce(const T (&v)[N], F f) {
+    if constexpr (N == 1) {
+        return v[0];
+    } else if constexpr (N == 2) {
+        return f(v[0], v[1]);
+    } else {
+        constexpr int M = (N + 2) / 3;
+        T w[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            T x = v[3 * i];
+            if (3 * i + 1 < N)
+                x = f(x, v[3 * i + 1]);
+            if (3 * i + 2 < N)
+                x = f(x, v[3 * i + 2]);
+            w[i] = x;
+        }
+        return tree_reduce<T, F, M>(w, f);
+    }
+}
+
 __device__ __forceinline__ void lds_inc(uint32_t addr) {
     __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -649,12 +673,13 @@ __device__ __forceinline__ uint32_t step_fp32(const PairArgs &a, const JobDev &j
     if (!MASKED) {
         // every pair of the step certainly beyond the last edge (q >= 0, so the
         // bit patterns order like the values): count them in a register
-        uint32_t m = __float_as_uint(q[0][0]);
+        uint32_t qb[JN * P];
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                m = min(m, __float_as_uint(q[t][p]));
+                qb[t * P + p] = __float_as_uint(q[t][p]);
+        const uint32_t m = tree_reduce(qb, [](uint32_t x, uint32_t y) { return min(x, y); });
         qmin = m;
         if (wave_all(m >= k.beyond))
             return kBeyond;
@@ -665,12 +690,7 @@ __device__ __forceinline__ uint32_t step_fp32(const PairArgs &a, const JobDev &j
             // at angles large against their extent this is common; with pruning
             // such blocks are mostly pruned, and the kernel skips the test to
             // save its registers)
-            uint32_t mx = __float_as_uint(q[0][0]);
-#pragma unroll
-            for (int t = 0; t < JN; ++t)
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-                    mx = max(mx, __float_as_uint(q[t][p]));
+            const uint32_t mx = tree_reduce(qb, [](uint32_t x, uint32_t y) { return max(x, y); });
             uint32_t base, span;
             slot_range<LUT8>(lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(m, k)),
                              lds_read_entry<LUT8>(addr32<LUT8, DIRECT>(mx, k)), base, span);
@@ -780,20 +800,16 @@ __device__ __forceinline__ uint32_t step_dot(const PairArgs &a, const Smem &s, c
 #pragma unroll
         for (int r = 0; r < P; ++r)
             p[t][r] = __fmaf_rn(zi[r], zj[t], __fmaf_rn(yi[r], yj[t], xi[r] * xj[t]));
-    float pmax = p[0][0];
+    float pf[JN * P];
 #pragma unroll
     for (int t = 0; t < JN; ++t)
 #pragma unroll
         for (int r = 0; r < P; ++r)
-            pmax = fmaxf(pmax, p[t][r]);
+            pf[t * P + r] = p[t][r];
+    const float pmax = tree_reduce(pf, [](float x, float y) { return fmaxf(x, y); });
     if (wave_all(pmax <= k.pbeyond))
         return kBeyond;
-    float pmin = p[0][0];
-#pragma unroll
-    for (int t = 0; t < JN; ++t)
-#pragma unroll
-        for (int r = 0; r < P; ++r)
-            pmin = fminf(pmin, p[t][r]);
+    const float pmin = tree_reduce(pf, [](float x, float y) { return fminf(x, y); });
     uint32_t base, span;
     slot_range<LUT8>(lds_read_entry<LUT8>(paddr<LUT8>(__fmaf_rn(-2.0f, pmax, 2.0f), k)),
                      lds_read_entry<LUT8>(paddr<LUT8>(__fmaf_rn(-2.0f, pmin, 2.0f), k)), base, span);
@@ -948,25 +964,52 @@ template <bool LUT8, int P>
 __device__ __forceinline__ int dot_run(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                        const float (&xi)[P], const float (&yi)[P], const float (&zi)[P], int j,
                                        int j1, Counters &cnt) {
+    // Two steps per iteration with two sets of column registers: the reads
+    // of the next step's columns are issued before the current step
+    // computes.  They are volatile so that the compiler keeps them there
+    // rather than moving them below the step to the only place their values
+    // are used (the explicit wait at each step's top covers them; the
+    // catalogs do not change during a launch).  Only 4-byte alignment is
+    // assumed, which is all scalar loads need.
     constexpr int W = kColsPerStepF32;
+    typedef float f4 __attribute__((ext_vector_type(4), aligned(4)));
+    typedef const volatile __attribute__((address_space(4))) f4 *vf4_p;
     cfloat_p bx = (cfloat_p)jb.bx32;
     cfloat_p by = (cfloat_p)jb.by32;
     cfloat_p bz = (cfloat_p)jb.bz32;
-    // steps beyond, in one slot, in two slots: 16-bit fields as in
-    // Counters::steps (a column range holds at most kFoldCols / W steps)
     uint64_t n = 0;
-    for (; j + W <= j1; j += W) {
-        float xj[W], yj[W], zj[W];
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-            xj[t] = bx[j + t];
-            yj[t] = by[j + t];
-            zj[t] = bz[j + t];
-        }
+    if (j + W > j1)
+        return j;
+    f4 cx = *(vf4_p)(bx + j), cy = *(vf4_p)(by + j), cz = *(vf4_p)(bz + j);
+    for (;;) {
+        __builtin_amdgcn_s_waitcnt(0x0070);
+        const int jn = j + 2 * W <= j1 ? j + W : j;
+        const f4 nx = *(vf4_p)(bx + jn), ny = *(vf4_p)(by + jn), nz = *(vf4_p)(bz + jn);
+        __builtin_amdgcn_sched_barrier(0);
+        const float xj[W] = {cx[0], cx[1], cx[2], cx[3]}, yj[W] = {cy[0], cy[1], cy[2], cy[3]},
+                    zj[W] = {cz[0], cz[1], cz[2], cz[3]};
         const uint32_t code = step_dot<LUT8, P, W>(a, s, k, xi, yi, zi, xj, yj, zj, cnt);
         if (code == kUndecided)
             break;
         n += (uint64_t)1 << (16 * code);
+        j += W;
+        if (j + W > j1)
+            break;
+        __builtin_amdgcn_s_waitcnt(0x0070);
+        const int jm = j + 2 * W <= j1 ? j + W : j;
+        cx = *(vf4_p)(bx + jm);
+        cy = *(vf4_p)(by + jm);
+        cz = *(vf4_p)(bz + jm);
+        __builtin_amdgcn_sched_barrier(0);
+        const float x2[W] = {nx[0], nx[1], nx[2], nx[3]}, y2[W] = {ny[0], ny[1], ny[2], ny[3]},
+                    z2[W] = {nz[0], nz[1], nz[2], nz[3]};
+        const uint32_t c2 = step_dot<LUT8, P, W>(a, s, k, xi, yi, zi, x2, y2, z2, cnt);
+        if (c2 == kUndecided)
+            break;
+        n += (uint64_t)1 << (16 * c2);
+        j += W;
+        if (j + W > j1)
+            break;
     }
     cnt.beyond += (uint32_t)(n & 0xFFFF) * (uint32_t)(W * P);
     cnt.steps += n;
