@@ -1287,7 +1287,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             if (PREC == 0 || PREC == 3 || PREC == 5 || PREC == 6 || PREC == 7) {
                 constexpr bool M3 = PREC == 5;
                 constexpr bool DIRECT = PREC == 3 || PREC == 7;
-                constexpr bool DOT = PREC >= 6;
+                // with pruning, the blocks left to evaluate lie across edges,
+                // where the dot product rarely settles a step: chord only
+                constexpr bool DOT = PREC >= 6 && !PRUNE;
                 if (masked)
                     rows_fp32<LUT8, true, P, DIRECT, PRUNE, M3, DOT>(a, jb, s, k, ib, ie, un.j0, un.j1, lane, cnt);
                 else
