@@ -306,6 +306,38 @@ def test_timing_and_stats(ctx, patch):
     assert (beyond + one_slot + two_slot + rare) * 512 <= pairs
 
 
+def test_dot_product_path_settles_large_angle_steps(ctx, patch):
+    """FP32 angular launches decide most steps of the 30 x 30 deg patch (edges
+    up to 10 deg) from the dot product alone; the steps that formed the chord
+    are counted apart; every count equals the oracle's.  A dense 0.3 x 0.3 deg
+    patch binned to 0.1 deg keeps its steps on the chord (small angles, where
+    the dot product cannot resolve the bins), with the same counts as the
+    oracle."""
+    wl, cd, cr, ref = patch
+    steps = lambda st: st.pairs / 1024.0     # 4 rows x 4 columns per lane
+    ctx.stats(reset=True)
+    assert np.array_equal(ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP32_CHORD), ref["DR"])
+    st = ctx.stats(reset=True)
+    assert st.beyond_steps > 0 and st.two_slot_steps > 0
+    assert 0 < st.chord_steps < 0.5 * steps(st)
+    # FP64 launches never take it
+    assert np.array_equal(ctx.count(tp.DR, cd, wl.edges_deg, cat_b=cr, precision=tp.FP64), ref["DR"])
+    assert ctx.stats(reset=True).chord_steps == 0
+    g = synthcat.rng_for(97, 1)
+    box = (10.0, 10.3, 20.0, 20.3)
+    d, r = synthcat.uniform_patch(20_000, box, g), synthcat.uniform_patch(20_000, box, g)
+    e = synthcat.log_edges(0.001, 0.1, 12)
+    dr_ref = oracle.count(oracle.DR, oracle.radec_to_xyz(*d), e, oracle.radec_to_xyz(*r))
+    a, b = ctx.upload_catalog(*d), ctx.upload_catalog(*r)
+    try:
+        assert np.array_equal(ctx.count(tp.DR, a, e, cat_b=b, precision=tp.FP32_CHORD), dr_ref)
+        st = ctx.stats(reset=True)
+        assert st.chord_steps > 0.9 * steps(st)
+    finally:
+        ctx.release_catalog(a)
+        ctx.release_catalog(b)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_pruning_keeps_counts_exact(ctx, patch, prec):
     """Exact tile pruning on the 30 x 30 deg patch: the same counts as the oracle, with
