@@ -1048,9 +1048,11 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
             const int base = lds_bytes(nbins + 2, hist_copies_of(ctx->tune, nbins + 2), a.lut_cells, cp.entry_bytes,
                                        nbins + 1, cp.cells.direct ? cp.cells.aux_off : -1);
             a.plut_lds = (base + 15) & ~15;
-            // steps are tried with the dot product first where its error is
-            // below 1 % of the chord^2 (about 0.6 deg); a heuristic only
-            a.q_dot = (float)(400.0 * dot_error32(cp.delta));
+            // the chord loop hands steps to the dot product at chord^2 above
+            // 0.018 (about 7.7 deg), where p's error is ~2e-5 of q and a
+            // lane's pairs seldom span several bins: a heuristic, measured
+            // best on the octant workloads (0.6 to 25 deg tried)
+            a.q_dot = std::max(0.018f, (float)(400.0 * dot_error32(cp.delta)));
         }
     } else {
         const double t = cp.edges.E[last];

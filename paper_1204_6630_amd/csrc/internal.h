@@ -113,8 +113,9 @@ struct PairArgs {
     // the key q' = fl(2 - 2p) (cell = clamp(bits(q') >> plut_shift, plut_lo,
     // plut_hi), plut_cells entries at byte plut_src of lut, copied to LDS byte
     // plut_lds), and the band in p, nedges (plo, phi) pairs after the chord
-    // band in qlo / qhi.  Steps are tried with p first while the previous
-    // chord step's smallest q was at least q_dot.
+    // band in qlo / qhi.  The chord loop hands the steps after a chord step
+    // that needed no lookup and whose smallest q was at least q_dot to the
+    // dot product.
     int32_t plut_cells;
     int32_t plut_shift, plut_lo, plut_hi;
     int32_t plut_src, plut_lds;

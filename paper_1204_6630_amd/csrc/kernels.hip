@@ -1018,9 +1018,10 @@ __device__ __forceinline__ int dot_run(const PairArgs &a, const JobDev &jb, cons
 
 // Columns [j0, j1) against the P rows of every lane (FP32 path).  With DOT
 // (angular kernels with the dot-product table), after an unmasked chord step
-// whose smallest q reached q_dot on every lane (the wavefront works at
-// angles where p decides most steps), the following steps go to dot_run;
-// the chord loop resumes at the first step p leaves undecided.
+// that needed no per-pair lookup and whose smallest q reached q_dot on every
+// lane (the wavefront works at angles where p decides most steps), the
+// following steps go to dot_run; the chord loop resumes at the first step p
+// leaves undecided.
 template <bool LUT8, bool MASKED, int P, bool DIRECT, bool M3, bool ONE, bool DOT>
 __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, const Consts &k,
                                           const float (&xi)[P], const float (&yi)[P], const float (&zi)[P],
@@ -1054,9 +1055,9 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             // keep the prefetch at the top of the step
             __builtin_amdgcn_sched_barrier(0);
             uint32_t qmin = 0;
-            account<JN * P>(__builtin_amdgcn_readfirstlane(step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(
-                                a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, qmin, cnt)),
-                            cnt);
+            const uint32_t code = __builtin_amdgcn_readfirstlane(step_fp32<LUT8, MASKED, P, JN, DIRECT, M3, ONE>(
+                a, jb, s, k, xi, yi, zi, ii, ib, lane, ie, j, xj, yj, zj, qmin, cnt));
+            account<JN * P>(code, cnt);
 #pragma unroll
             for (int t = 0; t < JN; ++t) {
                 xj[t] = xn[t];
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void cols_fp32(const PairArgs &a, const JobDev &jb, c
             }
             if constexpr (DOT && !MASKED && !M3) {
                 cnt.steps += (uint64_t)1 << 48;     // a step that formed the chord
-                if (wave_all(qmin >= k.qdot)) {
+                if (code != kLookup && wave_all(qmin >= k.qdot)) {
                     const int js = dot_run<LUT8, P>(a, jb, s, k, xi, yi, zi, j + JN, j1, cnt);
                     if (js != j + JN) {
                         j = js - JN;
