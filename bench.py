@@ -43,11 +43,17 @@ TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_octant_1e6x2e6.txt")
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources with comments and layout removed, so that
+    an edit of a comment does not orphan counters taken on the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(HERE, "paper_1204_6630_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "paper_1204_6630_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

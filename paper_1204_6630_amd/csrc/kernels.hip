@@ -788,8 +788,8 @@ __device__ __forceinline__ uint32_t paddr(float qd, const Consts &k) {
 // or in two adjacent slots with every pair outside the band in p of the edge
 // between them.  The slot range of a lane comes from the cells of the key
 // q' = fl(2 - 2p) of its largest and smallest p (q' does not increase with
-// p).  Returns false, having counted nothing, when p does not decide the
-// step; the caller then forms the chord.
+// p).  Returns the step's code, or kUndecided, having counted nothing, when
+// p does not decide the step; the caller then forms the chord.
 template <bool LUT8, int P, int JN>
 __device__ __forceinline__ uint32_t step_dot(const PairArgs &a, const Smem &s, const Consts &k, const float (&xi)[P],
                                          const float (&yi)[P], const float (&zi)[P], const float (&xj)[JN],
