@@ -555,14 +555,16 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
     c->metric = metric;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    // angular FP32: the dot-product table takes kDotLutBytes of LDS, and by
-    // default the chord table leaves room for it within kLdsTarget
+    // angular FP32: the dot-product table takes kDotLutBytes of LDS and the
+    // column staging kStageBytes, and by default the chord table leaves room
+    // for both within kLdsTarget
     const bool dot = !metric && precision == TPCF_FP32_CHORD;
     const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
     const int pbytes = dot ? kDotLutBytes : 0;
+    const int extra = dot ? pbytes + kStageBytes + 32 : 0;
     int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
     if (dot && !tune.lut_bytes)
-        table_bytes = std::min(table_bytes, std::max(4096, (kLdsTarget - aux - pbytes - 16) & ~15));
+        table_bytes = std::min(table_bytes, std::max(4096, (kLdsTarget - aux - extra) & ~15));
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     qlo->assign(c->edges.D.size(), 0.0f);
     qhi->assign(c->edges.D.size(), 0.0f);
@@ -578,7 +580,7 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
         c->band = make_band32(c->edges, delta);
         if (c->entry_bytes == 1 && tune.lut_direct) {
             Band32 fb = make_band32(c->edges, delta, floor_for(c->band));
-            const int wrap_bytes = tune.lut_bytes ? tune.lut_bytes : kWrapLutBytes - pbytes - 16;
+            const int wrap_bytes = tune.lut_bytes ? tune.lut_bytes : kWrapLutBytes - extra;
             c->cells = make_cells32_wrap(c->edges, fb, delta, wrap_bytes, aux);
             if (!c->cells.cells.empty())
                 c->band = fb;
@@ -1048,6 +1050,7 @@ PairArgs args_of(const tpcf_ctx *ctx, const Compiled &cp, int nbins, unsigned lo
             const int base = lds_bytes(nbins + 2, hist_copies_of(ctx->tune, nbins + 2), a.lut_cells, cp.entry_bytes,
                                        nbins + 1, cp.cells.direct ? cp.cells.aux_off : -1);
             a.plut_lds = (base + 15) & ~15;
+            a.stage_lds = (a.plut_lds + a.plut_cells * cp.entry_bytes + 15) & ~15;
             // the chord loop hands steps to the dot product at chord^2 above
             // 0.018 (about 7.7 deg), where p's error is ~2e-5 of q and a
             // lane's pairs seldom span several bins: a heuristic, measured

@@ -25,6 +25,10 @@ constexpr int kWrapLutBytes = 32768;
 // kLdsTarget (five blocks of four wavefronts in a CU's 160 KiB).
 constexpr int kDotLutBytes = 1024;
 constexpr int kLdsTarget = 32768;
+// Dot-product kernels: each wavefront stages kStageCols columns at a time in
+// LDS, in two buffers of x, y and z floats.
+constexpr int kStageCols = 64;
+constexpr int kStageBytes = kWaves * 2 * kStageCols * 12;
 // Work statistics words of a launch (see PairArgs::stats).
 constexpr int kStats = 9;
 // Histogram copies in global memory (u64), indexed by work unit.
@@ -119,6 +123,7 @@ struct PairArgs {
     int32_t plut_cells;
     int32_t plut_shift, plut_lo, plut_hi;
     int32_t plut_src, plut_lds;
+    int32_t stage_lds;           // LDS byte offset of the column staging buffers (kStageBytes)
     float q_dot;
 
     // Exact tile pruning: 1 = a wavefront bins a whole aligned 64-column
