@@ -700,29 +700,35 @@ __device__ __forceinline__ uint32_t step_fp32(const PairArgs &a, const JobDev &j
                 return kOneSlot;
             if (two_slot_range<LUT8>(base, span)) {
                 // a pair is past edge `base` when q >= qhi and not past it when
-                // q < qlo; x = fl(q - qhi) has the sign of q - qhi unless it is
-                // zero, and |x| > fl(qhi - qlo) puts q outside [qlo, qhi)
-                // (fl is monotone), so the sign of x decides every such pair;
-                // lanes with one slot compare with +inf (x = -inf)
-                // (a decided pair's x is nonzero, so its sign bit counts the
-                // pairs below the threshold: no compare-and-carry, whose
-                // mask hazard costs wait states on gfx950)
+                // q < qlo.  x = fl(q - qhi) is >= 0 exactly when q >= qhi
+                // (a difference of floats rounds to zero only when they are
+                // equal, and then to +0), and x < 0 with |x| > w = fl(qhi - qlo)
+                // puts q below qlo (fl is monotone): these pairs are decided,
+                // the sign bit of x marking those not past.  As int32 bit
+                // patterns, exactly the decided x lie above that of -w (a
+                // negative float's pattern grows with its magnitude), so one
+                // signed minimum checks every pair.  Lanes with one slot
+                // compare with +inf (x = -inf) and decide everything; a NaN
+                // width (an edge at 0) decides nothing.  (The sign bit counts
+                // the pairs: no compare-and-carry, whose mask hazard costs
+                // wait states on gfx950.)
                 const float2 b = s.qband[min(base, (uint32_t)(a.nedges - 1))];
                 const float thr = span ? b.y : __builtin_huge_valf();
-                const float width = b.y - b.x;
+                const float nw = -(b.y - b.x);
+                const int32_t lim = !span ? INT32_MIN : nw == nw ? (int32_t)__float_as_uint(nw) : INT32_MAX;
                 uint32_t n_below = 0;
-                float near = __builtin_huge_valf();
+                int32_t m = INT32_MAX;
 #pragma unroll
                 for (int t = 0; t < JN; ++t)
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const float x = q[t][p] - thr;
                         n_below += __float_as_uint(x) >> 31;
-                        near = fminf(near, fabsf(x));
+                        m = min(m, (int32_t)__float_as_uint(x));
                     }
                 // count before the test, so the differences die here
                 asm volatile("" : "+v"(n_below));
-                if (wave_all(near > width)) {
+                if (wave_all(m > lim)) {
                     two_slot_add(base, JN * P, JN * P - n_below, k, cnt);
                     return kTwoSlot;
                 }
@@ -819,25 +825,28 @@ __device__ __forceinline__ uint32_t step_dot(const PairArgs &a, const Smem &s, c
         return kOneSlot;
     if (two_slot_range<LUT8>(base, span)) {
         // a pair is past edge `base` when p <= plo and not past it when
-        // p >= phi; x = fl(p - phi) has the sign of p - phi unless it is
-        // zero, and |x| > fl(phi - plo) puts p outside (plo, phi) (fl is
-        // monotone), so the sign bit of x counts the pairs in the upper
-        // slot; lanes with one slot compare with -inf (x = +inf, lower slot)
+        // p >= phi.  x = fl(p - phi) is >= 0 exactly when p >= phi, and x < 0
+        // with |x| > w = fl(phi - plo) puts p below plo: these pairs are
+        // decided, the sign bit of x counting those in the upper slot, and
+        // as int32 bit patterns exactly they lie above that of -w (as on the
+        // chord path).  Lanes with one slot compare with -inf (x = +inf,
+        // lower slot) and decide everything; a NaN width decides nothing.
         const float2 b = s.pband[min(base, (uint32_t)(a.nedges - 1))];
         const float thr = span ? b.y : -__builtin_huge_valf();
-        const float width = b.y - b.x;
+        const float nw = -(b.y - b.x);
+        const int32_t lim = !span ? INT32_MIN : nw == nw ? (int32_t)__float_as_uint(nw) : INT32_MAX;
         uint32_t n_up = 0;
-        float near = __builtin_huge_valf();
+        int32_t m = INT32_MAX;
 #pragma unroll
         for (int t = 0; t < JN; ++t)
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 const float x = p[t][r] - thr;
                 n_up += __float_as_uint(x) >> 31;
-                near = fminf(near, fabsf(x));
+                m = min(m, (int32_t)__float_as_uint(x));
             }
         asm volatile("" : "+v"(n_up));
-        if (wave_all(near > width)) {
+        if (wave_all(m > lim)) {
             two_slot_add(base, JN * P, n_up, k, cnt);
             return kTwoSlot;
         }

@@ -188,13 +188,31 @@ def test_fp32_band_adversary(edges, floored):
     assert np.all(in_band[rel < 0.1 * half])
 
 
+def _two_slot_decided(x, w):
+    """The kernels' two-slot test, on the int32 bit patterns as they make
+    it: a lane decides its pairs when every x lies above the pattern of
+    -w (x >= 0 or x < -w), nothing for a NaN width.  Checked against the
+    float form of the same condition."""
+    x = np.asarray(x, np.float32)
+    w = np.asarray(w, np.float32)
+    nw = -w
+    lim = np.where(np.isnan(nw), np.int32(np.iinfo(np.int32).max), nw.view(np.int32))
+    dec = x.view(np.int32) > lim
+    with np.errstate(invalid="ignore"):
+        ref = ~np.isnan(w) & ((x >= 0) | (-x > w))
+    assert np.array_equal(dec, ref)
+    return dec
+
+
 @pytest.mark.parametrize("edges", [synthcat.log_edges(0.0005, 30.0, 40),
                                    synthcat.log_edges(0.001, 20.0, 30),
                                    np.array([0.0, 1.0, 90.0, 180.0])])
 def test_two_slot_decision_matches_the_band(edges):
     """The kernels' two-slot steps: for a pair whose slot is k or k+1, the
-    FP32 difference x = fl(q - qhi_k) decides it when |x| > fl(qhi_k - qlo_k),
-    and then the sign of x gives the slot the FP64 rule gives.  Pairs at
+    FP32 difference x = fl(q - qhi_k) decides it when x >= 0 or
+    -x > fl(qhi_k - qlo_k) (the kernels test both at once on the int32 bit
+    patterns: x above -fl(qhi_k - qlo_k)), and then the sign of x gives the
+    slot the FP64 rule gives.  Pairs at
     theta = e_k (1 +- 10^-s), s = 2..9, and spread between the neighbouring
     edges; band pairs are never decided, and most pairs are."""
     g = np.random.default_rng(11)
@@ -222,7 +240,7 @@ def test_two_slot_decision_matches_the_band(edges):
         # kernel, no pair is decided by the comparison (the lookup settles it)
         width = qhi.astype(np.float32)[k] - qlo.astype(np.float32)[k]
         x = q - thr                                 # FP32, round to nearest
-        decided = np.abs(x) > width
+        decided = _two_slot_decided(x, width)
     slot = k + (x >= 0).astype(np.int64)
     assert np.array_equal(slot[ours & decided], truth[ours & decided])
     in_band = (q >= qlo[k]) & (q < qhi[k])
@@ -312,8 +330,8 @@ def test_dot_path_decides_like_the_rule(edges, delta):
     (separate or fused roundings) and the key q' = fl32(2 - 2p) (negative read
     as +0): the cell of q' bounds the rule's slot; q' >= khi_k and q' < klo_k
     decide edge k as the rule does; p <= plo_k and p >= phi_k too; and the
-    two-slot decision (x = fl(p - phi_k) with |x| > fl(phi_k - plo_k), the
-    sign bit meaning past the edge) gives the rule's slot.  Pairs at
+    two-slot decision (x = fl(p - phi_k) with x >= 0 or -x > fl(phi_k -
+    plo_k), the sign bit meaning past the edge) gives the rule's slot.  Pairs at
     theta = e_k (1 +- 10^-s), s = 2..9, and spread between the edges, with
     norms perturbed by up to delta; most pairs away from the edges are
     decided (the path is not vacuous)."""
@@ -354,7 +372,7 @@ def test_dot_path_decides_like_the_rule(edges, delta):
         with np.errstate(invalid="ignore"):
             x = (p - phi).astype(np.float32)
             w = (phi - plo).astype(np.float32)
-            decided = np.abs(x) > w
+            decided = _two_slot_decided(x, w)
         two = (truth == k) | (truth == k + 1)
         got = np.where(x < 0, k + 1, k)
         assert np.array_equal(got[decided & two], truth[decided & two]), fused
