@@ -504,6 +504,7 @@ std::string edges_key(const double *edges, int nbins, int precision, double delt
     k.append((const char *)&t.lut_bytes, sizeof t.lut_bytes);
     k.append((const char *)&t.lut_direct, sizeof t.lut_direct);
     k.append((const char *)&t.hist_copies, sizeof t.hist_copies);   // sizes a wrapped table's free piece
+    k.append((const char *)&t.prune, sizeof t.prune);               // pruned: no dot-product tables
     return k;
 }
 
@@ -555,15 +556,18 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
     c->metric = metric;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    // angular FP32: the dot-product table takes kDotLutBytes of LDS and the
-    // column staging kStageBytes, and by default the chord table leaves room
-    // for both within kLdsTarget
-    const bool dot = !metric && precision == TPCF_FP32_CHORD;
+    // angular FP32: by default the chord table fits kLdsTarget with the
+    // histograms and edges and, with the dot-product path, its table
+    // (kDotLutBytes) and the column staging (kStageBytes).  Pruned kernels
+    // take the chord path alone (the blocks they evaluate lie across edges)
+    // and give the chord table the room.
+    const bool angular32 = !metric && precision == TPCF_FP32_CHORD;
+    const bool dot = angular32 && !tune.prune;
     const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
     const int pbytes = dot ? kDotLutBytes : 0;
     const int extra = dot ? pbytes + kStageBytes + 32 : 0;
     int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
-    if (dot && !tune.lut_bytes)
+    if (angular32 && !tune.lut_bytes)
         table_bytes = std::min(table_bytes, std::max(4096, (kLdsTarget - aux - extra) & ~15));
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     qlo->assign(c->edges.D.size(), 0.0f);
@@ -591,12 +595,14 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
         *qhi = c->band.qhi;
         // the dot-product key's table and the per-pair band in p, after the
         // chord band's entries in qlo / qhi
-        c->pcells = make_cells32_top(c->edges, make_band_dot32(c->edges, delta), dot_top_key(delta),
-                                     pbytes / c->entry_bytes);
-        std::vector<float> plo, phi;
-        make_pband32(c->edges, delta, &plo, &phi);
-        qlo->insert(qlo->end(), plo.begin(), plo.end());
-        qhi->insert(qhi->end(), phi.begin(), phi.end());
+        if (dot) {
+            c->pcells = make_cells32_top(c->edges, make_band_dot32(c->edges, delta), dot_top_key(delta),
+                                         pbytes / c->entry_bytes);
+            std::vector<float> plo, phi;
+            make_pband32(c->edges, delta, &plo, &phi);
+            qlo->insert(qlo->end(), plo.begin(), plo.end());
+            qhi->insert(qhi->end(), phi.begin(), phi.end());
+        }
     } else {
         c->cells = make_cells64(c->edges, max_cells);
     }
