@@ -338,6 +338,44 @@ def test_dot_product_path_settles_large_angle_steps(ctx, patch):
         ctx.release_catalog(b)
 
 
+@pytest.mark.parametrize("max_cols", [256, 4096])
+def test_dot_path_staging_on_ragged_column_ranges(ctx, max_cols):
+    """The dot-product steps read their columns from LDS, staged in blocks of
+    64 per wavefront with the last block clamped to the column range's end.
+    Uneven catalogs of dense 3 x 3 deg clumps 20 to 40 deg apart (data: 5003
+    + 5004 points in two clumps, randoms: 9973 in a third), so that the pairs
+    across clumps are settled from p; 30 edges from 0.5 to 120 deg; short
+    column chunks (256 columns) or the default; row ranges that start the
+    auto-pair column ranges at odd offsets.  DD and DR equal the oracle on
+    the stored rows, and most steps were settled from p."""
+    g = synthcat.rng_for(98, 1)
+    pa = synthcat.uniform_patch(5003, (10.0, 13.0, 0.0, 3.0), g)
+    pb = synthcat.uniform_patch(5004, (30.0, 33.0, 5.0, 8.0), g)
+    d = tuple(np.concatenate([u, v]) for u, v in zip(pa, pb))
+    r = synthcat.uniform_patch(9973, (50.0, 53.0, 20.0, 23.0), g)
+    e = synthcat.log_edges(0.5, 120.0, 30)
+    a, b = ctx.upload_catalog(*d), ctx.upload_catalog(*r)
+    try:
+        ctx.set_tuning(max_cols=max_cols)
+        xa = tuple(c[ctx.catalog_order(a)] for c in oracle.radec_to_xyz(*d))
+        xb = tuple(c[ctx.catalog_order(b)] for c in oracle.radec_to_xyz(*r))
+        ctx.stats(reset=True)
+        for rb, re in [(0, 10007), (333, 7777), (1001, 10006)]:
+            got = ctx.count(tp.DD, a, e, precision=tp.FP32_CHORD, row_begin=rb, row_end=re)
+            assert np.array_equal(got, oracle.count(oracle.DD, xa, e, row_begin=rb, row_end=re)), ("DD", rb)
+            got = ctx.count(tp.DR, a, e, cat_b=b, precision=tp.FP32_CHORD, row_begin=rb, row_end=re)
+            assert np.array_equal(got, oracle.count(oracle.DR, xa, e, b_xyz=xb, row_begin=rb, row_end=re)), \
+                ("DR", rb)
+        st = ctx.stats(reset=True)
+        steps = st.pairs / 1024.0
+        assert st.one_slot_steps + st.two_slot_steps > 0.4 * steps
+        assert st.chord_steps < 0.5 * steps
+    finally:
+        ctx.set_tuning()
+        ctx.release_catalog(a)
+        ctx.release_catalog(b)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_pruning_keeps_counts_exact(ctx, patch, prec):
     """Exact tile pruning on the 30 x 30 deg patch: the same counts as the oracle, with
