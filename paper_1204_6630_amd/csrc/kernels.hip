@@ -646,6 +646,16 @@ __device__ __forceinline__ void bin_block(int slot, uint32_t n, const PairArgs &
         lds_add(__umul24((uint32_t)slot, k.rowstep) + k.lanebase, n);
 }
 
+// Row p of a wavefront lane whose rows start at ib: lane L holds the P
+// consecutive rows ib + P L ... ib + P L + P - 1.  Rows are stored in Morton
+// order, so a lane's rows lie close together and its pairs of a step span a
+// narrow range of angles: more lanes fall in one slot, or in two adjacent
+// ones, than with rows 64 apart.
+template <int P>
+__device__ __forceinline__ int row_of(int ib, int lane, int p) {
+    return ib + lane * P + p;
+}
+
 // One step: JN columns against the P rows of every lane.  All JN * P table
 // lookups are issued first; one test sends the wavefront to the rare path if
 // any lane needs it; then the JN * P histogram increments follow.
@@ -762,7 +772,7 @@ __device__ __forceinline__ uint32_t step_fp32(const PairArgs &a, const JobDev &j
                     // lanes read row ib)
                     int l = lane;
                     asm volatile("" : "+v"(l));
-                    int i = ib + p * kWaveSize + l;
+                    int i = row_of<P>(ib, l, p);
                     i = i < ie ? i : ib;
                     ent[t][p] = resolve_fp32<LUT8, M3>(ent[t][p], k.flag, q[t][p], s, a, jb, i, j + t, cnt.exact);
                 }
@@ -1148,7 +1158,7 @@ __device__ void rows_fp32(const PairArgs &a, const JobDev &jb, const Smem &s, co
     int ii[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        int i = ib + p * kWaveSize + lane;
+        int i = row_of<P>(ib, lane, p);
         ii[p] = i;
         const int il = i < ie ? i : ib;    // tail lanes read a valid row; masked below
         xi[p] = jb.ax32[il];
@@ -1213,7 +1223,7 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
     int ii[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        int i = ib + p * kWaveSize + lane;
+        int i = row_of<P>(ib, lane, p);
         ii[p] = i;
         int il = i < ie ? i : ib;
         xi[p] = jb.ax64[il];
