@@ -414,10 +414,10 @@ __device__ __forceinline__ void slot_range(uint32_t e_lo, uint32_t e_hi, uint32_
 
 // One slot for all of a lane's pairs (span 0).  When that holds on every lane
 // the step adds its pairs with one LDS atomic per lane instead of a lookup and
-// an atomic per pair.  A wavefront's 256 rows are consecutive in the Morton
-// order, so at angles large against their extent this is common (on the
-// octant workload 45 % of the FP32 steps that are not beyond the last edge
-// pass).
+// an atomic per pair.  A lane's rows (and a wavefront's 256) are consecutive
+// in the Morton order, so at angles large against their extent this is
+// common (on the octant workload 49 % of the FP32 steps that are not beyond
+// the last edge pass).
 __device__ __forceinline__ bool one_slot_step(uint32_t lo, uint32_t span, uint32_t n, const Consts &k,
                                               Counters &cnt) {
     if (!wave_all(span == 0))
