@@ -556,18 +556,18 @@ int compile_host(const Tuning &tune, const double *edges, int nbins, int precisi
     c->metric = metric;
     const int nslots = nbins + 2;
     c->entry_bytes = nslots <= kMaxSlots8 ? 1 : 2;
-    // angular FP32: by default the chord table fits kLdsTarget with the
-    // histograms and edges and, with the dot-product path, its table
-    // (kDotLutBytes) and the column staging (kStageBytes).  Pruned kernels
-    // take the chord path alone (the blocks they evaluate lie across edges)
-    // and give the chord table the room.
+    // FP32: by default the table fits kLdsTarget with the histograms and
+    // edges and, with the angular dot-product path, its table (kDotLutBytes)
+    // and the column staging (kStageBytes).  Pruned angular kernels take the
+    // chord path alone (the blocks they evaluate lie across edges) and give
+    // the chord table the room.
     const bool angular32 = !metric && precision == TPCF_FP32_CHORD;
     const bool dot = angular32 && !tune.prune;
     const int aux = aux_lds_bytes(nslots, hist_copies_of(tune, nslots), nbins + 1);
     const int pbytes = dot ? kDotLutBytes : 0;
     const int extra = dot ? pbytes + kStageBytes + 32 : 0;
     int table_bytes = tune.lut_bytes ? tune.lut_bytes : kMaxLutBytes;
-    if (angular32 && !tune.lut_bytes)
+    if (precision == TPCF_FP32_CHORD && !tune.lut_bytes)
         table_bytes = std::min(table_bytes, std::max(4096, (kLdsTarget - aux - extra) & ~15));
     const int max_cells = std::min(table_bytes, kMaxLutBytes) / c->entry_bytes;
     qlo->assign(c->edges.D.size(), 0.0f);

@@ -20,11 +20,19 @@ constexpr int kMaxLutCells = kMaxLutBytes;        // with one-byte entries
 // tables' default budget (table, histograms and thresholds together).
 constexpr int kMaxDirectLutBytes = 33792;
 constexpr int kWrapLutBytes = 32768;
-// Angular FP32 launches also hold the dot-product key's cell table (bytes),
-// and by default size the chord table so that a block's LDS stays within
-// kLdsTarget (five blocks of four wavefronts in a CU's 160 KiB).
+// Angular FP32 launches also hold the dot-product key's cell table (bytes).
+// By default FP32 launches with clamped tables size them so that a block's
+// LDS stays within kLdsTarget: six blocks of four wavefronts in a CU's
+// 160 KiB, the occupancy those kernels are compiled for (waves_per_eu).
 constexpr int kDotLutBytes = 1024;
-constexpr int kLdsTarget = 32768;
+constexpr int kLdsTarget = 27296;
+// Wavefronts per SIMD a pair kernel is compiled for: 6 for the FP32 paths
+// with clamped tables (0, 5, 6; at most 80 VGPRs, a few spilled), 5 for the
+// FP64 paths (1, 4) and the wrapped FP32 tables (3, 7), whose 32 KB of LDS
+// per block allows no more.
+constexpr int waves_per_eu_of(int path) {
+    return path == 0 || path == 5 || path == 6 ? 6 : 5;
+}
 // Dot-product kernels: each wavefront stages kStageCols columns at a time in
 // LDS, in two buffers of x, y and z floats.
 constexpr int kStageCols = 64;

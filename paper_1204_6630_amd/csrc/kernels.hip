@@ -1259,7 +1259,8 @@ __device__ void rows_fp64(const PairArgs &a, const JobDev &jb, const Smem &s, co
 // clamped table, 4 FP64 vector.  P: rows per lane (a wavefront covers P * 64
 // rows of a unit).
 template <int PREC, bool LUT8, int P, bool PRUNE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void pairs_kernel(PairArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu_of(PREC)))) void pairs_kernel(
+    PairArgs a) {
     constexpr int kRowsPerWave = P * kWaveSize;
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem s = carve(smem, a);
