@@ -22,13 +22,16 @@ import time
 import numpy as np
 
 METRIC = "exact-count Gpairs/s, FP32-chord vs FP64 path; p50/p99 job latency"
-# ALU roofline of the FP32-chord path: 256 CUs x 4 SIMDs x 32 FP32 lanes x
-# 2.4 GHz = 78.6e12 FP32 lane operations per second (157.3 TFLOP/s counting an
-# FMA as two), and a pair needs at least 7 of them: 3 subtractions, one
-# multiply and two FMAs for the squared chord, one shift for the table key.
+# ALU roofline of the FP32 angular kernel: 256 CUs x 4 SIMDs x 32 FP32 lanes
+# x 2.4 GHz = 78.6e12 FP32 lane operations per second (157.3 TFLOP/s counting
+# an FMA as two).  The kernel decides a pair from the dot product of the FP32
+# copies where that suffices, so a pair needs at least 4 of them: one
+# multiply and two FMAs for p, one to bin it.  Chord-only kernels (pruned
+# launches) and the 3-D squared distance need at least 7: 3 subtractions,
+# one multiply and two FMAs, and the table key.
 FP32_LANE_OPS = 256 * 4 * 32 * 2.4e9
-OPS_PER_PAIR_FP32 = 7
-PEAK_GPAIRS = FP32_LANE_OPS / OPS_PER_PAIR_FP32 / 1e9
+OPS_PER_PAIR_FP32 = 4
+OPS_PER_PAIR_CHORD = 7
 # FP64 vector path: 78.6e12 FP64 lane operations per second; a pair needs 6
 # (three products, two sums, 1 - d) plus the key.
 FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -465,8 +468,7 @@ def main():
                   # the roofline of the pairs the kernel still evaluated
                   "roofline_evaluated_pairs": roofline(
                       tp.FP32_CHORD, evaluated / (kms / 1e3) / 1e9, kms / (3 * args.steps),
-                      kernel="pairs_kernel<6> with pruning (FP32)"
-                      if float(edges[-1]) < 90.0 else "pairs_kernel<0> with pruning (FP32 chord)"),
+                      kernel="pairs_kernel<0> with pruning (FP32 chord)", ops_per_pair=OPS_PER_PAIR_CHORD),
                   "note": "exact tile pruning (tuning prune=1): same counts; pairs of pruned "
                           "blocks are not evaluated, so not comparable to value"}
     jack = None
@@ -505,9 +507,7 @@ def main():
                 "ms_per_step": round(ms, 3), "kernel_ms_per_step": round(kms / args.steps, 3),
                 "roofline": roofline(tp.FP32_CHORD, pairs_step * args.steps / (kms / 1e3) / 1e9,
                                      kms / (3 * args.steps),
-                                     kernel="pairs_kernel<6> with region copies (FP32)"
-                                     if float(edges[-1]) < 90.0 else
-                                     "pairs_kernel<0> with region copies (FP32 chord)"),
+                                     kernel="pairs_kernel<6> with region copies (FP32)"),
                 "over_plain_step": round(ms / sums[tp.FP32_CHORD]["ms_per_step"], 3),
                 "note": "DD+DR+RR with per-region counts (FP32 chord) + host jackknife of w; "
                         "same totals as the plain step"}
@@ -562,7 +562,7 @@ def main():
                 "roofline": roofline(prec, pairs3 * args.steps / (kms / 1e3) / 1e9, kms / max(1, nl),
                                      kernel={tp.FP32_CHORD: "pairs_kernel<5> (3-D FP32)",
                                              tp.FP64: "pairs_kernel<4> (3-D FP64)"}[prec],
-                                     ops_per_pair=7 if prec == tp.FP32_CHORD else 8)}
+                                     ops_per_pair=OPS_PER_PAIR_CHORD if prec == tp.FP32_CHORD else 8)}
         for other in (tp.FP64,):
             if not all(np.array_equal(a, b) for a, b in zip(hist3[tp.FP32_CHORD], hist3[other])):
                 sys.exit("3-D histograms differ between precisions")
