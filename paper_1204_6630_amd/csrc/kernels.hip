@@ -1032,10 +1032,11 @@ __device__ __forceinline__ int dot_run(const PairArgs &a, const JobDev &jb, cons
     asm volatile("" : "+s"(px), "+s"(py), "+s"(pz));
     int cb = j;
     uint32_t buf = 0;
-    stage_columns(px, py, pz, lane, cb, j1 - W, st0);
-    // the first block has landed (and so have copies still in flight from an
-    // earlier run, which all target this wavefront's buffers)
+    // a copy still in flight from an earlier run (into either buffer) lands
+    // before the first block is copied, then the first block lands
     __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
+    stage_columns(px, py, pz, lane, cb, j1 - W, st0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     bool more = cb + C + W <= j1;
     if (more)
         stage_columns(px, py, pz, lane, cb + C, j1 - W, st0 + C * 12);
